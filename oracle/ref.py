@@ -1,0 +1,308 @@
+"""ctypes front-end of the C tier of the CPU oracle (test infrastructure only).
+
+The C tier (``bmg_oracle.c``) computes the BoxMG V-cycle in FP64 (and the FP32
+cycle of iterative refinement) in the paper's order of operations: Section 2
+and Fig. vcycle_flowchart for the cycle, Fig. restrict_kernel for restriction,
+Fig. stencil_operator for the nine-point stencil.  This module only marshals
+NumPy arrays; it does no arithmetic of the method.
+
+Array convention: level arrays are ``(n+2, n+2)`` float64, indexed ``[j, i]``
+with the Dirichlet ring at 0 and n+1.  Interpolation weights are
+``(8, nc+2, nc+2)`` in the plane order LNE, LA, LNW, LR, LL, LSE, LB, LSW.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+_dp = C.POINTER(C.c_double)
+_fp = C.POINTER(C.c_float)
+
+WEIGHT_PLANES = ("LNE", "LA", "LNW", "LR", "LL", "LSE", "LB", "LSW")
+FIELDS = {"O": 0, "W": 1, "S": 2, "SW": 3, "NW": 4, "Ci": 5, "u": 6, "b": 7, "r": 8}
+
+
+class OracleError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: oracle status {status}")
+        self.status = status
+
+
+def lib():
+    """Load (building first if the sources are newer) the oracle library."""
+    global _lib
+    if _lib is None:
+        if _build.needs_build():
+            _build.build()
+        L = C.CDLL(_build.LIB)
+        L.orc_discretize.argtypes = [C.c_int, _dp, _dp, _dp, _dp]
+        L.orc_discretize.restype = C.c_int
+        L.orc_interp_weights.argtypes = [C.c_int, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.orc_interp_weights.restype = C.c_int
+        L.orc_rap.argtypes = [C.c_int] + [_dp] * 11
+        L.orc_rap.restype = C.c_int
+        L.orc_ldlt_factor.argtypes = [C.c_int, _dp, _dp, _dp]
+        L.orc_ldlt_factor.restype = C.c_int
+        L.orc_ldlt_solve.argtypes = [C.c_int, _dp, _dp, _dp, _dp]
+        L.orc_ldlt_solve.restype = None
+        L.orc_sumsq.argtypes = [C.c_int, _dp]
+        L.orc_sumsq.restype = C.c_double
+        for nm, p in (("orc_gs", _dp), ("orc_gs_f", _fp)):
+            fn = getattr(L, nm)
+            fn.argtypes = [C.c_int] + [p] * 7 + [C.c_int]
+            fn.restype = None
+        for nm, p in (("orc_residual", _dp), ("orc_residual_f", _fp)):
+            fn = getattr(L, nm)
+            fn.argtypes = [C.c_int] + [p] * 8
+            fn.restype = None
+        for nm, p in (("orc_restrict", _dp), ("orc_restrict_f", _fp),
+                      ("orc_interp_add", _dp), ("orc_interp_add_f", _fp)):
+            fn = getattr(L, nm)
+            fn.argtypes = [C.c_int, p, p, p]
+            fn.restype = None
+        L.orc_setup.argtypes = [C.c_int, C.c_int, _dp, C.c_int, C.c_int, C.POINTER(C.c_int)]
+        L.orc_setup.restype = C.c_void_p
+        L.orc_destroy.argtypes = [C.c_void_p]
+        L.orc_destroy.restype = None
+        L.orc_num_levels.argtypes = [C.c_void_p]
+        L.orc_num_levels.restype = C.c_int
+        L.orc_level_n.argtypes = [C.c_void_p, C.c_int]
+        L.orc_level_n.restype = C.c_int
+        L.orc_field.argtypes = [C.c_void_p, C.c_int, C.c_int]
+        L.orc_field.restype = _dp
+        L.orc_coarse_factor.argtypes = [C.c_void_p, _dp, _dp]
+        L.orc_coarse_factor.restype = None
+        L.orc_vcycle.argtypes = [C.c_void_p, _dp, _dp]
+        L.orc_vcycle.restype = None
+        L.orc_step.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int]
+        L.orc_step.restype = None
+        L.orc_rel_residual.argtypes = [C.c_void_p, _dp, _dp]
+        L.orc_rel_residual.restype = C.c_double
+        L.orc_solve.argtypes = [C.c_void_p, _dp, _dp, C.c_double, C.c_int, _dp]
+        L.orc_solve.restype = C.c_int
+        L.orc_solve_ir.argtypes = [C.c_void_p, _dp, _dp, C.c_double, C.c_int, _dp]
+        L.orc_solve_ir.restype = C.c_int
+        L.orc_make_f32.argtypes = [C.c_void_p]
+        L.orc_make_f32.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray | None, dtype=np.float64):
+    if a is None:
+        return None
+    if a.dtype != dtype or not a.flags.c_contiguous:
+        raise TypeError("oracle arrays must be C-contiguous of the expected dtype")
+    return a.ctypes.data_as(_dp if dtype == np.float64 else _fp)
+
+
+def _c(a, dtype=np.float64):
+    return None if a is None else np.ascontiguousarray(a, dtype=dtype)
+
+
+# --------------------------------------------------------------- helpers
+def pad(a: np.ndarray) -> np.ndarray:
+    """Interior ``(n, n)`` array -> ``(n+2, n+2)`` with a zero ring."""
+    n = a.shape[0]
+    out = np.zeros((n + 2, n + 2), dtype=a.dtype)
+    out[1:-1, 1:-1] = a
+    return out
+
+
+def compact_from_stencil(st: np.ndarray):
+    """``[n][n][K]`` stencil (K=5: S,W,O,E,N; K=9: SW,S,SE,W,O,E,NW,N,NE) ->
+    padded compact planes ``(O, W, S, SW, NW)``; SW/NW are None for K=5."""
+    n, _, K = st.shape
+    if K == 5:
+        return pad(st[:, :, 2]), pad(st[:, :, 1]), pad(st[:, :, 0]), None, None
+    return (pad(st[:, :, 4]), pad(st[:, :, 3]), pad(st[:, :, 1]),
+            pad(st[:, :, 0]), pad(st[:, :, 6]))
+
+
+# ------------------------------------------------------------ operations
+def discretize(k: np.ndarray, f: np.ndarray):
+    """Five-point vertex-centred operator and right-hand side ``h^2 f``."""
+    n = f.shape[0]
+    k = _c(k)
+    f = _c(f)
+    st = np.zeros((n, n, 5))
+    rhs = np.zeros((n, n))
+    s = lib().orc_discretize(n, _p(k), _p(f), _p(st), _p(rhs))
+    if s:
+        raise OracleError(s, "discretize")
+    return st, rhs
+
+
+def interp_weights(O, W, S, SW=None, NW=None):
+    nf = O.shape[0] - 2
+    nc = (nf - 1) // 2
+    Ci = np.zeros((8, nc + 2, nc + 2))
+    s = lib().orc_interp_weights(nf, _p(_c(O)), _p(_c(W)), _p(_c(S)), _p(_c(SW)),
+                                 _p(_c(NW)), _p(Ci))
+    if s:
+        raise OracleError(s, "interp_weights")
+    return Ci
+
+
+def rap(O, W, S, SW, NW, Ci):
+    nf = O.shape[0] - 2
+    nc = (nf - 1) // 2
+    out = [np.zeros((nc + 2, nc + 2)) for _ in range(5)]
+    s = lib().orc_rap(nf, _p(_c(O)), _p(_c(W)), _p(_c(S)), _p(_c(SW)), _p(_c(NW)),
+                      _p(_c(Ci)), *[_p(o) for o in out])
+    if s:
+        raise OracleError(s, "rap")
+    return tuple(out)
+
+
+def ldlt_factor(A: np.ndarray):
+    m = A.shape[0]
+    L = np.zeros((m, m))
+    D = np.zeros(m)
+    s = lib().orc_ldlt_factor(m, _p(_c(A)), _p(L), _p(D))
+    if s:
+        raise OracleError(s, "ldlt_factor")
+    return L, D
+
+
+def ldlt_solve(L, D, b):
+    m = L.shape[0]
+    x = np.zeros(m)
+    lib().orc_ldlt_solve(m, _p(_c(L)), _p(_c(D)), _p(_c(b)), _p(x))
+    return x
+
+
+def sumsq(r: np.ndarray) -> float:
+    """Accurately rounded sum of squares over the interior of a padded array."""
+    return lib().orc_sumsq(r.shape[0] - 2, _p(_c(r)))
+
+
+def gs(O, W, S, SW, NW, b, u, sweeps=1, dtype=np.float64):
+    """Four-colour Gauss-Seidel sweeps; returns the updated copy of ``u``."""
+    u = np.array(u, dtype=dtype, copy=True)
+    fn = lib().orc_gs if dtype == np.float64 else lib().orc_gs_f
+    fn(O.shape[0] - 2, *[_p(_c(a, dtype), dtype) for a in (O, W, S, SW, NW, b)],
+       _p(u, dtype), sweeps)
+    return u
+
+
+def residual(O, W, S, SW, NW, b, u, dtype=np.float64):
+    r = np.zeros_like(np.asarray(u, dtype=dtype))
+    fn = lib().orc_residual if dtype == np.float64 else lib().orc_residual_f
+    fn(O.shape[0] - 2, *[_p(_c(a, dtype), dtype) for a in (O, W, S, SW, NW, b, u)],
+       _p(r, dtype))
+    return r
+
+
+def restrict(Ci, r, dtype=np.float64):
+    nf = r.shape[0] - 2
+    nc = (nf - 1) // 2
+    bc = np.zeros((nc + 2, nc + 2), dtype=dtype)
+    fn = lib().orc_restrict if dtype == np.float64 else lib().orc_restrict_f
+    fn(nf, _p(_c(Ci, dtype), dtype), _p(_c(r, dtype), dtype), _p(bc, dtype))
+    return bc
+
+
+def interp_add(Ci, ec, u, dtype=np.float64):
+    u = np.array(u, dtype=dtype, copy=True)
+    fn = lib().orc_interp_add if dtype == np.float64 else lib().orc_interp_add_f
+    fn(u.shape[0] - 2, _p(_c(Ci, dtype), dtype), _p(_c(ec, dtype), dtype), _p(u, dtype))
+    return u
+
+
+# ------------------------------------------------------------- hierarchy
+class Hierarchy:
+    """FP64 BoxMG hierarchy built from a ``[n][n][K]`` stencil."""
+
+    def __init__(self, stencil: np.ndarray, nu1: int = 2, nu2: int = 1):
+        st = _c(stencil)
+        n, _, K = st.shape
+        status = C.c_int(0)
+        h = lib().orc_setup(n, K, _p(st), nu1, nu2, C.byref(status))
+        if not h:
+            raise OracleError(status.value, "setup")
+        self._h = h
+        self.n = n
+        self.K = K
+        self.nu1, self.nu2 = nu1, nu2
+        self.nlev = lib().orc_num_levels(h)
+
+    def close(self):
+        if self._h:
+            lib().orc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def level_n(self, l: int) -> int:
+        return lib().orc_level_n(self._h, l)
+
+    def field(self, l: int, name: str) -> np.ndarray | None:
+        """Copy of a level array (O, W, S, SW, NW, Ci, u, b, r)."""
+        ptr = lib().orc_field(self._h, l, FIELDS[name])
+        if not ptr:
+            return None
+        n = self.level_n(l)
+        if name == "Ci":
+            nc = self.level_n(l + 1)
+            shape = (8, nc + 2, nc + 2)
+        else:
+            shape = (n + 2, n + 2)
+        return np.ctypeslib.as_array(ptr, shape=shape).copy()
+
+    def set_field(self, l: int, name: str, value: np.ndarray) -> None:
+        ptr = lib().orc_field(self._h, l, FIELDS[name])
+        n = self.level_n(l)
+        dst = np.ctypeslib.as_array(ptr, shape=(n + 2, n + 2))
+        dst[...] = value
+
+    def op(self, l: int):
+        return tuple(self.field(l, nm) for nm in ("O", "W", "S", "SW", "NW"))
+
+    def coarse_factor(self):
+        L = np.zeros(81)
+        D = np.zeros(9)
+        lib().orc_coarse_factor(self._h, _p(L), _p(D))
+        return L.reshape(9, 9), D
+
+    def step(self, l: int, op: str, arg: int = 1) -> None:
+        code = {"smooth": 0, "residual": 1, "restrict": 2, "interp": 3, "coarse": 4}[op]
+        lib().orc_step(self._h, l, code, arg)
+
+    def vcycle(self, b: np.ndarray, u: np.ndarray) -> np.ndarray:
+        u = np.array(u, dtype=np.float64, copy=True)
+        lib().orc_vcycle(self._h, _p(_c(b)), _p(u))
+        return u
+
+    def rel_residual(self, b, u) -> float:
+        return lib().orc_rel_residual(self._h, _p(_c(b)), _p(_c(u)))
+
+    def solve(self, b: np.ndarray, u: np.ndarray | None = None, tol: float = 1e-10,
+              max_cycles: int = 100):
+        """Returns ``(u, history)``; history[k] = ||b - A u^{k+1}|| / ||b||."""
+        u = np.zeros_like(b) if u is None else np.array(u, dtype=np.float64, copy=True)
+        hist = np.zeros(max_cycles)
+        k = lib().orc_solve(self._h, _p(_c(b)), _p(u), tol, max_cycles, _p(hist))
+        if k < 0:
+            raise OracleError(k, "solve")
+        return u, hist[:k].copy()
+
+    def solve_ir(self, b: np.ndarray, x: np.ndarray | None = None, tol: float = 1e-10,
+                 max_iter: int = 100):
+        """FP32-preconditioned FP64 iterative refinement; returns ``(x, history)``
+        with history[0] the initial relative residual."""
+        x = np.zeros_like(b) if x is None else np.array(x, dtype=np.float64, copy=True)
+        hist = np.zeros(max_iter + 1)
+        k = lib().orc_solve_ir(self._h, _p(_c(b)), _p(x), tol, max_iter, _p(hist))
+        if k < 0:
+            raise OracleError(k, "solve_ir")
+        return x, hist[:k + 1].copy()
