@@ -1,0 +1,202 @@
+/*
+ * bmg.h - C interface of the MI355X (gfx950) black-box multigrid library.
+ *
+ * The library solves the stencil system A u = b that a standard
+ * finite-difference discretisation of the 2D diffusion problem
+ * -div(k grad u) = f gives on a vertex-centred grid (Section 2, Eq. 1 of the
+ * paper), with the BoxMG V-cycle of Section 2 and Fig. vcycle_flowchart:
+ * Gauss-Seidel relaxation, residual, restriction, recursion to a direct solve
+ * on the coarsest grid, interpolation, relaxation.  Coarse operators are built
+ * by local stencil operations (Section 2), restriction follows
+ * Fig. restrict_kernel and the stencil of each point is the nine-point stencil
+ * of Fig. stencil_operator.  Every step runs in hand-written HIP kernels.
+ *
+ * Conventions for every entry point:
+ *  - Grids: interior n x n with n = 2^m - 1, m >= 2; the mesh width is
+ *    h = 1/(n+1); level l has n_l = 2^(m-l) - 1 down to n_L = 3.
+ *  - Pointers are DEVICE pointers unless the comment says "host".
+ *  - Work is enqueued on the stream given at set-up (NULL = the null stream);
+ *    entry points that return a number to the host synchronise that stream.
+ *  - Kernels never allocate: the caller supplies one workspace buffer of the
+ *    size bmg_workspace_bytes() reports.  The library keeps pointers into it
+ *    and into nothing else.
+ *  - Status codes only: no entry point throws or aborts; a failed call leaves
+ *    a one-line description for bmg_last_error() (per host thread).
+ *  - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef BMG_H
+#define BMG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bmg_solver bmg_solver;
+typedef void *bmg_stream; /* a hipStream_t */
+
+typedef enum {
+    BMG_OK = 0,
+    BMG_EINVAL = -1,      /* bad argument: size, pointer, option, stencil value */
+    BMG_EBREAKDOWN = -2,  /* interpolation denominator or coarse pivot <= 0 */
+    BMG_ENOCONV = -3,     /* max_cycles reached before tol */
+    BMG_EDIVERGED = -4,   /* residual grew by 1e3 or became non-finite */
+    BMG_EDEVICE = -5,     /* a HIP runtime call failed */
+    BMG_EWORKSPACE = -6   /* workspace missing, too small or misaligned */
+} bmg_status;
+
+enum { BMG_STENCIL_5PT = 5, BMG_STENCIL_9PT = 9 };
+enum { BMG_FP64 = 0, BMG_FP32_IR = 1 };
+enum { BMG_KERNELS_BASIC = 0, BMG_KERNELS_FUSED = 1 };
+
+typedef struct {
+    int nu1;         /* pre-smoothing sweeps (default 2) */
+    int nu2;         /* post-smoothing sweeps (default 1) */
+    int max_cycles;  /* cycle (or refinement step) limit of bmg_solve (default 100) */
+    int precision;   /* BMG_FP64, or BMG_FP32_IR: FP32 V-cycle inside FP64
+                        iterative refinement (default BMG_FP64) */
+    int kernels;     /* BMG_KERNELS_FUSED (default) or BMG_KERNELS_BASIC: one
+                        launch per colour and per step, for comparison */
+    int check_every; /* bmg_solve reads the residual history back every this many
+                        cycles; cycles past convergence are skipped on the device,
+                        so the iterates do not depend on it (default 8) */
+    int reserved[10];
+} bmg_options;
+
+typedef struct {
+    int cycles;       /* V-cycles (FP64) or refinement steps (FP32_IR) performed */
+    double rel_res;   /* final ||b - A x||_2 / ||b||_2 */
+    double rho;       /* geometric-mean reduction factor per cycle over the run */
+    double *history;  /* host, caller-owned, max_cycles+1 entries, or NULL:
+                         FP64: history[k] = relative residual after cycle k+1;
+                         FP32_IR: history[0] is the initial relative residual,
+                         history[k] the one after correction k */
+} bmg_info;
+
+/* Fills *o with the defaults above.  Host only. */
+bmg_status bmg_default_options(bmg_options *o);
+
+/* Bytes of device workspace bmg_setup needs for an n x n grid of the given
+ * stencil kind (5 or 9) and options (o may be NULL for the defaults).  The
+ * workspace must be 256-byte aligned.  Host only; no device call. */
+bmg_status bmg_workspace_bytes(int n, int kind, const bmg_options *o, size_t *bytes);
+
+/* Discretisation of -div(k grad u) = f (Section 2, Eq. 1) on the n x n
+ * interior grid, vertex-centred, with cell-constant k: the coupling across the
+ * dual-cell face between two neighbouring vertices is minus the mean of the two
+ * cells sharing that grid edge, the centre is minus the sum of the four
+ * couplings (taken before couplings to the Dirichlet boundary are set to zero),
+ * and the right-hand side is h^2 f.
+ *   k:       (n+1) x (n+1) cell coefficients, row-major, k[jc][ic], positive;
+ *   f:       n x n source, row-major, f[j-1][i-1];
+ *   stencil: out, n x n x 5 in the order S, W, O, E, N (signed matrix entries);
+ *   rhs:     out, n x n.
+ * Enqueued on `stream`; no synchronisation.  BMG_EINVAL on a bad n or NULL. */
+bmg_status bmg_discretize(const double *k, const double *f, int n, double *stencil,
+                          double *rhs, bmg_stream stream);
+
+/* Builds the multigrid hierarchy of the symmetric stencil operator (Section 2:
+ * coarse operators through local stencil operations):
+ *   per level, operator-induced interpolation weights (collapsed stencil, with
+ *   positive off-diagonal entries moved onto the diagonal before the collapse),
+ *   stored as the eight planes LNE, LA, LNW, LR, LL, LSE, LB, LSW of
+ *   Fig. restrict_kernel at the coarse point north-east of each F-point triple;
+ *   the Galerkin coarse operator P^T A P as a nine-point stencil; and the
+ *   square-root-free Cholesky (LDL^T) factor of the coarsest 9 x 9 matrix.
+ *   stencil: n x n x kind, row-major; kind 5: S, W, O, E, N; kind 9: SW, S, SE,
+ *            W, O, E, NW, N, NE (the rows of Fig. stencil_operator, south first).
+ *            Signed matrix entries, entries toward boundary vertices zero, the
+ *            operator symmetric (A_E(i,j) = A_W(i+1,j) etc. to 1e-14 relative),
+ *            A_O > 0, all finite.  Copied; not referenced after the call.
+ *   workspace: device buffer of ws_bytes >= bmg_workspace_bytes(); it must
+ *            outlive the handle.
+ * Synchronises `stream` once (to read the validation and breakdown flags).
+ * Errors: BMG_EINVAL (size, kind, NULL, stencil values), BMG_EWORKSPACE,
+ * BMG_EBREAKDOWN, BMG_EDEVICE.  *out is NULL on failure. */
+bmg_status bmg_setup(bmg_solver **out, const double *stencil, int n, int kind,
+                     const bmg_options *o, void *workspace, size_t ws_bytes,
+                     bmg_stream stream);
+
+/* One V(nu1,nu2)-cycle (Fig. vcycle_flowchart) on A x = rhs, in the
+ * precision of the options (FP32_IR: one refinement step).
+ *   rhs, x: n x n row-major; x is the initial guess in and the iterate out.
+ *   rel_res: host, nullable; if given, receives ||rhs - A x||_2/||rhs||_2 of
+ *   the new iterate (this synchronises the stream).  */
+bmg_status bmg_vcycle(bmg_solver *h, const double *rhs, double *x, double *rel_res);
+
+/* Cycles from the initial guess x until ||rhs - A x||_2 / ||rhs||_2 <= tol
+ * (checked after every cycle) or max_cycles.  rhs, x as in bmg_vcycle.
+ * info (host, nullable) receives the count, final residual and history.
+ * ||rhs|| = 0 gives x = 0 after 0 cycles.  Returns BMG_ENOCONV if max_cycles
+ * was reached (x and info still valid), BMG_EDIVERGED if the residual became
+ * non-finite or grew 1e3-fold over its initial value. */
+bmg_status bmg_solve(bmg_solver *h, const double *rhs, double *x, double tol,
+                     bmg_info *info);
+
+/* Releases the handle (host memory only; the workspace stays the caller's). */
+bmg_status bmg_destroy(bmg_solver *h);
+
+const char *bmg_status_string(int status);
+const char *bmg_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Level access and single steps, on the hierarchy's own level arrays.  These
+ * expose each step of the cycle for testing and tracing.
+ * ---------------------------------------------------------------------- */
+
+/* Fields of a level.  Transfers use the tight layout:
+ *   level arrays: (n_l+2) x (n_l+2) row-major with the Dirichlet ring;
+ *   BMG_F_CI: 8 x (n_{l+1}+2) x (n_{l+1}+2), planes LNE, LA, LNW, LR, LL, LSE,
+ *   LB, LSW (the weights between level l and l+1);
+ *   BMG_F_COARSE_LD: the coarsest factor, 81 entries of L (row-major, unit
+ *   lower triangular) followed by the 9 entries of D (level argument ignored).
+ * The *32 fields are the FP32 hierarchy (precision BMG_FP32_IR only) and
+ * transfer float data. */
+enum {
+    BMG_F_U = 0, BMG_F_B = 1, BMG_F_R = 2,
+    BMG_F_AO = 3, BMG_F_AW = 4, BMG_F_AS = 5, BMG_F_ASW = 6, BMG_F_ANW = 7,
+    BMG_F_CI = 8, BMG_F_COARSE_LD = 9,
+    BMG_F_U32 = 16, BMG_F_B32 = 17, BMG_F_R32 = 18,
+    BMG_F_AO32 = 19, BMG_F_AW32 = 20, BMG_F_AS32 = 21, BMG_F_ASW32 = 22,
+    BMG_F_ANW32 = 23, BMG_F_CI32 = 24
+};
+
+bmg_status bmg_num_levels(const bmg_solver *h, int *nlev);
+bmg_status bmg_level_n(const bmg_solver *h, int level, int *n);
+/* Device-to-device copies in the tight layout; enqueued on the stream. */
+bmg_status bmg_export(bmg_solver *h, int level, int field, void *dst);
+bmg_status bmg_import(bmg_solver *h, int level, int field, const void *src);
+
+/* Steps on level `level` (all on the handle's arrays, in the precision of
+ * the field set named by `fp32`: 0 = FP64, 1 = FP32 hierarchy):
+ *   BMG_STEP_SMOOTH:   `arg` four-colour Gauss-Seidel sweeps of u with b;
+ *   BMG_STEP_RESIDUAL: r = b - A u;
+ *   BMG_STEP_RESTRICT: b_{l+1} = P^T r (Fig. restrict_kernel), u_{l+1} = 0;
+ *   BMG_STEP_INTERP:   u += P u_{l+1};
+ *   BMG_STEP_COARSE:   u = A^{-1} b on the coarsest level (FP64 factor);
+ *   BMG_STEP_PRE:      the fused pre-smoothing pass: arg sweeps, residual and
+ *                      restriction (results equal to SMOOTH, RESIDUAL,
+ *                      RESTRICT in turn, r left unspecified);
+ *   BMG_STEP_POST:     the fused post pass: INTERP then arg sweeps.
+ * Enqueued on the stream. */
+enum {
+    BMG_STEP_SMOOTH = 0, BMG_STEP_RESIDUAL = 1, BMG_STEP_RESTRICT = 2,
+    BMG_STEP_INTERP = 3, BMG_STEP_COARSE = 4, BMG_STEP_PRE = 5, BMG_STEP_POST = 6
+};
+bmg_status bmg_step(bmg_solver *h, int level, int step, int arg, int fp32);
+
+/* Kernel timing with HIP events on the handle's stream.  While enabled, every
+ * launch of the kernels of class `kclass` on level `level` is bracketed by an
+ * event pair (at most 65536 pairs are kept).  bmg_trace_read synchronises the
+ * stream and returns the number of launches timed and their total duration in
+ * milliseconds, then clears the record.  Classes: */
+enum { BMG_TRACE_SMOOTH = 0, BMG_TRACE_PRE = 1, BMG_TRACE_POST = 2, BMG_TRACE_RESNORM = 3 };
+bmg_status bmg_trace_enable(bmg_solver *h, int kclass, int level, int on);
+bmg_status bmg_trace_read(bmg_solver *h, int *launches, double *total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BMG_H */

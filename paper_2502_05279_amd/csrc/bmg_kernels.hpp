@@ -1,0 +1,630 @@
+// HIP kernels (gfx950) of the black-box multigrid V-cycle: discretisation,
+// set-up (operator-induced interpolation, Galerkin coarse operators, coarsest
+// LDL^T factor) and the per-level cycle steps (four-colour Gauss-Seidel,
+// residual, restriction, interpolation, norms).
+//
+// All floating-point expressions are written in one fixed order and the
+// library is compiled with -ffp-contract=off, so every point's result is the
+// correctly rounded value of that expression sequence (IEEE division
+// included); schedules that respect the colour dependencies produce the same
+// bits.
+//
+// Level arrays are (n+2) rows of `ld` elements, row j (north) after row j-1,
+// element (i,j) at j*ld + i; rows/columns 0 and n+1 are the Dirichlet ring and
+// hold zeros.  Stencils are symmetric-compact: O, W, S on every level plus SW,
+// NW on nine-point levels; the east / north / north-east / south-east entries
+// of point p are W(p+1), S(p+ld), SW(p+ld+1), NW(p+1-ld).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bmg {
+
+template <typename T>
+struct Lev {
+    int n;   // interior points per side
+    int ld;  // row pitch (elements)
+    T *u, *b, *r;
+    T *O, *W, *S, *SW, *NW;  // SW, NW null on five-point levels
+};
+
+// Weights between a fine level and the next coarser one: 8 planes
+// (LNE, LA, LNW, LR, LL, LSE, LB, LSW) of the coarse level's shape.
+template <typename T>
+struct Wts {
+    T *p;
+    int ld;       // coarse row pitch
+    size_t ps;    // plane stride (elements)
+    __device__ __forceinline__ T at(int plane, size_t c) const { return p[plane * ps + c]; }
+};
+
+enum : int { LNE = 0, LA = 1, LNW = 2, LR = 3, LL = 4, LSE = 5, LB = 6, LSW = 7 };
+
+// validation / breakdown flag bits
+enum : int {
+    F_NONFINITE = 1, F_DIAG = 2, F_BOUNDARY = 4, F_ASYM = 8,
+    F_BREAK_INTERP = 16, F_BREAK_COARSE = 32
+};
+
+__device__ __forceinline__ bool stopped(const int *stop) { return stop && *stop; }
+
+// --------------------------------------------------------------- discretise
+// Vertex-centred five-point operator of -div(k grad u) = f, cell-constant k:
+// coupling = -(mean of the two cells sharing the grid edge), centre = minus the
+// sum of the four couplings (before the boundary couplings are zeroed),
+// right-hand side h^2 f.  Output [n][n][5] = S, W, O, E, N.
+__global__ void k_discretize(const double *__restrict__ k, const double *__restrict__ f,
+                             int n, double h2, double *__restrict__ st,
+                             double *__restrict__ rhs)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x + 1;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y + 1;
+    if (i > n || j > n) return;
+    const size_t lk = (size_t)n + 1;
+    const double kSW = k[(size_t)(j - 1) * lk + (i - 1)];
+    const double kSE = k[(size_t)(j - 1) * lk + i];
+    const double kNW = k[(size_t)j * lk + (i - 1)];
+    const double kNE = k[(size_t)j * lk + i];
+    double aW = -0.5 * (kSW + kNW);
+    double aE = -0.5 * (kSE + kNE);
+    double aS = -0.5 * (kSW + kSE);
+    double aN = -0.5 * (kNW + kNE);
+    const double aO = -(((aW + aE) + aS) + aN);
+    if (i == 1) aW = 0.0;
+    if (i == n) aE = 0.0;
+    if (j == 1) aS = 0.0;
+    if (j == n) aN = 0.0;
+    const size_t q = (size_t)(j - 1) * n + (i - 1);
+    double *o = st + q * 5;
+    o[0] = aS; o[1] = aW; o[2] = aO; o[3] = aE; o[4] = aN;
+    rhs[q] = h2 * f[q];
+}
+
+// ------------------------------------------------------------ import stencil
+__device__ __forceinline__ bool asym(double a, double b)
+{
+    const double d = fabs(a - b), m = fmax(fabs(a), fabs(b));
+    return !(d <= 1e-14 * m);
+}
+
+// [n][n][K] user stencil -> compact level-0 planes, with validation.
+__global__ void k_import_stencil(const double *__restrict__ st, int K, Lev<double> L,
+                                 int *__restrict__ flags)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x + 1;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y + 1;
+    const int n = L.n;
+    if (i > n || j > n) return;
+    const size_t q = ((size_t)(j - 1) * n + (i - 1)) * K;
+    const size_t p = (size_t)j * L.ld + i;
+    int bad = 0;
+    double e[9];
+    // e[] in the order SW, S, SE, W, O, E, NW, N, NE
+    if (K == 5) {
+        e[0] = 0.0; e[1] = st[q + 0]; e[2] = 0.0; e[3] = st[q + 1]; e[4] = st[q + 2];
+        e[5] = st[q + 3]; e[6] = 0.0; e[7] = st[q + 4]; e[8] = 0.0;
+    } else {
+#pragma unroll
+        for (int t = 0; t < 9; ++t) e[t] = st[q + t];
+    }
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+        if (!isfinite(e[t])) bad |= F_NONFINITE;
+    if (!(e[4] > 0.0)) bad |= F_DIAG;
+    if (i == 1 && (e[0] != 0.0 || e[3] != 0.0 || e[6] != 0.0)) bad |= F_BOUNDARY;
+    if (i == n && (e[2] != 0.0 || e[5] != 0.0 || e[8] != 0.0)) bad |= F_BOUNDARY;
+    if (j == 1 && (e[0] != 0.0 || e[1] != 0.0 || e[2] != 0.0)) bad |= F_BOUNDARY;
+    if (j == n && (e[6] != 0.0 || e[7] != 0.0 || e[8] != 0.0)) bad |= F_BOUNDARY;
+    // symmetry against the neighbours' west / south / south-west / north-west
+    if (i < n) {
+        const size_t qe = q + K;
+        if (asym(e[5], K == 5 ? st[qe + 1] : st[qe + 3])) bad |= F_ASYM;
+    }
+    if (j < n) {
+        const size_t qn = q + (size_t)n * K;
+        if (asym(e[7], K == 5 ? st[qn + 0] : st[qn + 1])) bad |= F_ASYM;
+    }
+    if (K == 9) {
+        if (i < n && j < n && asym(e[8], st[q + ((size_t)n + 1) * K + 0])) bad |= F_ASYM;
+        if (i < n && j > 1 && asym(e[2], st[q - ((size_t)n - 1) * K + 6])) bad |= F_ASYM;
+    }
+    L.O[p] = e[4];
+    L.W[p] = e[3];
+    L.S[p] = e[1];
+    if (L.SW) {
+        L.SW[p] = e[0];
+        L.NW[p] = e[6];
+    }
+    if (bad) atomicOr(flags, bad);
+}
+
+// ------------------------------------------------- interpolation weights
+// Row p of a compact stencil: SW, S, SE, W, O, E, NW, N, NE.
+__device__ __forceinline__ void row_of(const Lev<double> &L, size_t p, double a[9])
+{
+    const size_t ld = L.ld;
+    a[0] = L.SW ? L.SW[p] : 0.0;
+    a[1] = L.S[p];
+    a[2] = L.NW ? L.NW[p + 1 - ld] : 0.0;
+    a[3] = L.W[p];
+    a[4] = L.O[p];
+    a[5] = L.W[p + 1];
+    a[6] = L.NW ? L.NW[p] : 0.0;
+    a[7] = L.S[p + ld];
+    a[8] = L.SW ? L.SW[p + ld + 1] : 0.0;
+}
+
+// Positive off-diagonals moved onto the diagonal (SW,S,SE,W,E,NW,N,NE order).
+__device__ __forceinline__ void lump_row(double a[9])
+{
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+        if (e == 4) continue;
+        if (a[e] > 0.0) {
+            a[4] = a[4] + a[e];
+            a[e] = 0.0;
+        }
+    }
+}
+
+// Edge weights: x-edge X(I,J) = (2I-1, 2J) for I <= nc+1, J <= nc collapses the
+// lumped stencil along y; y-edge Y(I,J) = (2I, 2J-1) for I <= nc, J <= nc+1
+// collapses along x.
+__global__ void k_weights_edges(Lev<double> F, Wts<double> C, int nc, int *__restrict__ flags)
+{
+    const int I = blockIdx.x * blockDim.x + threadIdx.x + 1;
+    const int J = blockIdx.y * blockDim.y + threadIdx.y + 1;
+    if (I > nc + 1 || J > nc + 1) return;
+    const size_t c = (size_t)J * C.ld + I;
+    const size_t ld = F.ld;
+    int bad = 0;
+    double a[9];
+    if (J <= nc) {
+        row_of(F, (size_t)(2 * J) * ld + (2 * I - 1), a);
+        lump_row(a);
+        const double D = (a[4] + a[7]) + a[1];
+        if (!(D > 0.0)) bad = F_BREAK_INTERP;
+        C.p[LL * C.ps + c] = -((a[3] + a[6]) + a[0]) / D;
+        C.p[LR * C.ps + c] = -((a[5] + a[8]) + a[2]) / D;
+    }
+    if (I <= nc) {
+        row_of(F, (size_t)(2 * J - 1) * ld + (2 * I), a);
+        lump_row(a);
+        const double D = (a[4] + a[3]) + a[5];
+        if (!(D > 0.0)) bad = F_BREAK_INTERP;
+        C.p[LB * C.ps + c] = -((a[1] + a[0]) + a[2]) / D;
+        C.p[LA * C.ps + c] = -((a[7] + a[6]) + a[8]) / D;
+    }
+    if (bad) atomicOr(flags, bad);
+}
+
+// Cell-centre weights at Z(I,J) = (2I-1, 2J-1), I, J <= nc+1, from the lumped
+// stencil and the neighbouring edge weights.
+__global__ void k_weights_corners(Lev<double> F, Wts<double> C, int nc, int *__restrict__ flags)
+{
+    const int I = blockIdx.x * blockDim.x + threadIdx.x + 1;
+    const int J = blockIdx.y * blockDim.y + threadIdx.y + 1;
+    if (I > nc + 1 || J > nc + 1) return;
+    const size_t c = (size_t)J * C.ld + I;
+    const size_t cs = c - C.ld, cw = c - 1;
+    double a[9];
+    row_of(F, (size_t)(2 * J - 1) * F.ld + (2 * I - 1), a);
+    lump_row(a);
+    if (!(a[4] > 0.0)) atomicOr(flags, F_BREAK_INTERP);
+    const double lr = C.at(LR, c), ll = C.at(LL, c), la = C.at(LA, c), lb = C.at(LB, c);
+    const double lr_s = C.at(LR, cs), ll_s = C.at(LL, cs);
+    const double la_w = C.at(LA, cw), lb_w = C.at(LB, cw);
+    C.p[LNE * C.ps + c] = -((a[8] + a[7] * lr) + a[5] * la) / a[4];
+    C.p[LNW * C.ps + c] = -((a[6] + a[7] * ll) + a[3] * la_w) / a[4];
+    C.p[LSE * C.ps + c] = -((a[2] + a[1] * lr_s) + a[5] * lb) / a[4];
+    C.p[LSW * C.ps + c] = -((a[0] + a[1] * ll_s) + a[3] * lb_w) / a[4];
+}
+
+// --------------------------------------------------------- Galerkin RAP
+// Weight of coarse basis function K = (KI,KJ) at fine point 2K + (di,dj).
+__device__ __forceinline__ double basis_weight(const Wts<double> &C, int KI, int KJ, int di, int dj)
+{
+    const size_t c = (size_t)KJ * C.ld + KI;
+    if (dj == 0) {
+        if (di == 0) return 1.0;
+        return di < 0 ? C.at(LR, c) : C.at(LL, c + 1);
+    }
+    if (dj < 0) {
+        if (di == 0) return C.at(LA, c);
+        return di < 0 ? C.at(LNE, c) : C.at(LNW, c + 1);
+    }
+    if (di == 0) return C.at(LB, c + C.ld);
+    return di < 0 ? C.at(LSE, c + C.ld) : C.at(LSW, c + C.ld + 1);
+}
+
+// A_c(I,J;d) = sum_p P(p;IJ) sum_q A(p,q) P(q;IJ+d), d = O, W, S, SW, NW, p over
+// the fine 3x3 patch of (2I,2J) (rows south to north, west to east inside a
+// row), q over p's neighbours SW..NE inside the support of basis IJ+d; both
+// sums start from zero.  Couplings to ring coarse points are zero.
+__global__ void k_rap(Lev<double> F, Wts<double> C, Lev<double> Cl)
+{
+    const int I = blockIdx.x * blockDim.x + threadIdx.x + 1;
+    const int J = blockIdx.y * blockDim.y + threadIdx.y + 1;
+    const int nc = Cl.n;
+    if (I > nc || J > nc) return;
+    const int offI[5] = {0, -1, 0, -1, -1};
+    const int offJ[5] = {0, 0, -1, -1, 1};
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    bool live[5];
+#pragma unroll
+    for (int d = 0; d < 5; ++d) {
+        const int KI = I + offI[d], KJ = J + offJ[d];
+        live[d] = KI >= 1 && KJ >= 1 && KJ <= nc;
+    }
+#pragma unroll
+    for (int jj = -1; jj <= 1; ++jj) {
+#pragma unroll
+        for (int ii = -1; ii <= 1; ++ii) {
+            const int pi = 2 * I + ii, pj = 2 * J + jj;
+            double a[9];
+            row_of(F, (size_t)pj * F.ld + pi, a);
+            const double wp = basis_weight(C, I, J, ii, jj);
+#pragma unroll
+            for (int d = 0; d < 5; ++d) {
+                if (!live[d]) continue;
+                const int KI = I + offI[d], KJ = J + offJ[d];
+                double t = 0.0;
+#pragma unroll
+                for (int e = 0; e < 9; ++e) {
+                    const int qi = pi + (e % 3) - 1, qj = pj + (e / 3) - 1;
+                    const int di = qi - 2 * KI, dj = qj - 2 * KJ;
+                    if (di < -1 || di > 1 || dj < -1 || dj > 1) continue;
+                    t = t + a[e] * basis_weight(C, KI, KJ, di, dj);
+                }
+                acc[d] = acc[d] + wp * t;
+            }
+        }
+    }
+    const size_t c = (size_t)J * Cl.ld + I;
+    Cl.O[c] = acc[0];
+    Cl.W[c] = acc[1];
+    Cl.S[c] = acc[2];
+    Cl.SW[c] = acc[3];
+    Cl.NW[c] = acc[4];
+}
+
+// ------------------------------------------- coarsest LDL^T (3x3 interior)
+// Dense matrix in the unknown order k = (i-1) + 3(j-1), then the
+// square-root-free Cholesky: w_k = L_jk D_k, D_j = A_jj - sum L_jk w_k,
+// L_ij = (A_ij - sum L_ik w_k) / D_j (sums over increasing k).
+__global__ void k_coarse_factor(Lev<double> Cl, double *__restrict__ LD, int *__restrict__ flags)
+{
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    double A[81], Lm[81], D[9], w[9];
+    for (int t = 0; t < 81; ++t) { A[t] = 0.0; Lm[t] = 0.0; }
+    for (int j = 1; j <= 3; ++j) {
+        for (int i = 1; i <= 3; ++i) {
+            double a[9];
+            row_of(Cl, (size_t)j * Cl.ld + i, a);
+            const int k = (i - 1) + 3 * (j - 1);
+            for (int e = 0; e < 9; ++e) {
+                const int qi = i + (e % 3) - 1, qj = j + (e / 3) - 1;
+                if (qi < 1 || qi > 3 || qj < 1 || qj > 3) continue;
+                A[k * 9 + (qi - 1) + 3 * (qj - 1)] = a[e];
+            }
+        }
+    }
+    int bad = 0;
+    for (int j = 0; j < 9; ++j) {
+        for (int k = 0; k < j; ++k) w[k] = Lm[j * 9 + k] * D[k];
+        double s = A[j * 9 + j];
+        for (int k = 0; k < j; ++k) s = s - Lm[j * 9 + k] * w[k];
+        if (!(s > 0.0)) bad = F_BREAK_COARSE;
+        D[j] = s;
+        Lm[j * 9 + j] = 1.0;
+        for (int i = j + 1; i < 9; ++i) {
+            double t = A[i * 9 + j];
+            for (int k = 0; k < j; ++k) t = t - Lm[i * 9 + k] * w[k];
+            Lm[i * 9 + j] = t / s;
+        }
+    }
+    for (int t = 0; t < 81; ++t) LD[t] = Lm[t];
+    for (int t = 0; t < 9; ++t) LD[81 + t] = D[t];
+    if (bad) atomicOr(flags, bad);
+}
+
+// Solve with the factor: y = L^-1 b, z = y / D, x = L^-T z.  The right-hand side
+// and solution are level arrays of precision T (FP32 hierarchy: widened to
+// FP64 for the solve and rounded back).
+template <typename T>
+__global__ void k_coarse_solve(Lev<T> Cl, const double *__restrict__ LD, const int *stop)
+{
+    if (stopped(stop)) return;
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    double y[9], x[9];
+    for (int i = 0; i < 9; ++i) {
+        const int ci = 1 + i % 3, cj = 1 + i / 3;
+        double s = (double)Cl.b[(size_t)cj * Cl.ld + ci];
+        for (int k = 0; k < i; ++k) s = s - LD[i * 9 + k] * y[k];
+        y[i] = s;
+    }
+    for (int i = 0; i < 9; ++i) y[i] = y[i] / LD[81 + i];
+    for (int i = 8; i >= 0; --i) {
+        double s = y[i];
+        for (int k = i + 1; k < 9; ++k) s = s - LD[k * 9 + i] * x[k];
+        x[i] = s;
+    }
+    for (int i = 0; i < 9; ++i) {
+        const int ci = 1 + i % 3, cj = 1 + i / 3;
+        Cl.u[(size_t)cj * Cl.ld + ci] = (T)x[i];
+    }
+}
+
+// ------------------------------------------------------ basic cycle steps
+// One colour of four-colour Gauss-Seidel: colour(i,j) = (i mod 2) + 2 (j mod 2).
+// s = b; s -= A_d u_d for d = SW, S, SE, W, E, NW, N, NE; u = s / A_O.
+template <typename T, bool NINE>
+__device__ __forceinline__ T gs_point(const Lev<T> &L, size_t p)
+{
+    const size_t ld = L.ld;
+    const T *u = L.u;
+    T s = L.b[p];
+    if (NINE) s -= L.SW[p] * u[p - ld - 1];
+    s -= L.S[p] * u[p - ld];
+    if (NINE) s -= L.NW[p + 1 - ld] * u[p - ld + 1];
+    s -= L.W[p] * u[p - 1];
+    s -= L.W[p + 1] * u[p + 1];
+    if (NINE) s -= L.NW[p] * u[p + ld - 1];
+    s -= L.S[p + ld] * u[p + ld];
+    if (NINE) s -= L.SW[p + ld + 1] * u[p + ld + 1];
+    return s / L.O[p];
+}
+
+template <typename T, bool NINE>
+__global__ void k_gs_colour(Lev<T> L, int colour, const int *stop)
+{
+    if (stopped(stop)) return;
+    const int i = ((colour & 1) ? 1 : 2) + 2 * (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    const int j = ((colour >> 1) ? 1 : 2) + 2 * (int)(blockIdx.y * blockDim.y + threadIdx.y);
+    if (i > L.n || j > L.n) return;
+    const size_t p = (size_t)j * L.ld + i;
+    L.u[p] = gs_point<T, NINE>(L, p);
+}
+
+// r = b - A u, the centre term last.
+template <typename T, bool NINE>
+__device__ __forceinline__ T residual_point(const Lev<T> &L, const T *u, size_t p)
+{
+    const size_t ld = L.ld;
+    T s = L.b[p];
+    if (NINE) s -= L.SW[p] * u[p - ld - 1];
+    s -= L.S[p] * u[p - ld];
+    if (NINE) s -= L.NW[p + 1 - ld] * u[p - ld + 1];
+    s -= L.W[p] * u[p - 1];
+    s -= L.W[p + 1] * u[p + 1];
+    if (NINE) s -= L.NW[p] * u[p + ld - 1];
+    s -= L.S[p + ld] * u[p + ld];
+    if (NINE) s -= L.SW[p + ld + 1] * u[p + ld + 1];
+    s -= L.O[p] * u[p];
+    return s;
+}
+
+template <typename T, bool NINE>
+__global__ void k_residual(Lev<T> L, const int *stop)
+{
+    if (stopped(stop)) return;
+    const int i = 1 + blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = 1 + blockIdx.y * blockDim.y + threadIdx.y;
+    if (i > L.n || j > L.n) return;
+    const size_t p = (size_t)j * L.ld + i;
+    L.r[p] = residual_point<T, NINE>(L, L.u, p);
+}
+
+// b_c(I,J) = P^T r in the term order of Fig. restrict_kernel; u_c = 0.
+template <typename T>
+__global__ void k_restrict(const T *__restrict__ r, int ldf, Wts<T> C, Lev<T> Cl, const int *stop)
+{
+    if (stopped(stop)) return;
+    const int I = 1 + blockIdx.x * blockDim.x + threadIdx.x;
+    const int J = 1 + blockIdx.y * blockDim.y + threadIdx.y;
+    if (I > Cl.n || J > Cl.n) return;
+    const size_t c = (size_t)J * C.ld + I;
+    const size_t f = (size_t)(2 * J) * ldf + 2 * I;
+    const size_t cn = c + C.ld;
+    T s = C.at(LNE, c) * r[f - ldf - 1];
+    s = s + C.at(LA, c) * r[f - ldf];
+    s = s + C.at(LNW, c + 1) * r[f - ldf + 1];
+    s = s + C.at(LR, c) * r[f - 1];
+    s = s + r[f];
+    s = s + C.at(LL, c + 1) * r[f + 1];
+    s = s + C.at(LSE, cn) * r[f + ldf - 1];
+    s = s + C.at(LB, cn) * r[f + ldf];
+    s = s + C.at(LSW, cn + 1) * r[f + ldf + 1];
+    Cl.b[c] = s;
+    Cl.u[c] = (T)0;
+}
+
+// Correction e = P e_c at fine (i,j); e_c is zero on the ring.
+template <typename T>
+__device__ __forceinline__ T interp_point(const Wts<T> &C, const T *ec, int i, int j)
+{
+    const int ldc = C.ld;
+    if (!(i & 1) && !(j & 1)) return ec[(size_t)(j >> 1) * ldc + (i >> 1)];
+    if ((i & 1) && !(j & 1)) {
+        const size_t c = (size_t)(j >> 1) * ldc + ((i + 1) >> 1);
+        return C.at(LL, c) * ec[c - 1] + C.at(LR, c) * ec[c];
+    }
+    if (!(i & 1)) {
+        const size_t c = (size_t)((j + 1) >> 1) * ldc + (i >> 1);
+        return C.at(LB, c) * ec[c - ldc] + C.at(LA, c) * ec[c];
+    }
+    const size_t c = (size_t)((j + 1) >> 1) * ldc + ((i + 1) >> 1);
+    T e = C.at(LSW, c) * ec[c - ldc - 1] + C.at(LSE, c) * ec[c - ldc];
+    e = e + C.at(LNW, c) * ec[c - 1];
+    e = e + C.at(LNE, c) * ec[c];
+    return e;
+}
+
+template <typename T>
+__global__ void k_interp_add(Lev<T> L, Wts<T> C, const T *__restrict__ ec, const int *stop)
+{
+    if (stopped(stop)) return;
+    const int i = 1 + blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = 1 + blockIdx.y * blockDim.y + threadIdx.y;
+    if (i > L.n || j > L.n) return;
+    const size_t p = (size_t)j * L.ld + i;
+    L.u[p] = L.u[p] + interp_point<T>(C, ec, i, j);
+}
+
+// ------------------------------------------------------------ reductions
+// Wave64 + LDS block reduction of a double; result valid in thread 0.
+__device__ __forceinline__ double block_sum(double v)
+{
+    __shared__ double part[16];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) part[wid] = v;
+    __syncthreads();
+    if (wid == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        v = lane < nw ? part[lane] : 0.0;
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    }
+    return v;
+}
+
+// Per-block partial sums of squares of the residual (r_mode = 1: recompute
+// b - A u; 0: of the array x itself) over the interior, grid-stride over rows.
+template <typename T, bool NINE, bool RES>
+__global__ void k_sumsq_partial(Lev<T> L, const T *__restrict__ x, double *__restrict__ part,
+                                const int *stop)
+{
+    if (stopped(stop)) return;
+    double acc = 0.0;
+    const int n = L.n;
+    for (int j = 1 + blockIdx.x; j <= n; j += gridDim.x) {
+        for (int i = 1 + threadIdx.x; i <= n; i += blockDim.x) {
+            const size_t p = (size_t)j * L.ld + i;
+            const double v = RES ? (double)residual_point<T, NINE>(L, L.u, p) : (double)x[p];
+            acc += v * v;
+        }
+    }
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+// Final sum of the partials (fixed order) -> out[0].  With `hist` given, this
+// also records rel = sqrt(sum)/bnorm[0] into hist[*count], advances the count,
+// and raises *stop: 1 once rel <= tol, 2 if rel is not finite or exceeds
+// 1e3 times the initial relative residual bnorm[1], 3 when maxc entries exist.
+__global__ void k_sumsq_final(const double *__restrict__ part, int np, double *__restrict__ out,
+                              double *hist, int *count, int *stop, const double *bnorm,
+                              double tol, int maxc)
+{
+    if (stopped(stop)) return;
+    double v = 0.0;
+    for (int t = threadIdx.x; t < np; t += blockDim.x) v += part[t];
+    v = block_sum(v);
+    if (threadIdx.x == 0) {
+        out[0] = v;
+        if (hist) {
+            const int k = *count;
+            const double rel = sqrt(v) / bnorm[0];
+            hist[k] = rel;
+            *count = k + 1;
+            int s = 0;
+            if (rel <= tol) s = 1;
+            else if (!isfinite(rel) || rel > 1e3 * bnorm[1]) s = 2;
+            else if (k + 1 >= maxc) s = 3;
+            if (s) *stop = s;
+        }
+    }
+}
+
+// ---------------------------------------------------- layout conversions
+// [n][n] user array <-> padded level array.
+template <typename TI, typename TO>
+__global__ void k_pack_in(const TI *__restrict__ src, int n, TO *__restrict__ dst, int ld)
+{
+    const int i = 1 + blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = 1 + blockIdx.y * blockDim.y + threadIdx.y;
+    if (i > n || j > n) return;
+    dst[(size_t)j * ld + i] = (TO)src[(size_t)(j - 1) * n + (i - 1)];
+}
+
+template <typename TI, typename TO>
+__global__ void k_pack_out(const TI *__restrict__ src, int ld, int n, TO *__restrict__ dst)
+{
+    const int i = 1 + blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = 1 + blockIdx.y * blockDim.y + threadIdx.y;
+    if (i > n || j > n) return;
+    dst[(size_t)(j - 1) * n + (i - 1)] = (TO)src[(size_t)j * ld + i];
+}
+
+// Rounded copy of a padded array (the FP32 hierarchy from the FP64 set-up).
+__global__ void k_round_f32(const double *__restrict__ src, float *__restrict__ dst, size_t count)
+{
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < count;
+         t += (size_t)gridDim.x * blockDim.x)
+        dst[t] = (float)src[t];
+}
+
+// -------------------------------------------- FP64 iterative refinement
+// Per-block max |r| over the interior of the FP64 level-0 residual.
+__global__ void k_absmax_partial(Lev<double> L, double *__restrict__ part, const int *stop)
+{
+    if (stopped(stop)) return;
+    __shared__ double sm[16];
+    double m = 0.0;
+    for (int j = 1 + blockIdx.x; j <= L.n; j += gridDim.x)
+        for (int i = 1 + threadIdx.x; i <= L.n; i += blockDim.x) m = fmax(m, fabs(L.r[(size_t)j * L.ld + i]));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_down(m, o, 64));
+    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, sm[w]);
+        part[blockIdx.x] = m;
+    }
+}
+
+__global__ void k_absmax_final(const double *__restrict__ part, int np, double *__restrict__ out,
+                               const int *stop)
+{
+    if (stopped(stop)) return;
+    if (threadIdx.x != 0) return;
+    double m = 0.0;
+    for (int t = 0; t < np; ++t) m = fmax(m, part[t]);
+    out[0] = m;
+}
+
+// s = the smallest power of two >= ||r||_inf (1 if r = 0); the FP32 right-hand
+// side is fl32(r / s) (an exact scaling, then one rounding) and u32 = 0.
+__global__ void k_ir_scale(Lev<double> L, Lev<float> F, const double *__restrict__ rmax,
+                           double *__restrict__ scale, const int *stop)
+{
+    if (stopped(stop)) return;
+    int e = 0;
+    const double fr = frexp(*rmax, &e);  // rmax = fr 2^e, fr in [1/2, 1)
+    if (fr == 0.5) e -= 1;
+    if (fr == 0.0) e = 0;
+    const double inv = ldexp(1.0, -e);
+    const int i = 1 + blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = 1 + blockIdx.y * blockDim.y + threadIdx.y;
+    if (i == 1 && j == 1) scale[0] = ldexp(1.0, e);
+    if (i > L.n || j > L.n) return;
+    const size_t p = (size_t)j * L.ld + i;
+    F.b[p] = (float)(L.r[p] * inv);
+    F.u[p] = 0.0f;
+}
+
+// x = x + s * (double)d32 on the FP64 iterate.
+__global__ void k_ir_update(Lev<double> L, Lev<float> F, const double *__restrict__ scale, const int *stop)
+{
+    if (stopped(stop)) return;
+    const int i = 1 + blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = 1 + blockIdx.y * blockDim.y + threadIdx.y;
+    if (i > L.n || j > L.n) return;
+    const size_t p = (size_t)j * L.ld + i;
+    L.u[p] = L.u[p] + scale[0] * (double)F.u[p];
+}
+
+}  // namespace bmg

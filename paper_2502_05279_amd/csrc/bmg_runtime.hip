@@ -1,0 +1,768 @@
+// Host side of the black-box multigrid library: workspace planning, set-up,
+// the V-cycle driver, the solve loop and the C entry points of bmg.h.
+//
+// One level hierarchy lives in the caller's workspace; nothing here calls
+// hipMalloc.  Every launch goes to the handle's stream.
+#include "bmg.h"
+#include "bmg_kernels.hpp"
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+using namespace bmg;
+
+namespace {
+
+constexpr int MAXL = 20;
+constexpr int NPART = 1024;      // partial sums of a norm
+constexpr size_t ALIGN = 256;
+constexpr int MAX_TRACE = 65536;
+
+thread_local char g_err[512];
+
+bmg_status fail(bmg_status s, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+#define HIPCHK(call)                                                                    \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(BMG_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));    \
+    } while (0)
+
+#define LAUNCHCHK()                                                                     \
+    do {                                                                                \
+        hipError_t e_ = hipGetLastError();                                              \
+        if (e_ != hipSuccess)                                                           \
+            return fail(BMG_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e_)); \
+    } while (0)
+
+bool valid_n(int n) { return n >= 3 && n < (1 << 16) && ((n + 1) & n) == 0; }
+int pitch_of(int n) { return ((n + 2) + 15) & ~15; }
+
+dim3 grid2(int nx, int ny, dim3 blk) { return dim3((nx + blk.x - 1) / blk.x, (ny + blk.y - 1) / blk.y); }
+
+}  // namespace
+
+struct bmg_solver {
+    int n = 0, kind = 5, nlev = 0;
+    bmg_options opt{};
+    hipStream_t st = nullptr;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    Lev<double> L[MAXL];
+    Wts<double> C[MAXL];
+    bool nine[MAXL];
+    bool f32 = false;
+    Lev<float> L32[MAXL];
+    Wts<float> C32[MAXL];
+    double *LD = nullptr;       // coarsest factor: 81 L + 9 D
+    int *flags = nullptr;       // validation / breakdown bits
+    double *part = nullptr;     // NPART partial sums
+    double *scal = nullptr;     // scalars (see enum below)
+    double *hist = nullptr;     // residual history on the device
+    int *count = nullptr;       // entries in hist
+    int *stop = nullptr;        // stop code of the running solve
+    int hist_cap = 0;
+    // kernel timing
+    int tr_class = -1, tr_level = -1;
+    std::vector<hipEvent_t> tr_ev;
+    int tr_used = 0;
+};
+
+namespace {
+
+enum { S_SUMSQ = 0, S_BNORM = 1, S_REL0 = 2, S_TMP = 3, S_RMAX = 4, S_SCALE = 5, S_NSCAL = 8 };
+
+// Walks the workspace layout; with base == nullptr it only measures.
+size_t plan(bmg_solver *h, int n, int kind, const bmg_options &o, char *base)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char * {
+        off = (off + ALIGN - 1) & ~(ALIGN - 1);
+        char *p = base ? base + off : nullptr;
+        off += bytes;
+        return p;
+    };
+    int nl = 0, ns[MAXL];
+    for (int m = n; m >= 3 && nl < MAXL; m = (m - 1) / 2) ns[nl++] = m;
+    const bool f32 = o.precision == BMG_FP32_IR;
+    for (int l = 0; l < nl; ++l) {
+        const int ld = pitch_of(ns[l]);
+        const size_t pl = (size_t)(ns[l] + 2) * ld;
+        const bool nine = l > 0 || kind == 9;
+        Lev<double> D{};
+        D.n = ns[l];
+        D.ld = ld;
+        D.u = (double *)take(pl * 8);
+        D.b = (double *)take(pl * 8);
+        D.r = (double *)take(pl * 8);
+        D.O = (double *)take(pl * 8);
+        D.W = (double *)take(pl * 8);
+        D.S = (double *)take(pl * 8);
+        D.SW = nine ? (double *)take(pl * 8) : nullptr;
+        D.NW = nine ? (double *)take(pl * 8) : nullptr;
+        Wts<double> W{};
+        if (l + 1 < nl) {
+            const int ldc = pitch_of(ns[l + 1]);
+            W.ld = ldc;
+            W.ps = (size_t)(ns[l + 1] + 2) * ldc;
+            W.p = (double *)take(8 * W.ps * 8);
+        }
+        Lev<float> F{};
+        Wts<float> FW{};
+        if (f32) {
+            F.n = ns[l];
+            F.ld = ld;
+            F.u = (float *)take(pl * 4);
+            F.b = (float *)take(pl * 4);
+            F.r = (float *)take(pl * 4);
+            F.O = (float *)take(pl * 4);
+            F.W = (float *)take(pl * 4);
+            F.S = (float *)take(pl * 4);
+            F.SW = nine ? (float *)take(pl * 4) : nullptr;
+            F.NW = nine ? (float *)take(pl * 4) : nullptr;
+            if (l + 1 < nl) {
+                FW.ld = W.ld;
+                FW.ps = W.ps;
+                FW.p = (float *)take(8 * W.ps * 4);
+            }
+        }
+        if (h) {
+            h->L[l] = D;
+            h->C[l] = W;
+            h->nine[l] = nine;
+            h->L32[l] = F;
+            h->C32[l] = FW;
+        }
+    }
+    double *LD = (double *)take(90 * 8);
+    int *flags = (int *)take(64);
+    double *part = (double *)take(NPART * 8);
+    double *scal = (double *)take(S_NSCAL * 8);
+    const int cap = std::max(o.max_cycles, 1) + 2;
+    double *hist = (double *)take((size_t)cap * 8);
+    int *cnt = (int *)take(64);
+    if (h) {
+        h->nlev = nl;
+        h->LD = LD;
+        h->flags = flags;
+        h->part = part;
+        h->scal = scal;
+        h->hist = hist;
+        h->hist_cap = cap;
+        h->count = cnt;
+        h->stop = cnt + 1;
+        h->f32 = f32;
+    }
+    return (off + ALIGN - 1) & ~(ALIGN - 1);
+}
+
+bmg_status check_options(const bmg_options &o)
+{
+    if (o.nu1 < 0 || o.nu2 < 0 || o.nu1 + o.nu2 < 1 || o.nu1 > 64 || o.nu2 > 64)
+        return fail(BMG_EINVAL, "nu1=%d nu2=%d out of range", o.nu1, o.nu2);
+    if (o.max_cycles < 1 || o.max_cycles > 1000000)
+        return fail(BMG_EINVAL, "max_cycles=%d out of range", o.max_cycles);
+    if (o.precision != BMG_FP64 && o.precision != BMG_FP32_IR)
+        return fail(BMG_EINVAL, "unknown precision %d", o.precision);
+    if (o.kernels != BMG_KERNELS_BASIC)
+        return fail(BMG_EINVAL, "kernel path %d is not available", o.kernels);
+    if (o.check_every < 1 || o.check_every > 4096)
+        return fail(BMG_EINVAL, "check_every=%d out of range", o.check_every);
+    return BMG_OK;
+}
+
+// ------------------------------------------------------------ tracing
+void trace_begin(bmg_solver *h, int kclass, int level)
+{
+    if (h->tr_class != kclass || h->tr_level != level) return;
+    if (h->tr_used + 2 > (int)h->tr_ev.size()) {
+        if ((int)h->tr_ev.size() >= 2 * MAX_TRACE) return;
+        const size_t grow = std::min<size_t>(2 * MAX_TRACE, std::max<size_t>(64, 2 * h->tr_ev.size()));
+        size_t old = h->tr_ev.size();
+        h->tr_ev.resize(grow);
+        for (size_t t = old; t < grow; ++t) (void)hipEventCreate(&h->tr_ev[t]);
+    }
+    (void)hipEventRecord(h->tr_ev[h->tr_used], h->st);
+}
+
+void trace_end(bmg_solver *h, int kclass, int level)
+{
+    if (h->tr_class != kclass || h->tr_level != level) return;
+    if (h->tr_used + 2 > (int)h->tr_ev.size()) return;
+    (void)hipEventRecord(h->tr_ev[h->tr_used + 1], h->st);
+    h->tr_used += 2;
+}
+
+// -------------------------------------------------------- cycle steps
+const dim3 B2(64, 4);
+
+template <typename T>
+bmg_status smooth(bmg_solver *h, const Lev<T> &L, bool nine, int sweeps, const int *stop, int level)
+{
+    if (sweeps <= 0) return BMG_OK;
+    trace_begin(h, BMG_TRACE_SMOOTH, level);
+    for (int s = 0; s < sweeps; ++s) {
+        for (int c = 0; c < 4; ++c) {
+            const int ni = (c & 1) ? (L.n + 1) / 2 : (L.n - 1) / 2;
+            const int nj = (c >> 1) ? (L.n + 1) / 2 : (L.n - 1) / 2;
+            const dim3 g = grid2(ni, nj, B2);
+            if (nine) hipLaunchKernelGGL((k_gs_colour<T, true>), g, B2, 0, h->st, L, c, stop);
+            else hipLaunchKernelGGL((k_gs_colour<T, false>), g, B2, 0, h->st, L, c, stop);
+        }
+    }
+    trace_end(h, BMG_TRACE_SMOOTH, level);
+    LAUNCHCHK();
+    return BMG_OK;
+}
+
+template <typename T>
+bmg_status residual(bmg_solver *h, const Lev<T> &L, bool nine, const int *stop)
+{
+    const dim3 g = grid2(L.n, L.n, B2);
+    if (nine) hipLaunchKernelGGL((k_residual<T, true>), g, B2, 0, h->st, L, stop);
+    else hipLaunchKernelGGL((k_residual<T, false>), g, B2, 0, h->st, L, stop);
+    LAUNCHCHK();
+    return BMG_OK;
+}
+
+template <typename T>
+bmg_status restrict_(bmg_solver *h, const Lev<T> &F, const Wts<T> &C, const Lev<T> &Cl, const int *stop)
+{
+    hipLaunchKernelGGL((k_restrict<T>), grid2(Cl.n, Cl.n, B2), B2, 0, h->st, F.r, F.ld, C, Cl, stop);
+    LAUNCHCHK();
+    return BMG_OK;
+}
+
+template <typename T>
+bmg_status interp(bmg_solver *h, const Lev<T> &F, const Wts<T> &C, const Lev<T> &Cl, const int *stop)
+{
+    hipLaunchKernelGGL((k_interp_add<T>), grid2(F.n, F.n, B2), B2, 0, h->st, F, C, (const T *)Cl.u, stop);
+    LAUNCHCHK();
+    return BMG_OK;
+}
+
+template <typename T>
+bmg_status coarse(bmg_solver *h, const Lev<T> &Cl, const int *stop)
+{
+    hipLaunchKernelGGL((k_coarse_solve<T>), dim3(1), dim3(64), 0, h->st, Cl, (const double *)h->LD, stop);
+    LAUNCHCHK();
+    return BMG_OK;
+}
+
+template <typename T>
+const Lev<T> &lev(const bmg_solver *h, int l);
+template <>
+const Lev<double> &lev<double>(const bmg_solver *h, int l) { return h->L[l]; }
+template <>
+const Lev<float> &lev<float>(const bmg_solver *h, int l) { return h->L32[l]; }
+template <typename T>
+const Wts<T> &wts(const bmg_solver *h, int l);
+template <>
+const Wts<double> &wts<double>(const bmg_solver *h, int l) { return h->C[l]; }
+template <>
+const Wts<float> &wts<float>(const bmg_solver *h, int l) { return h->C32[l]; }
+
+#define TRY(x)                          \
+    do {                                \
+        bmg_status s_ = (x);            \
+        if (s_ != BMG_OK) return s_;    \
+    } while (0)
+
+// V(nu1,nu2) from level l down to the coarsest direct solve and back.
+template <typename T>
+bmg_status vcycle_from(bmg_solver *h, int l, const int *stop)
+{
+    const Lev<T> &F = lev<T>(h, l);
+    if (l == h->nlev - 1) return coarse<T>(h, F, stop);
+    const Lev<T> &Cl = lev<T>(h, l + 1);
+    const Wts<T> &C = wts<T>(h, l);
+    TRY(smooth<T>(h, F, h->nine[l], h->opt.nu1, stop, l));
+    TRY(residual<T>(h, F, h->nine[l], stop));
+    TRY(restrict_<T>(h, F, C, Cl, stop));
+    TRY(vcycle_from<T>(h, l + 1, stop));
+    TRY(interp<T>(h, F, C, Cl, stop));
+    TRY(smooth<T>(h, F, h->nine[l], h->opt.nu2, stop, l));
+    return BMG_OK;
+}
+
+// Fused passes (not built yet): the fused path is rejected by option checks.
+bmg_status fused_vcycle(bmg_solver *h, const int *stop) { return vcycle_from<double>(h, 0, stop); }
+bmg_status fused_vcycle32(bmg_solver *h, const int *stop) { return vcycle_from<float>(h, 0, stop); }
+template <typename T>
+bmg_status fused_pre(bmg_solver *, int, int, const int *) { return fail(BMG_EINVAL, "fused passes are not available"); }
+template <typename T>
+bmg_status fused_post(bmg_solver *, int, int, const int *) { return fail(BMG_EINVAL, "fused passes are not available"); }
+
+// Sum of squares of r = b - A u (res) or of the array x, into scal[slot]; with
+// record, also the history / stop bookkeeping of the running solve.
+template <typename T>
+bmg_status sumsq(bmg_solver *h, const Lev<T> &L, bool nine, bool res, const T *x, int slot,
+                 bool record, double tol, int maxc)
+{
+    const int nb = std::min(NPART, L.n);
+    const int *stop = record ? h->stop : nullptr;
+    trace_begin(h, BMG_TRACE_RESNORM, 0);
+    if (res) {
+        if (nine) hipLaunchKernelGGL((k_sumsq_partial<T, true, true>), dim3(nb), dim3(256), 0, h->st, L, x, h->part, stop);
+        else hipLaunchKernelGGL((k_sumsq_partial<T, false, true>), dim3(nb), dim3(256), 0, h->st, L, x, h->part, stop);
+    } else {
+        hipLaunchKernelGGL((k_sumsq_partial<T, false, false>), dim3(nb), dim3(256), 0, h->st, L, x, h->part, stop);
+    }
+    hipLaunchKernelGGL(k_sumsq_final, dim3(1), dim3(1024), 0, h->st, (const double *)h->part, nb,
+                       h->scal + slot, record ? h->hist : nullptr, h->count, h->stop,
+                       (const double *)(h->scal + S_BNORM), tol, maxc);
+    trace_end(h, BMG_TRACE_RESNORM, 0);
+    LAUNCHCHK();
+    return BMG_OK;
+}
+
+bmg_status read_scalars(bmg_solver *h, double *dst, int first, int count)
+{
+    HIPCHK(hipMemcpyAsync(dst, h->scal + first, count * sizeof(double), hipMemcpyDeviceToHost, h->st));
+    HIPCHK(hipStreamSynchronize(h->st));
+    return BMG_OK;
+}
+
+bmg_status pack_in(bmg_solver *h, const double *src, double *dst)
+{
+    const Lev<double> &L = h->L[0];
+    hipLaunchKernelGGL((k_pack_in<double, double>), grid2(L.n, L.n, B2), B2, 0, h->st, src, L.n, dst, L.ld);
+    LAUNCHCHK();
+    return BMG_OK;
+}
+
+bmg_status pack_out(bmg_solver *h, const double *src, double *dst)
+{
+    const Lev<double> &L = h->L[0];
+    hipLaunchKernelGGL((k_pack_out<double, double>), grid2(L.n, L.n, B2), B2, 0, h->st, src, L.ld, L.n, dst);
+    LAUNCHCHK();
+    return BMG_OK;
+}
+
+}  // namespace
+
+// ================================================================ C API
+extern "C" {
+
+const char *bmg_last_error(void) { return g_err; }
+
+const char *bmg_status_string(int s)
+{
+    switch (s) {
+    case BMG_OK: return "ok";
+    case BMG_EINVAL: return "invalid argument";
+    case BMG_EBREAKDOWN: return "breakdown (non-positive interpolation denominator or coarse pivot)";
+    case BMG_ENOCONV: return "not converged within max_cycles";
+    case BMG_EDIVERGED: return "diverged";
+    case BMG_EDEVICE: return "HIP runtime error";
+    case BMG_EWORKSPACE: return "workspace missing, too small or misaligned";
+    default: return "unknown status";
+    }
+}
+
+bmg_status bmg_default_options(bmg_options *o)
+{
+    if (!o) return fail(BMG_EINVAL, "options pointer is NULL");
+    memset(o, 0, sizeof *o);
+    o->nu1 = 2;
+    o->nu2 = 1;
+    o->max_cycles = 100;
+    o->precision = BMG_FP64;
+    o->kernels = BMG_KERNELS_BASIC;
+    o->check_every = 8;
+    return BMG_OK;
+}
+
+bmg_status bmg_workspace_bytes(int n, int kind, const bmg_options *o, size_t *bytes)
+{
+    if (!bytes) return fail(BMG_EINVAL, "bytes pointer is NULL");
+    if (!valid_n(n)) return fail(BMG_EINVAL, "n=%d is not 2^m-1 with 2 <= m <= 15", n);
+    if (kind != 5 && kind != 9) return fail(BMG_EINVAL, "stencil kind %d is not 5 or 9", kind);
+    bmg_options d;
+    bmg_default_options(&d);
+    const bmg_options &op = o ? *o : d;
+    TRY(check_options(op));
+    *bytes = plan(nullptr, n, kind, op, nullptr);
+    return BMG_OK;
+}
+
+bmg_status bmg_discretize(const double *k, const double *f, int n, double *stencil, double *rhs,
+                          bmg_stream stream)
+{
+    if (!valid_n(n)) return fail(BMG_EINVAL, "n=%d is not 2^m-1 with 2 <= m <= 15", n);
+    if (!k || !f || !stencil || !rhs) return fail(BMG_EINVAL, "NULL array");
+    int m = 0;
+    while ((1 << m) < n + 1) ++m;
+    const double h2 = ldexp(1.0, -2 * m);
+    hipLaunchKernelGGL(k_discretize, grid2(n, n, B2), B2, 0, (hipStream_t)stream, k, f, n, h2, stencil, rhs);
+    LAUNCHCHK();
+    return BMG_OK;
+}
+
+bmg_status bmg_setup(bmg_solver **out, const double *stencil, int n, int kind, const bmg_options *o,
+                     void *workspace, size_t ws_bytes, bmg_stream stream)
+{
+    if (!out) return fail(BMG_EINVAL, "out pointer is NULL");
+    *out = nullptr;
+    if (!valid_n(n)) return fail(BMG_EINVAL, "n=%d is not 2^m-1 with 2 <= m <= 15", n);
+    if (kind != 5 && kind != 9) return fail(BMG_EINVAL, "stencil kind %d is not 5 or 9", kind);
+    if (!stencil) return fail(BMG_EINVAL, "stencil is NULL");
+    bmg_options op;
+    bmg_default_options(&op);
+    if (o) op = *o;
+    TRY(check_options(op));
+    const size_t need = plan(nullptr, n, kind, op, nullptr);
+    if (!workspace || ws_bytes < need || ((uintptr_t)workspace & (ALIGN - 1)))
+        return fail(BMG_EWORKSPACE, "workspace %p of %zu bytes; need %zu bytes, 256-byte aligned",
+                    workspace, ws_bytes, need);
+    bmg_solver *h = new bmg_solver();
+    h->n = n;
+    h->kind = kind;
+    h->opt = op;
+    h->st = (hipStream_t)stream;
+    h->ws = (char *)workspace;
+    h->ws_bytes = ws_bytes;
+    plan(h, n, kind, op, h->ws);
+    auto bail = [&](bmg_status s) { delete h; return s; };
+#define SCHK(x)                                  \
+    do {                                         \
+        bmg_status s_ = (x);                     \
+        if (s_ != BMG_OK) return bail(s_);       \
+    } while (0)
+    if (hipMemsetAsync(h->ws, 0, need, h->st) != hipSuccess)
+        return bail(fail(BMG_EDEVICE, "hipMemsetAsync of the workspace failed"));
+    hipLaunchKernelGGL(k_import_stencil, grid2(n, n, B2), B2, 0, h->st, stencil, kind, h->L[0], h->flags);
+    for (int l = 0; l + 1 < h->nlev; ++l) {
+        const int nc = h->L[l + 1].n;
+        hipLaunchKernelGGL(k_weights_edges, grid2(nc + 1, nc + 1, B2), B2, 0, h->st, h->L[l], h->C[l], nc, h->flags);
+        hipLaunchKernelGGL(k_weights_corners, grid2(nc + 1, nc + 1, B2), B2, 0, h->st, h->L[l], h->C[l], nc, h->flags);
+        hipLaunchKernelGGL(k_rap, grid2(nc, nc, dim3(32, 4)), dim3(32, 4), 0, h->st, h->L[l], h->C[l], h->L[l + 1]);
+    }
+    hipLaunchKernelGGL(k_coarse_factor, dim3(1), dim3(64), 0, h->st, h->L[h->nlev - 1], h->LD, h->flags);
+    if (h->f32) {
+        for (int l = 0; l < h->nlev; ++l) {
+            const size_t pl = (size_t)(h->L[l].n + 2) * h->L[l].ld;
+            const dim3 g(std::min<size_t>((pl + 255) / 256, 4096)), b(256);
+            hipLaunchKernelGGL(k_round_f32, g, b, 0, h->st, h->L[l].O, h->L32[l].O, pl);
+            hipLaunchKernelGGL(k_round_f32, g, b, 0, h->st, h->L[l].W, h->L32[l].W, pl);
+            hipLaunchKernelGGL(k_round_f32, g, b, 0, h->st, h->L[l].S, h->L32[l].S, pl);
+            if (h->nine[l]) {
+                hipLaunchKernelGGL(k_round_f32, g, b, 0, h->st, h->L[l].SW, h->L32[l].SW, pl);
+                hipLaunchKernelGGL(k_round_f32, g, b, 0, h->st, h->L[l].NW, h->L32[l].NW, pl);
+            }
+            if (l + 1 < h->nlev) {
+                const size_t cp = 8 * h->C[l].ps;
+                hipLaunchKernelGGL(k_round_f32, dim3(std::min<size_t>((cp + 255) / 256, 4096)), b, 0, h->st,
+                                   h->C[l].p, h->C32[l].p, cp);
+            }
+        }
+    }
+    if (hipGetLastError() != hipSuccess) return bail(fail(BMG_EDEVICE, "set-up kernel launch failed"));
+    int flags = 0;
+    if (hipMemcpyAsync(&flags, h->flags, sizeof flags, hipMemcpyDeviceToHost, h->st) != hipSuccess ||
+        hipStreamSynchronize(h->st) != hipSuccess)
+        return bail(fail(BMG_EDEVICE, "reading the set-up flags failed"));
+    if (flags & (F_NONFINITE | F_DIAG | F_BOUNDARY | F_ASYM))
+        return bail(fail(BMG_EINVAL, "stencil rejected:%s%s%s%s", (flags & F_NONFINITE) ? " non-finite entry" : "",
+                         (flags & F_DIAG) ? " centre <= 0" : "", (flags & F_BOUNDARY) ? " coupling to the boundary" : "",
+                         (flags & F_ASYM) ? " not symmetric" : ""));
+    if (flags & (F_BREAK_INTERP | F_BREAK_COARSE))
+        return bail(fail(BMG_EBREAKDOWN, "%s", (flags & F_BREAK_INTERP) ? "interpolation denominator <= 0"
+                                                                         : "coarsest pivot <= 0"));
+#undef SCHK
+    *out = h;
+    return BMG_OK;
+}
+
+bmg_status bmg_destroy(bmg_solver *h)
+{
+    if (!h) return BMG_OK;
+    for (hipEvent_t e : h->tr_ev) (void)hipEventDestroy(e);
+    delete h;
+    return BMG_OK;
+}
+
+// One FP64 V-cycle on the level-0 arrays (b, u already packed).
+static bmg_status cycle64(bmg_solver *h, const int *stop)
+{
+    if (h->opt.kernels == BMG_KERNELS_FUSED) return fused_vcycle(h, stop);
+    return vcycle_from<double>(h, 0, stop);
+}
+
+// One refinement step on the level-0 FP64 arrays: r = b - A x is in L[0].r
+// and scal[S_RMAX] holds ||r||_inf; x += s * V32(0, fl32(r / s)).
+static bmg_status ir_step(bmg_solver *h, const int *stop)
+{
+    const Lev<double> &L = h->L[0];
+    const Lev<float> &F = h->L32[0];
+    hipLaunchKernelGGL(k_ir_scale, grid2(L.n, L.n, B2), B2, 0, h->st, L, F, (const double *)(h->scal + S_RMAX),
+                       h->scal + S_SCALE, stop);
+    LAUNCHCHK();
+    if (h->opt.kernels == BMG_KERNELS_FUSED) TRY(fused_vcycle32(h, stop));
+    else TRY(vcycle_from<float>(h, 0, stop));
+    hipLaunchKernelGGL(k_ir_update, grid2(L.n, L.n, B2), B2, 0, h->st, L, F, (const double *)(h->scal + S_SCALE), stop);
+    LAUNCHCHK();
+    return BMG_OK;
+}
+
+// FP64 residual of the iterate into L[0].r, its sum of squares (recorded in
+// the history when `record`) and, for refinement, its max norm.
+static bmg_status outer_residual(bmg_solver *h, bool record, double tol, int maxc, bool need_max)
+{
+    const Lev<double> &L = h->L[0];
+    TRY(residual<double>(h, L, h->nine[0], record ? h->stop : nullptr));
+    TRY(sumsq<double>(h, L, false, false, L.r, S_SUMSQ, record, tol, maxc));
+    if (need_max) {
+        const int nb = std::min(NPART, L.n);
+        hipLaunchKernelGGL(k_absmax_partial, dim3(nb), dim3(256), 0, h->st, L, h->part, (const int *)h->stop);
+        hipLaunchKernelGGL(k_absmax_final, dim3(1), dim3(1024), 0, h->st, (const double *)h->part, nb,
+                           h->scal + S_RMAX, (const int *)h->stop);
+        LAUNCHCHK();
+    }
+    return BMG_OK;
+}
+
+bmg_status bmg_vcycle(bmg_solver *h, const double *rhs, double *x, double *rel_res)
+{
+    if (!h || !rhs || !x) return fail(BMG_EINVAL, "NULL argument");
+    const Lev<double> &L = h->L[0];
+    TRY(pack_in(h, rhs, L.b));
+    TRY(pack_in(h, x, L.u));
+    if (h->f32) {
+        TRY(outer_residual(h, false, 0.0, 0, true));
+        TRY(ir_step(h, nullptr));
+    } else {
+        TRY(cycle64(h, nullptr));
+    }
+    TRY(pack_out(h, L.u, x));
+    if (rel_res) {
+        TRY(sumsq<double>(h, L, h->nine[0], true, nullptr, S_SUMSQ, false, 0.0, 0));
+        TRY(sumsq<double>(h, L, false, false, L.b, S_TMP, false, 0.0, 0));
+        double v[4];
+        TRY(read_scalars(h, v, 0, 4));
+        *rel_res = sqrt(v[S_SUMSQ]) / sqrt(v[S_TMP]);
+    }
+    return BMG_OK;
+}
+
+bmg_status bmg_solve(bmg_solver *h, const double *rhs, double *x, double tol, bmg_info *info)
+{
+    if (!h || !rhs || !x) return fail(BMG_EINVAL, "NULL argument");
+    if (!(tol >= 0.0)) return fail(BMG_EINVAL, "tol must be >= 0");
+    const Lev<double> &L = h->L[0];
+    TRY(pack_in(h, rhs, L.b));
+    TRY(pack_in(h, x, L.u));
+    // ||b|| and the initial residual, then the device-side stop bookkeeping
+    TRY(sumsq<double>(h, L, false, false, L.b, S_TMP, false, 0.0, 0));
+    TRY(sumsq<double>(h, L, h->nine[0], true, nullptr, S_SUMSQ, false, 0.0, 0));
+    double v[S_NSCAL];
+    TRY(read_scalars(h, v, 0, S_NSCAL));
+    const int maxc = h->opt.max_cycles;
+    if (v[S_TMP] == 0.0) {
+        HIPCHK(hipMemsetAsync(L.u, 0, (size_t)(L.n + 2) * L.ld * sizeof(double), h->st));
+        TRY(pack_out(h, L.u, x));
+        HIPCHK(hipStreamSynchronize(h->st));
+        if (info) { info->cycles = 0; info->rel_res = 0.0; info->rho = 0.0; }
+        return BMG_OK;
+    }
+    double init[2] = {sqrt(v[S_TMP]), sqrt(v[S_SUMSQ]) / sqrt(v[S_TMP])};
+    HIPCHK(hipMemcpyAsync(h->scal + S_BNORM, init, sizeof init, hipMemcpyHostToDevice, h->st));
+    HIPCHK(hipMemsetAsync(h->count, 0, 2 * sizeof(int), h->st));
+    int cs[2] = {0, 0};
+    const int every = h->opt.check_every;
+    if (!h->f32) {
+        // history[k] = relative residual after cycle k+1
+        while (true) {
+            for (int t = 0; t < every; ++t) {
+                TRY(cycle64(h, h->stop));
+                TRY(sumsq<double>(h, L, h->nine[0], true, nullptr, S_SUMSQ, true, tol, maxc));
+            }
+            HIPCHK(hipMemcpyAsync(cs, h->count, sizeof cs, hipMemcpyDeviceToHost, h->st));
+            HIPCHK(hipStreamSynchronize(h->st));
+            if (cs[1]) break;
+        }
+    } else {
+        // history[0] = initial residual, history[k] after correction k
+        const int maxe = maxc + 1;
+        TRY(outer_residual(h, true, tol, maxe, true));
+        while (true) {
+            for (int t = 0; t < every; ++t) {
+                TRY(ir_step(h, h->stop));
+                TRY(outer_residual(h, true, tol, maxe, true));
+            }
+            HIPCHK(hipMemcpyAsync(cs, h->count, sizeof cs, hipMemcpyDeviceToHost, h->st));
+            HIPCHK(hipStreamSynchronize(h->st));
+            if (cs[1]) break;
+        }
+    }
+    TRY(pack_out(h, L.u, x));
+    std::vector<double> hist(std::max(cs[0], 1));
+    HIPCHK(hipMemcpyAsync(hist.data(), h->hist, cs[0] * sizeof(double), hipMemcpyDeviceToHost, h->st));
+    HIPCHK(hipStreamSynchronize(h->st));
+    const int steps = h->f32 ? cs[0] - 1 : cs[0];
+    if (info) {
+        info->cycles = steps;
+        info->rel_res = hist[cs[0] - 1];
+        const double r0 = h->f32 ? hist[0] : init[1];
+        info->rho = steps > 0 ? pow(info->rel_res / r0, 1.0 / steps) : 0.0;
+        if (info->history) memcpy(info->history, hist.data(), cs[0] * sizeof(double));
+    }
+    if (cs[1] == 2) return fail(BMG_EDIVERGED, "residual %.3e after %d cycles", hist[cs[0] - 1], steps);
+    if (cs[1] == 3) return fail(BMG_ENOCONV, "relative residual %.3e > tol %.3e after %d cycles",
+                                hist[cs[0] - 1], tol, steps);
+    return BMG_OK;
+}
+
+// --------------------------------------------------------- level access
+bmg_status bmg_num_levels(const bmg_solver *h, int *nlev)
+{
+    if (!h || !nlev) return fail(BMG_EINVAL, "NULL argument");
+    *nlev = h->nlev;
+    return BMG_OK;
+}
+
+bmg_status bmg_level_n(const bmg_solver *h, int level, int *n)
+{
+    if (!h || !n) return fail(BMG_EINVAL, "NULL argument");
+    if (level < 0 || level >= h->nlev) return fail(BMG_EINVAL, "level %d out of range", level);
+    *n = h->L[level].n;
+    return BMG_OK;
+}
+
+// Resolves (level, field) to a device array, its element size, pitch, row
+// count and row width of the tight layout.
+static bmg_status locate(bmg_solver *h, int level, int field, char **ptr, size_t *es, size_t *pitch,
+                         size_t *rows, size_t *width)
+{
+    if (!h) return fail(BMG_EINVAL, "NULL handle");
+    if (field == BMG_F_COARSE_LD) {
+        *ptr = (char *)h->LD; *es = 8; *pitch = 90 * 8; *rows = 1; *width = 90;
+        return BMG_OK;
+    }
+    if (level < 0 || level >= h->nlev) return fail(BMG_EINVAL, "level %d out of range", level);
+    const bool f32 = field >= BMG_F_U32;
+    if (f32 && !h->f32) return fail(BMG_EINVAL, "FP32 fields need precision BMG_FP32_IR");
+    const int fb = f32 ? field - BMG_F_U32 : field;
+    const Lev<double> &L = h->L[level];
+    const Lev<float> &F = h->L32[level];
+    void *p = nullptr;
+    switch (fb) {
+    case BMG_F_U: p = f32 ? (void *)F.u : (void *)L.u; break;
+    case BMG_F_B: p = f32 ? (void *)F.b : (void *)L.b; break;
+    case BMG_F_R: p = f32 ? (void *)F.r : (void *)L.r; break;
+    case BMG_F_AO: p = f32 ? (void *)F.O : (void *)L.O; break;
+    case BMG_F_AW: p = f32 ? (void *)F.W : (void *)L.W; break;
+    case BMG_F_AS: p = f32 ? (void *)F.S : (void *)L.S; break;
+    case BMG_F_ASW: p = f32 ? (void *)F.SW : (void *)L.SW; break;
+    case BMG_F_ANW: p = f32 ? (void *)F.NW : (void *)L.NW; break;
+    case BMG_F_CI: {
+        if (level + 1 >= h->nlev) return fail(BMG_EINVAL, "the coarsest level has no weights");
+        p = f32 ? (void *)h->C32[level].p : (void *)h->C[level].p;
+        const int nc = h->L[level + 1].n;
+        *ptr = (char *)p; *es = f32 ? 4 : 8; *pitch = (size_t)h->C[level].ld * *es;
+        *rows = 8 * (size_t)(nc + 2); *width = nc + 2;
+        return BMG_OK;
+    }
+    default: return fail(BMG_EINVAL, "unknown field %d", field);
+    }
+    if (!p) return fail(BMG_EINVAL, "field %d does not exist on level %d", field, level);
+    *ptr = (char *)p; *es = f32 ? 4 : 8; *pitch = (size_t)L.ld * *es; *rows = L.n + 2; *width = L.n + 2;
+    return BMG_OK;
+}
+
+bmg_status bmg_export(bmg_solver *h, int level, int field, void *dst)
+{
+    char *p; size_t es, pitch, rows, width;
+    TRY(locate(h, level, field, &p, &es, &pitch, &rows, &width));
+    if (!dst) return fail(BMG_EINVAL, "dst is NULL");
+    HIPCHK(hipMemcpy2DAsync(dst, width * es, p, pitch, width * es, rows, hipMemcpyDeviceToDevice, h->st));
+    return BMG_OK;
+}
+
+bmg_status bmg_import(bmg_solver *h, int level, int field, const void *src)
+{
+    char *p; size_t es, pitch, rows, width;
+    TRY(locate(h, level, field, &p, &es, &pitch, &rows, &width));
+    if (!src) return fail(BMG_EINVAL, "src is NULL");
+    HIPCHK(hipMemcpy2DAsync(p, pitch, src, width * es, width * es, rows, hipMemcpyDeviceToDevice, h->st));
+    return BMG_OK;
+}
+
+}  // extern "C"
+
+template <typename T>
+static bmg_status step_t(bmg_solver *h, int l, int step, int arg)
+{
+    const Lev<T> &F = lev<T>(h, l);
+    const bool last = l == h->nlev - 1;
+    if (last && step != BMG_STEP_SMOOTH && step != BMG_STEP_RESIDUAL && step != BMG_STEP_COARSE)
+        return fail(BMG_EINVAL, "step %d needs a coarser level below level %d", step, l);
+    switch (step) {
+    case BMG_STEP_SMOOTH: return smooth<T>(h, F, h->nine[l], arg, nullptr, l);
+    case BMG_STEP_RESIDUAL: return residual<T>(h, F, h->nine[l], nullptr);
+    case BMG_STEP_RESTRICT: return restrict_<T>(h, F, wts<T>(h, l), lev<T>(h, l + 1), nullptr);
+    case BMG_STEP_INTERP: return interp<T>(h, F, wts<T>(h, l), lev<T>(h, l + 1), nullptr);
+    case BMG_STEP_COARSE:
+        if (!last) return fail(BMG_EINVAL, "the direct solve runs on the coarsest level only");
+        return coarse<T>(h, F, nullptr);
+    case BMG_STEP_PRE: return fused_pre<T>(h, l, arg, nullptr);
+    case BMG_STEP_POST: return fused_post<T>(h, l, arg, nullptr);
+    default: return fail(BMG_EINVAL, "unknown step %d", step);
+    }
+}
+
+extern "C" bmg_status bmg_step(bmg_solver *h, int level, int step, int arg, int fp32)
+{
+    if (!h) return fail(BMG_EINVAL, "NULL handle");
+    if (level < 0 || level >= h->nlev) return fail(BMG_EINVAL, "level %d out of range", level);
+    if (arg < 0 || arg > 64) return fail(BMG_EINVAL, "step argument %d out of range", arg);
+    if (fp32) {
+        if (!h->f32) return fail(BMG_EINVAL, "FP32 steps need precision BMG_FP32_IR");
+        return step_t<float>(h, level, step, arg);
+    }
+    return step_t<double>(h, level, step, arg);
+}
+
+extern "C" {
+
+bmg_status bmg_trace_enable(bmg_solver *h, int kclass, int level, int on)
+{
+    if (!h) return fail(BMG_EINVAL, "NULL handle");
+    if (kclass < BMG_TRACE_SMOOTH || kclass > BMG_TRACE_RESNORM) return fail(BMG_EINVAL, "unknown class");
+    h->tr_class = on ? kclass : -1;
+    h->tr_level = level;
+    h->tr_used = 0;
+    return BMG_OK;
+}
+
+bmg_status bmg_trace_read(bmg_solver *h, int *launches, double *total_ms)
+{
+    if (!h || !launches || !total_ms) return fail(BMG_EINVAL, "NULL argument");
+    HIPCHK(hipStreamSynchronize(h->st));
+    double tot = 0.0;
+    for (int t = 0; t + 1 < h->tr_used; t += 2) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, h->tr_ev[t], h->tr_ev[t + 1]));
+        tot += ms;
+    }
+    *launches = h->tr_used / 2;
+    *total_ms = tot;
+    h->tr_used = 0;
+    return BMG_OK;
+}
+
+}  // extern "C"
