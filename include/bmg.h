@@ -61,7 +61,12 @@ typedef struct {
     int check_every; /* bmg_solve reads the residual history back every this many
                         cycles; cycles past convergence are skipped on the device,
                         so the iterates do not depend on it (default 8) */
-    int reserved[10];
+    int refine_factor; /* FP64: once the relative residual is <= refine_factor *
+                        tol, the iterate becomes a double-FP64 pair (x, x_lo)
+                        and each cycle is one refinement step with an accurate
+                        residual, which converges below the residual floor of
+                        FP64 vectors; 0 = never (default 16) */
+    int reserved[9];
 } bmg_options;
 
 typedef struct {
@@ -126,7 +131,15 @@ bmg_status bmg_setup(bmg_solver **out, const double *stencil, int n, int kind,
 bmg_status bmg_vcycle(bmg_solver *h, const double *rhs, double *x, double *rel_res);
 
 /* Cycles from the initial guess x until ||rhs - A x||_2 / ||rhs||_2 <= tol
- * (checked after every cycle) or max_cycles.  rhs, x as in bmg_vcycle.
+ * (checked after every cycle, with a residual computed by error-free
+ * transformations, as accurate as one in twice FP64) or max_cycles.
+ * FP64: V(nu1,nu2)-cycles on x; once the residual is <= refine_factor * tol,
+ * x is carried as the double-FP64 pair x + x_lo and a cycle is one refinement
+ * step: r = rhs - A (x + x_lo) (accurate, rounded once), d = V(0, r),
+ * (x, x_lo) += d in double-FP64.  FP32_IR: the same refinement from the first
+ * step, with d = s V32(0, fl32(r / s)), s the power of two >= ||r||_inf.
+ * The residual reported is that of the pair; x receives the high part and
+ * BMG_F_XLO the low part.  rhs, x as in bmg_vcycle.
  * info (host, nullable) receives the count, final residual and history.
  * ||rhs|| = 0 gives x = 0 after 0 cycles.  Returns BMG_ENOCONV if max_cycles
  * was reached (x and info still valid), BMG_EDIVERGED if the residual became
@@ -150,13 +163,15 @@ const char *bmg_last_error(void);
  *   BMG_F_CI: 8 x (n_{l+1}+2) x (n_{l+1}+2), planes LNE, LA, LNW, LR, LL, LSE,
  *   LB, LSW (the weights between level l and l+1);
  *   BMG_F_COARSE_LD: the coarsest factor, 81 entries of L (row-major, unit
- *   lower triangular) followed by the 9 entries of D (level argument ignored).
+ *   lower triangular) followed by the 9 entries of D (level argument ignored);
+ *   BMG_F_XLO: the low part of the last solve's double-FP64 iterate, level-0
+ *   layout (zero if the solve never switched to refinement).
  * The *32 fields are the FP32 hierarchy (precision BMG_FP32_IR only) and
  * transfer float data. */
 enum {
     BMG_F_U = 0, BMG_F_B = 1, BMG_F_R = 2,
     BMG_F_AO = 3, BMG_F_AW = 4, BMG_F_AS = 5, BMG_F_ASW = 6, BMG_F_ANW = 7,
-    BMG_F_CI = 8, BMG_F_COARSE_LD = 9,
+    BMG_F_CI = 8, BMG_F_COARSE_LD = 9, BMG_F_XLO = 10,
     BMG_F_U32 = 16, BMG_F_B32 = 17, BMG_F_R32 = 18,
     BMG_F_AO32 = 19, BMG_F_AW32 = 20, BMG_F_AS32 = 21, BMG_F_ASW32 = 22,
     BMG_F_ANW32 = 23, BMG_F_CI32 = 24

@@ -43,6 +43,75 @@
 #undef REAL
 #undef SFX
 
+/* Error-free transformations: Knuth's TwoSum and the fma TwoProduct. */
+static inline void two_sum_(double a, double b, double *s, double *e)
+{
+    const double x = a + b, z = x - a;
+    *s = x;
+    *e = (a - (x - z)) + (b - z);
+}
+
+/* Accurate residual r = b - A (xh + xl) on the fine level, xl nullable: the
+ * terms of the plain residual in the same order (SW, S, SE, W, E, NW, N, NE,
+ * centre), every product split exactly into value and error (TwoProduct by
+ * fma), every subtraction into value and error (TwoSum), the errors summed
+ * apart, then the products with xl (whose own rounding is below the result's
+ * precision), and one final rounding of value + errors (the compensated dot
+ * product of Ogita, Rump and Oishi, 2005).  It is as accurate as a residual
+ * computed in twice the working precision. */
+static void residual_dd(int n, const double *O, const double *W, const double *S,
+                        const double *SW, const double *NW, const double *b,
+                        const double *xh, const double *xl, double *r)
+{
+    const size_t ld = (size_t)n + 2;
+#pragma omp parallel for schedule(static)
+    for (int j = 1; j <= n; ++j) {
+        for (int i = 1; i <= n; ++i) {
+            const size_t p = (size_t)j * ld + (size_t)i;
+            const size_t q[9] = {p - ld - 1, p - ld, p - ld + 1, p - 1, p + 1,
+                                 p + ld - 1, p + ld, p + ld + 1, p};
+            double a[9];
+            a[0] = SW ? SW[p] : 0.0;
+            a[1] = S[p];
+            a[2] = NW ? NW[p + 1 - ld] : 0.0;
+            a[3] = W[p];
+            a[4] = W[p + 1];
+            a[5] = NW ? NW[p] : 0.0;
+            a[6] = S[p + ld];
+            a[7] = SW ? SW[p + ld + 1] : 0.0;
+            a[8] = O[p];
+            double s = b[p], c = 0.0, ns, se;
+            for (int t = 0; t < 9; ++t) {
+                const double pr = a[t] * xh[q[t]];
+                const double pe = fma(a[t], xh[q[t]], -pr);
+                two_sum_(s, -pr, &ns, &se);
+                s = ns;
+                c = c + (se - pe);
+            }
+            if (xl) {
+                for (int t = 0; t < 9; ++t) {
+                    two_sum_(s, -(a[t] * xl[q[t]]), &ns, &se);
+                    s = ns;
+                    c = c + se;
+                }
+            }
+            r[p] = s + c;
+        }
+    }
+}
+
+/* (xh, xl) + d in double-FP64: TwoSum of the high parts, the low part added to
+ * the error, then renormalised (Dekker's fast TwoSum). */
+static inline void dd_add(double *xh, double *xl, double d)
+{
+    double s, e;
+    two_sum_(*xh, d, &s, &e);
+    e = e + *xl;
+    const double hi = s + e;
+    *xl = e - (hi - s);
+    *xh = hi;
+}
+
 static int valid_n(int n) { return n >= 3 && ((n + 1) & n) == 0; }
 
 /* ----------------------------------------------------- a0: discretisation */
@@ -628,63 +697,94 @@ void orc_step(orc_hier *H, int l, int op, int arg)
     }
 }
 
-/* Relative residual ||b - A u||_2 / ||b||_2 over the interior of level 0. */
-double orc_rel_residual(orc_hier *H, const double *b, const double *u)
+/* Relative residual ||b - A (xh + xl)||_2 / ||b||_2 over the interior of
+ * level 0, with the accurate residual (xl nullable). */
+double orc_rel_residual(orc_hier *H, const double *b, const double *xh, const double *xl)
 {
     const int n = H->n[0];
-    residual_d(n, H->O[0], H->W[0], H->S[0], H->SW[0], H->NW[0], b, u, H->r[0]);
+    residual_dd(n, H->O[0], H->W[0], H->S[0], H->SW[0], H->NW[0], b, xh, xl, H->r[0]);
     const double nr = orc_sumsq(n, H->r[0]);
     const double nb = orc_sumsq(n, b);
     return sqrt(nr) / sqrt(nb);
 }
 
-/* Solve to ||b - A u||/||b|| <= tol (checked after every cycle) or max_cycles.
+/* Solve to ||b - A x||_2/||b||_2 <= tol, checked after every cycle with the
+ * accurate residual, or max_cycles.  V(nu1,nu2)-cycles on the FP64 iterate
+ * until the relative residual is <= refine_factor * tol (refine_factor = 0:
+ * never); from then on the iterate is carried as a double-FP64 pair
+ * (xh, xl) and each cycle is one refinement step: r = b - A (xh + xl)
+ * (accurate residual, rounded once), d = V(nu1,nu2)(0, r), (xh, xl) += d in
+ * double-FP64.  In exact arithmetic both forms are the same iteration; the
+ * second one keeps converging below the residual floor of FP64 vectors.
+ * u: (n+2)^2 initial guess in, xh out; xl: (n+2)^2 out or NULL.
  * hist receives the relative residual after each cycle; returns the number of
- * cycles run (negative status on failure).  ||b|| = 0 gives u = 0, 0 cycles. */
-int orc_solve(orc_hier *H, const double *b, double *u, double tol, int max_cycles,
-              double *hist)
+ * cycles run.  ||b|| = 0 gives u = 0 after 0 cycles. */
+int orc_solve(orc_hier *H, const double *b, double *u, double *xl_out, double tol,
+              int max_cycles, int refine_factor, double *hist)
 {
     const int n = H->n[0];
     const size_t sz = (size_t)(n + 2) * (n + 2);
+    if (xl_out) memset(xl_out, 0, sz * sizeof(double));
     if (orc_sumsq(n, b) == 0.0) {
         memset(u, 0, sz * sizeof(double));
         return 0;
     }
+    const double nb = sqrt(orc_sumsq(n, b));
+    double *xl = (double *)calloc(sz, sizeof(double));
+    double *r = (double *)calloc(sz, sizeof(double));
     memcpy(H->b[0], b, sz * sizeof(double));
     memcpy(H->u[0], u, sz * sizeof(double));
-    const double nb = sqrt(orc_sumsq(n, b));
-    int k = 0;
+    int k = 0, phase = 0;
     while (k < max_cycles) {
         vcycle_d(H, 0);
-        residual_d(n, H->O[0], H->W[0], H->S[0], H->SW[0], H->NW[0], H->b[0], H->u[0], H->r[0]);
-        const double rho = sqrt(orc_sumsq(n, H->r[0])) / nb;
+        if (phase == 0) {
+            residual_dd(n, H->O[0], H->W[0], H->S[0], H->SW[0], H->NW[0], b, H->u[0], NULL, r);
+        } else {
+            for (size_t t = 0; t < sz; ++t) dd_add(&u[t], &xl[t], H->u[0][t]);
+            residual_dd(n, H->O[0], H->W[0], H->S[0], H->SW[0], H->NW[0], b, u, xl, r);
+        }
+        const double rho = sqrt(orc_sumsq(n, r)) / nb;
         if (hist) hist[k] = rho;
         ++k;
         if (!(rho > tol)) break;
+        if (phase == 0 && refine_factor > 0 && rho <= refine_factor * tol) {
+            phase = 1;
+            memcpy(u, H->u[0], sz * sizeof(double));
+        }
+        if (phase == 1) {
+            memcpy(H->b[0], r, sz * sizeof(double));
+            memset(H->u[0], 0, sz * sizeof(double));
+        }
     }
-    memcpy(u, H->u[0], sz * sizeof(double));
+    if (phase == 0) memcpy(u, H->u[0], sz * sizeof(double));
+    else if (xl_out) memcpy(xl_out, xl, sz * sizeof(double));
+    free(xl);
+    free(r);
     return k;
 }
 
 /* FP32 V-cycle (FP32-rounded hierarchy, FP64 coarsest solve) as the
- * preconditioner of FP64 iterative refinement, the mixed-precision form:
- *   x = given; loop: r = b - A x (FP64); rho = ||r||/||b||, stop if <= tol;
- *   s = 2^e the smallest power of two >= ||r||_inf; r32 = fl32(r / s);
- *   d32 = V32(nu1,nu2)(0, r32); x = x + s * d32 (FP64).
+ * preconditioner of iterative refinement on a double-FP64 iterate:
+ *   (xh, xl) = (given, 0); loop: r = b - A (xh + xl) (accurate residual);
+ *   rho = ||r||/||b||, stop if <= tol; s = the smallest power of two
+ *   >= ||r||_inf; r32 = fl32(r / s); d32 = V32(nu1,nu2)(0, r32);
+ *   (xh, xl) += s * d32 in double-FP64.
  * hist receives rho before each correction (hist[0] is the initial residual);
  * returns the number of corrections applied. */
-int orc_solve_ir(orc_hier *H, const double *b, double *x, double tol, int max_iter,
-                 double *hist)
+int orc_solve_ir(orc_hier *H, const double *b, double *x, double *xl_out, double tol,
+                 int max_iter, double *hist)
 {
     const int n = H->n[0];
     const size_t ld = (size_t)n + 2, sz = ld * ld;
     orc_make_f32(H);
+    if (xl_out) memset(xl_out, 0, sz * sizeof(double));
     const double nb = sqrt(orc_sumsq(n, b));
     if (nb == 0.0) { memset(x, 0, sz * sizeof(double)); return 0; }
     double *r = H->r[0];
+    double *xl = (double *)calloc(sz, sizeof(double));
     int it = 0;
     for (;;) {
-        residual_d(n, H->O[0], H->W[0], H->S[0], H->SW[0], H->NW[0], b, x, r);
+        residual_dd(n, H->O[0], H->W[0], H->S[0], H->SW[0], H->NW[0], b, x, xl, r);
         const double rho = sqrt(orc_sumsq(n, r)) / nb;
         if (hist) hist[it] = rho;
         if (!(rho > tol) || it >= max_iter) break;
@@ -700,8 +800,10 @@ int orc_solve_ir(orc_hier *H, const double *b, double *x, double tol, int max_it
         for (size_t t = 0; t < sz; ++t) H->fb[0][t] = (float)(r[t] * inv);
         memset(H->fu[0], 0, sz * sizeof(float));
         vcycle_f(H, 0);
-        for (size_t t = 0; t < sz; ++t) x[t] = x[t] + s * (double)H->fu[0][t];
+        for (size_t t = 0; t < sz; ++t) dd_add(&x[t], &xl[t], s * (double)H->fu[0][t]);
         ++it;
     }
+    if (xl_out) memcpy(xl_out, xl, sz * sizeof(double));
+    free(xl);
     return it;
 }

@@ -81,11 +81,11 @@ def lib():
         L.orc_vcycle.restype = None
         L.orc_step.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int]
         L.orc_step.restype = None
-        L.orc_rel_residual.argtypes = [C.c_void_p, _dp, _dp]
+        L.orc_rel_residual.argtypes = [C.c_void_p, _dp, _dp, _dp]
         L.orc_rel_residual.restype = C.c_double
-        L.orc_solve.argtypes = [C.c_void_p, _dp, _dp, C.c_double, C.c_int, _dp]
+        L.orc_solve.argtypes = [C.c_void_p, _dp, _dp, _dp, C.c_double, C.c_int, C.c_int, _dp]
         L.orc_solve.restype = C.c_int
-        L.orc_solve_ir.argtypes = [C.c_void_p, _dp, _dp, C.c_double, C.c_int, _dp]
+        L.orc_solve_ir.argtypes = [C.c_void_p, _dp, _dp, _dp, C.c_double, C.c_int, _dp]
         L.orc_solve_ir.restype = C.c_int
         L.orc_make_f32.argtypes = [C.c_void_p]
         L.orc_make_f32.restype = C.c_int
@@ -231,6 +231,7 @@ class Hierarchy:
         self.K = K
         self.nu1, self.nu2 = nu1, nu2
         self.nlev = lib().orc_num_levels(h)
+        self.xl = None
 
     def close(self):
         if self._h:
@@ -283,26 +284,33 @@ class Hierarchy:
         lib().orc_vcycle(self._h, _p(_c(b)), _p(u))
         return u
 
-    def rel_residual(self, b, u) -> float:
-        return lib().orc_rel_residual(self._h, _p(_c(b)), _p(_c(u)))
+    def rel_residual(self, b, u, xl=None) -> float:
+        """||b - A (u + xl)|| / ||b|| with the accurate residual."""
+        return lib().orc_rel_residual(self._h, _p(_c(b)), _p(_c(u)), _p(_c(xl)))
 
     def solve(self, b: np.ndarray, u: np.ndarray | None = None, tol: float = 1e-10,
-              max_cycles: int = 100):
-        """Returns ``(u, history)``; history[k] = ||b - A u^{k+1}|| / ||b||."""
+              max_cycles: int = 100, refine_factor: int = 16):
+        """Returns ``(u, history)``; history[k] = ||b - A x^{k+1}|| / ||b||.
+        Once the relative residual is <= refine_factor * tol the iterate is a
+        double-FP64 pair; its low part is left in ``self.xl``."""
         u = np.zeros_like(b) if u is None else np.array(u, dtype=np.float64, copy=True)
         hist = np.zeros(max_cycles)
-        k = lib().orc_solve(self._h, _p(_c(b)), _p(u), tol, max_cycles, _p(hist))
+        self.xl = np.zeros_like(u)
+        k = lib().orc_solve(self._h, _p(_c(b)), _p(u), _p(self.xl), tol, max_cycles,
+                            refine_factor, _p(hist))
         if k < 0:
             raise OracleError(k, "solve")
         return u, hist[:k].copy()
 
     def solve_ir(self, b: np.ndarray, x: np.ndarray | None = None, tol: float = 1e-10,
                  max_iter: int = 100):
-        """FP32-preconditioned FP64 iterative refinement; returns ``(x, history)``
-        with history[0] the initial relative residual."""
+        """FP32-preconditioned refinement of a double-FP64 iterate; returns
+        ``(x_high, history)`` with history[0] the initial relative residual; the
+        low part is left in ``self.xl``."""
         x = np.zeros_like(b) if x is None else np.array(x, dtype=np.float64, copy=True)
         hist = np.zeros(max_iter + 1)
-        k = lib().orc_solve_ir(self._h, _p(_c(b)), _p(x), tol, max_iter, _p(hist))
+        self.xl = np.zeros_like(x)
+        k = lib().orc_solve_ir(self._h, _p(_c(b)), _p(x), _p(self.xl), tol, max_iter, _p(hist))
         if k < 0:
             raise OracleError(k, "solve_ir")
         return x, hist[:k + 1].copy()

@@ -23,6 +23,7 @@ BMG_FP64, BMG_FP32_IR = 0, 1
 BMG_KERNELS_BASIC, BMG_KERNELS_FUSED = 0, 1
 
 FIELDS = {"u": 0, "b": 1, "r": 2, "O": 3, "W": 4, "S": 5, "SW": 6, "NW": 7, "Ci": 8, "LD": 9,
+          "xlo": 10,
           "u32": 16, "b32": 17, "r32": 18, "O32": 19, "W32": 20, "S32": 21, "SW32": 22,
           "NW32": 23, "Ci32": 24}
 STEPS = {"smooth": 0, "residual": 1, "restrict": 2, "interp": 3, "coarse": 4, "pre": 5, "post": 6}
@@ -32,7 +33,7 @@ TRACE = {"smooth": 0, "pre": 1, "post": 2, "resnorm": 3}
 class Options(C.Structure):
     _fields_ = [("nu1", C.c_int), ("nu2", C.c_int), ("max_cycles", C.c_int),
                 ("precision", C.c_int), ("kernels", C.c_int), ("check_every", C.c_int),
-                ("reserved", C.c_int * 10)]
+                ("refine_factor", C.c_int), ("reserved", C.c_int * 9)]
 
 
 class Info(C.Structure):
@@ -197,6 +198,8 @@ class Solver:
         dtype = torch.float32 if field.endswith("32") else torch.float64
         if base == "LD":
             return (90,), torch.float64
+        if base == "xlo":
+            return (self.n + 2, self.n + 2), torch.float64
         if base == "Ci":
             nc = self.level_n(level + 1)
             return (8, nc + 2, nc + 2), dtype

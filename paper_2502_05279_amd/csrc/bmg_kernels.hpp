@@ -514,10 +514,11 @@ __global__ void k_sumsq_partial(Lev<T> L, const T *__restrict__ x, double *__res
 // Final sum of the partials (fixed order) -> out[0].  With `hist` given, this
 // also records rel = sqrt(sum)/bnorm[0] into hist[*count], advances the count,
 // and raises *stop: 1 once rel <= tol, 2 if rel is not finite or exceeds
-// 1e3 times the initial relative residual bnorm[1], 3 when maxc entries exist.
+// 1e3 times the initial relative residual bnorm[1], 3 when maxc entries exist,
+// 4 once rel <= refine (refine > 0): the solve switches to refinement.
 __global__ void k_sumsq_final(const double *__restrict__ part, int np, double *__restrict__ out,
                               double *hist, int *count, int *stop, const double *bnorm,
-                              double tol, int maxc)
+                              double tol, int maxc, double refine)
 {
     if (stopped(stop)) return;
     double v = 0.0;
@@ -534,6 +535,7 @@ __global__ void k_sumsq_final(const double *__restrict__ part, int np, double *_
             if (rel <= tol) s = 1;
             else if (!isfinite(rel) || rel > 1e3 * bnorm[1]) s = 2;
             else if (k + 1 >= maxc) s = 3;
+            else if (refine > 0.0 && rel <= refine) s = 4;
             if (s) *stop = s;
         }
     }
@@ -616,15 +618,95 @@ __global__ void k_ir_scale(Lev<double> L, Lev<float> F, const double *__restrict
     F.u[p] = 0.0f;
 }
 
-// x = x + s * (double)d32 on the FP64 iterate.
-__global__ void k_ir_update(Lev<double> L, Lev<float> F, const double *__restrict__ scale, const int *stop)
+// ------------------------------------------------ double-FP64 iterate
+__device__ __forceinline__ void two_sum(double a, double b, double &s, double &e)
+{
+    const double x = a + b, z = x - a;
+    s = x;
+    e = (a - (x - z)) + (b - z);
+}
+
+// Accurate residual r = B - A (XH + XL) (XL nullable) on the fine level: the
+// plain residual's terms in its order (SW, S, SE, W, E, NW, N, NE, centre),
+// each product split into value and exact error by fma, each subtraction by
+// TwoSum, the errors summed apart, then the XL products, one final rounding.
+// MODE 0: sum of squares only; 1: also r -> rout; 2: also r -> L.b and 0 -> L.u
+// (the next refinement cycle starts from zero on the right-hand side r).
+template <bool NINE, int MODE>
+__global__ void k_resid_dd(Lev<double> L, const double *__restrict__ B, const double *__restrict__ XH,
+                           const double *__restrict__ XL, double *__restrict__ rout,
+                           double *__restrict__ part, const int *stop)
+{
+    if (stopped(stop)) return;
+    const size_t ld = L.ld;
+    const int n = L.n;
+    double acc = 0.0;
+    for (int j = 1 + blockIdx.x; j <= n; j += gridDim.x) {
+        for (int i = 1 + threadIdx.x; i <= n; i += blockDim.x) {
+            const size_t p = (size_t)j * ld + i;
+            double a[9];
+            size_t q[9] = {p - ld - 1, p - ld, p - ld + 1, p - 1, p + 1, p + ld - 1, p + ld, p + ld + 1, p};
+            a[0] = NINE ? L.SW[p] : 0.0;
+            a[1] = L.S[p];
+            a[2] = NINE ? L.NW[p + 1 - ld] : 0.0;
+            a[3] = L.W[p];
+            a[4] = L.W[p + 1];
+            a[5] = NINE ? L.NW[p] : 0.0;
+            a[6] = L.S[p + ld];
+            a[7] = NINE ? L.SW[p + ld + 1] : 0.0;
+            a[8] = L.O[p];
+            double s = B[p], c = 0.0, ns, se;
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                if (!NINE && (t == 0 || t == 2 || t == 5 || t == 7)) continue;
+                const double x = XH[q[t]];
+                const double pr = a[t] * x;
+                const double pe = fma(a[t], x, -pr);
+                two_sum(s, -pr, ns, se);
+                s = ns;
+                c = c + (se - pe);
+            }
+            if (XL) {
+#pragma unroll
+                for (int t = 0; t < 9; ++t) {
+                    if (!NINE && (t == 0 || t == 2 || t == 5 || t == 7)) continue;
+                    two_sum(s, -(a[t] * XL[q[t]]), ns, se);
+                    s = ns;
+                    c = c + se;
+                }
+            }
+            const double r = s + c;
+            if (MODE == 1) rout[p] = r;
+            if (MODE == 2) {
+                L.b[p] = r;
+                L.u[p] = 0.0;
+            }
+            acc += r * r;
+        }
+    }
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+// (XH, XL) += d in double-FP64 with d = L.u (FP64 inner cycle) or
+// d = scale * (double)U32 (FP32 inner cycle): TwoSum, add the low part,
+// renormalise with Dekker's fast TwoSum.
+__global__ void k_dd_update(Lev<double> L, double *__restrict__ XH, double *__restrict__ XL,
+                            const float *__restrict__ U32, const double *__restrict__ scale,
+                            const int *stop)
 {
     if (stopped(stop)) return;
     const int i = 1 + blockIdx.x * blockDim.x + threadIdx.x;
     const int j = 1 + blockIdx.y * blockDim.y + threadIdx.y;
     if (i > L.n || j > L.n) return;
     const size_t p = (size_t)j * L.ld + i;
-    L.u[p] = L.u[p] + scale[0] * (double)F.u[p];
+    const double d = U32 ? scale[0] * (double)U32[p] : L.u[p];
+    double s, e;
+    two_sum(XH[p], d, s, e);
+    e = e + XL[p];
+    const double hi = s + e;
+    XL[p] = e - (hi - s);
+    XH[p] = hi;
 }
 
 }  // namespace bmg

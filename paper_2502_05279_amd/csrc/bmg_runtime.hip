@@ -68,6 +68,9 @@ struct bmg_solver {
     bool f32 = false;
     Lev<float> L32[MAXL];
     Wts<float> C32[MAXL];
+    double *B0 = nullptr;       // fine right-hand side during refinement
+    double *XH = nullptr;       // double-FP64 iterate, high part
+    double *XL = nullptr;       // double-FP64 iterate, low part
     double *LD = nullptr;       // coarsest factor: 81 L + 9 D
     int *flags = nullptr;       // validation / breakdown bits
     double *part = nullptr;     // NPART partial sums
@@ -148,6 +151,10 @@ size_t plan(bmg_solver *h, int n, int kind, const bmg_options &o, char *base)
             h->C32[l] = FW;
         }
     }
+    const size_t pl0 = (size_t)(ns[0] + 2) * pitch_of(ns[0]);
+    double *B0 = (double *)take(pl0 * 8);
+    double *XH = (double *)take(pl0 * 8);
+    double *XL = (double *)take(pl0 * 8);
     double *LD = (double *)take(90 * 8);
     int *flags = (int *)take(64);
     double *part = (double *)take(NPART * 8);
@@ -157,6 +164,9 @@ size_t plan(bmg_solver *h, int n, int kind, const bmg_options &o, char *base)
     int *cnt = (int *)take(64);
     if (h) {
         h->nlev = nl;
+        h->B0 = B0;
+        h->XH = XH;
+        h->XL = XL;
         h->LD = LD;
         h->flags = flags;
         h->part = part;
@@ -182,6 +192,8 @@ bmg_status check_options(const bmg_options &o)
         return fail(BMG_EINVAL, "kernel path %d is not available", o.kernels);
     if (o.check_every < 1 || o.check_every > 4096)
         return fail(BMG_EINVAL, "check_every=%d out of range", o.check_every);
+    if (o.refine_factor < 0)
+        return fail(BMG_EINVAL, "refine_factor=%d must be >= 0", o.refine_factor);
     return BMG_OK;
 }
 
@@ -324,7 +336,34 @@ bmg_status sumsq(bmg_solver *h, const Lev<T> &L, bool nine, bool res, const T *x
     }
     hipLaunchKernelGGL(k_sumsq_final, dim3(1), dim3(1024), 0, h->st, (const double *)h->part, nb,
                        h->scal + slot, record ? h->hist : nullptr, h->count, h->stop,
-                       (const double *)(h->scal + S_BNORM), tol, maxc);
+                       (const double *)(h->scal + S_BNORM), tol, maxc, 0.0);
+    trace_end(h, BMG_TRACE_RESNORM, 0);
+    LAUNCHCHK();
+    return BMG_OK;
+}
+
+// Accurate residual of (XH, XL) against B on the fine level, its sum of
+// squares into scal[slot] and, with record, the history / stop bookkeeping
+// (refine > 0: raise the switch-to-refinement code at that residual).
+// mode: 0 norm only, 1 r -> rout, 2 r -> L0.b and 0 -> L0.u.
+bmg_status resnorm_dd(bmg_solver *h, const double *B, const double *XH, const double *XL, int mode,
+                      double *rout, int slot, bool record, double tol, int maxc, double refine)
+{
+    const Lev<double> &L = h->L[0];
+    const int nb = std::min(NPART, L.n);
+    const int *stop = record ? h->stop : nullptr;
+    const dim3 g(nb), b(256);
+#define RDD(NINE, MODE) hipLaunchKernelGGL((k_resid_dd<NINE, MODE>), g, b, 0, h->st, L, B, XH, XL, rout, h->part, stop)
+    trace_begin(h, BMG_TRACE_RESNORM, 0);
+    if (h->nine[0]) {
+        if (mode == 0) RDD(true, 0); else if (mode == 1) RDD(true, 1); else RDD(true, 2);
+    } else {
+        if (mode == 0) RDD(false, 0); else if (mode == 1) RDD(false, 1); else RDD(false, 2);
+    }
+#undef RDD
+    hipLaunchKernelGGL(k_sumsq_final, dim3(1), dim3(1024), 0, h->st, (const double *)h->part, nb,
+                       h->scal + slot, record ? h->hist : nullptr, h->count, h->stop,
+                       (const double *)(h->scal + S_BNORM), tol, maxc, refine);
     trace_end(h, BMG_TRACE_RESNORM, 0);
     LAUNCHCHK();
     return BMG_OK;
@@ -384,6 +423,7 @@ bmg_status bmg_default_options(bmg_options *o)
     o->precision = BMG_FP64;
     o->kernels = BMG_KERNELS_BASIC;
     o->check_every = 8;
+    o->refine_factor = 16;
     return BMG_OK;
 }
 
@@ -496,43 +536,42 @@ bmg_status bmg_destroy(bmg_solver *h)
     return BMG_OK;
 }
 
-// One FP64 V-cycle on the level-0 arrays (b, u already packed).
+// One FP64 V-cycle on the level-0 arrays (b, u already set).
 static bmg_status cycle64(bmg_solver *h, const int *stop)
 {
     if (h->opt.kernels == BMG_KERNELS_FUSED) return fused_vcycle(h, stop);
     return vcycle_from<double>(h, 0, stop);
 }
 
-// One refinement step on the level-0 FP64 arrays: r = b - A x is in L[0].r
-// and scal[S_RMAX] holds ||r||_inf; x += s * V32(0, fl32(r / s)).
-static bmg_status ir_step(bmg_solver *h, const int *stop)
+// One FP32 refinement step: r = B0 - A (XH + XL) is in L0.r; scale to the
+// power of two s >= ||r||_inf, round to FP32, V32 from zero, (XH, XL) += s d32.
+static bmg_status ir_correct(bmg_solver *h, const int *stop)
 {
     const Lev<double> &L = h->L[0];
     const Lev<float> &F = h->L32[0];
+    const int nb = std::min(NPART, L.n);
+    hipLaunchKernelGGL(k_absmax_partial, dim3(nb), dim3(256), 0, h->st, L, h->part, stop);
+    hipLaunchKernelGGL(k_absmax_final, dim3(1), dim3(1024), 0, h->st, (const double *)h->part, nb,
+                       h->scal + S_RMAX, stop);
     hipLaunchKernelGGL(k_ir_scale, grid2(L.n, L.n, B2), B2, 0, h->st, L, F, (const double *)(h->scal + S_RMAX),
                        h->scal + S_SCALE, stop);
     LAUNCHCHK();
     if (h->opt.kernels == BMG_KERNELS_FUSED) TRY(fused_vcycle32(h, stop));
     else TRY(vcycle_from<float>(h, 0, stop));
-    hipLaunchKernelGGL(k_ir_update, grid2(L.n, L.n, B2), B2, 0, h->st, L, F, (const double *)(h->scal + S_SCALE), stop);
+    hipLaunchKernelGGL(k_dd_update, grid2(L.n, L.n, B2), B2, 0, h->st, L, h->XH, h->XL, (const float *)F.u,
+                       (const double *)(h->scal + S_SCALE), stop);
     LAUNCHCHK();
     return BMG_OK;
 }
 
-// FP64 residual of the iterate into L[0].r, its sum of squares (recorded in
-// the history when `record`) and, for refinement, its max norm.
-static bmg_status outer_residual(bmg_solver *h, bool record, double tol, int maxc, bool need_max)
+// One FP64 refinement step: L0.b holds r, L0.u = 0; V-cycle, (XH, XL) += u.
+static bmg_status refine_step64(bmg_solver *h, const int *stop)
 {
     const Lev<double> &L = h->L[0];
-    TRY(residual<double>(h, L, h->nine[0], record ? h->stop : nullptr));
-    TRY(sumsq<double>(h, L, false, false, L.r, S_SUMSQ, record, tol, maxc));
-    if (need_max) {
-        const int nb = std::min(NPART, L.n);
-        hipLaunchKernelGGL(k_absmax_partial, dim3(nb), dim3(256), 0, h->st, L, h->part, (const int *)h->stop);
-        hipLaunchKernelGGL(k_absmax_final, dim3(1), dim3(1024), 0, h->st, (const double *)h->part, nb,
-                           h->scal + S_RMAX, (const int *)h->stop);
-        LAUNCHCHK();
-    }
+    TRY(cycle64(h, stop));
+    hipLaunchKernelGGL(k_dd_update, grid2(L.n, L.n, B2), B2, 0, h->st, L, h->XH, h->XL, (const float *)nullptr,
+                       (const double *)nullptr, stop);
+    LAUNCHCHK();
     return BMG_OK;
 }
 
@@ -540,22 +579,40 @@ bmg_status bmg_vcycle(bmg_solver *h, const double *rhs, double *x, double *rel_r
 {
     if (!h || !rhs || !x) return fail(BMG_EINVAL, "NULL argument");
     const Lev<double> &L = h->L[0];
-    TRY(pack_in(h, rhs, L.b));
-    TRY(pack_in(h, x, L.u));
     if (h->f32) {
-        TRY(outer_residual(h, false, 0.0, 0, true));
-        TRY(ir_step(h, nullptr));
+        TRY(pack_in(h, rhs, h->B0));
+        TRY(pack_in(h, x, h->XH));
+        HIPCHK(hipMemsetAsync(h->XL, 0, (size_t)(L.n + 2) * L.ld * sizeof(double), h->st));
+        TRY(resnorm_dd(h, h->B0, h->XH, nullptr, 1, L.r, S_TMP, false, 0.0, 0, 0.0));
+        TRY(ir_correct(h, nullptr));
+        TRY(pack_out(h, h->XH, x));
+        if (rel_res) {
+            TRY(sumsq<double>(h, L, false, false, h->B0, S_TMP, false, 0.0, 0));
+            TRY(resnorm_dd(h, h->B0, h->XH, h->XL, 0, nullptr, S_SUMSQ, false, 0.0, 0, 0.0));
+        }
     } else {
+        TRY(pack_in(h, rhs, L.b));
+        TRY(pack_in(h, x, L.u));
         TRY(cycle64(h, nullptr));
+        TRY(pack_out(h, L.u, x));
+        if (rel_res) {
+            TRY(sumsq<double>(h, L, false, false, L.b, S_TMP, false, 0.0, 0));
+            TRY(resnorm_dd(h, L.b, L.u, nullptr, 0, nullptr, S_SUMSQ, false, 0.0, 0, 0.0));
+        }
     }
-    TRY(pack_out(h, L.u, x));
     if (rel_res) {
-        TRY(sumsq<double>(h, L, h->nine[0], true, nullptr, S_SUMSQ, false, 0.0, 0));
-        TRY(sumsq<double>(h, L, false, false, L.b, S_TMP, false, 0.0, 0));
         double v[4];
         TRY(read_scalars(h, v, 0, 4));
         *rel_res = sqrt(v[S_SUMSQ]) / sqrt(v[S_TMP]);
     }
+    return BMG_OK;
+}
+
+// Reads (count, stop) back after a batch of cycles.
+static bmg_status poll(bmg_solver *h, int cs[2])
+{
+    HIPCHK(hipMemcpyAsync(cs, h->count, 2 * sizeof(int), hipMemcpyDeviceToHost, h->st));
+    HIPCHK(hipStreamSynchronize(h->st));
     return BMG_OK;
 }
 
@@ -564,17 +621,19 @@ bmg_status bmg_solve(bmg_solver *h, const double *rhs, double *x, double tol, bm
     if (!h || !rhs || !x) return fail(BMG_EINVAL, "NULL argument");
     if (!(tol >= 0.0)) return fail(BMG_EINVAL, "tol must be >= 0");
     const Lev<double> &L = h->L[0];
-    TRY(pack_in(h, rhs, L.b));
-    TRY(pack_in(h, x, L.u));
-    // ||b|| and the initial residual, then the device-side stop bookkeeping
-    TRY(sumsq<double>(h, L, false, false, L.b, S_TMP, false, 0.0, 0));
-    TRY(sumsq<double>(h, L, h->nine[0], true, nullptr, S_SUMSQ, false, 0.0, 0));
+    const size_t pl0 = (size_t)(L.n + 2) * L.ld * sizeof(double);
+    // ||b|| and the initial residual; the iterate starts in L0.u (FP64) or XH
+    TRY(pack_in(h, rhs, h->B0));
+    TRY(pack_in(h, x, h->XH));
+    HIPCHK(hipMemsetAsync(h->XL, 0, pl0, h->st));
+    TRY(sumsq<double>(h, L, false, false, h->B0, S_TMP, false, 0.0, 0));
+    TRY(resnorm_dd(h, h->B0, h->XH, nullptr, 0, nullptr, S_SUMSQ, false, 0.0, 0, 0.0));
     double v[S_NSCAL];
     TRY(read_scalars(h, v, 0, S_NSCAL));
     const int maxc = h->opt.max_cycles;
     if (v[S_TMP] == 0.0) {
-        HIPCHK(hipMemsetAsync(L.u, 0, (size_t)(L.n + 2) * L.ld * sizeof(double), h->st));
-        TRY(pack_out(h, L.u, x));
+        HIPCHK(hipMemsetAsync(h->XH, 0, pl0, h->st));
+        TRY(pack_out(h, h->XH, x));
         HIPCHK(hipStreamSynchronize(h->st));
         if (info) { info->cycles = 0; info->rel_res = 0.0; info->rho = 0.0; }
         return BMG_OK;
@@ -584,32 +643,55 @@ bmg_status bmg_solve(bmg_solver *h, const double *rhs, double *x, double tol, bm
     HIPCHK(hipMemsetAsync(h->count, 0, 2 * sizeof(int), h->st));
     int cs[2] = {0, 0};
     const int every = h->opt.check_every;
+    bool refining = false;
     if (!h->f32) {
-        // history[k] = relative residual after cycle k+1
+        // plain V-cycles on L0.u until rel <= refine_factor * tol, then
+        // refinement steps on (XH, XL); history[k] = residual after cycle k+1
+        HIPCHK(hipMemcpyAsync(L.b, h->B0, pl0, hipMemcpyDeviceToDevice, h->st));
+        HIPCHK(hipMemcpyAsync(L.u, h->XH, pl0, hipMemcpyDeviceToDevice, h->st));
+        const double refine = h->opt.refine_factor > 0 ? h->opt.refine_factor * tol : 0.0;
         while (true) {
             for (int t = 0; t < every; ++t) {
-                TRY(cycle64(h, h->stop));
-                TRY(sumsq<double>(h, L, h->nine[0], true, nullptr, S_SUMSQ, true, tol, maxc));
+                if (!refining) {
+                    TRY(cycle64(h, h->stop));
+                    TRY(resnorm_dd(h, L.b, L.u, nullptr, 0, nullptr, S_SUMSQ, true, tol, maxc, refine));
+                } else {
+                    TRY(refine_step64(h, h->stop));
+                    TRY(resnorm_dd(h, h->B0, h->XH, h->XL, 2, nullptr, S_SUMSQ, true, tol, maxc, 0.0));
+                }
             }
-            HIPCHK(hipMemcpyAsync(cs, h->count, sizeof cs, hipMemcpyDeviceToHost, h->st));
-            HIPCHK(hipStreamSynchronize(h->st));
+            TRY(poll(h, cs));
+            if (cs[1] == 4 && !refining) {
+                // the iterate becomes (XH, XL) = (u, 0); the next cycle starts
+                // from zero on r = B0 - A XH (the residual just recorded)
+                refining = true;
+                HIPCHK(hipMemcpyAsync(h->XH, L.u, pl0, hipMemcpyDeviceToDevice, h->st));
+                HIPCHK(hipMemsetAsync(h->XL, 0, pl0, h->st));
+                TRY(resnorm_dd(h, h->B0, h->XH, h->XL, 2, nullptr, S_TMP, false, 0.0, 0, 0.0));
+                HIPCHK(hipMemsetAsync(h->stop, 0, sizeof(int), h->st));
+                continue;
+            }
             if (cs[1]) break;
         }
     } else {
         // history[0] = initial residual, history[k] after correction k
+        refining = true;
         const int maxe = maxc + 1;
-        TRY(outer_residual(h, true, tol, maxe, true));
+        TRY(resnorm_dd(h, h->B0, h->XH, h->XL, 1, L.r, S_SUMSQ, true, tol, maxe, 0.0));
         while (true) {
             for (int t = 0; t < every; ++t) {
-                TRY(ir_step(h, h->stop));
-                TRY(outer_residual(h, true, tol, maxe, true));
+                TRY(ir_correct(h, h->stop));
+                TRY(resnorm_dd(h, h->B0, h->XH, h->XL, 1, L.r, S_SUMSQ, true, tol, maxe, 0.0));
             }
-            HIPCHK(hipMemcpyAsync(cs, h->count, sizeof cs, hipMemcpyDeviceToHost, h->st));
-            HIPCHK(hipStreamSynchronize(h->st));
+            TRY(poll(h, cs));
             if (cs[1]) break;
         }
     }
-    TRY(pack_out(h, L.u, x));
+    if (!refining) {
+        HIPCHK(hipMemcpyAsync(h->XH, L.u, pl0, hipMemcpyDeviceToDevice, h->st));
+        HIPCHK(hipMemsetAsync(h->XL, 0, pl0, h->st));
+    }
+    TRY(pack_out(h, h->XH, x));
     std::vector<double> hist(std::max(cs[0], 1));
     HIPCHK(hipMemcpyAsync(hist.data(), h->hist, cs[0] * sizeof(double), hipMemcpyDeviceToHost, h->st));
     HIPCHK(hipStreamSynchronize(h->st));
@@ -651,6 +733,11 @@ static bmg_status locate(bmg_solver *h, int level, int field, char **ptr, size_t
     if (!h) return fail(BMG_EINVAL, "NULL handle");
     if (field == BMG_F_COARSE_LD) {
         *ptr = (char *)h->LD; *es = 8; *pitch = 90 * 8; *rows = 1; *width = 90;
+        return BMG_OK;
+    }
+    if (field == BMG_F_XLO) {
+        *ptr = (char *)h->XL; *es = 8; *pitch = (size_t)h->L[0].ld * 8;
+        *rows = h->L[0].n + 2; *width = h->L[0].n + 2;
         return BMG_OK;
     }
     if (level < 0 || level >= h->nlev) return fail(BMG_EINVAL, "level %d out of range", level);

@@ -175,20 +175,49 @@ def test_poisson_127_ten_cycles_bitwise(gpu):
         assert abs(rel - rel_o) <= 1e-12 * rel_o, (k, rel, rel_o)
 
 
-@pytest.mark.parametrize("kind,n,tol", [("lognormal", 255, 1e-10), ("jump16", 127, 1e-10),
-                                        ("poisson", 1023, 1e-10)])
-def test_solve_matches_oracle(gpu, kind, n, tol):
+@pytest.mark.parametrize("kind,n,tol,rf", [("lognormal", 255, 1e-10, 16), ("jump16", 127, 1e-10, 16),
+                                           ("poisson", 1023, 1e-10, 16), ("jump64", 255, 1e-16, 10**5),
+                                           ("jump64", 255, 1e-16, 0)])
+def test_solve_matches_oracle(gpu, kind, n, tol, rf):
+    """Whole solves: cycle count, both parts of the iterate bitwise, history to
+    1e-12; including the double-FP64 refinement phase below the FP64 floor."""
     p = problem(kind, n, 11)
     st, rhs = gpu_problem(p)
-    S = boxmg.Solver(st, max_cycles=400)
-    x, info = S.solve(rhs, tol=tol)
+    S = boxmg.Solver(st, max_cycles=300, refine_factor=rf)
+    x, info = S.solve(rhs, tol=tol, raise_on_noconv=False)
     H = ref.Hierarchy(host(st))
-    u, hist = H.solve(ref.pad(host(rhs)), tol=tol, max_cycles=400)
+    u, hist = H.solve(ref.pad(host(rhs)), tol=tol, max_cycles=300, refine_factor=rf)
     assert info["cycles"] == len(hist)
-    same(host(x), u[1:-1, 1:-1], "solution")
+    same(host(x), u[1:-1, 1:-1], "solution (high part)")
+    same(host(S.export(0, "xlo")), H.xl, "solution (low part)")
     h = np.array(info["history"])
     assert np.all(np.abs(h - hist) <= 1e-12 * hist), np.abs(h / hist - 1).max()
-    assert info["rel_res"] <= tol
+    if rf:
+        assert info["rel_res"] <= tol and info["status"] == 0
+
+
+@pytest.mark.parametrize("kind,n", [("lognormal", 127), ("jump16", 255)])
+def test_fp32_refinement_matches_oracle(gpu, kind, n):
+    """FP32 V-cycles inside double-FP64 refinement: the FP32 hierarchy is the
+    rounded FP64 one, and every refinement iterate matches the oracle bitwise."""
+    p = problem(kind, n, 5)
+    st, rhs = gpu_problem(p)
+    S = boxmg.Solver(st, max_cycles=300, precision=boxmg.BMG_FP32_IR)
+    H = ref.Hierarchy(host(st))
+    H.solve_ir(ref.pad(host(rhs)), tol=1.0, max_iter=0)     # builds the FP32 copy
+    for l in range(H.nlev):
+        for nm in ("O", "W", "S", "SW", "NW"):
+            want = H.field(l, nm)
+            if want is not None:
+                same(host(S.export(l, nm + "32")), want.astype(np.float32), f"{nm}32 l={l}")
+    x, info = S.solve(rhs, tol=1e-11)
+    u, hist = H.solve_ir(ref.pad(host(rhs)), tol=1e-11, max_iter=300)
+    assert info["cycles"] == len(hist) - 1
+    same(host(x), u[1:-1, 1:-1], "refined solution (high part)")
+    same(host(S.export(0, "xlo")), H.xl, "refined solution (low part)")
+    h = np.array(info["history"])
+    assert np.all(np.abs(h - hist) <= 1e-12 * hist)
+    assert info["rel_res"] <= 1e-11
 
 
 # ----------------------------------------------------------- edge cases

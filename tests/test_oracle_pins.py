@@ -396,3 +396,28 @@ def test_ir_reaches_fp64_accuracy_with_fp32_cycles():
     u64, h64 = H.solve(b, tol=1e-13, max_cycles=400)
     assert np.abs(x - u64).max() <= 1e-9 * np.abs(u64).max()
     assert len(hist) - 1 <= 2 * len(h64) + 5
+
+
+def test_refinement_converges_below_the_fp64_floor():
+    """The plain FP64 iteration stagnates at the residual floor of FP64 vectors;
+    carrying the iterate as a double-FP64 pair with an accurate residual keeps
+    the same contraction and goes 1e3 below it.  Before the switch the two are
+    the same iteration bit for bit."""
+    n = 255
+    p = inputs.jumping(n, 64, -4, 4, 201, 202)
+    st, rhs = ref.discretize(p.k, p.f)
+    H = ref.Hierarchy(st)
+    b = ref.pad(rhs)
+    u0, h0 = H.solve(b, tol=1e-17, max_cycles=60, refine_factor=0)
+    floor = h0.min()
+    assert floor > 1e-15                                  # plain FP64 stalls
+    u1, h1 = H.solve(b, tol=1e-17, max_cycles=60, refine_factor=10**5)
+    k = int(np.argmax(h1 <= 1e-12))                       # the switch cycle
+    assert np.array_equal(h0[:k + 1], h1[:k + 1])
+    assert h1.min() < 1e-3 * floor
+    rho = (h1[k + 6] / h1[k + 1]) ** (1 / 5)              # refinement contraction
+    rho0 = (h0[k] / h0[k - 5]) ** (1 / 5)                 # plain contraction
+    assert abs(rho - rho0) < 0.1
+    # the pair's residual is the reported one; the high part alone sits at the floor
+    assert H.rel_residual(b, u1, H.xl) == pytest.approx(h1[-1], rel=1e-6)
+    assert H.rel_residual(b, u1) > 10 * h1[-1]
