@@ -67,7 +67,7 @@ def cpu_baseline(p, gpu_cycles: int, sample_cycles: int):
     st, rhs = ref.discretize(p.k, p.f)
     b = ref.pad(rhs)
     t0 = time.perf_counter()
-    H = ref.Hierarchy(st, compensated=True)
+    H = ref.Hierarchy(st)
     t_setup = time.perf_counter() - t0
     u = np.zeros_like(b)
     t0 = time.perf_counter()

@@ -66,7 +66,9 @@ typedef struct {
                         and each cycle is one refinement step with an accurate
                         residual, which converges below the residual floor of
                         FP64 vectors; 0 = never (default 16) */
-    int reserved[9];
+    int tile_rows;   /* grid rows per workgroup tile of the fused passes
+                        (even, 0 = the default of 128) */
+    int reserved[8];
 } bmg_options;
 
 typedef struct {

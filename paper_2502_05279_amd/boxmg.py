@@ -33,7 +33,7 @@ TRACE = {"smooth": 0, "pre": 1, "post": 2, "resnorm": 3}
 class Options(C.Structure):
     _fields_ = [("nu1", C.c_int), ("nu2", C.c_int), ("max_cycles", C.c_int),
                 ("precision", C.c_int), ("kernels", C.c_int), ("check_every", C.c_int),
-                ("refine_factor", C.c_int), ("reserved", C.c_int * 9)]
+                ("refine_factor", C.c_int), ("tile_rows", C.c_int), ("reserved", C.c_int * 8)]
 
 
 class Info(C.Structure):

@@ -4,7 +4,7 @@
 // One level hierarchy lives in the caller's workspace; nothing here calls
 // hipMalloc.  Every launch goes to the handle's stream.
 #include "bmg.h"
-#include "bmg_kernels.hpp"
+#include "bmg_fused.hpp"
 
 #include <math.h>
 #include <stdarg.h>
@@ -13,6 +13,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <type_traits>
+#include <utility>
 #include <vector>
 
 using namespace bmg;
@@ -20,7 +22,8 @@ using namespace bmg;
 namespace {
 
 constexpr int MAXL = 20;
-constexpr int NPART = 1024;      // partial sums of a norm
+constexpr int NPART = 8192;      // partial sums of a norm (>= fused tiles)
+constexpr int NPART_ROWS = 1024; // partial sums of the row-parallel reductions
 constexpr size_t ALIGN = 256;
 constexpr int MAX_TRACE = 65536;
 
@@ -68,6 +71,10 @@ struct bmg_solver {
     bool f32 = false;
     Lev<float> L32[MAXL];
     Wts<float> C32[MAXL];
+    double *ualt[MAXL];         // second iterate buffer of each level (fused passes)
+    float *ualt32[MAXL];
+    int tile_rows = 128;        // rows per tile of the fused passes
+    int norm_parts = 0;         // partial sums left by the last fused norm
     double *B0 = nullptr;       // fine right-hand side during refinement
     double *XH = nullptr;       // double-FP64 iterate, high part
     double *XL = nullptr;       // double-FP64 iterate, low part
@@ -109,6 +116,7 @@ size_t plan(bmg_solver *h, int n, int kind, const bmg_options &o, char *base)
         Lev<double> D{};
         D.n = ns[l];
         D.ld = ld;
+        double *ua = (double *)take(pl * 8);
         D.u = (double *)take(pl * 8);
         D.b = (double *)take(pl * 8);
         D.r = (double *)take(pl * 8);
@@ -126,9 +134,11 @@ size_t plan(bmg_solver *h, int n, int kind, const bmg_options &o, char *base)
         }
         Lev<float> F{};
         Wts<float> FW{};
+        float *ua32 = nullptr;
         if (f32) {
             F.n = ns[l];
             F.ld = ld;
+            ua32 = (float *)take(pl * 4);
             F.u = (float *)take(pl * 4);
             F.b = (float *)take(pl * 4);
             F.r = (float *)take(pl * 4);
@@ -149,6 +159,8 @@ size_t plan(bmg_solver *h, int n, int kind, const bmg_options &o, char *base)
             h->nine[l] = nine;
             h->L32[l] = F;
             h->C32[l] = FW;
+            h->ualt[l] = ua;
+            h->ualt32[l] = ua32;
         }
     }
     const size_t pl0 = (size_t)(ns[0] + 2) * pitch_of(ns[0]);
@@ -188,12 +200,14 @@ bmg_status check_options(const bmg_options &o)
         return fail(BMG_EINVAL, "max_cycles=%d out of range", o.max_cycles);
     if (o.precision != BMG_FP64 && o.precision != BMG_FP32_IR)
         return fail(BMG_EINVAL, "unknown precision %d", o.precision);
-    if (o.kernels != BMG_KERNELS_BASIC)
-        return fail(BMG_EINVAL, "kernel path %d is not available", o.kernels);
+    if (o.kernels != BMG_KERNELS_BASIC && o.kernels != BMG_KERNELS_FUSED)
+        return fail(BMG_EINVAL, "unknown kernel path %d", o.kernels);
     if (o.check_every < 1 || o.check_every > 4096)
         return fail(BMG_EINVAL, "check_every=%d out of range", o.check_every);
     if (o.refine_factor < 0)
         return fail(BMG_EINVAL, "refine_factor=%d must be >= 0", o.refine_factor);
+    if (o.tile_rows < 0 || (o.tile_rows & 1) || o.tile_rows > 65536)
+        return fail(BMG_EINVAL, "tile_rows=%d must be even and in [0, 65536]", o.tile_rows);
     return BMG_OK;
 }
 
@@ -311,13 +325,115 @@ bmg_status vcycle_from(bmg_solver *h, int l, const int *stop)
     return BMG_OK;
 }
 
-// Fused passes (not built yet): the fused path is rejected by option checks.
-bmg_status fused_vcycle(bmg_solver *h, const int *stop) { return vcycle_from<double>(h, 0, stop); }
-bmg_status fused_vcycle32(bmg_solver *h, const int *stop) { return vcycle_from<float>(h, 0, stop); }
+// ------------------------------------------------------- fused passes
 template <typename T>
-bmg_status fused_pre(bmg_solver *, int, int, const int *) { return fail(BMG_EINVAL, "fused passes are not available"); }
+Lev<T> &levm(bmg_solver *h, int l);
+template <>
+Lev<double> &levm<double>(bmg_solver *h, int l) { return h->L[l]; }
+template <>
+Lev<float> &levm<float>(bmg_solver *h, int l) { return h->L32[l]; }
 template <typename T>
-bmg_status fused_post(bmg_solver *, int, int, const int *) { return fail(BMG_EINVAL, "fused passes are not available"); }
+T *&ualt(bmg_solver *h, int l);
+template <>
+double *&ualt<double>(bmg_solver *h, int l) { return h->ualt[l]; }
+template <>
+float *&ualt<float>(bmg_solver *h, int l) { return h->ualt32[l]; }
+
+TileGeo tile_geo(int n, int hx, int ht)
+{
+    TileGeo g;
+    g.hx = hx;
+    g.ht = std::max(2, std::min(ht, (n + 2) & ~1));
+    const int useful = FW - 2 * hx;
+    g.tiles_x = (n + useful - 1) / useful;
+    g.ntiles = g.tiles_x * ((n + g.ht - 1) / g.ht);
+    return g;
+}
+
+dim3 tile_grid(const TileGeo &g) { return dim3(((g.ntiles + 7) / 8) * 8); }
+
+// nu sweeps, residual and restriction in one pass (results as SMOOTH,
+// RESIDUAL, RESTRICT in turn); the level's iterate moves to the other buffer.
+template <typename T>
+bmg_status fused_pre(bmg_solver *h, int l, int nu, const int *stop)
+{
+    Lev<T> &F = levm<T>(h, l);
+    const Lev<T> &Cl = lev<T>(h, l + 1);
+    const Wts<T> &C = wts<T>(h, l);
+    const bool nine = h->nine[l];
+    if (nu < 1 || nu > 3) {
+        TRY(smooth<T>(h, F, nine, nu, stop, l));
+        TRY(residual<T>(h, F, nine, stop));
+        return restrict_<T>(h, F, C, Cl, stop);
+    }
+    const TileGeo g = tile_geo(F.n, nine ? 4 * nu + 2 : 2 * nu + 2, h->tile_rows);
+    T *out = ualt<T>(h, l);
+    const dim3 grid = tile_grid(g), blk(FW);
+#define PRE(NINE, NU) hipLaunchKernelGGL((k_pre<T, NINE, NU>), grid, blk, 0, h->st, F, out, C, Cl, g, stop)
+    trace_begin(h, BMG_TRACE_PRE, l);
+    if (nine) {
+        if (nu == 1) PRE(true, 1); else if (nu == 2) PRE(true, 2); else PRE(true, 3);
+    } else {
+        if (nu == 1) PRE(false, 1); else if (nu == 2) PRE(false, 2); else PRE(false, 3);
+    }
+    trace_end(h, BMG_TRACE_PRE, l);
+#undef PRE
+    LAUNCHCHK();
+    std::swap(F.u, ualt<T>(h, l));
+    return BMG_OK;
+}
+
+// Interpolation and nu sweeps in one pass; with `norm` (FP64 fine level) the
+// tiles also leave partial sums of the squared accurate residual in h->part
+// (their count in h->norm_parts; 0 if the pass could not fuse it).
+template <typename T>
+bmg_status fused_post(bmg_solver *h, int l, int nu, const int *stop, bool norm = false)
+{
+    Lev<T> &F = levm<T>(h, l);
+    const Lev<T> &Cl = lev<T>(h, l + 1);
+    const Wts<T> &C = wts<T>(h, l);
+    const bool nine = h->nine[l];
+    h->norm_parts = 0;
+    if (nu < 1 || nu > 2) {
+        TRY(interp<T>(h, F, C, Cl, stop));
+        return smooth<T>(h, F, nine, nu, stop, l);
+    }
+    const TileGeo g = tile_geo(F.n, nine ? 4 * nu + 1 : 2 * nu + 1, h->tile_rows);
+    norm = norm && std::is_same<T, double>::value && g.ntiles <= NPART;
+    T *out = ualt<T>(h, l);
+    const dim3 grid = tile_grid(g), blk(FW);
+#define POST(NINE, NU, NORM) \
+    hipLaunchKernelGGL((k_post<T, NINE, NU, NORM>), grid, blk, 0, h->st, F, out, C, (const T *)Cl.u, g, h->part, stop)
+    trace_begin(h, BMG_TRACE_POST, l);
+    if (norm) {
+        if (nine) { if (nu == 1) POST(true, 1, true); else POST(true, 2, true); }
+        else { if (nu == 1) POST(false, 1, true); else POST(false, 2, true); }
+    } else {
+        if (nine) { if (nu == 1) POST(true, 1, false); else POST(true, 2, false); }
+        else { if (nu == 1) POST(false, 1, false); else POST(false, 2, false); }
+    }
+    trace_end(h, BMG_TRACE_POST, l);
+#undef POST
+    LAUNCHCHK();
+    std::swap(F.u, ualt<T>(h, l));
+    if (norm) h->norm_parts = g.ntiles;
+    return BMG_OK;
+}
+
+template <typename T>
+bmg_status fused_cycle_from(bmg_solver *h, int l, const int *stop, bool norm)
+{
+    if (l == h->nlev - 1) return coarse<T>(h, lev<T>(h, l), stop);
+    TRY(fused_pre<T>(h, l, h->opt.nu1, stop));
+    TRY(fused_cycle_from<T>(h, l + 1, stop, false));
+    return fused_post<T>(h, l, h->opt.nu2, stop, norm && l == 0);
+}
+
+bmg_status fused_vcycle(bmg_solver *h, const int *stop, bool norm = false)
+{
+    return fused_cycle_from<double>(h, 0, stop, norm);
+}
+bmg_status fused_vcycle32(bmg_solver *h, const int *stop) { return fused_cycle_from<float>(h, 0, stop, false); }
 
 // Sum of squares of r = b - A u (res) or of the array x, into scal[slot]; with
 // record, also the history / stop bookkeeping of the running solve.
@@ -325,7 +441,7 @@ template <typename T>
 bmg_status sumsq(bmg_solver *h, const Lev<T> &L, bool nine, bool res, const T *x, int slot,
                  bool record, double tol, int maxc)
 {
-    const int nb = std::min(NPART, L.n);
+    const int nb = std::min(NPART_ROWS, L.n);
     const int *stop = record ? h->stop : nullptr;
     trace_begin(h, BMG_TRACE_RESNORM, 0);
     if (res) {
@@ -350,7 +466,7 @@ bmg_status resnorm_dd(bmg_solver *h, const double *B, const double *XH, const do
                       double *rout, int slot, bool record, double tol, int maxc, double refine)
 {
     const Lev<double> &L = h->L[0];
-    const int nb = std::min(NPART, L.n);
+    const int nb = std::min(NPART_ROWS, L.n);
     const int *stop = record ? h->stop : nullptr;
     const dim3 g(nb), b(256);
 #define RDD(NINE, MODE) hipLaunchKernelGGL((k_resid_dd<NINE, MODE>), g, b, 0, h->st, L, B, XH, XL, rout, h->part, stop)
@@ -421,7 +537,7 @@ bmg_status bmg_default_options(bmg_options *o)
     o->nu2 = 1;
     o->max_cycles = 100;
     o->precision = BMG_FP64;
-    o->kernels = BMG_KERNELS_BASIC;
+    o->kernels = BMG_KERNELS_FUSED;
     o->check_every = 8;
     o->refine_factor = 16;
     return BMG_OK;
@@ -476,6 +592,7 @@ bmg_status bmg_setup(bmg_solver **out, const double *stencil, int n, int kind, c
     h->st = (hipStream_t)stream;
     h->ws = (char *)workspace;
     h->ws_bytes = ws_bytes;
+    h->tile_rows = op.tile_rows > 0 ? op.tile_rows : 128;
     plan(h, n, kind, op, h->ws);
     auto bail = [&](bmg_status s) { delete h; return s; };
 #define SCHK(x)                                  \
@@ -549,7 +666,7 @@ static bmg_status ir_correct(bmg_solver *h, const int *stop)
 {
     const Lev<double> &L = h->L[0];
     const Lev<float> &F = h->L32[0];
-    const int nb = std::min(NPART, L.n);
+    const int nb = std::min(NPART_ROWS, L.n);
     hipLaunchKernelGGL(k_absmax_partial, dim3(nb), dim3(256), 0, h->st, L, h->part, stop);
     hipLaunchKernelGGL(k_absmax_final, dim3(1), dim3(1024), 0, h->st, (const double *)h->part, nb,
                        h->scal + S_RMAX, stop);
@@ -562,6 +679,29 @@ static bmg_status ir_correct(bmg_solver *h, const int *stop)
                        (const double *)(h->scal + S_SCALE), stop);
     LAUNCHCHK();
     return BMG_OK;
+}
+
+// One plain FP64 cycle of the solve and its recorded accurate residual norm:
+// fused into the fine level's last pass when the fused path can, else a
+// separate residual pass.
+static bmg_status cycle_and_norm(bmg_solver *h, double tol, int maxc, double refine)
+{
+    const Lev<double> &L = h->L[0];
+    if (h->opt.kernels == BMG_KERNELS_FUSED) {
+        TRY(fused_vcycle(h, h->stop, true));
+        if (h->norm_parts > 0) {
+            trace_begin(h, BMG_TRACE_RESNORM, 0);
+            hipLaunchKernelGGL(k_sumsq_final, dim3(1), dim3(1024), 0, h->st, (const double *)h->part,
+                               h->norm_parts, h->scal + S_SUMSQ, h->hist, h->count, h->stop,
+                               (const double *)(h->scal + S_BNORM), tol, maxc, refine);
+            trace_end(h, BMG_TRACE_RESNORM, 0);
+            LAUNCHCHK();
+            return BMG_OK;
+        }
+    } else {
+        TRY(vcycle_from<double>(h, 0, h->stop));
+    }
+    return resnorm_dd(h, L.b, L.u, nullptr, 0, nullptr, S_SUMSQ, true, tol, maxc, refine);
 }
 
 // One FP64 refinement step: L0.b holds r, L0.u = 0; V-cycle, (XH, XL) += u.
@@ -653,8 +793,7 @@ bmg_status bmg_solve(bmg_solver *h, const double *rhs, double *x, double tol, bm
         while (true) {
             for (int t = 0; t < every; ++t) {
                 if (!refining) {
-                    TRY(cycle64(h, h->stop));
-                    TRY(resnorm_dd(h, L.b, L.u, nullptr, 0, nullptr, S_SUMSQ, true, tol, maxc, refine));
+                    TRY(cycle_and_norm(h, tol, maxc, refine));
                 } else {
                     TRY(refine_step64(h, h->stop));
                     TRY(resnorm_dd(h, h->B0, h->XH, h->XL, 2, nullptr, S_SUMSQ, true, tol, maxc, 0.0));

@@ -302,3 +302,60 @@ def test_breakdown_is_reported(gpu):
     with pytest.raises(boxmg.BoxMGError) as e:
         boxmg.Solver(dev(st))
     assert e.value.status == boxmg.BMG_EBREAKDOWN
+
+
+# ------------------------------------------------------------ fused passes
+@pytest.mark.parametrize("kind,n,tile_rows", [("jump16", 15, 0), ("lognormal", 127, 6),
+                                              ("jump64", 511, 32), ("lognormal", 1023, 64)])
+@pytest.mark.parametrize("fp32", [False, True])
+def test_fused_passes_bitwise(gpu, kind, n, tile_rows, fp32):
+    """The fused pre pass (nu sweeps + residual + restriction) and post pass
+    (interpolation + nu sweeps) equal the single steps of the oracle bit for bit,
+    on five- and nine-point levels, across several strips and row tiles (small
+    tile_rows), in FP64 and in the FP32 hierarchy."""
+    p = problem(kind, n, 9)
+    st, _ = gpu_problem(p)
+    opts = dict(tile_rows=tile_rows)
+    if fp32:
+        opts["precision"] = boxmg.BMG_FP32_IR
+    S = boxmg.Solver(st, **opts)
+    H = ref.Hierarchy(host(st))
+    dt = np.float32 if fp32 else np.float64
+    sfx = "32" if fp32 else ""
+    rng = np.random.default_rng(n + 1)
+    for l in range(H.nlev - 1):
+        nl, nc = H.level_n(l), H.level_n(l + 1)
+        op = tuple(None if a is None else a.astype(dt) for a in H.op(l))
+        Ci = H.field(l, "Ci").astype(dt)
+        u, b = rand_level(rng, nl).astype(dt), rand_level(rng, nl).astype(dt)
+        for nu in (1, 2, 3):
+            S.import_(l, "u" + sfx, dev(u)); S.import_(l, "b" + sfx, dev(b))
+            S.import_(l + 1, "u" + sfx, dev(rand_level(rng, nc).astype(dt)))
+            S.step(l, "pre", nu, fp32=fp32)
+            us = ref.gs(*op, b, u, nu, dtype=dt)
+            same(host(S.export(l, "u" + sfx)), us, f"pre u l={l} nu={nu}")
+            bc = ref.restrict(Ci, ref.residual(*op, b, us, dtype=dt), dtype=dt)
+            same(host(S.export(l + 1, "b" + sfx)), bc, f"pre b_c l={l} nu={nu}")
+            assert not host(S.export(l + 1, "u" + sfx)).any()
+        for nu in (1, 2):
+            ec = rand_level(rng, nc).astype(dt)
+            S.import_(l, "u" + sfx, dev(u)); S.import_(l, "b" + sfx, dev(b))
+            S.import_(l + 1, "u" + sfx, dev(ec))
+            S.step(l, "post", nu, fp32=fp32)
+            want = ref.gs(*op, b, ref.interp_add(Ci, ec, u, dtype=dt), nu, dtype=dt)
+            same(host(S.export(l, "u" + sfx)), want, f"post u l={l} nu={nu}")
+
+
+@pytest.mark.parametrize("kernels", [boxmg.BMG_KERNELS_BASIC, boxmg.BMG_KERNELS_FUSED])
+@pytest.mark.parametrize("nu1,nu2", [(2, 1), (1, 1), (3, 2)])
+def test_cycle_variants_match_oracle(gpu, kernels, nu1, nu2):
+    """V(nu1,nu2) solves on both kernel paths equal the oracle's bit for bit."""
+    p = problem("jump16", 255, 13)
+    st, rhs = gpu_problem(p)
+    S = boxmg.Solver(st, kernels=kernels, nu1=nu1, nu2=nu2, max_cycles=200, tile_rows=48)
+    x, info = S.solve(rhs, tol=1e-9)
+    H = ref.Hierarchy(host(st), nu1, nu2)
+    u, hist = H.solve(ref.pad(host(rhs)), tol=1e-9, max_cycles=200)
+    assert info["cycles"] == len(hist)
+    same(host(x), u[1:-1, 1:-1], "solution")
+    assert np.all(np.abs(np.array(info["history"]) - hist) <= 1e-12 * hist)
