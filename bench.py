@@ -94,6 +94,9 @@ def main():
     ap.add_argument("--kernels", default="fused", choices=["fused", "basic"])
     ap.add_argument("--cpu-sample-cycles", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device-to-device (a kernel of known traffic, to "
+                         "calibrate hardware byte counters) and print the achieved GB/s")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -108,6 +111,20 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     dev = torch.device("cuda:0")
+    if args.copy_probe:
+        a = torch.ones(args.copy_probe << 17, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(10):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 10
+        print(json.dumps({"copy_probe_bytes": 2 * a.numel() * 8, "seconds": dt,
+                          "GB_per_s": 2 * a.numel() * 8 / dt / 1e9}))
+        return
     p = workload(args.workload)
     n = p.n
     k = torch.from_numpy(p.k).to(dev)

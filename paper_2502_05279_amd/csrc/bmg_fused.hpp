@@ -90,7 +90,9 @@ __device__ __forceinline__ T res_lds(const T *su, const T *sW, const T *sSW, con
 
 // ----------------------------------------------------------- pre pass
 // u_out = GS^NU(u_in); b_c = P^T (b - A u_out) on the coarse rows owned by the
-// tile; u_c = 0 there.  Window: rows e-2NU-2 .. e+1 (RW rows) at step e.
+// tile; u_c = 0 there.  Window: rows e-2NU-2 .. e+1 (RW rows) at step e.  All
+// global data of step e+2 (rows e+2, e+3 and the weights of its restriction
+// row) is requested before step e computes, so the loads overlap the compute.
 template <typename T, bool NINE, int NU>
 __global__ __launch_bounds__(FW) void k_pre(Lev<T> L, T *__restrict__ uout, Wts<T> C, Lev<T> Cl,
                                              TileGeo G, const int *stop)
@@ -103,7 +105,7 @@ __global__ __launch_bounds__(FW) void k_pre(Lev<T> L, T *__restrict__ uout, Wts<
     __shared__ T su[RU * FW], sW[RU * FW], sr[4 * FW];
     __shared__ T sSW[NINE ? RU * FW : 1], sNW[NINE ? RU * FW : 1];
 
-    const int n = L.n, ld = L.ld, lane = threadIdx.x;
+    const int n = L.n, ld = L.ld, lane = threadIdx.x, nc = Cl.n;
     const int useful = FW - 2 * G.hx;
     const int tx = tid % G.tiles_x, ty = tid / G.tiles_x;
     const int x0 = 1 + tx * useful;                // first owned column
@@ -113,21 +115,35 @@ __global__ __launch_bounds__(FW) void k_pre(Lev<T> L, T *__restrict__ uout, Wts<
     const bool col_own = i >= x0 && i < x0 + useful && i <= n;
     const int y0 = 1 + ty * G.ht;                  // owned rows [y0, y1)
     const int y1 = min(y0 + G.ht, n + 1);
-    const int es = (y0 - 2 * NU) & ~1;             // first even row of sweep 0: the
-                                                   // warm-up below y0 that makes the
-                                                   // owned rows and coarse rows exact
+    const int es = (y0 - 2 * NU) & ~1;             // warm-up rows below y0 that make
+                                                   // the owned rows and coarse rows exact
     const int jlast = (y1 - 1) >> 1;               // last owned coarse row
     const int elast = 2 * jlast + 2 * NU + 2;      // step that restricts it
+    const int I = i >> 1;
+    const bool restrictor = !(i & 1) && col_own && I >= 1 && I <= nc;
 
-    // register windows: k <-> row e - 2NU - 2 + k
     T rO[RW], rS[RW], rB[RW];
     auto ld_row = [&](const T *a, int row) -> T {
         return (col_in && row >= 0 && row <= n + 1) ? a[(size_t)row * ld + i] : (T)0;
     };
-    // initial window for step es: rows es-2NU-2 .. es-1 (the loop loads es, es+1)
+    // the eight weights of coarse point (I, J) in the order the restriction uses
+    auto ld_w = [&](int J, T w[8]) {
+        const bool ok = restrictor && J >= 1 && J <= nc;
+        const size_t c = ok ? (size_t)J * C.ld + I : 0, cn = c + C.ld;
+        w[0] = ok ? C.at(LNE, c) : (T)0;
+        w[1] = ok ? C.at(LA, c) : (T)0;
+        w[2] = ok ? C.at(LNW, c + 1) : (T)0;
+        w[3] = ok ? C.at(LR, c) : (T)0;
+        w[4] = ok ? C.at(LL, c + 1) : (T)0;
+        w[5] = ok ? C.at(LSE, cn) : (T)0;
+        w[6] = ok ? C.at(LB, cn) : (T)0;
+        w[7] = ok ? C.at(LSW, cn + 1) : (T)0;
+    };
+    // window of step es without its own two rows: rows es-2NU-2 .. es-1, placed
+    // at positions 2..RW-1 so that the first shift by two aligns them
 #pragma unroll
-    for (int k = 0; k < RW - 2; ++k) {
-        const int row = es - 2 * NU - 2 + k;
+    for (int k = 2; k < RW; ++k) {
+        const int row = es - 2 * NU - 4 + k;
         su[slot<RU>(row) * FW + lane] = ld_row(L.u, row);
         sW[slot<RU>(row) * FW + lane] = ld_row(L.W, row);
         if (NINE) {
@@ -138,17 +154,22 @@ __global__ __launch_bounds__(FW) void k_pre(Lev<T> L, T *__restrict__ uout, Wts<
         rS[k] = ld_row(L.S, row);
         rB[k] = ld_row(L.b, row);
     }
-    // prefetch for the first step
-    T pu0 = ld_row(L.u, es), pu1 = ld_row(L.u, es + 1);
-    T pW0 = ld_row(L.W, es), pW1 = ld_row(L.W, es + 1);
-    T pO0 = ld_row(L.O, es), pO1 = ld_row(L.O, es + 1);
-    T pS0 = ld_row(L.S, es), pS1 = ld_row(L.S, es + 1);
-    T pB0 = ld_row(L.b, es), pB1 = ld_row(L.b, es + 1);
-    T pSW0 = 0, pSW1 = 0, pNW0 = 0, pNW1 = 0;
-    if (NINE) {
-        pSW0 = ld_row(L.SW, es); pSW1 = ld_row(L.SW, es + 1);
-        pNW0 = ld_row(L.NW, es); pNW1 = ld_row(L.NW, es + 1);
-    }
+    // data of the first step
+    T pu0, pu1, pW0, pW1, pO0, pO1, pS0, pS1, pB0, pB1, pSW0 = 0, pSW1 = 0, pNW0 = 0, pNW1 = 0;
+    T pw[8], w[8];
+    auto fetch = [&](int e) {
+        pu0 = ld_row(L.u, e); pu1 = ld_row(L.u, e + 1);
+        pW0 = ld_row(L.W, e); pW1 = ld_row(L.W, e + 1);
+        pO0 = ld_row(L.O, e); pO1 = ld_row(L.O, e + 1);
+        pS0 = ld_row(L.S, e); pS1 = ld_row(L.S, e + 1);
+        pB0 = ld_row(L.b, e); pB1 = ld_row(L.b, e + 1);
+        if (NINE) {
+            pSW0 = ld_row(L.SW, e); pSW1 = ld_row(L.SW, e + 1);
+            pNW0 = ld_row(L.NW, e); pNW1 = ld_row(L.NW, e + 1);
+        }
+        ld_w((e - 2 * NU - 2) >> 1, pw);
+    };
+    fetch(es);
 
     for (int e = es; e <= elast; e += 2) {
         __syncthreads();  // the previous step is done with the slots reused below
@@ -162,19 +183,10 @@ __global__ __launch_bounds__(FW) void k_pre(Lev<T> L, T *__restrict__ uout, Wts<
             rO[RW - 2] = pO0; rO[RW - 1] = pO1;
             rS[RW - 2] = pS0; rS[RW - 1] = pS1;
             rB[RW - 2] = pB0; rB[RW - 1] = pB1;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) w[q] = pw[q];
         }
-        // prefetch the next step's rows
-        if (e + 2 <= elast) {
-            pu0 = ld_row(L.u, e + 2); pu1 = ld_row(L.u, e + 3);
-            pW0 = ld_row(L.W, e + 2); pW1 = ld_row(L.W, e + 3);
-            pO0 = ld_row(L.O, e + 2); pO1 = ld_row(L.O, e + 3);
-            pS0 = ld_row(L.S, e + 2); pS1 = ld_row(L.S, e + 3);
-            pB0 = ld_row(L.b, e + 2); pB1 = ld_row(L.b, e + 3);
-            if (NINE) {
-                pSW0 = ld_row(L.SW, e + 2); pSW1 = ld_row(L.SW, e + 3);
-                pNW0 = ld_row(L.NW, e + 2); pNW1 = ld_row(L.NW, e + 3);
-            }
-        }
+        if (e + 2 <= elast) fetch(e + 2);
         __syncthreads();
         // NU sweeps, each over colours 0,1 (even row) then 2,3 (odd row)
 #pragma unroll
@@ -210,20 +222,20 @@ __global__ __launch_bounds__(FW) void k_pre(Lev<T> L, T *__restrict__ uout, Wts<
         __syncthreads();
         // restriction of coarse row J = (e - 2NU - 2) / 2 by the even columns
         {
-            const int f = e - 2 * NU - 2, J = f >> 1, I = i >> 1;
-            if (!(i & 1) && col_own && J >= 1 && J <= Cl.n && f >= y0 && f < y1 && I >= 1 && I <= Cl.n) {
-                const size_t c = (size_t)J * C.ld + I, cn = c + C.ld;
+            const int f = e - 2 * NU - 2, J = f >> 1;
+            if (restrictor && J >= 1 && J <= nc && f >= y0 && f < y1) {
+                const size_t c = (size_t)J * C.ld + I;
                 const T *rd = sr + ((f - 1) & 3) * FW + lane, *r0 = sr + (f & 3) * FW + lane,
                         *ru = sr + ((f + 1) & 3) * FW + lane;
-                T s = C.at(LNE, c) * rd[-1];
-                s = s + C.at(LA, c) * rd[0];
-                s = s + C.at(LNW, c + 1) * rd[1];
-                s = s + C.at(LR, c) * r0[-1];
+                T s = w[0] * rd[-1];
+                s = s + w[1] * rd[0];
+                s = s + w[2] * rd[1];
+                s = s + w[3] * r0[-1];
                 s = s + r0[0];
-                s = s + C.at(LL, c + 1) * r0[1];
-                s = s + C.at(LSE, cn) * ru[-1];
-                s = s + C.at(LB, cn) * ru[0];
-                s = s + C.at(LSW, cn + 1) * ru[1];
+                s = s + w[4] * r0[1];
+                s = s + w[5] * ru[-1];
+                s = s + w[6] * ru[0];
+                s = s + w[7] * ru[1];
                 Cl.b[c] = s;
                 Cl.u[c] = (T)0;
             }
@@ -234,7 +246,9 @@ __global__ __launch_bounds__(FW) void k_pre(Lev<T> L, T *__restrict__ uout, Wts<
 // ---------------------------------------------------------- post pass
 // u_out = GS^NU(u_in + P e_c).  With NORM (FP64 fine level) also the
 // per-tile sum of squares of the accurate residual b - A u_out over the owned
-// points into part[tile].  Window: rows e-2NU-2 .. e+1 at step e.
+// points into part[tile].  Window: rows e-2NU-2 .. e+1 at step e; the data of
+// step e+2 (rows, coarse row, interpolation weights) is requested while step
+// e computes.
 template <typename T, bool NINE, int NU, bool NORM>
 __global__ __launch_bounds__(FW) void k_post(Lev<T> L, T *__restrict__ uout, Wts<T> C, const T *__restrict__ ec,
                                               TileGeo G, double *__restrict__ part, const int *stop)
@@ -242,6 +256,7 @@ __global__ __launch_bounds__(FW) void k_post(Lev<T> L, T *__restrict__ uout, Wts
     if (stopped(stop)) return;
     const int tid = tile_id(G.ntiles);
     if (tid < 0) return;
+    static_assert(NU <= 2, "post pass supports up to two sweeps");
     constexpr int RW = 2 * NU + 4;
     constexpr int RU = RW <= 8 ? 8 : 16;
     __shared__ T su[RU * FW], sW[RU * FW], sec[4 * FW];
@@ -263,6 +278,8 @@ __global__ __launch_bounds__(FW) void k_post(Lev<T> L, T *__restrict__ uout, Wts
     const int ib = (x0 - G.hx) >> 1;
     const int Ie = ib + lane;
     const bool ccol_in = lane < FW / 2 + 2 && Ie >= 0 && Ie <= nc + 1;
+    const bool odd_i = i & 1;
+    const int Ix = (i + 1) >> 1;                   // coarse column east of an odd column
 
     T rO[RW], rS[RW], rB[RW];
     auto ld_row = [&](const T *a, int row) -> T {
@@ -271,74 +288,114 @@ __global__ __launch_bounds__(FW) void k_post(Lev<T> L, T *__restrict__ uout, Wts
     auto ld_crow = [&](int J) -> T {
         return (ccol_in && J >= 0 && J <= nc + 1) ? ec[(size_t)J * ldc + Ie] : (T)0;
     };
-    // u + P e_c at (i, row), e_c rows of the LDS ring
-    auto interp = [&](int row, T u) -> T {
+    // interpolation weights of this column for fine rows e (even) and e+1 (odd):
+    // odd columns: LL, LR at (Ix, e/2), then LSW, LSE, LNW, LNE at (Ix, e/2+1);
+    // even columns: LB, LA at (i/2, e/2+1)
+    struct IW { T w[6]; };
+    auto ld_iw = [&](int e) -> IW {
+        IW r;
+        T *w = r.w;
+        const int J0 = e >> 1, J1 = J0 + 1;
+        const bool ok0 = col_upd && odd_i && e >= 1 && e <= n;
+        const bool ok1 = col_upd && e + 1 >= 1 && e + 1 <= n;
+        const size_t c0 = ok0 ? (size_t)J0 * ldc + Ix : 0;
+        const size_t c1 = ok1 ? (size_t)J1 * ldc + (odd_i ? Ix : (i >> 1)) : 0;
+        w[0] = ok0 ? C.at(LL, c0) : (T)0;
+        w[1] = ok0 ? C.at(LR, c0) : (T)0;
+        if (odd_i) {
+            w[2] = ok1 ? C.at(LSW, c1) : (T)0;
+            w[3] = ok1 ? C.at(LSE, c1) : (T)0;
+            w[4] = ok1 ? C.at(LNW, c1) : (T)0;
+            w[5] = ok1 ? C.at(LNE, c1) : (T)0;
+        } else {
+            w[2] = ok1 ? C.at(LB, c1) : (T)0;
+            w[3] = ok1 ? C.at(LA, c1) : (T)0;
+            w[4] = w[5] = (T)0;
+        }
+        return r;
+    };
+    // u + P e_c at (i, row) for an even (row = e) or odd (row = e+1) row, with
+    // the weights w of ld_iw and e_c from the LDS ring
+    auto interp = [&](int row, T u, const IW &iw) -> T {
+        const T *w = iw.w;
         if (!col_upd || row < 1 || row > n) return u;
         T e;
-        const int li = lane;  // fine column i <-> coarse column (i >> 1) - ib
-        if (!(i & 1) && !(row & 1)) {
-            e = sec[((row >> 1) & 3) * FW + (i >> 1) - ib];
-        } else if ((i & 1) && !(row & 1)) {
-            const int J = row >> 1, I = (i + 1) >> 1;
-            const size_t c = (size_t)J * ldc + I;
-            const T *er = sec + (J & 3) * FW + (I - ib);
-            e = C.at(LL, c) * er[-1] + C.at(LR, c) * er[0];
-        } else if (!(i & 1)) {
-            const int J = (row + 1) >> 1, I = i >> 1;
-            const size_t c = (size_t)J * ldc + I;
-            e = C.at(LB, c) * sec[((J - 1) & 3) * FW + (I - ib)] + C.at(LA, c) * sec[(J & 3) * FW + (I - ib)];
+        if (!(row & 1)) {
+            const T *er = sec + ((row >> 1) & 3) * FW;
+            if (!odd_i) e = er[(i >> 1) - ib];
+            else e = w[0] * er[Ix - 1 - ib] + w[1] * er[Ix - ib];
         } else {
-            const int J = (row + 1) >> 1, I = (i + 1) >> 1;
-            const size_t c = (size_t)J * ldc + I;
-            const T *es_ = sec + ((J - 1) & 3) * FW + (I - ib), *en = sec + (J & 3) * FW + (I - ib);
-            e = C.at(LSW, c) * es_[-1] + C.at(LSE, c) * es_[0];
-            e = e + C.at(LNW, c) * en[-1];
-            e = e + C.at(LNE, c) * en[0];
+            const int J = (row + 1) >> 1;
+            const T *es_ = sec + ((J - 1) & 3) * FW, *en = sec + (J & 3) * FW;
+            if (!odd_i) {
+                e = w[2] * es_[(i >> 1) - ib] + w[3] * en[(i >> 1) - ib];
+            } else {
+                e = w[2] * es_[Ix - 1 - ib] + w[3] * es_[Ix - ib];
+                e = e + w[4] * en[Ix - 1 - ib];
+                e = e + w[5] * en[Ix - ib];
+            }
         }
-        (void)li;
         return u + e;
     };
 
-    // initial window rows es-2NU-2 .. es-1: interpolated u; their coarse rows
-    // are (es-2NU-2)/2 .. es/2 (NU + 2 <= 4 rows, the e_c ring)
-    static_assert(NU <= 2, "post pass supports up to two sweeps");
+    // window of step es without its own two rows: rows es-2NU-2 .. es-1,
+    // interpolated, at positions 2..RW-1 (aligned by the first shift); their
+    // coarse rows are (es-2NU-2)/2 .. es/2, at most four (the e_c ring)
     for (int J = (es - 2 * NU - 2) >> 1; J <= (es >> 1); ++J) sec[(J & 3) * FW + lane] = ld_crow(J);
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < RW - 2; ++k) {
-        const int row = es - 2 * NU - 2 + k;
-        su[slot<RU>(row) * FW + lane] = interp(row, ld_row(L.u, row));
-        sW[slot<RU>(row) * FW + lane] = ld_row(L.W, row);
-        if (NINE) {
-            sSW[slot<RU>(row) * FW + lane] = ld_row(L.SW, row);
-            sNW[slot<RU>(row) * FW + lane] = ld_row(L.NW, row);
+    for (int k = 2; k < RW; k += 2) {
+        const int row = es - 2 * NU - 4 + k;      // even
+        const IW wk = ld_iw(row);
+        su[slot<RU>(row) * FW + lane] = interp(row, ld_row(L.u, row), wk);
+        su[slot<RU>(row + 1) * FW + lane] = interp(row + 1, ld_row(L.u, row + 1), wk);
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            sW[slot<RU>(row + t) * FW + lane] = ld_row(L.W, row + t);
+            if (NINE) {
+                sSW[slot<RU>(row + t) * FW + lane] = ld_row(L.SW, row + t);
+                sNW[slot<RU>(row + t) * FW + lane] = ld_row(L.NW, row + t);
+            }
+            rO[k + t] = ld_row(L.O, row + t);
+            rS[k + t] = ld_row(L.S, row + t);
+            rB[k + t] = ld_row(L.b, row + t);
         }
-        rO[k] = ld_row(L.O, row);
-        rS[k] = ld_row(L.S, row);
-        rB[k] = ld_row(L.b, row);
     }
+    T pu0, pu1, pW0, pW1, pO0, pO1, pS0, pS1, pB0, pB1, pSW0 = 0, pSW1 = 0, pNW0 = 0, pNW1 = 0, pec;
+    IW pw;
+    auto fetch = [&](int e) {
+        pu0 = ld_row(L.u, e); pu1 = ld_row(L.u, e + 1);
+        pW0 = ld_row(L.W, e); pW1 = ld_row(L.W, e + 1);
+        pO0 = ld_row(L.O, e); pO1 = ld_row(L.O, e + 1);
+        pS0 = ld_row(L.S, e); pS1 = ld_row(L.S, e + 1);
+        pB0 = ld_row(L.b, e); pB1 = ld_row(L.b, e + 1);
+        if (NINE) {
+            pSW0 = ld_row(L.SW, e); pSW1 = ld_row(L.SW, e + 1);
+            pNW0 = ld_row(L.NW, e); pNW1 = ld_row(L.NW, e + 1);
+        }
+        pec = ld_crow((e >> 1) + 1);
+        pw = ld_iw(e);
+    };
+    fetch(es);
     double acc = 0.0;
     for (int e = es; e <= elast; e += 2) {
         __syncthreads();
         // coarse row e/2 + 1 joins the e_c ring (rows e/2 and e/2 + 1 are used)
-        sec[(((e >> 1) + 1) & 3) * FW + lane] = ld_crow((e >> 1) + 1);
-        const T u0 = ld_row(L.u, e), u1 = ld_row(L.u, e + 1);
-        const T w0 = ld_row(L.W, e), w1 = ld_row(L.W, e + 1);
-        T sw0 = 0, sw1 = 0, nw0 = 0, nw1 = 0;
-        if (NINE) { sw0 = ld_row(L.SW, e); sw1 = ld_row(L.SW, e + 1); nw0 = ld_row(L.NW, e); nw1 = ld_row(L.NW, e + 1); }
+        sec[(((e >> 1) + 1) & 3) * FW + lane] = pec;
 #pragma unroll
         for (int k = 0; k < RW - 2; ++k) { rO[k] = rO[k + 2]; rS[k] = rS[k + 2]; rB[k] = rB[k + 2]; }
-        rO[RW - 2] = ld_row(L.O, e); rO[RW - 1] = ld_row(L.O, e + 1);
-        rS[RW - 2] = ld_row(L.S, e); rS[RW - 1] = ld_row(L.S, e + 1);
-        rB[RW - 2] = ld_row(L.b, e); rB[RW - 1] = ld_row(L.b, e + 1);
+        rO[RW - 2] = pO0; rO[RW - 1] = pO1;
+        rS[RW - 2] = pS0; rS[RW - 1] = pS1;
+        rB[RW - 2] = pB0; rB[RW - 1] = pB1;
         __syncthreads();
         {
             const int s0 = slot<RU>(e) * FW + lane, s1 = slot<RU>(e + 1) * FW + lane;
-            su[s0] = interp(e, u0);
-            su[s1] = interp(e + 1, u1);
-            sW[s0] = w0; sW[s1] = w1;
-            if (NINE) { sSW[s0] = sw0; sSW[s1] = sw1; sNW[s0] = nw0; sNW[s1] = nw1; }
+            su[s0] = interp(e, pu0, pw);
+            su[s1] = interp(e + 1, pu1, pw);
+            sW[s0] = pW0; sW[s1] = pW1;
+            if (NINE) { sSW[s0] = pSW0; sSW[s1] = pSW1; sNW[s0] = pNW0; sNW[s1] = pNW1; }
         }
+        if (e + 2 <= elast) fetch(e + 2);
         __syncthreads();
 #pragma unroll
         for (int s = 0; s < NU; ++s) {
@@ -397,6 +454,198 @@ __global__ __launch_bounds__(FW) void k_post(Lev<T> L, T *__restrict__ uout, Wts
     if (NORM) {
         acc = block_sum(acc);
         if (threadIdx.x == 0) part[tid] = acc;
+    }
+}
+
+}  // namespace bmg
+
+namespace bmg {
+
+// ---------------------------------------------- persistent small levels
+// The whole V-cycle below (and including) a small level runs in one workgroup:
+// the iterates, right-hand sides and the residual of these levels stay in LDS
+// (tight pitch n+2), the stencils and weights are read from global memory (they
+// are a few hundred KB and stay in L2), and every phase of the cycle is
+// separated by a workgroup barrier instead of a kernel launch.  The arithmetic
+// per point is the same expression as in the single-step kernels.
+constexpr int SMALL_MAXL = 6;
+constexpr int SMALL_THREADS = 1024;
+
+template <typename T>
+struct SmallH {
+    int nl;                    // levels in the kernel: first .. coarsest
+    Lev<T> L[SMALL_MAXL];
+    Wts<T> C[SMALL_MAXL];      // C[l]: weights between L[l] and L[l+1]
+    int off_u[SMALL_MAXL], off_b[SMALL_MAXL], off_r;
+    const double *LD;          // coarsest LDL^T factor
+    int nu1, nu2;
+};
+
+template <typename T, bool NINE>
+__device__ __forceinline__ void small_gs_colour(const Lev<T> &L, T *u, const T *b, int c)
+{
+    const int n = L.n, p = n + 2;
+    const int i0 = (c & 1) ? 1 : 2, j0 = (c >> 1) ? 1 : 2;
+    const int ni = (c & 1) ? (n + 1) / 2 : (n - 1) / 2, nj = (c >> 1) ? (n + 1) / 2 : (n - 1) / 2;
+    for (int t = threadIdx.x; t < ni * nj; t += blockDim.x) {
+        const int i = i0 + 2 * (t % ni), j = j0 + 2 * (t / ni);
+        const size_t g = (size_t)j * L.ld + i;
+        const int q = j * p + i;
+        T s = b[q];
+        if (NINE) s -= L.SW[g] * u[q - p - 1];
+        s -= L.S[g] * u[q - p];
+        if (NINE) s -= L.NW[g + 1 - L.ld] * u[q - p + 1];
+        s -= L.W[g] * u[q - 1];
+        s -= L.W[g + 1] * u[q + 1];
+        if (NINE) s -= L.NW[g] * u[q + p - 1];
+        s -= L.S[g + L.ld] * u[q + p];
+        if (NINE) s -= L.SW[g + L.ld + 1] * u[q + p + 1];
+        u[q] = s / L.O[g];
+    }
+}
+
+template <typename T, bool NINE>
+__device__ __forceinline__ void small_smooth(const Lev<T> &L, T *u, const T *b, int sweeps)
+{
+    for (int s = 0; s < sweeps; ++s)
+        for (int c = 0; c < 4; ++c) {
+            small_gs_colour<T, NINE>(L, u, b, c);
+            __syncthreads();
+        }
+}
+
+template <typename T, bool NINE>
+__device__ __forceinline__ void small_residual(const Lev<T> &L, const T *u, const T *b, T *r)
+{
+    const int n = L.n, p = n + 2;
+    for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+        const int i = 1 + t % n, j = 1 + t / n;
+        const size_t g = (size_t)j * L.ld + i;
+        const int q = j * p + i;
+        T s = b[q];
+        if (NINE) s -= L.SW[g] * u[q - p - 1];
+        s -= L.S[g] * u[q - p];
+        if (NINE) s -= L.NW[g + 1 - L.ld] * u[q - p + 1];
+        s -= L.W[g] * u[q - 1];
+        s -= L.W[g + 1] * u[q + 1];
+        if (NINE) s -= L.NW[g] * u[q + p - 1];
+        s -= L.S[g + L.ld] * u[q + p];
+        if (NINE) s -= L.SW[g + L.ld + 1] * u[q + p + 1];
+        s -= L.O[g] * u[q];
+        r[q] = s;
+    }
+}
+
+template <typename T, bool NINE0>
+__global__ __launch_bounds__(SMALL_THREADS) void k_small_vcycle(SmallH<T> H, const int *stop)
+{
+    if (stopped(stop)) return;
+    extern __shared__ unsigned char smem_raw[];
+    T *sm = reinterpret_cast<T *>(smem_raw);
+    const int nl = H.nl, last = nl - 1;
+    // fetch b of the first level, zero every iterate and the coarser b
+    for (int l = 0; l < nl; ++l) {
+        const int n = H.L[l].n, p = n + 2;
+        T *u = sm + H.off_u[l], *b = sm + H.off_b[l];
+        for (int t = threadIdx.x; t < p * p; t += blockDim.x) {
+            const int i = t % p, j = t / p;
+            u[t] = (T)0;
+            b[t] = (l == 0 && i >= 1 && i <= n && j >= 1 && j <= n) ? H.L[0].b[(size_t)j * H.L[0].ld + i] : (T)0;
+        }
+    }
+    T *r = sm + H.off_r;
+    for (int t = threadIdx.x; t < (H.L[0].n + 2) * (H.L[0].n + 2); t += blockDim.x) r[t] = (T)0;
+    __syncthreads();
+    // down: relax, residual, restrict
+    for (int l = 0; l < last; ++l) {
+        const Lev<T> &L = H.L[l];
+        T *u = sm + H.off_u[l], *b = sm + H.off_b[l];
+        const bool nine = (l > 0) || NINE0;
+        if (nine) small_smooth<T, true>(L, u, b, H.nu1); else small_smooth<T, false>(L, u, b, H.nu1);
+        if (nine) small_residual<T, true>(L, u, b, r); else small_residual<T, false>(L, u, b, r);
+        __syncthreads();
+        const int nf = L.n, pf = nf + 2, nc = H.L[l + 1].n, pc = nc + 2;
+        const Wts<T> &C = H.C[l];
+        T *bc = sm + H.off_b[l + 1];
+        for (int t = threadIdx.x; t < nc * nc; t += blockDim.x) {
+            const int I = 1 + t % nc, J = 1 + t / nc;
+            const size_t c = (size_t)J * C.ld + I, cn = c + C.ld;
+            const int f = (2 * J) * pf + 2 * I;
+            T s = C.at(LNE, c) * r[f - pf - 1];
+            s = s + C.at(LA, c) * r[f - pf];
+            s = s + C.at(LNW, c + 1) * r[f - pf + 1];
+            s = s + C.at(LR, c) * r[f - 1];
+            s = s + r[f];
+            s = s + C.at(LL, c + 1) * r[f + 1];
+            s = s + C.at(LSE, cn) * r[f + pf - 1];
+            s = s + C.at(LB, cn) * r[f + pf];
+            s = s + C.at(LSW, cn + 1) * r[f + pf + 1];
+            bc[J * pc + I] = s;
+        }
+        __syncthreads();
+    }
+    // coarsest 3x3: y = L^-1 b, z = y / D, x = L^-T z in FP64
+    if (threadIdx.x == 0) {
+        const double *LD = H.LD;
+        const T *b = sm + H.off_b[last];
+        T *u = sm + H.off_u[last];
+        double y[9], x[9];
+        for (int i = 0; i < 9; ++i) {
+            double s = (double)b[(1 + i / 3) * 5 + 1 + i % 3];
+            for (int k = 0; k < i; ++k) s = s - LD[i * 9 + k] * y[k];
+            y[i] = s;
+        }
+        for (int i = 0; i < 9; ++i) y[i] = y[i] / LD[81 + i];
+        for (int i = 8; i >= 0; --i) {
+            double s = y[i];
+            for (int k = i + 1; k < 9; ++k) s = s - LD[k * 9 + i] * x[k];
+            x[i] = s;
+        }
+        for (int i = 0; i < 9; ++i) u[(1 + i / 3) * 5 + 1 + i % 3] = (T)x[i];
+    }
+    __syncthreads();
+    // up: interpolate and correct, relax
+    for (int l = last - 1; l >= 0; --l) {
+        const Lev<T> &L = H.L[l];
+        T *u = sm + H.off_u[l], *b = sm + H.off_b[l];
+        const T *ec = sm + H.off_u[l + 1];
+        const int n = L.n, p = n + 2, pc = H.L[l + 1].n + 2;
+        const Wts<T> &C = H.C[l];
+        for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+            const int i = 1 + t % n, j = 1 + t / n;
+            T e;
+            if (!(i & 1) && !(j & 1)) {
+                e = ec[(j >> 1) * pc + (i >> 1)];
+            } else if ((i & 1) && !(j & 1)) {
+                const int I = (i + 1) >> 1, J = j >> 1;
+                const size_t c = (size_t)J * C.ld + I;
+                e = C.at(LL, c) * ec[J * pc + I - 1] + C.at(LR, c) * ec[J * pc + I];
+            } else if (!(i & 1)) {
+                const int I = i >> 1, J = (j + 1) >> 1;
+                const size_t c = (size_t)J * C.ld + I;
+                e = C.at(LB, c) * ec[(J - 1) * pc + I] + C.at(LA, c) * ec[J * pc + I];
+            } else {
+                const int I = (i + 1) >> 1, J = (j + 1) >> 1;
+                const size_t c = (size_t)J * C.ld + I;
+                e = C.at(LSW, c) * ec[(J - 1) * pc + I - 1] + C.at(LSE, c) * ec[(J - 1) * pc + I];
+                e = e + C.at(LNW, c) * ec[J * pc + I - 1];
+                e = e + C.at(LNE, c) * ec[J * pc + I];
+            }
+            u[j * p + i] = u[j * p + i] + e;
+        }
+        __syncthreads();
+        const bool nine = (l > 0) || NINE0;
+        if (nine) small_smooth<T, true>(L, u, b, H.nu2); else small_smooth<T, false>(L, u, b, H.nu2);
+    }
+    // the first level's iterate back to global memory
+    {
+        const Lev<T> &L = H.L[0];
+        const int n = L.n, p = n + 2;
+        const T *u = sm + H.off_u[0];
+        for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+            const int i = 1 + t % n, j = 1 + t / n;
+            L.u[(size_t)j * L.ld + i] = u[j * p + i];
+        }
     }
 }
 

@@ -73,7 +73,6 @@ struct bmg_solver {
     Wts<float> C32[MAXL];
     double *ualt[MAXL];         // second iterate buffer of each level (fused passes)
     float *ualt32[MAXL];
-    int tile_rows = 128;        // rows per tile of the fused passes
     int norm_parts = 0;         // partial sums left by the last fused norm
     double *B0 = nullptr;       // fine right-hand side during refinement
     double *XH = nullptr;       // double-FP64 iterate, high part
@@ -339,6 +338,18 @@ double *&ualt<double>(bmg_solver *h, int l) { return h->ualt[l]; }
 template <>
 float *&ualt<float>(bmg_solver *h, int l) { return h->ualt32[l]; }
 
+// Rows per tile of a fused pass: the caller's choice, else by level size (a
+// measured trade-off between enough tiles to fill the chip and the warm-up
+// rows every tile re-reads).
+int level_tile_rows(const bmg_solver *h, int n)
+{
+    if (h->opt.tile_rows > 0) return h->opt.tile_rows;
+    if (n >= 4095) return 128;
+    if (n >= 2047) return 64;
+    if (n >= 1023) return 16;
+    return 8;
+}
+
 TileGeo tile_geo(int n, int hx, int ht)
 {
     TileGeo g;
@@ -366,7 +377,9 @@ bmg_status fused_pre(bmg_solver *h, int l, int nu, const int *stop)
         TRY(residual<T>(h, F, nine, stop));
         return restrict_<T>(h, F, C, Cl, stop);
     }
-    const TileGeo g = tile_geo(F.n, nine ? 4 * nu + 2 : 2 * nu + 2, h->tile_rows);
+    // halo: each sweep invalidates 2 (five-point) or 4 (nine-point) columns at
+    // each edge of the strip, the residual and the restriction one more each
+    const TileGeo g = tile_geo(F.n, nine ? 4 * nu + 2 : 2 * nu + 2, level_tile_rows(h, F.n));
     T *out = ualt<T>(h, l);
     const dim3 grid = tile_grid(g), blk(FW);
 #define PRE(NINE, NU) hipLaunchKernelGGL((k_pre<T, NINE, NU>), grid, blk, 0, h->st, F, out, C, Cl, g, stop)
@@ -398,7 +411,10 @@ bmg_status fused_post(bmg_solver *h, int l, int nu, const int *stop, bool norm =
         TRY(interp<T>(h, F, C, Cl, stop));
         return smooth<T>(h, F, nine, nu, stop, l);
     }
-    const TileGeo g = tile_geo(F.n, nine ? 4 * nu + 1 : 2 * nu + 1, h->tile_rows);
+    // halo: the edge lanes are never interpolated (stale from the start), then
+    // each sweep invalidates 2 (five-point) or 4 (nine-point) more columns and
+    // the fused residual one more
+    const TileGeo g = tile_geo(F.n, nine ? 4 * nu + 2 : 2 * nu + 2, level_tile_rows(h, F.n));
     norm = norm && std::is_same<T, double>::value && g.ntiles <= NPART;
     T *out = ualt<T>(h, l);
     const dim3 grid = tile_grid(g), blk(FW);
@@ -420,10 +436,49 @@ bmg_status fused_post(bmg_solver *h, int l, int nu, const int *stop, bool norm =
     return BMG_OK;
 }
 
+// Coarse levels of at most SMALL_N points per side: their whole sub-cycle in
+// one workgroup (k_small_vcycle), iterates and right-hand sides in LDS.
+constexpr int SMALL_N = 63;
+
+template <typename T>
+bmg_status small_cycle(bmg_solver *h, int l, const int *stop)
+{
+    SmallH<T> S{};
+    S.nl = h->nlev - l;
+    if (S.nl > SMALL_MAXL) return fail(BMG_EINVAL, "too many small levels");
+    int off = 0;
+    for (int k = 0; k < S.nl; ++k) {
+        S.L[k] = lev<T>(h, l + k);
+        if (k + 1 < S.nl) S.C[k] = wts<T>(h, l + k);
+        const int p = S.L[k].n + 2;
+        S.off_u[k] = off;
+        off += p * p;
+        S.off_b[k] = off;
+        off += p * p;
+    }
+    S.off_r = off;
+    off += (S.L[0].n + 2) * (S.L[0].n + 2);
+    S.LD = h->LD;
+    S.nu1 = h->opt.nu1;
+    S.nu2 = h->opt.nu2;
+    const size_t shmem = (size_t)off * sizeof(T);
+    static bool attr_set[2] = {false, false};
+    const int which = sizeof(T) == 8 ? 0 : 1;
+    if (!attr_set[which]) {
+        HIPCHK(hipFuncSetAttribute((const void *)k_small_vcycle<T, true>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+        attr_set[which] = true;
+    }
+    hipLaunchKernelGGL((k_small_vcycle<T, true>), dim3(1), dim3(SMALL_THREADS), shmem, h->st, S, stop);
+    LAUNCHCHK();
+    return BMG_OK;
+}
+
 template <typename T>
 bmg_status fused_cycle_from(bmg_solver *h, int l, const int *stop, bool norm)
 {
     if (l == h->nlev - 1) return coarse<T>(h, lev<T>(h, l), stop);
+    if (l >= 1 && lev<T>(h, l).n <= SMALL_N) return small_cycle<T>(h, l, stop);
     TRY(fused_pre<T>(h, l, h->opt.nu1, stop));
     TRY(fused_cycle_from<T>(h, l + 1, stop, false));
     return fused_post<T>(h, l, h->opt.nu2, stop, norm && l == 0);
@@ -592,7 +647,6 @@ bmg_status bmg_setup(bmg_solver **out, const double *stencil, int n, int kind, c
     h->st = (hipStream_t)stream;
     h->ws = (char *)workspace;
     h->ws_bytes = ws_bytes;
-    h->tile_rows = op.tile_rows > 0 ? op.tile_rows : 128;
     plan(h, n, kind, op, h->ws);
     auto bail = [&](bmg_status s) { delete h; return s; };
 #define SCHK(x)                                  \

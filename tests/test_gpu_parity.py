@@ -352,10 +352,10 @@ def test_cycle_variants_match_oracle(gpu, kernels, nu1, nu2):
     """V(nu1,nu2) solves on both kernel paths equal the oracle's bit for bit."""
     p = problem("jump16", 255, 13)
     st, rhs = gpu_problem(p)
-    S = boxmg.Solver(st, kernels=kernels, nu1=nu1, nu2=nu2, max_cycles=200, tile_rows=48)
-    x, info = S.solve(rhs, tol=1e-9)
+    S = boxmg.Solver(st, kernels=kernels, nu1=nu1, nu2=nu2, max_cycles=60, tile_rows=48)
+    x, info = S.solve(rhs, tol=1e-9, raise_on_noconv=False)
     H = ref.Hierarchy(host(st), nu1, nu2)
-    u, hist = H.solve(ref.pad(host(rhs)), tol=1e-9, max_cycles=200)
+    u, hist = H.solve(ref.pad(host(rhs)), tol=1e-9, max_cycles=60)
     assert info["cycles"] == len(hist)
     same(host(x), u[1:-1, 1:-1], "solution")
     assert np.all(np.abs(np.array(info["history"]) - hist) <= 1e-12 * hist)
