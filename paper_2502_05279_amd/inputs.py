@@ -41,6 +41,11 @@ __all__ = [
     "jumping",
     "batch_512",
     "learned_train_field",
+    "NET_SHAPES",
+    "NET_SIZE",
+    "net_init",
+    "net_random",
+    "residual_probe",
 ]
 
 
@@ -142,3 +147,45 @@ def learned_train_field(seed: int, n: int = 255, block: int = 16,
                         lo: float = -4.0, hi: float = 4.0) -> Problem:
     """A training coefficient field for the learned interpolation."""
     return jumping(n, block, lo, hi, seed, seed + 7_000_000, f"train_{seed}")
+
+
+# ------------------------------------------------------ learned interpolation
+# Shapes of the network parameters, in the order of the flat parameter vector:
+# conv1 weights [tap][in][out], bias, conv2 weights and bias, conv3 weights and
+# bias.  A tap t = 3 (dy + 1) + (dx + 1) reads the point offset by (dx, dy).
+NET_SHAPES = (("W1", (9, 9, 32)), ("b1", (32,)), ("W2", (9, 32, 32)), ("b2", (32,)),
+              ("W3", (9, 32, 8)), ("b3", (8,)))
+NET_SIZE = sum(int(np.prod(s)) for _, s in NET_SHAPES)
+
+
+def net_init(seed: int = 501) -> np.ndarray:
+    """Initial flat parameter vector (float32): weights uniform in
+    +-sqrt(6 / fan_in) (fan_in = 9 taps x input channels), biases zero."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for name, shape in NET_SHAPES:
+        if name.startswith("W"):
+            bound = np.sqrt(6.0 / (shape[0] * shape[1]))
+            out.append(rng.uniform(-bound, bound, size=shape).ravel())
+        else:
+            out.append(np.zeros(shape).ravel())
+    return np.concatenate(out).astype(np.float32)
+
+
+def net_random(seed: int, bias_scale: float = 0.1) -> np.ndarray:
+    """A random parameter vector with non-zero biases, for parity tests."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for name, shape in NET_SHAPES:
+        if name.startswith("W"):
+            bound = np.sqrt(6.0 / (shape[0] * shape[1]))
+            out.append(rng.uniform(-bound, bound, size=shape).ravel())
+        else:
+            out.append(rng.uniform(-bias_scale, bias_scale, size=shape).ravel())
+    return np.concatenate(out).astype(np.float32)
+
+
+def residual_probe(n: int, seed: int) -> np.ndarray:
+    """Random initial residual r0 of a two-grid training sample, uniform[-1,1]
+    on the n x n interior."""
+    return np.random.default_rng(seed).uniform(-1.0, 1.0, size=(n, n))
