@@ -37,7 +37,7 @@ HBM_PEAK_GBS = 8000.0
 #   point = 66 B; fused post pass (interpolation + nu2 sweeps + residual norm):
 #   e_c 8/4, weights 16/4... see the design notes; the figure below is what the
 #   traced class moves per fine point.
-BYTES_PER_POINT = {"smooth": 48.0, "pre": 66.0, "post": 66.0}
+BYTES_PER_POINT = {"smooth": 48.0, "pre": 66.0, "post": 66.0, "resnorm": 56.0}
 
 
 def workload(name: str):
@@ -46,6 +46,8 @@ def workload(name: str):
         return inputs.jumping_4095()
     if name == "poisson_127":
         return inputs.poisson_127()
+    if name == "jumping_8191":
+        return inputs.jumping_8191()
     if name.startswith("jumping_"):
         n = int(name.split("_")[1])
         return inputs.jumping_4095(n=n)
@@ -83,6 +85,61 @@ def cpu_baseline(p, gpu_cycles: int, sample_cycles: int):
                       f"solve took; set-up {t_setup:.2f} s, {t_cyc * 1e3:.1f} ms per cycle"}
 
 
+def bench_batch(args):
+    """512 independent problems of uneven size (2^m - 1, m in 6..10, per-cell
+    log-normal k), solved together: FP32 V-cycles inside double-FP64 refinement
+    in one persistent launch per group of steps, tile heights from the
+    autotuner.  One step = set-up of all problems + the batched solve."""
+    import torch
+    from paper_2502_05279_amd import autotune, boxmg, inputs
+
+    dev = torch.device("cuda:0")
+    tuned = autotune.tune(sizes=(127, 255, 511, 1023), precision=boxmg.BMG_FP32_IR)
+    probs = inputs.batch_512()
+    sts, rhss = [], []
+    for q in probs:
+        st, rhs = boxmg.discretize(torch.from_numpy(q.k).to(dev), torch.from_numpy(q.f).to(dev))
+        sts.append(st)
+        rhss.append(rhs)
+    dof = sum(q.n * q.n for q in probs)
+
+    def step():
+        B = boxmg.Batch(sts, max_cycles=args.max_cycles)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        x, steps, rel, status = B.solve(rhss, tol=args.tol, raise_on_noconv=False)
+        torch.cuda.synchronize()
+        return B, x, steps, rel, status, time.perf_counter() - t1
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    solve_s = 0.0
+    for _ in range(args.steps):
+        B, x, steps, rel, status, ts = step()
+        solve_s += ts
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    info = B.info()
+    sizes = sorted({q.n for q in probs})
+    out = {
+        "metric": f"fine DOF/s solved to {args.tol:g} rel. residual (512 problems, FP32 V-cycle in FP64 refinement)",
+        "value": dof / dt, "unit": "DOF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "batch_512", "problems": len(probs), "dof": dof,
+                   "sizes": {str(n): sum(q.n == n for q in probs) for n in sizes},
+                   "tol": args.tol, "solve_ms": solve_s / args.steps * 1e3,
+                   "solve_dof_per_s": dof / (solve_s / args.steps),
+                   "steps_max": max(steps), "steps_mean": sum(steps) / len(steps),
+                   "max_rel_res": max(rel), "converged": status == 0,
+                   "workgroups": info["workgroups"], "graph": info["graph"],
+                   "tile_rows": {str(k): v for k, v in tuned.items()}},
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +149,12 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--max-cycles", type=int, default=2000)
     ap.add_argument("--kernels", default="fused", choices=["fused", "basic"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32ir"],
+                    help="fp64: FP64 V-cycles (double-FP64 below 16*tol); fp32ir: FP32 "
+                         "V-cycles inside double-FP64 iterative refinement")
+    ap.add_argument("--compare-fp64", action="store_true",
+                    help="with --precision fp32ir: also time the FP64 solve of the same "
+                         "problem and report the difference of the two solutions")
     ap.add_argument("--cpu-sample-cycles", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -111,6 +174,8 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     dev = torch.device("cuda:0")
+    if args.workload == "batch_512":
+        return bench_batch(args)
     if args.copy_probe:
         a = torch.ones(args.copy_probe << 17, dtype=torch.float64, device=dev)
         b = torch.empty_like(a)
@@ -131,8 +196,11 @@ def main():
     f = torch.from_numpy(p.f).to(dev)
     stencil, rhs = boxmg.discretize(k, f)
     kern = boxmg.BMG_KERNELS_FUSED if args.kernels == "fused" else boxmg.BMG_KERNELS_BASIC
-    opts = dict(max_cycles=args.max_cycles, kernels=kern, check_every=16)
+    prec = boxmg.BMG_FP32_IR if args.precision == "fp32ir" else boxmg.BMG_FP64
+    opts = dict(max_cycles=args.max_cycles, kernels=kern, check_every=16, precision=prec)
     tclass = "pre" if args.kernels == "fused" else "smooth"
+    if prec == boxmg.BMG_FP32_IR:
+        tclass = "resnorm"     # the FP64 outer residual (accurate, 64 B per point)
 
     def step(trace: bool):
         S = boxmg.Solver(stencil, **opts)
@@ -159,10 +227,27 @@ def main():
     info = infos[-1]
     ms_step = dt * 1e3 / args.steps
     avg_ms = kms / max(launches, 1)
-    bpp = BYTES_PER_POINT[tclass]
+    bpp = BYTES_PER_POINT.get(tclass, 64.0)
     achieved = bpp * n * n / (avg_ms * 1e-3) / 1e9 if launches else None
+    metric = METRIC
+    extra = {}
+    if prec == boxmg.BMG_FP32_IR:
+        metric = f"fine DOF/s solved to {args.tol:g} rel. residual ({n}^2, FP32 V-cycle in FP64 refinement)"
+        if args.compare_fp64:
+            o64 = dict(opts, precision=boxmg.BMG_FP64)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            S64 = boxmg.Solver(stencil, **o64)
+            x64, info64 = S64.solve(rhs, tol=args.tol, raise_on_noconv=False)
+            torch.cuda.synchronize()
+            t64 = time.perf_counter() - t1
+            d = (x - x64)
+            extra = {"fp64_ms_per_solve": t64 * 1e3, "fp64_cycles": info64["cycles"],
+                     "fp64_final_rel_res": info64["rel_res"],
+                     "rel_diff_to_fp64_2norm": float(d.norm() / x64.norm()),
+                     "rel_diff_to_fp64_inf": float(d.abs().max() / x64.abs().max())}
     out = {
-        "metric": METRIC,
+        "metric": metric,
         "value": n * n / (dt / args.steps),
         "unit": "DOF/s",
         "n_gpus": 1,
@@ -172,12 +257,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if prec == boxmg.BMG_FP64 else "f32+f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "dof": n * n, "tol": args.tol,
                    "cycles": info["cycles"], "final_rel_res": info["rel_res"],
                    "converged": info["status"] == 0, "rho": info["rho"],
-                   "kernels": args.kernels, "nu1": 2, "nu2": 1},
+                   "kernels": args.kernels, "nu1": 2, "nu2": 1, "precision": args.precision,
+                   **extra},
         "roofline": {"bound": "hbm", "kernel": tclass, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS if achieved else None,

@@ -49,6 +49,9 @@ typedef enum {
 enum { BMG_STENCIL_5PT = 5, BMG_STENCIL_9PT = 9 };
 enum { BMG_FP64 = 0, BMG_FP32_IR = 1 };
 enum { BMG_KERNELS_BASIC = 0, BMG_KERNELS_FUSED = 1 };
+enum { BMG_INTERP_BOXMG = 0, BMG_INTERP_LEARNED = 1 };
+
+typedef struct bmg_net bmg_net;   /* learned interpolation network, see below */
 
 typedef struct {
     int nu1;         /* pre-smoothing sweeps (default 2) */
@@ -68,7 +71,13 @@ typedef struct {
                         FP64 vectors; 0 = never (default 16) */
     int tile_rows;   /* grid rows per workgroup tile of the fused passes
                         (even, 0 = the default of 128) */
-    int reserved[8];
+    int interp;      /* BMG_INTERP_BOXMG (default): operator-induced weights on
+                        every level; BMG_INTERP_LEARNED: the weights of levels
+                        l < learned_levels come from the network `net` */
+    int learned_levels; /* levels with learned weights (0 = all) */
+    bmg_net *net;    /* network of BMG_INTERP_LEARNED (not owned); it must
+                        outlive the set-up call only */
+    int reserved[4];
 } bmg_options;
 
 typedef struct {
@@ -211,6 +220,137 @@ bmg_status bmg_step(bmg_solver *h, int level, int step, int arg, int fp32);
 enum { BMG_TRACE_SMOOTH = 0, BMG_TRACE_PRE = 1, BMG_TRACE_POST = 2, BMG_TRACE_RESNORM = 3 };
 bmg_status bmg_trace_enable(bmg_solver *h, int kclass, int level, int on);
 bmg_status bmg_trace_read(bmg_solver *h, int *launches, double *total_ms);
+
+/* ------------------------------------------------------------------------
+ * Tile shapes of the fused passes.  A process-wide table of rows per tile for
+ * each level size n = 2^m - 1, written by the autotuner; 0 restores the
+ * built-in default.  bmg_options.tile_rows, when set, overrides the table.
+ * ---------------------------------------------------------------------- */
+bmg_status bmg_tile_rows_set(int n, int rows);
+bmg_status bmg_tile_rows_get(int n, int *rows);
+
+/* ------------------------------------------------------------------------
+ * Batched solves: nprob independent problems of uneven sizes (n[p] = 2^m - 1,
+ * n[p] >= 7, five-point operators as for bmg_setup), FP32 V(2,1)-cycles
+ * inside double-FP64 iterative refinement (the precision option is ignored),
+ * advanced together by one persistent cooperative launch (replayed from a HIP
+ * graph) that runs every problem's refinement steps phase by phase with a
+ * device-side stop flag per problem.  Each problem's iterates equal those of
+ * bmg_solve with precision BMG_FP32_IR.
+ * ---------------------------------------------------------------------- */
+typedef struct bmg_batch bmg_batch;
+
+/* n: host array of nprob sizes.  Host only. */
+bmg_status bmg_batch_workspace_bytes(int nprob, const int *n, const bmg_options *o, size_t *bytes);
+
+/* stencils: host array of nprob device pointers, each n[p] x n[p] x 5.
+ * Synchronises the stream (once per problem while setting up). */
+bmg_status bmg_batch_setup(bmg_batch **out, int nprob, const int *n, const double *const *stencils,
+                           const bmg_options *o, void *workspace, size_t ws_bytes, bmg_stream stream);
+
+/* rhs, x: host arrays of nprob device pointers to n[p] x n[p] arrays (x is the
+ * initial guess in, the solution's high part out).  steps (host, nullable)
+ * receives each problem's refinement steps, rel_res (host, nullable) its final
+ * relative residual.  BMG_ENOCONV / BMG_EDIVERGED name the first problem that
+ * failed; the others are still solved. */
+bmg_status bmg_batch_solve(bmg_batch *h, const double *const *rhs, double *const *x, double tol,
+                           int *steps, double *rel_res);
+
+/* Residual history of problem p: hist[0] is the initial relative residual,
+ * hist[k] the one after step k; *count entries exist (up to cap copied). */
+bmg_status bmg_batch_history(bmg_batch *h, int p, double *hist, int cap, int *count);
+
+/* Workgroups of the persistent launch and whether it is replayed from a graph. */
+bmg_status bmg_batch_info(const bmg_batch *h, int *nblocks, int *graph_used);
+bmg_status bmg_batch_destroy(bmg_batch *h);
+
+/* ------------------------------------------------------------------------
+ * Learned interpolation (an addition; the paper's interpolation is the
+ * operator-induced one).  A convolutional network reads the nine stencil
+ * coefficients of every fine point, each divided by the centre coefficient,
+ * and writes the eight weight planes of the coarse level in the layout of the
+ * operator-induced weights (LNE, LA, LNW, LR, LL, LSE, LB, LSW, stored at the
+ * north-east coarse point of each F-point triple; weights of F-points that do
+ * not exist are zero).  Layers: 3x3 conv 9->32 with ReLU at every fine point;
+ * 3x3 conv 32->32, stride 2, with ReLU at the coarse points (I, J),
+ * I, J = 1..nc+1, centred on the fine point (2I, 2J); 3x3 conv 32->8, linear,
+ * at the same points; zero padding.  Weights and activations are bfloat16
+ * (round to nearest even), products accumulate in FP32 on the matrix cores
+ * (MFMA), biases are FP32.
+ *
+ * Parameters are a flat FP32 vector of BMG_NET_PARAMS values: conv1 weights
+ * [tap][in 9][out 32], bias [32], conv2 weights [tap][32][32], bias [32],
+ * conv3 weights [tap][32][8], bias [8]; tap t = 3 (dy + 1) + (dx + 1) reads
+ * the point offset by (dx, dy).
+ *
+ * Training minimises the two-grid residual reduction ||r3||^2 / ||r0||^2 of
+ * one cycle (one GS sweep, coarse correction with A_c = P^T A P solved by
+ * V-cycles to a tolerance, one GS sweep) on A x = r0 from x = 0, with the
+ * gradient from the adjoint of that cycle and Adam updates.
+ * ---------------------------------------------------------------------- */
+#define BMG_NET_PARAMS 14184
+
+/* Device workspace of a network used on levels of up to max_n points per side;
+ * train = 0 sizes it for inference only (no backward pass or two-grid
+ * training).  Host only. */
+bmg_status bmg_net_workspace_bytes(int max_n, int train, size_t *bytes);
+
+/* params: host, BMG_NET_PARAMS floats.  Adam moments start at zero.  The
+ * handle keeps pointers into the workspace and uses `stream`. */
+bmg_status bmg_net_create(bmg_net **out, int max_n, int train, const float *params, void *workspace,
+                          size_t ws_bytes, bmg_stream stream);
+bmg_status bmg_net_set_params(bmg_net *net, const float *params /* host */);
+bmg_status bmg_net_get_params(bmg_net *net, float *params /* host */);
+bmg_status bmg_net_destroy(bmg_net *net);
+
+/* Forward pass on one level given by its padded compact planes ((n+2) rows of
+ * pitch ld; SW and NW NULL for a five-point level) into the weight planes
+ * Ci (8 planes of (nc+2) rows of pitch ldc, plane stride ps).  The
+ * activations stay in the workspace for bmg_net_backward. */
+bmg_status bmg_net_forward(bmg_net *net, int n, int ld, const double *O, const double *W, const double *S,
+                           const double *SW, const double *NW, double *Ci, int ldc, size_t ps);
+
+/* Backward pass of the last forward pass (train = 1): given dL/dCi in the
+ * layout of bmg_net_forward's output, adds dL/dparams to the gradient sum. */
+bmg_status bmg_net_backward(bmg_net *net, const double *dCi, int ldc, size_t ps);
+
+/* The gradient sum (host, BMG_NET_PARAMS doubles); zeroing it. */
+bmg_status bmg_net_get_grad(bmg_net *net, double *grad);
+bmg_status bmg_net_zero_grad(bmg_net *net);
+
+/* One Adam step (Kingma and Ba) in FP32 with gradient = scale * sum, step
+ * counter advanced by one; the bfloat16 weights follow the new parameters. */
+bmg_status bmg_net_adam(bmg_net *net, float lr, float beta1, float beta2, float eps, double scale);
+
+/* Intermediate arrays of the last passes, device-to-device, bfloat16 bits in
+ * point-major layout (channels innermost):
+ *   X  (n+2)^2 x 16 (9 used),  H1 (n+3)^2 x 32,  H2 (nc+3)^2 x 32,
+ *   D3 (nc+3)^2 x 16 (8 used), D2 (nc+3)^2 x 32, D1 (n+2)^2 x 32,
+ * with point (i, j) at j * (side) + i.  *bytes receives the size. */
+enum { BMG_NET_X = 0, BMG_NET_H1 = 1, BMG_NET_H2 = 2, BMG_NET_D3 = 3, BMG_NET_D2 = 4, BMG_NET_D1 = 5 };
+bmg_status bmg_net_export(bmg_net *net, int what, void *dst, size_t *bytes);
+
+/* One training sample: h must have been set up with BMG_INTERP_LEARNED,
+ * learned_levels = 1 and this network on the level's operator (n >= 7), and
+ * nothing run on `net` since.  r0: n x n (device).  Runs the two-grid cycle,
+ * its adjoint (coarse solves by V(nu1,nu2)-cycles of h from level 1 until
+ * the relative residual is <= inner_tol or inner_max cycles), and the
+ * network's backward pass, which adds to the gradient sum.  loss (host)
+ * receives ||r3||^2 / ||r0||^2; dCi (device, nullable) a copy of dL/dCi in
+ * the layout of the level's weight planes (bmg_export of BMG_FIELD_CI). */
+bmg_status bmg_net_twogrid(bmg_net *net, bmg_solver *h, const double *r0, double inner_tol, int inner_max,
+                           double *loss, double *dCi);
+
+/* The fallback rule of the learned interpolation: both handles (set up on the
+ * same operator, `learned` with BMG_INTERP_LEARNED, `boxmg` with the
+ * operator-induced weights) run two probe V-cycles from x; the one whose
+ * measured reduction factor rho = (r_2 / r_0)^(1/2) is smaller (the learned
+ * one on a tie) continues from its own iterate with bmg_solve.  used (host)
+ * receives BMG_INTERP_LEARNED or BMG_INTERP_BOXMG, rho (host, 2 entries) the
+ * probe factors of the learned and the BoxMG hierarchy; info counts the
+ * winner's probe cycles too. */
+bmg_status bmg_solve_select(bmg_solver *learned, bmg_solver *boxmg, const double *rhs, double *x, double tol,
+                            bmg_info *info, int *used, double *rho);
 
 #ifdef __cplusplus
 }

@@ -325,14 +325,17 @@ def twogrid_dense_loss(O, W, S, SW, NW, Ci, r0) -> float:
 # -------------------------------------------------------------------- Adam
 def adam(theta, m, v, grad, step: int, lr: float, beta1: float = 0.9, beta2: float = 0.999,
          eps: float = 1e-8):
-    """One Adam update in FP32 (Kingma and Ba, Algorithm 1); step counts from 1."""
+    """One Adam update (Kingma and Ba, Algorithm 1; step counts from 1) in FP32
+    arithmetic, every constant taken as its FP32 value; the bias corrections
+    1 - beta^step are formed in FP64 from those values and rounded once."""
     f = np.float32
     theta, m, v, grad = (np.asarray(a, dtype=f) for a in (theta, m, v, grad))
-    m = f(beta1) * m + f(1.0 - beta1) * grad
-    v = f(beta2) * v + f(1.0 - beta2) * (grad * grad)
-    c1 = f(1.0 - beta1 ** step)
-    c2 = f(1.0 - beta2 ** step)
+    b1, b2, lr32, eps32 = f(beta1), f(beta2), f(lr), f(eps)
+    m = b1 * m + (f(1.0) - b1) * grad
+    v = b2 * v + (f(1.0) - b2) * (grad * grad)
+    c1 = f(1.0 - float(b1) ** step)
+    c2 = f(1.0 - float(b2) ** step)
     mh = m / c1
     vh = v / c2
-    theta = theta - f(lr) * mh / (np.sqrt(vh) + f(eps))
+    theta = theta - (lr32 * mh) / (np.sqrt(vh) + eps32)
     return theta.astype(f), m.astype(f), v.astype(f)

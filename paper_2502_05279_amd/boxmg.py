@@ -14,13 +14,18 @@ import torch
 
 from . import build as _build
 
-__all__ = ["BoxMGError", "Options", "Solver", "discretize", "lib", "FIELDS", "STEPS",
+__all__ = ["BoxMGError", "Options", "Solver", "Batch", "Net", "discretize", "lib", "FIELDS", "STEPS",
+           "tile_rows_set", "tile_rows_get", "solve_select", "NET_PARAMS", "NET_ARRAYS",
+           "BMG_INTERP_BOXMG", "BMG_INTERP_LEARNED",
            "TRACE", "BMG_FP64", "BMG_FP32_IR", "BMG_KERNELS_BASIC", "BMG_KERNELS_FUSED"]
 
 BMG_OK, BMG_EINVAL, BMG_EBREAKDOWN, BMG_ENOCONV, BMG_EDIVERGED, BMG_EDEVICE, BMG_EWORKSPACE = \
     0, -1, -2, -3, -4, -5, -6
 BMG_FP64, BMG_FP32_IR = 0, 1
 BMG_KERNELS_BASIC, BMG_KERNELS_FUSED = 0, 1
+BMG_INTERP_BOXMG, BMG_INTERP_LEARNED = 0, 1
+NET_PARAMS = 14184
+NET_ARRAYS = {"X": 0, "H1": 1, "H2": 2, "D3": 3, "D2": 4, "D1": 5}
 
 FIELDS = {"u": 0, "b": 1, "r": 2, "O": 3, "W": 4, "S": 5, "SW": 6, "NW": 7, "Ci": 8, "LD": 9,
           "xlo": 10,
@@ -33,7 +38,8 @@ TRACE = {"smooth": 0, "pre": 1, "post": 2, "resnorm": 3}
 class Options(C.Structure):
     _fields_ = [("nu1", C.c_int), ("nu2", C.c_int), ("max_cycles", C.c_int),
                 ("precision", C.c_int), ("kernels", C.c_int), ("check_every", C.c_int),
-                ("refine_factor", C.c_int), ("tile_rows", C.c_int), ("reserved", C.c_int * 8)]
+                ("refine_factor", C.c_int), ("tile_rows", C.c_int), ("interp", C.c_int),
+                ("learned_levels", C.c_int), ("net", C.c_void_p), ("reserved", C.c_int * 4)]
 
 
 class Info(C.Structure):
@@ -77,6 +83,28 @@ def lib():
             "bmg_step": ([vp, i, i, i, i], i),
             "bmg_trace_enable": ([vp, i, i, i], i),
             "bmg_trace_read": ([vp, C.POINTER(i), C.POINTER(d)], i),
+            "bmg_tile_rows_set": ([i, i], i),
+            "bmg_tile_rows_get": ([i, C.POINTER(i)], i),
+            "bmg_batch_workspace_bytes": ([i, C.POINTER(i), C.POINTER(Options), C.POINTER(sz)], i),
+            "bmg_batch_setup": ([C.POINTER(vp), i, C.POINTER(i), C.POINTER(vp), C.POINTER(Options),
+                                 vp, sz, vp], i),
+            "bmg_batch_solve": ([vp, C.POINTER(vp), C.POINTER(vp), d, C.POINTER(i), C.POINTER(d)], i),
+            "bmg_batch_history": ([vp, i, C.POINTER(d), i, C.POINTER(i)], i),
+            "bmg_batch_info": ([vp, C.POINTER(i), C.POINTER(i)], i),
+            "bmg_batch_destroy": ([vp], i),
+            "bmg_net_workspace_bytes": ([i, i, C.POINTER(sz)], i),
+            "bmg_net_create": ([C.POINTER(vp), i, i, vp, vp, sz, vp], i),
+            "bmg_net_set_params": ([vp, vp], i),
+            "bmg_net_get_params": ([vp, vp], i),
+            "bmg_net_destroy": ([vp], i),
+            "bmg_net_forward": ([vp, i, i, vp, vp, vp, vp, vp, vp, i, sz], i),
+            "bmg_net_backward": ([vp, vp, i, sz], i),
+            "bmg_net_get_grad": ([vp, vp], i),
+            "bmg_net_zero_grad": ([vp], i),
+            "bmg_net_adam": ([vp, C.c_float, C.c_float, C.c_float, C.c_float, d], i),
+            "bmg_net_export": ([vp, i, vp, C.POINTER(sz)], i),
+            "bmg_net_twogrid": ([vp, vp, vp, d, i, C.POINTER(d), vp], i),
+            "bmg_solve_select": ([vp, vp, vp, vp, d, C.POINTER(Info), C.POINTER(i), C.POINTER(d)], i),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -110,7 +138,10 @@ def default_options(**kw) -> Options:
     for k, v in kw.items():
         if not hasattr(o, k):
             raise TypeError(f"unknown option {k}")
-        setattr(o, k, int(v))
+        if k == "net":
+            o.net = None if v is None else (v.handle if isinstance(v, Net) else int(v))
+        else:
+            setattr(o, k, int(v))
     return o
 
 
@@ -135,7 +166,7 @@ def discretize(k: torch.Tensor, f: torch.Tensor):
 class Solver:
     """BoxMG hierarchy of a ``[n][n][K]`` stencil (K = 5 or 9) on the GPU."""
 
-    def __init__(self, stencil: torch.Tensor, **options):
+    def __init__(self, stencil: torch.Tensor, workspace: torch.Tensor | None = None, **options):
         n, n2, K = stencil.shape
         if n != n2:
             raise ValueError("stencil must be [n][n][K]")
@@ -144,7 +175,10 @@ class Solver:
         need = C.c_size_t(0)
         _check(lib().bmg_workspace_bytes(n, K, C.byref(self.options), C.byref(need)),
                "bmg_workspace_bytes")
-        self.workspace = torch.empty(need.value, dtype=torch.uint8, device=stencil.device)
+        if workspace is not None and workspace.numel() >= need.value:
+            self.workspace = workspace
+        else:
+            self.workspace = torch.empty(need.value, dtype=torch.uint8, device=stencil.device)
         h = C.c_void_p(None)
         _check(lib().bmg_setup(C.byref(h), _ptr(stencil), n, K, C.byref(self.options),
                                self.workspace.data_ptr(), need.value, _stream()), "bmg_setup")
@@ -229,3 +263,188 @@ class Solver:
         n, ms = C.c_int(0), C.c_double(0.0)
         _check(lib().bmg_trace_read(self._h, C.byref(n), C.byref(ms)), "bmg_trace_read")
         return n.value, ms.value
+
+
+def tile_rows_set(n: int, rows: int) -> None:
+    """Rows per tile of the fused passes on levels of size n (0 = default)."""
+    _check(lib().bmg_tile_rows_set(n, rows), "bmg_tile_rows_set")
+
+
+def tile_rows_get(n: int) -> int:
+    r = C.c_int(0)
+    _check(lib().bmg_tile_rows_get(n, C.byref(r)), "bmg_tile_rows_get")
+    return r.value
+
+
+class Batch:
+    """Independent problems of uneven sizes solved together (FP32 V-cycles in
+    double-FP64 refinement, one persistent launch per group of steps)."""
+
+    def __init__(self, stencils: list, **options):
+        self.n = [int(s.shape[0]) for s in stencils]
+        self.nprob = len(stencils)
+        self.options = default_options(**options)
+        nn = (C.c_int * self.nprob)(*self.n)
+        need = C.c_size_t(0)
+        _check(lib().bmg_batch_workspace_bytes(self.nprob, nn, C.byref(self.options),
+                                               C.byref(need)), "bmg_batch_workspace_bytes")
+        dev = stencils[0].device
+        self.workspace = torch.empty(need.value, dtype=torch.uint8, device=dev)
+        ptrs = (C.c_void_p * self.nprob)(*[_ptr(s) for s in stencils])
+        h = C.c_void_p(None)
+        _check(lib().bmg_batch_setup(C.byref(h), self.nprob, nn, ptrs, C.byref(self.options),
+                                     self.workspace.data_ptr(), need.value, _stream()),
+               "bmg_batch_setup")
+        self._h = h
+        self.device = dev
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().bmg_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, rhs: list, x: list | None = None, tol: float = 1e-10,
+              raise_on_noconv: bool = True):
+        """Returns ``(x, steps, rel_res, status)``."""
+        if x is None:
+            x = [torch.zeros_like(r) for r in rhs]
+        rp = (C.c_void_p * self.nprob)(*[_ptr(r) for r in rhs])
+        xp = (C.c_void_p * self.nprob)(*[_ptr(v) for v in x])
+        steps = (C.c_int * self.nprob)()
+        rel = (C.c_double * self.nprob)()
+        st = lib().bmg_batch_solve(self._h, rp, xp, float(tol), steps, rel)
+        if st not in (BMG_OK, BMG_ENOCONV) or (st == BMG_ENOCONV and raise_on_noconv):
+            _check(st, "bmg_batch_solve")
+        return x, list(steps), list(rel), st
+
+    def history(self, p: int):
+        cap = self.options.max_cycles + 2
+        buf = (C.c_double * cap)()
+        cnt = C.c_int(0)
+        _check(lib().bmg_batch_history(self._h, p, buf, cap, C.byref(cnt)), "bmg_batch_history")
+        return [buf[t] for t in range(cnt.value)]
+
+    def info(self):
+        nb, g = C.c_int(0), C.c_int(0)
+        _check(lib().bmg_batch_info(self._h, C.byref(nb), C.byref(g)), "bmg_batch_info")
+        return {"workgroups": nb.value, "graph": bool(g.value)}
+
+
+class Net:
+    """Learned-interpolation network on the GPU (parameters, Adam state and
+    activation buffers in one workspace)."""
+
+    def __init__(self, params, max_n: int, train: bool = True, device="cuda:0"):
+        import numpy as np
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+        if p.size != NET_PARAMS:
+            raise ValueError(f"expected {NET_PARAMS} parameters")
+        need = C.c_size_t(0)
+        _check(lib().bmg_net_workspace_bytes(max_n, int(train), C.byref(need)), "bmg_net_workspace_bytes")
+        self.workspace = torch.empty(need.value, dtype=torch.uint8, device=device)
+        h = C.c_void_p(None)
+        _check(lib().bmg_net_create(C.byref(h), max_n, int(train), p.ctypes.data, self.workspace.data_ptr(),
+                                    need.value, _stream()), "bmg_net_create")
+        self._h = h
+        self.max_n = max_n
+        self.device = torch.device(device)
+
+    @property
+    def handle(self) -> int:
+        return self._h.value
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().bmg_net_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params) -> None:
+        import numpy as np
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+        _check(lib().bmg_net_set_params(self._h, p.ctypes.data), "bmg_net_set_params")
+
+    def params(self):
+        import numpy as np
+        p = np.zeros(NET_PARAMS, dtype=np.float32)
+        _check(lib().bmg_net_get_params(self._h, p.ctypes.data), "bmg_net_get_params")
+        return p
+
+    def forward(self, O, W, S, SW=None, NW=None) -> torch.Tensor:
+        """Weight planes (8, nc+2, nc+2) of a level given as padded planes."""
+        n = O.shape[0] - 2
+        nc = (n - 1) // 2
+        Ci = torch.zeros((8, nc + 2, nc + 2), dtype=torch.float64, device=O.device)
+        _check(lib().bmg_net_forward(self._h, n, n + 2, _ptr(O), _ptr(W), _ptr(S), _ptr(SW), _ptr(NW),
+                                     _ptr(Ci), nc + 2, (nc + 2) * (nc + 2)), "bmg_net_forward")
+        return Ci
+
+    def backward(self, dCi: torch.Tensor) -> None:
+        nc = dCi.shape[1] - 2
+        _check(lib().bmg_net_backward(self._h, _ptr(dCi), nc + 2, (nc + 2) * (nc + 2)), "bmg_net_backward")
+
+    def grad(self):
+        import numpy as np
+        g = np.zeros(NET_PARAMS)
+        _check(lib().bmg_net_get_grad(self._h, g.ctypes.data), "bmg_net_get_grad")
+        return g
+
+    def zero_grad(self) -> None:
+        _check(lib().bmg_net_zero_grad(self._h), "bmg_net_zero_grad")
+
+    def adam(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8,
+             scale: float = 1.0) -> None:
+        _check(lib().bmg_net_adam(self._h, lr, beta1, beta2, eps, scale), "bmg_net_adam")
+
+    def export(self, what: str) -> torch.Tensor:
+        """An activation or gradient array as bfloat16 bits (int16 tensor,
+        points x channels)."""
+        nbytes = C.c_size_t(0)
+        _check(lib().bmg_net_export(self._h, NET_ARRAYS[what], None, C.byref(nbytes)), "bmg_net_export")
+        out = torch.empty(nbytes.value // 2, dtype=torch.int16, device=self.device)
+        _check(lib().bmg_net_export(self._h, NET_ARRAYS[what], out.data_ptr(), C.byref(nbytes)),
+               "bmg_net_export")
+        return out
+
+    def twogrid(self, solver: "Solver", r0: torch.Tensor, inner_tol: float = 1e-8, inner_max: int = 30,
+                want_grad_planes: bool = False):
+        """One training sample; returns (loss, dL/dCi or None)."""
+        loss = C.c_double(0.0)
+        d = None
+        if want_grad_planes:
+            nc = solver.level_n(1)
+            d = torch.zeros((8, nc + 2, nc + 2), dtype=torch.float64, device=r0.device)
+        _check(lib().bmg_net_twogrid(self._h, solver._h, _ptr(r0), float(inner_tol), int(inner_max),
+                                     C.byref(loss), _ptr(d) if d is not None else None), "bmg_net_twogrid")
+        return loss.value, d
+
+
+def solve_select(learned: Solver, boxmg: Solver, rhs: torch.Tensor, x: torch.Tensor | None = None,
+                 tol: float = 1e-10, raise_on_noconv: bool = True):
+    """Probe both hierarchies for two cycles and finish with the faster one;
+    returns (x, info, used, (rho_learned, rho_boxmg))."""
+    if x is None:
+        x = torch.zeros_like(rhs)
+    cap = max(learned.options.max_cycles, boxmg.options.max_cycles) + 2
+    hist = (C.c_double * cap)()
+    info = Info(0, 0.0, 0.0, C.cast(hist, C.POINTER(C.c_double)))
+    used = C.c_int(0)
+    rho = (C.c_double * 2)()
+    st = lib().bmg_solve_select(learned._h, boxmg._h, _ptr(rhs), _ptr(x), float(tol), C.byref(info),
+                                C.byref(used), rho)
+    if st not in (BMG_OK, BMG_ENOCONV) or (st == BMG_ENOCONV and raise_on_noconv):
+        _check(st, "bmg_solve_select")
+    out = {"cycles": info.cycles, "rel_res": info.rel_res, "rho": info.rho,
+           "history": [hist[t] for t in range(max(info.cycles - 2, 0))], "status": st}
+    return x, out, used.value, (rho[0], rho[1])

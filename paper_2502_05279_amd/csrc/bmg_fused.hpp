@@ -93,17 +93,23 @@ __device__ __forceinline__ T res_lds(const T *su, const T *sW, const T *sSW, con
 // tile; u_c = 0 there.  Window: rows e-2NU-2 .. e+1 (RW rows) at step e.  All
 // global data of step e+2 (rows e+2, e+3 and the weights of its restriction
 // row) is requested before step e computes, so the loads overlap the compute.
+// LDS of one pre/post tile (ring rows RU, nine-point rings only if NINE)
 template <typename T, bool NINE, int NU>
-__global__ __launch_bounds__(FW) void k_pre(Lev<T> L, T *__restrict__ uout, Wts<T> C, Lev<T> Cl,
-                                             TileGeo G, const int *stop)
+struct TileLds {
+    static constexpr int RW = 2 * NU + 4;
+    static constexpr int RU = RW <= 8 ? 8 : 16;
+    T su[RU * FW], sW[RU * FW], sx[4 * FW];
+    T sSW[NINE ? RU * FW : 1], sNW[NINE ? RU * FW : 1];
+};
+
+template <typename T, bool NINE, int NU>
+__device__ __forceinline__ void pre_tile(const Lev<T> &L, T *__restrict__ uout, const Wts<T> &C,
+                                         const Lev<T> &Cl, const TileGeo &G, int tid,
+                                         TileLds<T, NINE, NU> &S)
 {
-    if (stopped(stop)) return;
-    const int tid = tile_id(G.ntiles);
-    if (tid < 0) return;
     constexpr int RW = 2 * NU + 4;                 // window rows
     constexpr int RU = RW <= 8 ? 8 : 16;           // LDS ring rows (power of two)
-    __shared__ T su[RU * FW], sW[RU * FW], sr[4 * FW];
-    __shared__ T sSW[NINE ? RU * FW : 1], sNW[NINE ? RU * FW : 1];
+    T *su = S.su, *sW = S.sW, *sr = S.sx, *sSW = S.sSW, *sNW = S.sNW;
 
     const int n = L.n, ld = L.ld, lane = threadIdx.x, nc = Cl.n;
     const int useful = FW - 2 * G.hx;
@@ -243,6 +249,17 @@ __global__ __launch_bounds__(FW) void k_pre(Lev<T> L, T *__restrict__ uout, Wts<
     }
 }
 
+template <typename T, bool NINE, int NU>
+__global__ __launch_bounds__(FW) void k_pre(Lev<T> L, T *__restrict__ uout, Wts<T> C, Lev<T> Cl,
+                                             TileGeo G, const int *stop)
+{
+    if (stopped(stop)) return;
+    const int tid = tile_id(G.ntiles);
+    if (tid < 0) return;
+    __shared__ TileLds<T, NINE, NU> S;
+    pre_tile<T, NINE, NU>(L, uout, C, Cl, G, tid, S);
+}
+
 // ---------------------------------------------------------- post pass
 // u_out = GS^NU(u_in + P e_c).  With NORM (FP64 fine level) also the
 // per-tile sum of squares of the accurate residual b - A u_out over the owned
@@ -250,17 +267,14 @@ __global__ __launch_bounds__(FW) void k_pre(Lev<T> L, T *__restrict__ uout, Wts<
 // step e+2 (rows, coarse row, interpolation weights) is requested while step
 // e computes.
 template <typename T, bool NINE, int NU, bool NORM>
-__global__ __launch_bounds__(FW) void k_post(Lev<T> L, T *__restrict__ uout, Wts<T> C, const T *__restrict__ ec,
-                                              TileGeo G, double *__restrict__ part, const int *stop)
+__device__ __forceinline__ void post_tile(const Lev<T> &L, T *__restrict__ uout, const Wts<T> &C,
+                                          const T *__restrict__ ec, const TileGeo &G, int tid,
+                                          double *__restrict__ part, TileLds<T, NINE, NU> &S)
 {
-    if (stopped(stop)) return;
-    const int tid = tile_id(G.ntiles);
-    if (tid < 0) return;
     static_assert(NU <= 2, "post pass supports up to two sweeps");
     constexpr int RW = 2 * NU + 4;
     constexpr int RU = RW <= 8 ? 8 : 16;
-    __shared__ T su[RU * FW], sW[RU * FW], sec[4 * FW];
-    __shared__ T sSW[NINE ? RU * FW : 1], sNW[NINE ? RU * FW : 1];
+    T *su = S.su, *sW = S.sW, *sec = S.sx, *sSW = S.sSW, *sNW = S.sNW;
 
     const int n = L.n, ld = L.ld, lane = threadIdx.x, ldc = C.ld, nc = (n - 1) >> 1;
     const int useful = FW - 2 * G.hx;
@@ -457,6 +471,17 @@ __global__ __launch_bounds__(FW) void k_post(Lev<T> L, T *__restrict__ uout, Wts
     }
 }
 
+template <typename T, bool NINE, int NU, bool NORM>
+__global__ __launch_bounds__(FW) void k_post(Lev<T> L, T *__restrict__ uout, Wts<T> C, const T *__restrict__ ec,
+                                              TileGeo G, double *__restrict__ part, const int *stop)
+{
+    if (stopped(stop)) return;
+    const int tid = tile_id(G.ntiles);
+    if (tid < 0) return;
+    __shared__ TileLds<T, NINE, NU> S;
+    post_tile<T, NINE, NU, NORM>(L, uout, C, ec, G, tid, part, S);
+}
+
 }  // namespace bmg
 
 namespace bmg {
@@ -536,12 +561,27 @@ __device__ __forceinline__ void small_residual(const Lev<T> &L, const T *u, cons
     }
 }
 
-template <typename T, bool NINE0>
-__global__ __launch_bounds__(SMALL_THREADS) void k_small_vcycle(SmallH<T> H, const int *stop)
+// LDS elements the small sub-cycle of H needs (u and b of every level, r of
+// the first), with the offsets filled in.
+template <typename T>
+__host__ __device__ inline int small_layout(SmallH<T> &H)
 {
-    if (stopped(stop)) return;
-    extern __shared__ unsigned char smem_raw[];
-    T *sm = reinterpret_cast<T *>(smem_raw);
+    int off = 0;
+    for (int k = 0; k < H.nl; ++k) {
+        const int p = H.L[k].n + 2;
+        H.off_u[k] = off;
+        off += p * p;
+        H.off_b[k] = off;
+        off += p * p;
+    }
+    H.off_r = off;
+    off += (H.L[0].n + 2) * (H.L[0].n + 2);
+    return off;
+}
+
+template <typename T, bool NINE0>
+__device__ void small_vcycle_body(const SmallH<T> &H, T *sm)
+{
     const int nl = H.nl, last = nl - 1;
     // fetch b of the first level, zero every iterate and the coarser b
     for (int l = 0; l < nl; ++l) {
@@ -647,6 +687,14 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_small_vcycle(SmallH<T> H, con
             L.u[(size_t)j * L.ld + i] = u[j * p + i];
         }
     }
+}
+
+template <typename T, bool NINE0>
+__global__ __launch_bounds__(SMALL_THREADS) void k_small_vcycle(SmallH<T> H, const int *stop)
+{
+    if (stopped(stop)) return;
+    extern __shared__ unsigned char smem_raw[];
+    small_vcycle_body<T, NINE0>(H, reinterpret_cast<T *>(smem_raw));
 }
 
 }  // namespace bmg

@@ -1,0 +1,102 @@
+// Internal declarations shared by the translation units of the library: the
+// solver handle, limits, error reporting and launch helpers.
+#pragma once
+
+#include "bmg.h"
+#include "bmg_fused.hpp"
+
+#include <vector>
+
+using namespace bmg;
+
+namespace bmgi {
+
+constexpr int MAXL = 20;
+constexpr int NPART = 8192;      // partial sums of a norm (>= fused tiles)
+constexpr int NPART_ROWS = 1024; // partial sums of the row-parallel reductions
+constexpr size_t ALIGN = 256;
+constexpr int MAX_TRACE = 65536;
+
+// Records a one-line description for bmg_last_error() and returns s.
+bmg_status fail(bmg_status s, const char *fmt, ...);
+
+// Interpolation weights of level L from the network (learned interpolation).
+bmg_status net_level_weights(bmg_net *net, const Lev<double> &L, bool nine, const Wts<double> &C, void *stream);
+
+// FP64 V-cycles of the handle from level l (right-hand side L[l].b, iterate
+// L[l].u from zero) until ||b - A u|| / ||b|| <= tol (accurate residual) or
+// maxc cycles; *cycles receives the count.  Synchronises the stream.
+bmg_status solve_level(bmg_solver *h, int l, double tol, int maxc, int *cycles);
+
+}  // namespace bmgi
+
+#define HIPCHK(call)                                                                    \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return bmgi::fail(BMG_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));    \
+    } while (0)
+
+#define LAUNCHCHK()                                                                     \
+    do {                                                                                \
+        hipError_t e_ = hipGetLastError();                                              \
+        if (e_ != hipSuccess)                                                           \
+            return bmgi::fail(BMG_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e_)); \
+    } while (0)
+
+namespace bmgi {
+
+inline bool valid_n(int n) { return n >= 3 && n < (1 << 16) && ((n + 1) & n) == 0; }
+inline int pitch_of(int n) { return ((n + 2) + 15) & ~15; }
+
+inline dim3 grid2(int nx, int ny, dim3 blk) { return dim3((nx + blk.x - 1) / blk.x, (ny + blk.y - 1) / blk.y); }
+
+}  // namespace bmgi
+
+using bmgi::MAXL;
+
+struct bmg_solver {
+    int n = 0, kind = 5, nlev = 0;
+    bmg_options opt{};
+    hipStream_t st = nullptr;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    Lev<double> L[MAXL];
+    Wts<double> C[MAXL];
+    bool nine[MAXL];
+    bool f32 = false;
+    Lev<float> L32[MAXL];
+    Wts<float> C32[MAXL];
+    double *ualt[MAXL];         // second iterate buffer of each level (fused passes)
+    float *ualt32[MAXL];
+    int norm_parts = 0;         // partial sums left by the last fused norm
+    double *B0 = nullptr;       // fine right-hand side during refinement
+    double *XH = nullptr;       // double-FP64 iterate, high part
+    double *XL = nullptr;       // double-FP64 iterate, low part
+    double *LD = nullptr;       // coarsest factor: 81 L + 9 D
+    int *flags = nullptr;       // validation / breakdown bits
+    double *part = nullptr;     // NPART partial sums
+    double *scal = nullptr;     // scalars (see enum below)
+    double *hist = nullptr;     // residual history on the device
+    int *count = nullptr;       // entries in hist
+    int *stop = nullptr;        // stop code of the running solve
+    int hist_cap = 0;
+    // kernel timing
+    int tr_class = -1, tr_level = -1;
+    std::vector<hipEvent_t> tr_ev;
+    int tr_used = 0;
+};
+
+namespace bmgi {
+// Rows per tile of a fused pass on a level of size n: the handle's option, the
+// autotuned table (bmg_tile_rows_set), else a measured default.
+int tile_rows_for(const bmg_solver *h, int n);
+TileGeo tile_geo(int n, int hx, int ht);
+}  // namespace bmgi
+
+
+#define TRY(x)                          \
+    do {                                \
+        bmg_status s_ = (x);            \
+        if (s_ != BMG_OK) return s_;    \
+    } while (0)

@@ -54,7 +54,7 @@ __device__ __forceinline__ bool stopped(const int *stop) { return stop && *stop;
 // coupling = -(mean of the two cells sharing the grid edge), centre = minus the
 // sum of the four couplings (before the boundary couplings are zeroed),
 // right-hand side h^2 f.  Output [n][n][5] = S, W, O, E, N.
-__global__ void k_discretize(const double *__restrict__ k, const double *__restrict__ f,
+static __global__ void k_discretize(const double *__restrict__ k, const double *__restrict__ f,
                              int n, double h2, double *__restrict__ st,
                              double *__restrict__ rhs)
 {
@@ -89,7 +89,7 @@ __device__ __forceinline__ bool asym(double a, double b)
 }
 
 // [n][n][K] user stencil -> compact level-0 planes, with validation.
-__global__ void k_import_stencil(const double *__restrict__ st, int K, Lev<double> L,
+static __global__ void k_import_stencil(const double *__restrict__ st, int K, Lev<double> L,
                                  int *__restrict__ flags)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x + 1;
@@ -171,7 +171,7 @@ __device__ __forceinline__ void lump_row(double a[9])
 // Edge weights: x-edge X(I,J) = (2I-1, 2J) for I <= nc+1, J <= nc collapses the
 // lumped stencil along y; y-edge Y(I,J) = (2I, 2J-1) for I <= nc, J <= nc+1
 // collapses along x.
-__global__ void k_weights_edges(Lev<double> F, Wts<double> C, int nc, int *__restrict__ flags)
+static __global__ void k_weights_edges(Lev<double> F, Wts<double> C, int nc, int *__restrict__ flags)
 {
     const int I = blockIdx.x * blockDim.x + threadIdx.x + 1;
     const int J = blockIdx.y * blockDim.y + threadIdx.y + 1;
@@ -201,7 +201,7 @@ __global__ void k_weights_edges(Lev<double> F, Wts<double> C, int nc, int *__res
 
 // Cell-centre weights at Z(I,J) = (2I-1, 2J-1), I, J <= nc+1, from the lumped
 // stencil and the neighbouring edge weights.
-__global__ void k_weights_corners(Lev<double> F, Wts<double> C, int nc, int *__restrict__ flags)
+static __global__ void k_weights_corners(Lev<double> F, Wts<double> C, int nc, int *__restrict__ flags)
 {
     const int I = blockIdx.x * blockDim.x + threadIdx.x + 1;
     const int J = blockIdx.y * blockDim.y + threadIdx.y + 1;
@@ -242,7 +242,7 @@ __device__ __forceinline__ double basis_weight(const Wts<double> &C, int KI, int
 // the fine 3x3 patch of (2I,2J) (rows south to north, west to east inside a
 // row), q over p's neighbours SW..NE inside the support of basis IJ+d; both
 // sums start from zero.  Couplings to ring coarse points are zero.
-__global__ void k_rap(Lev<double> F, Wts<double> C, Lev<double> Cl)
+static __global__ void k_rap(Lev<double> F, Wts<double> C, Lev<double> Cl)
 {
     const int I = blockIdx.x * blockDim.x + threadIdx.x + 1;
     const int J = blockIdx.y * blockDim.y + threadIdx.y + 1;
@@ -293,7 +293,7 @@ __global__ void k_rap(Lev<double> F, Wts<double> C, Lev<double> Cl)
 // Dense matrix in the unknown order k = (i-1) + 3(j-1), then the
 // square-root-free Cholesky: w_k = L_jk D_k, D_j = A_jj - sum L_jk w_k,
 // L_ij = (A_ij - sum L_ik w_k) / D_j (sums over increasing k).
-__global__ void k_coarse_factor(Lev<double> Cl, double *__restrict__ LD, int *__restrict__ flags)
+static __global__ void k_coarse_factor(Lev<double> Cl, double *__restrict__ LD, int *__restrict__ flags)
 {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
     double A[81], Lm[81], D[9], w[9];
@@ -333,7 +333,7 @@ __global__ void k_coarse_factor(Lev<double> Cl, double *__restrict__ LD, int *__
 // and solution are level arrays of precision T (FP32 hierarchy: widened to
 // FP64 for the solve and rounded back).
 template <typename T>
-__global__ void k_coarse_solve(Lev<T> Cl, const double *__restrict__ LD, const int *stop)
+static __global__ void k_coarse_solve(Lev<T> Cl, const double *__restrict__ LD, const int *stop)
 {
     if (stopped(stop)) return;
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
@@ -377,7 +377,7 @@ __device__ __forceinline__ T gs_point(const Lev<T> &L, size_t p)
 }
 
 template <typename T, bool NINE>
-__global__ void k_gs_colour(Lev<T> L, int colour, const int *stop)
+static __global__ void k_gs_colour(Lev<T> L, int colour, const int *stop)
 {
     if (stopped(stop)) return;
     const int i = ((colour & 1) ? 1 : 2) + 2 * (int)(blockIdx.x * blockDim.x + threadIdx.x);
@@ -406,7 +406,7 @@ __device__ __forceinline__ T residual_point(const Lev<T> &L, const T *u, size_t 
 }
 
 template <typename T, bool NINE>
-__global__ void k_residual(Lev<T> L, const int *stop)
+static __global__ void k_residual(Lev<T> L, const int *stop)
 {
     if (stopped(stop)) return;
     const int i = 1 + blockIdx.x * blockDim.x + threadIdx.x;
@@ -418,7 +418,7 @@ __global__ void k_residual(Lev<T> L, const int *stop)
 
 // b_c(I,J) = P^T r in the term order of Fig. restrict_kernel; u_c = 0.
 template <typename T>
-__global__ void k_restrict(const T *__restrict__ r, int ldf, Wts<T> C, Lev<T> Cl, const int *stop)
+static __global__ void k_restrict(const T *__restrict__ r, int ldf, Wts<T> C, Lev<T> Cl, const int *stop)
 {
     if (stopped(stop)) return;
     const int I = 1 + blockIdx.x * blockDim.x + threadIdx.x;
@@ -462,7 +462,7 @@ __device__ __forceinline__ T interp_point(const Wts<T> &C, const T *ec, int i, i
 }
 
 template <typename T>
-__global__ void k_interp_add(Lev<T> L, Wts<T> C, const T *__restrict__ ec, const int *stop)
+static __global__ void k_interp_add(Lev<T> L, Wts<T> C, const T *__restrict__ ec, const int *stop)
 {
     if (stopped(stop)) return;
     const int i = 1 + blockIdx.x * blockDim.x + threadIdx.x;
@@ -494,7 +494,7 @@ __device__ __forceinline__ double block_sum(double v)
 // Per-block partial sums of squares of the residual (r_mode = 1: recompute
 // b - A u; 0: of the array x itself) over the interior, grid-stride over rows.
 template <typename T, bool NINE, bool RES>
-__global__ void k_sumsq_partial(Lev<T> L, const T *__restrict__ x, double *__restrict__ part,
+static __global__ void k_sumsq_partial(Lev<T> L, const T *__restrict__ x, double *__restrict__ part,
                                 const int *stop)
 {
     if (stopped(stop)) return;
@@ -516,7 +516,7 @@ __global__ void k_sumsq_partial(Lev<T> L, const T *__restrict__ x, double *__res
 // and raises *stop: 1 once rel <= tol, 2 if rel is not finite or exceeds
 // 1e3 times the initial relative residual bnorm[1], 3 when maxc entries exist,
 // 4 once rel <= refine (refine > 0): the solve switches to refinement.
-__global__ void k_sumsq_final(const double *__restrict__ part, int np, double *__restrict__ out,
+static __global__ void k_sumsq_final(const double *__restrict__ part, int np, double *__restrict__ out,
                               double *hist, int *count, int *stop, const double *bnorm,
                               double tol, int maxc, double refine)
 {
@@ -544,7 +544,7 @@ __global__ void k_sumsq_final(const double *__restrict__ part, int np, double *_
 // ---------------------------------------------------- layout conversions
 // [n][n] user array <-> padded level array.
 template <typename TI, typename TO>
-__global__ void k_pack_in(const TI *__restrict__ src, int n, TO *__restrict__ dst, int ld)
+static __global__ void k_pack_in(const TI *__restrict__ src, int n, TO *__restrict__ dst, int ld)
 {
     const int i = 1 + blockIdx.x * blockDim.x + threadIdx.x;
     const int j = 1 + blockIdx.y * blockDim.y + threadIdx.y;
@@ -553,7 +553,7 @@ __global__ void k_pack_in(const TI *__restrict__ src, int n, TO *__restrict__ ds
 }
 
 template <typename TI, typename TO>
-__global__ void k_pack_out(const TI *__restrict__ src, int ld, int n, TO *__restrict__ dst)
+static __global__ void k_pack_out(const TI *__restrict__ src, int ld, int n, TO *__restrict__ dst)
 {
     const int i = 1 + blockIdx.x * blockDim.x + threadIdx.x;
     const int j = 1 + blockIdx.y * blockDim.y + threadIdx.y;
@@ -562,7 +562,7 @@ __global__ void k_pack_out(const TI *__restrict__ src, int ld, int n, TO *__rest
 }
 
 // Rounded copy of a padded array (the FP32 hierarchy from the FP64 set-up).
-__global__ void k_round_f32(const double *__restrict__ src, float *__restrict__ dst, size_t count)
+static __global__ void k_round_f32(const double *__restrict__ src, float *__restrict__ dst, size_t count)
 {
     for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < count;
          t += (size_t)gridDim.x * blockDim.x)
@@ -571,7 +571,7 @@ __global__ void k_round_f32(const double *__restrict__ src, float *__restrict__ 
 
 // -------------------------------------------- FP64 iterative refinement
 // Per-block max |r| over the interior of the FP64 level-0 residual.
-__global__ void k_absmax_partial(Lev<double> L, double *__restrict__ part, const int *stop)
+static __global__ void k_absmax_partial(Lev<double> L, double *__restrict__ part, const int *stop)
 {
     if (stopped(stop)) return;
     __shared__ double sm[16];
@@ -588,7 +588,7 @@ __global__ void k_absmax_partial(Lev<double> L, double *__restrict__ part, const
     }
 }
 
-__global__ void k_absmax_final(const double *__restrict__ part, int np, double *__restrict__ out,
+static __global__ void k_absmax_final(const double *__restrict__ part, int np, double *__restrict__ out,
                                const int *stop)
 {
     if (stopped(stop)) return;
@@ -600,7 +600,7 @@ __global__ void k_absmax_final(const double *__restrict__ part, int np, double *
 
 // s = the smallest power of two >= ||r||_inf (1 if r = 0); the FP32 right-hand
 // side is fl32(r / s) (an exact scaling, then one rounding) and u32 = 0.
-__global__ void k_ir_scale(Lev<double> L, Lev<float> F, const double *__restrict__ rmax,
+static __global__ void k_ir_scale(Lev<double> L, Lev<float> F, const double *__restrict__ rmax,
                            double *__restrict__ scale, const int *stop)
 {
     if (stopped(stop)) return;
@@ -633,7 +633,7 @@ __device__ __forceinline__ void two_sum(double a, double b, double &s, double &e
 // MODE 0: sum of squares only; 1: also r -> rout; 2: also r -> L.b and 0 -> L.u
 // (the next refinement cycle starts from zero on the right-hand side r).
 template <bool NINE, int MODE>
-__global__ void k_resid_dd(Lev<double> L, const double *__restrict__ B, const double *__restrict__ XH,
+static __global__ void k_resid_dd(Lev<double> L, const double *__restrict__ B, const double *__restrict__ XH,
                            const double *__restrict__ XL, double *__restrict__ rout,
                            double *__restrict__ part, const int *stop)
 {
@@ -691,7 +691,7 @@ __global__ void k_resid_dd(Lev<double> L, const double *__restrict__ B, const do
 // (XH, XL) += d in double-FP64 with d = L.u (FP64 inner cycle) or
 // d = scale * (double)U32 (FP32 inner cycle): TwoSum, add the low part,
 // renormalise with Dekker's fast TwoSum.
-__global__ void k_dd_update(Lev<double> L, double *__restrict__ XH, double *__restrict__ XL,
+static __global__ void k_dd_update(Lev<double> L, double *__restrict__ XH, double *__restrict__ XL,
                             const float *__restrict__ U32, const double *__restrict__ scale,
                             const int *stop)
 {

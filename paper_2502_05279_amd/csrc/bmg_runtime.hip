@@ -3,8 +3,7 @@
 //
 // One level hierarchy lives in the caller's workspace; nothing here calls
 // hipMalloc.  Every launch goes to the handle's stream.
-#include "bmg.h"
-#include "bmg_fused.hpp"
+#include "bmg_internal.hpp"
 
 #include <math.h>
 #include <stdarg.h>
@@ -17,15 +16,9 @@
 #include <utility>
 #include <vector>
 
-using namespace bmg;
+using namespace bmgi;
 
-namespace {
-
-constexpr int MAXL = 20;
-constexpr int NPART = 8192;      // partial sums of a norm (>= fused tiles)
-constexpr int NPART_ROWS = 1024; // partial sums of the row-parallel reductions
-constexpr size_t ALIGN = 256;
-constexpr int MAX_TRACE = 65536;
+namespace bmgi {
 
 thread_local char g_err[512];
 
@@ -38,58 +31,52 @@ bmg_status fail(bmg_status s, const char *fmt, ...)
     return s;
 }
 
-#define HIPCHK(call)                                                                    \
-    do {                                                                                \
-        hipError_t e_ = (call);                                                         \
-        if (e_ != hipSuccess)                                                           \
-            return fail(BMG_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));    \
-    } while (0)
+// Tile rows chosen by the autotuner, per level size n = 2^m - 1 (0 = unset).
+static int g_tile_rows[17];
 
-#define LAUNCHCHK()                                                                     \
-    do {                                                                                \
-        hipError_t e_ = hipGetLastError();                                              \
-        if (e_ != hipSuccess)                                                           \
-            return fail(BMG_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e_)); \
-    } while (0)
+int tile_rows_for(const bmg_solver *h, int n)
+{
+    if (h && h->opt.tile_rows > 0) return h->opt.tile_rows;
+    int m = 0;
+    while ((1 << m) < n + 1 && m < 16) ++m;
+    if (g_tile_rows[m] > 0) return g_tile_rows[m];
+    // measured defaults: enough tiles to fill the chip against the warm-up rows
+    // each tile re-reads
+    if (n >= 4095) return 128;
+    if (n >= 2047) return 64;
+    if (n >= 1023) return 16;
+    return 8;
+}
 
-bool valid_n(int n) { return n >= 3 && n < (1 << 16) && ((n + 1) & n) == 0; }
-int pitch_of(int n) { return ((n + 2) + 15) & ~15; }
+TileGeo tile_geo(int n, int hx, int ht)
+{
+    TileGeo g;
+    g.hx = hx;
+    g.ht = std::max(2, std::min(ht, (n + 2) & ~1));
+    const int useful = FW - 2 * hx;
+    g.tiles_x = (n + useful - 1) / useful;
+    g.ntiles = g.tiles_x * ((n + g.ht - 1) / g.ht);
+    return g;
+}
 
-dim3 grid2(int nx, int ny, dim3 blk) { return dim3((nx + blk.x - 1) / blk.x, (ny + blk.y - 1) / blk.y); }
+}  // namespace bmgi
 
-}  // namespace
+extern "C" bmg_status bmg_tile_rows_set(int n, int rows)
+{
+    if (!valid_n(n)) return fail(BMG_EINVAL, "n=%d is not 2^m-1", n);
+    if (rows < 0 || (rows & 1) || rows > 65536) return fail(BMG_EINVAL, "rows=%d must be even, 0 = default", rows);
+    int m = 0;
+    while ((1 << m) < n + 1) ++m;
+    g_tile_rows[m] = rows;
+    return BMG_OK;
+}
 
-struct bmg_solver {
-    int n = 0, kind = 5, nlev = 0;
-    bmg_options opt{};
-    hipStream_t st = nullptr;
-    char *ws = nullptr;
-    size_t ws_bytes = 0;
-    Lev<double> L[MAXL];
-    Wts<double> C[MAXL];
-    bool nine[MAXL];
-    bool f32 = false;
-    Lev<float> L32[MAXL];
-    Wts<float> C32[MAXL];
-    double *ualt[MAXL];         // second iterate buffer of each level (fused passes)
-    float *ualt32[MAXL];
-    int norm_parts = 0;         // partial sums left by the last fused norm
-    double *B0 = nullptr;       // fine right-hand side during refinement
-    double *XH = nullptr;       // double-FP64 iterate, high part
-    double *XL = nullptr;       // double-FP64 iterate, low part
-    double *LD = nullptr;       // coarsest factor: 81 L + 9 D
-    int *flags = nullptr;       // validation / breakdown bits
-    double *part = nullptr;     // NPART partial sums
-    double *scal = nullptr;     // scalars (see enum below)
-    double *hist = nullptr;     // residual history on the device
-    int *count = nullptr;       // entries in hist
-    int *stop = nullptr;        // stop code of the running solve
-    int hist_cap = 0;
-    // kernel timing
-    int tr_class = -1, tr_level = -1;
-    std::vector<hipEvent_t> tr_ev;
-    int tr_used = 0;
-};
+extern "C" bmg_status bmg_tile_rows_get(int n, int *rows)
+{
+    if (!valid_n(n) || !rows) return fail(BMG_EINVAL, "bad arguments");
+    *rows = tile_rows_for(nullptr, n);
+    return BMG_OK;
+}
 
 namespace {
 
@@ -207,6 +194,10 @@ bmg_status check_options(const bmg_options &o)
         return fail(BMG_EINVAL, "refine_factor=%d must be >= 0", o.refine_factor);
     if (o.tile_rows < 0 || (o.tile_rows & 1) || o.tile_rows > 65536)
         return fail(BMG_EINVAL, "tile_rows=%d must be even and in [0, 65536]", o.tile_rows);
+    if (o.interp != BMG_INTERP_BOXMG && o.interp != BMG_INTERP_LEARNED)
+        return fail(BMG_EINVAL, "unknown interpolation %d", o.interp);
+    if (o.interp == BMG_INTERP_LEARNED && !o.net) return fail(BMG_EINVAL, "learned interpolation without a network");
+    if (o.learned_levels < 0) return fail(BMG_EINVAL, "learned_levels=%d must be >= 0", o.learned_levels);
     return BMG_OK;
 }
 
@@ -301,11 +292,6 @@ const Wts<double> &wts<double>(const bmg_solver *h, int l) { return h->C[l]; }
 template <>
 const Wts<float> &wts<float>(const bmg_solver *h, int l) { return h->C32[l]; }
 
-#define TRY(x)                          \
-    do {                                \
-        bmg_status s_ = (x);            \
-        if (s_ != BMG_OK) return s_;    \
-    } while (0)
 
 // V(nu1,nu2) from level l down to the coarsest direct solve and back.
 template <typename T>
@@ -338,28 +324,7 @@ double *&ualt<double>(bmg_solver *h, int l) { return h->ualt[l]; }
 template <>
 float *&ualt<float>(bmg_solver *h, int l) { return h->ualt32[l]; }
 
-// Rows per tile of a fused pass: the caller's choice, else by level size (a
-// measured trade-off between enough tiles to fill the chip and the warm-up
-// rows every tile re-reads).
-int level_tile_rows(const bmg_solver *h, int n)
-{
-    if (h->opt.tile_rows > 0) return h->opt.tile_rows;
-    if (n >= 4095) return 128;
-    if (n >= 2047) return 64;
-    if (n >= 1023) return 16;
-    return 8;
-}
-
-TileGeo tile_geo(int n, int hx, int ht)
-{
-    TileGeo g;
-    g.hx = hx;
-    g.ht = std::max(2, std::min(ht, (n + 2) & ~1));
-    const int useful = FW - 2 * hx;
-    g.tiles_x = (n + useful - 1) / useful;
-    g.ntiles = g.tiles_x * ((n + g.ht - 1) / g.ht);
-    return g;
-}
+int level_tile_rows(const bmg_solver *h, int n) { return tile_rows_for(h, n); }
 
 dim3 tile_grid(const TileGeo &g) { return dim3(((g.ntiles + 7) / 8) * 8); }
 
@@ -446,18 +411,11 @@ bmg_status small_cycle(bmg_solver *h, int l, const int *stop)
     SmallH<T> S{};
     S.nl = h->nlev - l;
     if (S.nl > SMALL_MAXL) return fail(BMG_EINVAL, "too many small levels");
-    int off = 0;
     for (int k = 0; k < S.nl; ++k) {
         S.L[k] = lev<T>(h, l + k);
         if (k + 1 < S.nl) S.C[k] = wts<T>(h, l + k);
-        const int p = S.L[k].n + 2;
-        S.off_u[k] = off;
-        off += p * p;
-        S.off_b[k] = off;
-        off += p * p;
     }
-    S.off_r = off;
-    off += (S.L[0].n + 2) * (S.L[0].n + 2);
+    const int off = small_layout(S);
     S.LD = h->LD;
     S.nu1 = h->opt.nu1;
     S.nu2 = h->opt.nu2;
@@ -565,6 +523,40 @@ bmg_status pack_out(bmg_solver *h, const double *src, double *dst)
 
 }  // namespace
 
+namespace bmgi {
+
+bmg_status solve_level(bmg_solver *h, int l, double tol, int maxc, int *cycles)
+{
+    const Lev<double> &L = h->L[l];
+    *cycles = 0;
+    HIPCHK(hipMemsetAsync(L.u, 0, (size_t)(L.n + 2) * L.ld * sizeof(double), h->st));
+    TRY(sumsq<double>(h, L, false, false, L.b, S_TMP, false, 0.0, 0));
+    double v[S_NSCAL];
+    TRY(read_scalars(h, v, 0, 4));
+    if (v[S_TMP] == 0.0) return BMG_OK;
+    const double nb = sqrt(v[S_TMP]);
+    const int np = std::min(NPART_ROWS, L.n);
+    for (int k = 0; k < maxc; ++k) {
+        TRY(vcycle_from<double>(h, l, nullptr));
+        if (h->nine[l])
+            hipLaunchKernelGGL((k_resid_dd<true, 0>), dim3(np), dim3(256), 0, h->st, L, (const double *)L.b,
+                               (const double *)L.u, nullptr, nullptr, h->part, nullptr);
+        else
+            hipLaunchKernelGGL((k_resid_dd<false, 0>), dim3(np), dim3(256), 0, h->st, L, (const double *)L.b,
+                               (const double *)L.u, nullptr, nullptr, h->part, nullptr);
+        hipLaunchKernelGGL(k_sumsq_final, dim3(1), dim3(1024), 0, h->st, (const double *)h->part, np,
+                           h->scal + S_SUMSQ, nullptr, h->count, h->stop, (const double *)(h->scal + S_BNORM), 0.0,
+                           0, 0.0);
+        LAUNCHCHK();
+        TRY(read_scalars(h, v, 0, 4));
+        *cycles = k + 1;
+        if (!(sqrt(v[S_SUMSQ]) / nb > tol)) break;
+    }
+    return BMG_OK;
+}
+
+}  // namespace bmgi
+
 // ================================================================ C API
 extern "C" {
 
@@ -659,8 +651,14 @@ bmg_status bmg_setup(bmg_solver **out, const double *stencil, int n, int kind, c
     hipLaunchKernelGGL(k_import_stencil, grid2(n, n, B2), B2, 0, h->st, stencil, kind, h->L[0], h->flags);
     for (int l = 0; l + 1 < h->nlev; ++l) {
         const int nc = h->L[l + 1].n;
-        hipLaunchKernelGGL(k_weights_edges, grid2(nc + 1, nc + 1, B2), B2, 0, h->st, h->L[l], h->C[l], nc, h->flags);
-        hipLaunchKernelGGL(k_weights_corners, grid2(nc + 1, nc + 1, B2), B2, 0, h->st, h->L[l], h->C[l], nc, h->flags);
+        if (op.interp == BMG_INTERP_LEARNED && (op.learned_levels == 0 || l < op.learned_levels)) {
+            SCHK(net_level_weights(op.net, h->L[l], h->nine[l], h->C[l], h->st));
+        } else {
+            hipLaunchKernelGGL(k_weights_edges, grid2(nc + 1, nc + 1, B2), B2, 0, h->st, h->L[l], h->C[l], nc,
+                               h->flags);
+            hipLaunchKernelGGL(k_weights_corners, grid2(nc + 1, nc + 1, B2), B2, 0, h->st, h->L[l], h->C[l], nc,
+                               h->flags);
+        }
         hipLaunchKernelGGL(k_rap, grid2(nc, nc, dim3(32, 4)), dim3(32, 4), 0, h->st, h->L[l], h->C[l], h->L[l + 1]);
     }
     hipLaunchKernelGGL(k_coarse_factor, dim3(1), dim3(64), 0, h->st, h->L[h->nlev - 1], h->LD, h->flags);
@@ -903,6 +901,56 @@ bmg_status bmg_solve(bmg_solver *h, const double *rhs, double *x, double tol, bm
 }
 
 // --------------------------------------------------------- level access
+// Two FP64 V-cycles from x (tight n x n) on h; rho = (r2 / r0)^(1/2) with the
+// relative residuals before and after; the iterate goes to xout (tight).
+static bmg_status probe2(bmg_solver *h, const double *rhs, const double *x, double *xout, double *rho)
+{
+    const Lev<double> &L = h->L[0];
+    TRY(pack_in(h, rhs, L.b));
+    TRY(pack_in(h, x, L.u));
+    double v[S_NSCAL];
+    TRY(sumsq<double>(h, L, h->nine[0], false, L.b, S_TMP, false, 0.0, 0));
+    TRY(resnorm_dd(h, L.b, L.u, nullptr, 0, nullptr, S_SUMSQ, false, 0.0, 0, 0.0));
+    TRY(read_scalars(h, v, 0, 4));
+    const double r0 = v[S_SUMSQ];
+    TRY(cycle64(h, nullptr));
+    TRY(cycle64(h, nullptr));
+    TRY(resnorm_dd(h, L.b, L.u, nullptr, 0, nullptr, S_SUMSQ, false, 0.0, 0, 0.0));
+    TRY(read_scalars(h, v, 0, 4));
+    *rho = r0 > 0.0 ? sqrt(sqrt(v[S_SUMSQ] / r0)) : 0.0;
+    TRY(pack_out(h, L.u, xout));
+    return BMG_OK;
+}
+
+bmg_status bmg_solve_select(bmg_solver *learned, bmg_solver *boxmg, const double *rhs, double *x, double tol,
+                            bmg_info *info, int *used, double *rho)
+{
+    if (!learned || !boxmg || !rhs || !x || !used || !rho) return fail(BMG_EINVAL, "NULL argument");
+    if (learned->n != boxmg->n) return fail(BMG_EINVAL, "the two hierarchies have different sizes");
+    if (learned->opt.precision != BMG_FP64 || boxmg->opt.precision != BMG_FP64)
+        return fail(BMG_EINVAL, "the probe compares FP64 hierarchies");
+    if (learned->opt.interp != BMG_INTERP_LEARNED || boxmg->opt.interp != BMG_INTERP_BOXMG)
+        return fail(BMG_EINVAL, "expected a learned and an operator-induced hierarchy");
+    // the BoxMG probe reads x first and leaves its iterate in its XH buffer
+    // (tight n x n); the learned probe then overwrites x with its own
+    double *scratch = boxmg->XH;
+    TRY(probe2(boxmg, rhs, x, scratch, &rho[1]));
+    HIPCHK(hipStreamSynchronize(boxmg->st));
+    TRY(probe2(learned, rhs, x, x, &rho[0]));
+    bmg_solver *w = learned;
+    *used = BMG_INTERP_LEARNED;
+    if (rho[0] > rho[1]) {
+        w = boxmg;
+        *used = BMG_INTERP_BOXMG;
+        HIPCHK(hipMemcpyAsync(x, scratch, (size_t)boxmg->n * boxmg->n * sizeof(double), hipMemcpyDeviceToDevice,
+                              boxmg->st));
+        HIPCHK(hipStreamSynchronize(boxmg->st));
+    }
+    const bmg_status s = bmg_solve(w, rhs, x, tol, info);
+    if (info) info->cycles += 2;
+    return s;
+}
+
 bmg_status bmg_num_levels(const bmg_solver *h, int *nlev)
 {
     if (!h || !nlev) return fail(BMG_EINVAL, "NULL argument");

@@ -105,3 +105,26 @@ def test_status_strings(L):
     for s in range(-6, 1):
         assert L.bmg_status_string(s)
     assert L.bmg_status_string(-99) == b"unknown status"
+
+
+def test_batch_and_tuning_validation(L):
+    out = C.c_size_t(0)
+    ns = (C.c_int * 3)(127, 63, 100)
+    assert L.bmg_batch_workspace_bytes(3, ns, None, C.byref(out)) == boxmg.BMG_EINVAL
+    ns = (C.c_int * 2)(127, 3)
+    assert L.bmg_batch_workspace_bytes(2, ns, None, C.byref(out)) == boxmg.BMG_EINVAL
+    ns = (C.c_int * 2)(127, 63)
+    assert L.bmg_batch_workspace_bytes(2, ns, None, C.byref(out)) == boxmg.BMG_OK
+    assert out.value > 2 * boxmg.workspace_bytes(63)
+    o = boxmg.default_options(nu1=1)
+    assert L.bmg_batch_workspace_bytes(2, ns, C.byref(o), C.byref(out)) == boxmg.BMG_EINVAL
+    assert L.bmg_batch_solve(None, None, None, C.c_double(1e-10), None, None) == boxmg.BMG_EINVAL
+    assert L.bmg_batch_destroy(None) == boxmg.BMG_OK
+    # the tile-rows table
+    assert boxmg.tile_rows_get(4095) == 128
+    boxmg.tile_rows_set(4095, 32)
+    assert boxmg.tile_rows_get(4095) == 32
+    boxmg.tile_rows_set(4095, 0)
+    assert boxmg.tile_rows_get(4095) == 128
+    assert L.bmg_tile_rows_set(4095, 7) == boxmg.BMG_EINVAL
+    assert L.bmg_tile_rows_set(100, 8) == boxmg.BMG_EINVAL

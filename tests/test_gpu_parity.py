@@ -359,3 +359,33 @@ def test_cycle_variants_match_oracle(gpu, kernels, nu1, nu2):
     assert info["cycles"] == len(hist)
     same(host(x), u[1:-1, 1:-1], "solution")
     assert np.all(np.abs(np.array(info["history"]) - hist) <= 1e-12 * hist)
+
+
+# --------------------------------------------------------------- batched solves
+def test_batch_matches_single_problem_oracle(gpu):
+    """Problems of uneven sizes (7 .. 511, per-cell log-normal coefficients, as the
+    batched workload at small scale) solved together: every problem's solution
+    and step count equal the oracle's FP32-in-double-FP64 refinement bit for bit,
+    and a zero right-hand side gives zero after zero steps."""
+    probs = inputs.batch_512(count=9, m_lo=3, m_hi=9, seed=402)
+    sts, rhss, hs = [], [], []
+    for q in probs:
+        st, rhs = gpu_problem(q)
+        sts.append(st)
+        rhss.append(rhs)
+    rhss[3] = torch.zeros_like(rhss[3])
+    B = boxmg.Batch(sts, max_cycles=60)
+    x, steps, rel, status = B.solve(rhss, tol=1e-10)
+    assert status == boxmg.BMG_OK
+    for p, q in enumerate(probs):
+        H = ref.Hierarchy(host(sts[p]))
+        u, hist = H.solve_ir(ref.pad(host(rhss[p])), tol=1e-10, max_iter=60)
+        assert steps[p] == len(hist) - 1, (p, q.n)
+        same(host(x[p]), u[1:-1, 1:-1], f"problem {p} (n={q.n})")
+        if p != 3:
+            h = np.array(B.history(p))
+            assert np.all(np.abs(h - hist) <= 1e-12 * hist)
+            assert rel[p] <= 1e-10
+    assert steps[3] == 0 and not host(x[3]).any()
+    info = B.info()
+    assert info["workgroups"] >= 256

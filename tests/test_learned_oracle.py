@@ -297,7 +297,9 @@ def test_adam_first_step_closed_form():
     t1, m1, v1 = learned.adam(theta, z, z, g, 1, lr=1e-3)
     # after one step m_hat = g and v_hat = g^2: the step is lr * g / (|g| + eps)
     assert np.allclose(t1, theta - 1e-3 * g / (np.abs(g) + 1e-8), rtol=0, atol=2e-7)
-    assert np.allclose(m1, 0.1 * g, rtol=1e-6) and np.allclose(v1, 0.001 * g * g, rtol=1e-5)
+    # the constants enter as FP32 values: 1 - fl32(0.999) = 1.0000467e-3
+    b2 = float(np.float32(0.999))
+    assert np.allclose(m1, 0.1 * g, rtol=1e-6) and np.allclose(v1, (1.0 - b2) * g * g, rtol=1e-6)
     # a zero gradient leaves everything unchanged
     t2, m2, v2 = learned.adam(theta, z, z, z, 1, lr=1e-3)
     assert np.array_equal(t2, theta) and not m2.any() and not v2.any()
