@@ -135,7 +135,72 @@ def bench_batch(args):
                    "steps_max": max(steps), "steps_mean": sum(steps) / len(steps),
                    "max_rel_res": max(rel), "converged": status == 0,
                    "workgroups": info["workgroups"], "graph": info["graph"],
-                   "tile_rows": {str(k): v for k, v in tuned.items()}},
+                   "tile_rows": {str(k): v for k, v in tuned.items()},
+                   "tile_ms": {str(k): {str(r): round(t, 4) for r, t in v.items()}
+                               for k, v in autotune.LAST.items()}},
+    }
+    print(json.dumps(out))
+
+
+def bench_learned(args):
+    """Learned interpolation against BoxMG's on a 4095^2 field of contrast 1e6:
+    one step = BoxMG set-up, learned set-up (network on every level), two
+    probe cycles on each hierarchy and the solve to the tolerance with the one
+    whose probe factor is smaller.  BoxMG alone and the learned hierarchy
+    alone are timed beside it (reported in config)."""
+    import torch
+    from paper_2502_05279_amd import boxmg, inputs, learned
+
+    dev = torch.device("cuda:0")
+    params = learned.load_params(args.params or learned.DEFAULT_PARAMS)
+    p = inputs.learned_eval_4095(n=args.learned_n)
+    n = p.n
+    st, rhs = boxmg.discretize(torch.from_numpy(p.k).to(dev), torch.from_numpy(p.f).to(dev))
+    net = boxmg.Net(params, max_n=n, train=False)
+    opts = dict(max_cycles=args.max_cycles, check_every=16)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return out, time.perf_counter() - t0
+
+    def run_boxmg():
+        B = boxmg.Solver(st, **opts)
+        return B.solve(rhs, tol=args.tol, raise_on_noconv=False)
+
+    def run_learned():
+        L = boxmg.Solver(st, interp=boxmg.BMG_INTERP_LEARNED, net=net, **opts)
+        return L.solve(rhs, tol=args.tol, raise_on_noconv=False)
+
+    def run_select():
+        L = boxmg.Solver(st, interp=boxmg.BMG_INTERP_LEARNED, net=net, **opts)
+        B = boxmg.Solver(st, **opts)
+        return boxmg.solve_select(L, B, rhs, tol=args.tol, raise_on_noconv=False)
+
+    for _ in range(args.warmup):
+        run_select()
+    (_, ib), tb = timed(run_boxmg)
+    (_, il), tl = timed(run_learned)
+    times = []
+    for _ in range(args.steps):
+        (x, info, used, rho), ts = timed(run_select)
+        times.append(ts)
+    dt = float(np.mean(times))
+    out = {
+        "metric": f"fine DOF/s solved to {args.tol:g} rel. residual ({n}^2, contrast 1e6), learned "
+                  "interpolation with BoxMG fallback",
+        "value": n * n / dt, "unit": "DOF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 (network bf16/f32)", "data": "synthetic",
+        "config": {"workload": f"learned_eval_{n}", "n": n, "tol": args.tol,
+                   "used": "learned" if used == boxmg.BMG_INTERP_LEARNED else "boxmg",
+                   "probe_rho_learned": rho[0], "probe_rho_boxmg": rho[1],
+                   "cycles": info["cycles"], "final_rel_res": info["rel_res"],
+                   "boxmg_ms": tb * 1e3, "boxmg_cycles": ib["cycles"], "boxmg_rho": ib["rho"],
+                   "learned_ms": tl * 1e3, "learned_cycles": il["cycles"], "learned_rho": il["rho"],
+                   "learned_final_rel_res": il["rel_res"]},
     }
     print(json.dumps(out))
 
@@ -160,6 +225,8 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device (a kernel of known traffic, to "
                          "calibrate hardware byte counters) and print the achieved GB/s")
+    ap.add_argument("--params", default=None, help="learned_4095: network parameters (.npy)")
+    ap.add_argument("--learned-n", type=int, default=4095)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -176,6 +243,8 @@ def main():
     dev = torch.device("cuda:0")
     if args.workload == "batch_512":
         return bench_batch(args)
+    if args.workload == "learned_4095":
+        return bench_learned(args)
     if args.copy_probe:
         a = torch.ones(args.copy_probe << 17, dtype=torch.float64, device=dev)
         b = torch.empty_like(a)

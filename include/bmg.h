@@ -176,13 +176,16 @@ const char *bmg_last_error(void);
  *   BMG_F_COARSE_LD: the coarsest factor, 81 entries of L (row-major, unit
  *   lower triangular) followed by the 9 entries of D (level argument ignored);
  *   BMG_F_XLO: the low part of the last solve's double-FP64 iterate, level-0
- *   layout (zero if the solve never switched to refinement).
+ *   layout (zero if the solve never switched to refinement);
+ *   BMG_F_STENCIL (export only): the level's operator as bmg_setup reads it,
+ *   n_l x n_l x K with K = 5 (S, W, O, E, N) on a five-point level and K = 9
+ *   (SW, S, SE, W, O, E, NW, N, NE) otherwise.
  * The *32 fields are the FP32 hierarchy (precision BMG_FP32_IR only) and
  * transfer float data. */
 enum {
     BMG_F_U = 0, BMG_F_B = 1, BMG_F_R = 2,
     BMG_F_AO = 3, BMG_F_AW = 4, BMG_F_AS = 5, BMG_F_ASW = 6, BMG_F_ANW = 7,
-    BMG_F_CI = 8, BMG_F_COARSE_LD = 9, BMG_F_XLO = 10,
+    BMG_F_CI = 8, BMG_F_COARSE_LD = 9, BMG_F_XLO = 10, BMG_F_STENCIL = 11,
     BMG_F_U32 = 16, BMG_F_B32 = 17, BMG_F_R32 = 18,
     BMG_F_AO32 = 19, BMG_F_AW32 = 20, BMG_F_AS32 = 21, BMG_F_ASW32 = 22,
     BMG_F_ANW32 = 23, BMG_F_CI32 = 24
@@ -260,7 +263,10 @@ bmg_status bmg_batch_solve(bmg_batch *h, const double *const *rhs, double *const
  * hist[k] the one after step k; *count entries exist (up to cap copied). */
 bmg_status bmg_batch_history(bmg_batch *h, int p, double *hist, int cap, int *count);
 
-/* Workgroups of the persistent launch and whether it is replayed from a graph. */
+/* Workgroups of the persistent launch and how it is launched: graph_used = 1
+ * replayed from a HIP graph (one cooperative kernel node); 0 the runtime could
+ * not build that graph; 2 a replay ran without the grid barrier (detected by
+ * the kernel before any work) and direct cooperative launches took over. */
 bmg_status bmg_batch_info(const bmg_batch *h, int *nblocks, int *graph_used);
 bmg_status bmg_batch_destroy(bmg_batch *h);
 
@@ -337,7 +343,7 @@ bmg_status bmg_net_export(bmg_net *net, int what, void *dst, size_t *bytes);
  * the relative residual is <= inner_tol or inner_max cycles), and the
  * network's backward pass, which adds to the gradient sum.  loss (host)
  * receives ||r3||^2 / ||r0||^2; dCi (device, nullable) a copy of dL/dCi in
- * the layout of the level's weight planes (bmg_export of BMG_FIELD_CI). */
+ * the layout of the level's weight planes (bmg_export of BMG_F_CI). */
 bmg_status bmg_net_twogrid(bmg_net *net, bmg_solver *h, const double *r0, double inner_tol, int inner_max,
                            double *loss, double *dCi);
 

@@ -177,40 +177,57 @@ def output_mask(nc: int) -> np.ndarray:
     return m
 
 
-def backward(fw: dict, dCi: np.ndarray) -> dict:
-    """Gradients of a scalar with respect to the parameters, given its
-    gradient ``dCi`` with respect to the weight planes."""
-    p, rounding = fw["params"], fw["rounding"]
-    n, nc = fw["n"], fw["nc"]
-    X, H1, H2 = fw["X"], fw["H1"], fw["H2"]
-    g = {}
-    # conv3: y(Q) = b3 + sum_t H2(Q + t) W3[t], Q in [1, nc+1]^2
-    dY = grad_in(np.moveaxis(dCi[:, 1:, 1:], 0, -1) * output_mask(nc), rounding)
+def bwd_conv3(fw: dict, dY: np.ndarray):
+    """conv3, y(Q) = b3 + sum_t H2(Q + t) W3[t] for Q in [1, nc+1]^2: given
+    dL/dy (nc+1, nc+1, 8), returns (dW3, db3, dL/dH2 on [1, nc+1]^2)."""
+    p, nc, H2 = fw["params"], fw["nc"], fw["H2"]
     D3 = np.zeros((nc + 3, nc + 3, 8))
     D3[1:nc + 2, 1:nc + 2] = dY
-    g["b3"] = dY.sum(axis=(0, 1))
-    g["W3"] = np.stack([np.einsum("abi,abo->io", H2[1 + dy:nc + 2 + dy, 1 + dx:nc + 2 + dx], dY)
-                        for dx, dy in TAPS])
+    gW = np.stack([np.einsum("abi,abo->io", H2[1 + dy:nc + 2 + dy, 1 + dx:nc + 2 + dx], dY)
+                   for dx, dy in TAPS])
     dh2 = np.zeros((nc + 1, nc + 1, 32))
     for t, (dx, dy) in enumerate(TAPS):                           # dH2(P) += W3[t] dY(P - t)
         dh2 += D3[1 - dy:nc + 2 - dy, 1 - dx:nc + 2 - dx] @ p["W3"][t].T
-    live2 = (H2[1:nc + 2, 1:nc + 2] > 0) if rounding else (fw["z2"] > 0)
-    d2 = grad_in(dh2 * live2, rounding)
-    # conv2: z2(Q) = b2 + sum_t H1(2Q + t) W2[t]
-    g["b2"] = d2.sum(axis=(0, 1))
-    g["W2"] = np.stack([np.einsum("abi,abo->io",
-                                  H1[2 + dy:2 * (nc + 1) + dy + 1:2, 2 + dx:2 * (nc + 1) + dx + 1:2], d2)
-                        for dx, dy in TAPS])
+    return gW, dY.sum(axis=(0, 1)), dh2
+
+
+def bwd_conv2(fw: dict, d2: np.ndarray):
+    """conv2, z2(Q) = b2 + sum_t H1(2Q + t) W2[t]: given dL/dz2 (nc+1, nc+1,
+    32), returns (dW2, db2, dL/dH1 on the fine points [1, n]^2)."""
+    p, n, nc, H1 = fw["params"], fw["n"], fw["nc"], fw["H1"]
+    gW = np.stack([np.einsum("abi,abo->io",
+                             H1[2 + dy:2 * (nc + 1) + dy + 1:2, 2 + dx:2 * (nc + 1) + dx + 1:2], d2)
+                   for dx, dy in TAPS])
     dh1 = np.zeros((n + 3, n + 3, 32))
     for t, (dx, dy) in enumerate(TAPS):                           # scatter to the fine points 2Q + t
         dh1[2 + dy:2 * (nc + 1) + dy + 1:2, 2 + dx:2 * (nc + 1) + dx + 1:2] += d2 @ p["W2"][t].T
-    dh1 = dh1[1:n + 1, 1:n + 1]
-    live1 = (H1[1:n + 1, 1:n + 1] > 0) if rounding else (fw["z1"] > 0)
+    return gW, d2.sum(axis=(0, 1)), dh1[1:n + 1, 1:n + 1]
+
+
+def bwd_conv1(fw: dict, d1: np.ndarray):
+    """conv1, z1(q) = b1 + sum_t X(q + t) W1[t]: given dL/dz1 (n, n, 32),
+    returns (dW1, db1)."""
+    n, X = fw["n"], fw["X"]
+    gW = np.stack([np.einsum("abi,abo->io", X[1 + dy:n + 1 + dy, 1 + dx:n + 1 + dx], d1)
+                   for dx, dy in TAPS])
+    return gW, d1.sum(axis=(0, 1))
+
+
+def backward(fw: dict, dCi: np.ndarray) -> dict:
+    """Gradients of a scalar with respect to the parameters, given its
+    gradient ``dCi`` with respect to the weight planes: the three layers in
+    reverse order, the gradient entering each rounded as specified and masked
+    by the ReLU (where the stored activation is non-zero)."""
+    rounding, n, nc = fw["rounding"], fw["n"], fw["nc"]
+    g = {}
+    dY = grad_in(np.moveaxis(dCi[:, 1:, 1:], 0, -1) * output_mask(nc), rounding)
+    g["W3"], g["b3"], dh2 = bwd_conv3(fw, dY)
+    live2 = (fw["H2"][1:nc + 2, 1:nc + 2] > 0) if rounding else (fw["z2"] > 0)
+    d2 = grad_in(dh2 * live2, rounding)
+    g["W2"], g["b2"], dh1 = bwd_conv2(fw, d2)
+    live1 = (fw["H1"][1:n + 1, 1:n + 1] > 0) if rounding else (fw["z1"] > 0)
     d1 = grad_in(dh1 * live1, rounding)
-    # conv1: z1(q) = b1 + sum_t X(q + t) W1[t]
-    g["b1"] = d1.sum(axis=(0, 1))
-    g["W1"] = np.stack([np.einsum("abi,abo->io", X[1 + dy:n + 1 + dy, 1 + dx:n + 1 + dx], d1)
-                        for dx, dy in TAPS])
+    g["W1"], g["b1"] = bwd_conv1(fw, d1)
     return {"grad": pack(g), "dY": dY, "d2": d2, "d1": d1, "dh2": dh2, "dh1": dh1}
 
 
@@ -243,7 +260,7 @@ def padded_stencil(O, W, S, SW, NW) -> np.ndarray:
 
 def coarse_solver(cO, cW, cS, cSW, cNW, tol: float, max_cycles: int, exact: bool):
     nc = cO.shape[0] - 2
-    if exact or nc < 7:
+    if exact:
         A = dense.matrix_from_compact(cO, cW, cS, cSW, cNW).toarray()
 
         def solve(rhs):

@@ -18,6 +18,9 @@ from . import boxmg, inputs
 
 DEFAULT_CANDIDATES = (8, 16, 32, 64, 128)
 
+# timings (ms per pre+post pass pair, by tile height) of the last tune() call
+LAST: dict = {}
+
 
 def _cache_path() -> str:
     return os.environ.get("BMG_TUNE_CACHE",
@@ -63,6 +66,7 @@ def tune(sizes=(127, 255, 511, 1023, 2047), precision: int = boxmg.BMG_FP64,
         key = f"{_arch()}:{'fp32' if precision == boxmg.BMG_FP32_IR else 'fp64'}:{n}"
         if key in cache:
             out[n] = int(cache[key]["rows"])
+            LAST[n] = cache[key]["ms"]
             boxmg.tile_rows_set(n, out[n])
             continue
         timings = {}
@@ -78,6 +82,7 @@ def tune(sizes=(127, 255, 511, 1023, 2047), precision: int = boxmg.BMG_FP64,
         best = min(timings, key=timings.get)
         out[n] = best
         cache[key] = {"rows": best, "ms": timings}
+        LAST[n] = timings
         boxmg.tile_rows_set(n, best)
         if verbose:
             print(f"tile rows n={n}: " + ", ".join(f"{r}:{t * 1e3:.0f}us" for r, t in timings.items())

@@ -28,7 +28,7 @@ NET_PARAMS = 14184
 NET_ARRAYS = {"X": 0, "H1": 1, "H2": 2, "D3": 3, "D2": 4, "D1": 5}
 
 FIELDS = {"u": 0, "b": 1, "r": 2, "O": 3, "W": 4, "S": 5, "SW": 6, "NW": 7, "Ci": 8, "LD": 9,
-          "xlo": 10,
+          "xlo": 10, "stencil": 11,
           "u32": 16, "b32": 17, "r32": 18, "O32": 19, "W32": 20, "S32": 21, "SW32": 22,
           "NW32": 23, "Ci32": 24}
 STEPS = {"smooth": 0, "residual": 1, "restrict": 2, "interp": 3, "coarse": 4, "pre": 5, "post": 6}
@@ -234,6 +234,9 @@ class Solver:
             return (90,), torch.float64
         if base == "xlo":
             return (self.n + 2, self.n + 2), torch.float64
+        if base == "stencil":
+            n = self.level_n(level)
+            return (n, n, 5 if (level == 0 and self.kind == 5) else 9), torch.float64
         if base == "Ci":
             nc = self.level_n(level + 1)
             return (8, nc + 2, nc + 2), dtype
@@ -333,7 +336,7 @@ class Batch:
     def info(self):
         nb, g = C.c_int(0), C.c_int(0)
         _check(lib().bmg_batch_info(self._h, C.byref(nb), C.byref(g)), "bmg_batch_info")
-        return {"workgroups": nb.value, "graph": bool(g.value)}
+        return {"workgroups": nb.value, "graph": {0: "not built", 1: "replayed", 2: "refused"}[g.value]}
 
 
 class Net:

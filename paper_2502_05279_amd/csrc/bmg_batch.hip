@@ -132,6 +132,12 @@ __global__ __launch_bounds__(BT) void k_batch(BArgs A, int mode, int steps)
     BProb *P = A.P;
     const int2 *items = A.items;
     const int nb = gridDim.x, bid = blockIdx.x;
+    // a launch that is not cooperative has no grid barrier: leave at once,
+    // before any barrier, and tell the host through the active count
+    if (!grid.is_valid()) {
+        if (bid == 0 && threadIdx.x == 0) *A.active = -1;
+        return;
+    }
 
     if (mode == MODE_INIT) {
         // pack the caller's arrays, x_lo = 0, and ||b||^2 by chunks
@@ -343,6 +349,7 @@ struct bmg_batch {
     bool graph_tried = false, graph_ok = false;
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
+    bool graph_refused = false;     // a replay ran without the grid barrier
     int graph_steps = 0;
     double graph_tol = -1.0;
 };
@@ -541,7 +548,7 @@ bmg_status bmg_batch_setup(bmg_batch **out, int nprob, const int *n, const doubl
 
 namespace {
 
-bmg_status batch_launch(bmg_batch *B, int mode, int steps, double tol)
+BArgs batch_args(const bmg_batch *B, double tol)
 {
     BArgs A;
     A.P = B->dP;
@@ -551,13 +558,21 @@ bmg_status batch_launch(bmg_batch *B, int mode, int steps, double tol)
     A.tol = tol;
     A.maxc = B->maxc;
     A.active = B->dactive;
+    return A;
+}
+
+bmg_status batch_launch(bmg_batch *B, int mode, int steps, double tol)
+{
+    BArgs A = batch_args(B, tol);
     void *args[] = {&A, &mode, &steps};
     HIPCHK(hipLaunchCooperativeKernel((const void *)k_batch, dim3(B->nblocks), dim3(BT), args, B->lds, B->st));
     return BMG_OK;
 }
 
-// The launch of `steps` refinement steps, captured once in a HIP graph and
-// replayed; direct launches if the runtime cannot capture it.
+// The launch of `steps` refinement steps as a HIP graph of one cooperative
+// kernel node, built once per (steps, tol) and replayed; direct cooperative
+// launches if the runtime cannot build it or runs the node without the grid
+// barrier (the kernel then reports active = -1 before doing any work).
 bmg_status batch_steps(bmg_batch *B, int steps, double tol)
 {
     if (!B->graph_tried || B->graph_steps != steps || B->graph_tol != tol) {
@@ -567,15 +582,28 @@ bmg_status batch_steps(bmg_batch *B, int steps, double tol)
         B->graph_ok = false;
         B->graph_steps = steps;
         B->graph_tol = tol;
-        if (hipStreamBeginCapture(B->st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
-            const bmg_status s = batch_launch(B, MODE_STEPS, steps, tol);
-            hipGraph_t g = nullptr;
-            const hipError_t e = hipStreamEndCapture(B->st, &g);
-            if (s == BMG_OK && e == hipSuccess && g &&
+        hipGraph_t g = nullptr;
+        if (!B->graph_refused && hipGraphCreate(&g, 0) == hipSuccess) {
+            BArgs A = batch_args(B, tol);
+            int mode = MODE_STEPS, st = steps;
+            void *args[] = {&A, &mode, &st};
+            hipKernelNodeParams p;
+            memset(&p, 0, sizeof p);
+            p.func = (void *)k_batch;
+            p.gridDim = dim3(B->nblocks);
+            p.blockDim = dim3(BT);
+            p.sharedMemBytes = B->lds;
+            p.kernelParams = args;
+            hipKernelNodeAttrValue v;
+            memset(&v, 0, sizeof v);
+            v.cooperative = 1;
+            hipGraphNode_t node = nullptr;
+            if (hipGraphAddKernelNode(&node, g, nullptr, 0, &p) == hipSuccess &&
+                hipGraphKernelNodeSetAttribute(node, hipKernelNodeAttributeCooperative, &v) == hipSuccess &&
                 hipGraphInstantiate(&B->exec, g, nullptr, nullptr, 0) == hipSuccess) {
                 B->graph = g;
                 B->graph_ok = true;
-            } else if (g) {
+            } else {
                 (void)hipGraphDestroy(g);
             }
         }
@@ -609,9 +637,21 @@ bmg_status bmg_batch_solve(bmg_batch *B, const double *const *rhs, double *const
     const int per_launch = 8;
     int active = 1;
     for (int done_steps = 0; active > 0 && done_steps <= B->maxc; done_steps += per_launch) {
+        const bool via_graph = B->graph_ok || !B->graph_tried;
         TRY(batch_steps(B, per_launch, tol));
         HIPCHK(hipMemcpyAsync(&active, B->dactive, sizeof(int), hipMemcpyDeviceToHost, B->st));
         HIPCHK(hipStreamSynchronize(B->st));
+        if (active < 0) {
+            if (!via_graph || !B->graph_ok) return fail(BMG_EDEVICE, "the persistent launch was not cooperative");
+            // the graph node ran without a grid barrier and did nothing: use
+            // direct launches from here on
+            B->graph_ok = false;
+            B->graph_refused = true;
+            TRY(batch_launch(B, MODE_STEPS, per_launch, tol));
+            HIPCHK(hipMemcpyAsync(&active, B->dactive, sizeof(int), hipMemcpyDeviceToHost, B->st));
+            HIPCHK(hipStreamSynchronize(B->st));
+            if (active < 0) return fail(BMG_EDEVICE, "the persistent launch was not cooperative");
+        }
     }
     TRY(batch_launch(B, MODE_FINISH, 0, tol));
     std::vector<BProb> hp(B->nprob);
@@ -648,7 +688,7 @@ bmg_status bmg_batch_info(const bmg_batch *B, int *nblocks, int *graph_used)
 {
     if (!B) return fail(BMG_EINVAL, "NULL handle");
     if (nblocks) *nblocks = B->nblocks;
-    if (graph_used) *graph_used = B->graph_ok ? 1 : 0;
+    if (graph_used) *graph_used = B->graph_ok ? 1 : (B->graph_refused ? 2 : 0);
     return BMG_OK;
 }
 

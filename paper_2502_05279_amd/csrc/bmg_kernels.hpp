@@ -511,8 +511,8 @@ static __global__ void k_sumsq_partial(Lev<T> L, const T *__restrict__ x, double
     if (threadIdx.x == 0) part[blockIdx.x] = acc;
 }
 
-// Final sum of the partials (fixed order) -> out[0].  With `hist` given, this
-// also records rel = sqrt(sum)/bnorm[0] into hist[*count], advances the count,
+// Final sum of the partials (fixed order) -> out[0].  With `hist` given (and
+// the solve not stopped), this also records rel = sqrt(sum)/bnorm[0] into hist[*count], advances the count,
 // and raises *stop: 1 once rel <= tol, 2 if rel is not finite or exceeds
 // 1e3 times the initial relative residual bnorm[1], 3 when maxc entries exist,
 // 4 once rel <= refine (refine > 0): the solve switches to refinement.
@@ -520,7 +520,7 @@ static __global__ void k_sumsq_final(const double *__restrict__ part, int np, do
                               double *hist, int *count, int *stop, const double *bnorm,
                               double tol, int maxc, double refine)
 {
-    if (stopped(stop)) return;
+    if (hist && stopped(stop)) return;   // a finished solve records nothing more
     double v = 0.0;
     for (int t = threadIdx.x; t < np; t += blockDim.x) v += part[t];
     v = block_sum(v);

@@ -36,7 +36,6 @@ constexpr int PKO1 = 0, PKO2 = PKO1 + PK1, PKO3 = PKO2 + PK2, PKO2T = PKO3 + PK3
 
 constexpr int WG_WAVES = 512;                       // waves of a weight-gradient launch
 constexpr int WG_SLOT = 9 * 32 * 32 + 32;           // partial of one wave (largest layer)
-constexpr int NVEC = 14;                            // fine-level vectors of a two-grid sample
 
 __device__ __forceinline__ bf16_t bf16_rne(float f)
 {
@@ -455,6 +454,7 @@ struct bmg_net {
     bf16_t *X = nullptr, *H1 = nullptr, *H2 = nullptr, *D3 = nullptr, *D2 = nullptr, *D1 = nullptr;
     float *part = nullptr;
     double *vec = nullptr;                            // two-grid vectors
+    size_t vec_cap = 0;                               // doubles in vec
     int steps = 0;
     int last_n = 0;                                   // level of the last forward pass
     bool last_nine = false;
@@ -473,6 +473,8 @@ size_t net_plan(bmg_net *h, int max_n, int train, char *base)
         return p;
     };
     const size_t n = max_n, nc = (max_n - 1) / 2;
+    // two-grid vectors: 12 of the fine level, then dL/dCi in the coarse weight layout
+    const size_t vec_cap = 12 * (n + 2) * pitch_of((int)n) + 8 * (nc + 2) * pitch_of((int)nc);
     float *P = (float *)take(NP * 4), *M = (float *)take(NP * 4), *V = (float *)take(NP * 4);
     double *G = (double *)take(NP * 8);
     uint2 *PK = (uint2 *)take((size_t)PK_TOTAL * 8);
@@ -487,12 +489,12 @@ size_t net_plan(bmg_net *h, int max_n, int train, char *base)
         D2 = (bf16_t *)take((nc + 3) * (nc + 3) * 32 * 2);
         D1 = (bf16_t *)take((n + 2) * (n + 2) * 32 * 2);
         part = (float *)take((size_t)WG_WAVES * WG_SLOT * 4);
-        vec = (double *)take((size_t)NVEC * (n + 2) * pitch_of((int)n) * 8);
+        vec = (double *)take(vec_cap * 8);
     }
     if (h) {
         h->P = P; h->M = M; h->V = V; h->G = G; h->PK = PK;
         h->X = X; h->H1 = H1; h->H2 = H2; h->D3 = D3; h->D2 = D2; h->D1 = D1;
-        h->part = part; h->vec = vec;
+        h->part = part; h->vec = vec; h->vec_cap = train ? vec_cap : 0;
     }
     return (off + ALIGN - 1) & ~(ALIGN - 1);
 }
@@ -832,8 +834,7 @@ bmg_status twogrid(bmg_net *net, bmg_solver *h, const double *r0, double inner_t
     // dL/dCi in the layout of the level's weight planes (after the vectors)
     Wts<double> dC = C;
     dC.p = net->vec + 12 * pl;
-    if (12 * pl + 8 * C.ps > (size_t)NVEC * (net->max_n + 2) * pitch_of(net->max_n))
-        return fail(BMG_EINVAL, "network workspace too small for this level");
+    if (12 * pl + 8 * C.ps > net->vec_cap) return fail(BMG_EINVAL, "network workspace too small for this level");
     HIPCHK(hipMemsetAsync(net->vec, 0, (12 * pl + 8 * C.ps) * sizeof(double), h->st));
     hipLaunchKernelGGL((k_pack_in<double, double>), grid2(n, n, dim3(64, 4)), dim3(64, 4), 0, h->st, r0, n, V[0],
                        F.ld);

@@ -814,6 +814,8 @@ bmg_status bmg_solve(bmg_solver *h, const double *rhs, double *x, double tol, bm
     if (!(tol >= 0.0)) return fail(BMG_EINVAL, "tol must be >= 0");
     const Lev<double> &L = h->L[0];
     const size_t pl0 = (size_t)(L.n + 2) * L.ld * sizeof(double);
+    // a new solve: no history, no stop code left from the last one
+    HIPCHK(hipMemsetAsync(h->count, 0, 2 * sizeof(int), h->st));
     // ||b|| and the initial residual; the iterate starts in L0.u (FP64) or XH
     TRY(pack_in(h, rhs, h->B0));
     TRY(pack_in(h, x, h->XH));
@@ -1012,8 +1014,43 @@ static bmg_status locate(bmg_solver *h, int level, int field, char **ptr, size_t
     return BMG_OK;
 }
 
+// The level operator in the input layout of bmg_setup.
+static __global__ void k_export_stencil(Lev<double> L, bool nine, double *__restrict__ st)
+{
+    const int i = 1 + blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = 1 + blockIdx.y * blockDim.y + threadIdx.y;
+    if (i > L.n || j > L.n) return;
+    const size_t ld = L.ld, p = (size_t)j * ld + i;
+    const size_t o = ((size_t)(j - 1) * L.n + (i - 1)) * (nine ? 9 : 5);
+    if (nine) {
+        st[o + 0] = L.SW[p];
+        st[o + 1] = L.S[p];
+        st[o + 2] = L.NW[p + 1 - ld];
+        st[o + 3] = L.W[p];
+        st[o + 4] = L.O[p];
+        st[o + 5] = L.W[p + 1];
+        st[o + 6] = L.NW[p];
+        st[o + 7] = L.S[p + ld];
+        st[o + 8] = L.SW[p + ld + 1];
+    } else {
+        st[o + 0] = L.S[p];
+        st[o + 1] = L.W[p];
+        st[o + 2] = L.O[p];
+        st[o + 3] = L.W[p + 1];
+        st[o + 4] = L.S[p + ld];
+    }
+}
+
 bmg_status bmg_export(bmg_solver *h, int level, int field, void *dst)
 {
+    if (field == BMG_F_STENCIL) {
+        if (!h || !dst) return fail(BMG_EINVAL, "NULL argument");
+        if (level < 0 || level >= h->nlev) return fail(BMG_EINVAL, "level %d out of range", level);
+        const Lev<double> &L = h->L[level];
+        hipLaunchKernelGGL(k_export_stencil, grid2(L.n, L.n, B2), B2, 0, h->st, L, h->nine[level], (double *)dst);
+        LAUNCHCHK();
+        return BMG_OK;
+    }
     char *p; size_t es, pitch, rows, width;
     TRY(locate(h, level, field, &p, &es, &pitch, &rows, &width));
     if (!dst) return fail(BMG_EINVAL, "dst is NULL");

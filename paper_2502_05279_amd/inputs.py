@@ -46,6 +46,7 @@ __all__ = [
     "net_init",
     "net_random",
     "residual_probe",
+    "learned_eval_4095",
 ]
 
 
@@ -189,3 +190,9 @@ def residual_probe(n: int, seed: int) -> np.ndarray:
     """Random initial residual r0 of a two-grid training sample, uniform[-1,1]
     on the n x n interior."""
     return np.random.default_rng(seed).uniform(-1.0, 1.0, size=(n, n))
+
+
+def learned_eval_4095(seed_k: int = 601, seed_f: int = 602, n: int = 4095, block: int = 16) -> Problem:
+    """Evaluation field of the learned interpolation: contrast 1e6 (log10 k
+    uniform in [-3, 3]) on blocks of the training fields' size."""
+    return jumping(n, block, -3.0, 3.0, seed_k, seed_f, f"learned_eval_{n}")

@@ -1,0 +1,322 @@
+"""Parity of the learned-interpolation kernels with the oracle (GPU).
+
+The network layers accumulate bfloat16 products in FP32 on the matrix cores,
+in an order the oracle does not reproduce, so each layer is checked on the
+GPU's own inputs against the oracle's exact (FP64) sum z: the GPU's FP32 sum
+lies within gamma_K * sum|terms| of z (K terms, unit roundoff 2^-23 to allow
+for any rounding mode), and a stored bfloat16 activation must lie between the
+roundings of the two ends of that interval (rounding is monotone).  At least
+99% of the stored values must equal the oracle's own rounding of z.  Every
+other step (input features, gradient packing, the two-grid cycle and its
+adjoint, Adam) is compared bit for bit or to 1e-12 where a norm enters.
+All calls go through the C-ABI (``boxmg`` binding)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import learned, ref
+from paper_2502_05279_amd import boxmg, inputs
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+U = 2.0 ** -23
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def gamma(k):
+    return k * U / (1.0 - k * U)
+
+
+def bf16_values(t, side, ch):
+    """int16 tensor of bfloat16 bits -> float64 (side, side, ch)."""
+    b = host(t).view(np.uint16).astype(np.uint32) << 16
+    return b.view(np.float32).astype(np.float64).reshape(side, side, ch)
+
+
+def rnd(z):
+    return learned.bf16(z).astype(np.float64)
+
+
+def check_interval(got, z, zabs, K, what, relu):
+    """got: the GPU's stored bf16 values; z, zabs: exact sum and sum of |terms|."""
+    e = gamma(K + 1) * zabs
+    f = (lambda v: rnd(np.maximum(v, 0.0))) if relu else rnd
+    lo, hi = f(z - e), f(z + e)
+    bad = (got < lo) | (got > hi)
+    assert not bad.any(), f"{what}: {bad.sum()} of {got.size} outside the FP32 bound; first at " \
+                          f"{np.argwhere(bad)[0]}: {got[bad][0]} not in [{lo[bad][0]}, {hi[bad][0]}]"
+    exact = np.mean(got == f(z))
+    assert exact > 0.99, f"{what}: only {exact:.4f} equal to the oracle's rounding"
+
+
+def level_planes(kind, n, seed):
+    """A level operator from a BoxMG hierarchy on the GPU: the fine level of an
+    n x n problem (5-point) or level 1 of a (2n+1)^2 problem (9-point)."""
+    m = n if kind == 5 else 2 * n + 1
+    p = inputs.jumping(m, max(2, (m + 1) // 16), -3.0, 3.0, seed, seed + 1)
+    st, rhs = boxmg.discretize(dev(p.k), dev(p.f))
+    S = boxmg.Solver(st)
+    lvl = 0 if kind == 5 else 1
+    planes = [S.export(lvl, nm) if (kind == 9 or nm in ("O", "W", "S")) else None
+              for nm in ("O", "W", "S", "SW", "NW")]
+    return planes, S, st
+
+
+CASES = [(5, 7, 11), (5, 31, 12), (9, 31, 13), (5, 127, 14), (9, 127, 15), (9, 255, 16)]
+
+
+def gpu_forward(net, planes):
+    Ci = net.forward(*planes)
+    n = planes[0].shape[0] - 2
+    nc = (n - 1) // 2
+    X = bf16_values(net.export("X"), n + 2, 16)
+    H1 = bf16_values(net.export("H1"), n + 3, 32)
+    H2 = bf16_values(net.export("H2"), nc + 3, 32)
+    return Ci, X, H1, H2
+
+
+@pytest.mark.parametrize("kind,n,seed", CASES)
+def test_net_forward_layers(gpu, kind, n, seed):
+    planes, _, _ = level_planes(kind, n, seed)
+    theta = inputs.net_random(seed)
+    net = boxmg.Net(theta, max_n=max(n, 7), train=True)
+    Ci, X, H1, H2 = gpu_forward(net, planes)
+    hp = [None if a is None else host(a) for a in planes]
+    nc = (n - 1) // 2
+    p = learned.rounded(learned.unpack(theta), True)
+    pa = {k: np.abs(v) for k, v in p.items()}
+    # input features: bit for bit, channels 9..15 and the ring zero
+    Xo = learned.features(*hp)
+    assert np.array_equal(X[:, :, :9], Xo) and not X[:, :, 9:].any()
+    fine = np.arange(1, n + 1)
+    cen = 2 * np.arange(1, nc + 2)
+    crs = np.arange(1, nc + 2)
+    # conv1 on the GPU's input
+    z1 = learned.conv(X[:, :, :9], p["W1"], p["b1"], fine, fine)
+    a1 = learned.conv(np.abs(X[:, :, :9]), pa["W1"], pa["b1"], fine, fine)
+    check_interval(H1[1:n + 1, 1:n + 1], z1, a1, 81, "H1", relu=True)
+    ring = H1.copy()
+    ring[1:n + 1, 1:n + 1] = 0
+    assert not ring.any(), "H1 ring"
+    # conv2 on the GPU's H1
+    z2 = learned.conv(H1, p["W2"], p["b2"], cen, cen)
+    a2 = learned.conv(np.abs(H1), pa["W2"], pa["b2"], cen, cen)
+    check_interval(H2[1:nc + 2, 1:nc + 2], z2, a2, 288, "H2", relu=True)
+    ring = H2.copy()
+    ring[1:nc + 2, 1:nc + 2] = 0
+    assert not ring.any(), "H2 ring"
+    # conv3 on the GPU's H2 -> the weight planes (FP32 values)
+    y = learned.conv(H2, p["W3"], p["b3"], crs, crs)
+    ay = learned.conv(np.abs(H2), pa["W3"], pa["b3"], crs, crs)
+    got = host(Ci)
+    want = np.zeros_like(got)
+    want[:, 1:, 1:] = np.moveaxis(y, -1, 0)
+    bound = np.zeros_like(got)
+    bound[:, 1:, 1:] = np.moveaxis(gamma(289) * ay + np.abs(y) * 2.0 ** -24, -1, 0)
+    live = np.zeros_like(got, dtype=bool)
+    live[:, 1:, 1:] = np.moveaxis(learned.output_mask(nc), -1, 0) > 0
+    assert np.all(np.abs(got - want)[live] <= bound[live]), "weight planes outside the FP32 bound"
+    assert not got[~live].any(), "missing F-points and the ring must be zero"
+    assert np.array_equal(got.astype(np.float32).astype(np.float64), got)
+
+
+@pytest.mark.parametrize("kind,n,seed", CASES)
+def test_net_backward_layers(gpu, kind, n, seed):
+    planes, _, _ = level_planes(kind, n, seed)
+    theta = inputs.net_random(seed + 100)
+    net = boxmg.Net(theta, max_n=max(n, 7), train=True)
+    Ci, X, H1, H2 = gpu_forward(net, planes)
+    nc = (n - 1) // 2
+    rng = np.random.default_rng(seed)
+    dCi = rng.standard_normal((8, nc + 2, nc + 2)) * 1e-2
+    net.zero_grad()
+    net.backward(dev(dCi))
+    D3 = bf16_values(net.export("D3"), nc + 3, 16)
+    D2 = bf16_values(net.export("D2"), nc + 3, 32)
+    D1 = bf16_values(net.export("D1"), n + 2, 32)
+    G = net.grad()
+    p = learned.rounded(learned.unpack(theta), True)
+    pa = {k: np.abs(v) for k, v in p.items()}
+    fw = {"params": p, "n": n, "nc": nc, "X": X[:, :, :9], "H1": H1, "H2": H2}
+    fa = {"params": pa, "n": n, "nc": nc, "X": np.abs(X[:, :, :9]), "H1": np.abs(H1), "H2": np.abs(H2)}
+    # dL/dy as the layer input: bit for bit
+    dY = rnd(np.moveaxis(dCi[:, 1:, 1:], 0, -1) * learned.output_mask(nc))
+    assert np.array_equal(D3[1:nc + 2, 1:nc + 2, :8], dY) and not D3[:, :, 8:].any()
+    # conv3: weights and the input gradient on the GPU's D3
+    gW3, gb3, dh2 = learned.bwd_conv3(fw, dY)
+    aW3, ab3, ah2 = learned.bwd_conv3(fa, np.abs(dY))
+    live2 = H2[1:nc + 2, 1:nc + 2] > 0
+    got = D2[1:nc + 2, 1:nc + 2]
+    check_interval(got[live2], dh2[live2], ah2[live2], 72, "D2", relu=False)
+    assert not got[~live2].any()
+    # conv2 on the GPU's D2
+    d2 = D2[1:nc + 2, 1:nc + 2]
+    gW2, gb2, dh1 = learned.bwd_conv2(fw, d2)
+    aW2, ab2, ah1 = learned.bwd_conv2(fa, np.abs(d2))
+    live1 = H1[1:n + 1, 1:n + 1] > 0
+    got = D1[1:n + 1, 1:n + 1]
+    check_interval(got[live1], dh1[live1], ah1[live1], 9 * 32, "D1", relu=False)
+    assert not got[~live1].any()
+    # conv1 on the GPU's D1
+    gW1, gb1 = learned.bwd_conv1(fw, D1[1:n + 1, 1:n + 1])
+    aW1, ab1 = learned.bwd_conv1(fa, np.abs(D1[1:n + 1, 1:n + 1]))
+    want = learned.pack({"W1": gW1, "b1": gb1, "W2": gW2, "b2": gb2, "W3": gW3, "b3": gb3})
+    absd = learned.pack({"W1": aW1, "b1": ab1, "W2": aW2, "b2": ab2, "W3": aW3, "b3": ab3})
+    K = (n + 2) ** 2
+    err = np.abs(G - want)
+    assert np.all(err <= gamma(K) * absd + 1e-300), f"parameter gradient: worst {np.max(err / (absd + 1e-300))}"
+
+
+def same_params(got, want, before, what):
+    """FP32 Adam: the device square root and division may round the update
+    term differently by one unit, so each parameter is allowed two units in the
+    last place of max(|theta_before|, |update|); at least 99% must agree bit for
+    bit."""
+    got = np.asarray(got, np.float32)
+    want = np.asarray(want, np.float32)
+    upd = np.abs(before.astype(np.float64) - want.astype(np.float64))
+    scale = np.maximum(np.abs(before.astype(np.float64)), upd).astype(np.float32)
+    tol = 2.0 * np.spacing(scale).astype(np.float64)
+    err = np.abs(got.astype(np.float64) - want.astype(np.float64))
+    bad = err > tol
+    for t in np.flatnonzero(bad)[:5]:
+        print(f"{what}: entry {t}: got {got[t]!r} want {want[t]!r} before {before[t]!r}")
+    assert not bad.any(), f"{what}: {bad.sum()} entries beyond two ulp of the update"
+    exact = np.mean(got == want)
+    assert exact >= 0.99, f"{what}: only {exact:.4f} bit for bit"
+    print(f"{what}: {np.sum(got != want)} of {got.size} entries not bit for bit")
+
+
+def test_adam_matches_oracle(gpu):
+    planes, _, _ = level_planes(5, 31, 21)
+    theta = inputs.net_random(21)
+    net = boxmg.Net(theta, max_n=31, train=True)
+    net.forward(*planes)
+    rng = np.random.default_rng(3)
+    dCi = dev(rng.standard_normal((8, 17, 17)))
+    net.zero_grad()
+    net.backward(dCi)
+    G1 = net.grad()
+    net.adam(1e-3, scale=0.5)
+    t1, m1, v1 = learned.adam(theta, np.zeros_like(theta), np.zeros_like(theta),
+                              (G1 * 0.5).astype(np.float32), 1, lr=1e-3)
+    net_t1 = net.params()
+    same_params(net_t1, t1, theta, "first step")
+    # second step: the moments carry over, the gradient sum was not cleared
+    net.backward(dCi)
+    G2 = net.grad()
+    net.adam(2e-3, beta1=0.8, beta2=0.99, eps=1e-6, scale=0.25)
+    t2, _, _ = learned.adam(net_t1, m1, v1, (G2 * 0.25).astype(np.float32), 2, lr=2e-3, beta1=0.8,
+                            beta2=0.99, eps=1e-6)
+    same_params(net.params(), t2, net_t1, "second step")
+
+
+@pytest.mark.parametrize("kind,n,seed", [(5, 7, 31), (5, 31, 32), (9, 31, 33), (5, 63, 34), (9, 127, 35)])
+def test_twogrid_matches_oracle(gpu, kind, n, seed):
+    planes, _, _ = level_planes(kind, n, seed)
+    # the level's operator as a [n][n][K] stencil for a training solver
+    hp = [None if a is None else host(a) for a in planes]
+    st9 = learned.stencil9(*hp)
+    st = dev(st9 if kind == 9 else st9[:, :, [1, 3, 4, 5, 7]])
+    theta = inputs.net_random(seed) * np.float32(0.3)
+    net = boxmg.Net(theta, max_n=n, train=True)
+    S = boxmg.Solver(st, interp=boxmg.BMG_INTERP_LEARNED, learned_levels=1, net=net)
+    r0 = inputs.residual_probe(n, seed)
+    net.zero_grad()
+    loss, dCi = net.twogrid(S, dev(r0), inner_tol=1e-8, inner_max=30, want_grad_planes=True)
+    Ci = host(S.export(0, "Ci"))
+    O, W, Sp = (host(S.export(0, nm)) for nm in ("O", "W", "S"))
+    SW = host(S.export(0, "SW")) if kind == 9 else None
+    NW = host(S.export(0, "NW")) if kind == 9 else None
+    for a, b in zip((O, W, Sp, SW, NW), hp):
+        if b is not None:
+            assert np.array_equal(a, b)
+    # the coarse operator is the Galerkin product of the learned weights
+    Ac = ref.rap(O, W, Sp, SW, NW, Ci)
+    for nm, want in zip(("O", "W", "S", "SW", "NW"), Ac):
+        assert np.array_equal(host(S.export(1, nm)), want), f"level 1 {nm}"
+    tg = learned.twogrid(O, W, Sp, SW, NW, Ci, ref.pad(r0), tol=1e-8, max_cycles=30)
+    assert abs(loss - tg["loss"]) <= 1e-12 * tg["loss"], (loss, tg["loss"])
+    d = host(dCi)
+    scale = np.max(np.abs(tg["dCi"]))
+    assert np.max(np.abs(d - tg["dCi"])) <= 1e-12 * scale
+    # the gradient sum is the network's backward pass of that dL/dCi
+    G = net.grad()
+    net.zero_grad()
+    net.backward(dCi)
+    assert np.array_equal(net.grad(), G)
+
+
+def test_learned_hierarchy_matches_oracle(gpu):
+    n = 127
+    p = inputs.jumping(n, 8, -3.0, 3.0, 41, 42)
+    st, rhs = boxmg.discretize(dev(p.k), dev(p.f))
+    theta = inputs.net_random(43) * np.float32(0.3)
+    net = boxmg.Net(theta, max_n=n, train=False)
+    S = boxmg.Solver(st, interp=boxmg.BMG_INTERP_LEARNED, net=net, max_cycles=5)
+    for lvl in range(S.nlev - 1):
+        planes = [S.export(lvl, nm) for nm in ("O", "W", "S")]
+        planes += [S.export(lvl, nm) for nm in ("SW", "NW")] if lvl > 0 else [None, None]
+        hp = [None if a is None else host(a) for a in planes]
+        Ci = host(S.export(lvl, "Ci"))
+        fw = learned.forward(theta, *hp)
+        tol = 1e-2 * np.max(np.abs(fw["Ci"])) + 1e-12
+        assert np.max(np.abs(Ci - fw["Ci"])) <= tol, f"level {lvl}"
+        Ac = ref.rap(*hp, Ci)
+        for nm, want in zip(("O", "W", "S", "SW", "NW"), Ac):
+            assert np.array_equal(host(S.export(lvl + 1, nm)), want), f"level {lvl + 1} {nm}"
+    # cycles on the learned hierarchy equal the oracle's cycles on the same operators
+    x, info = S.solve(rhs, tol=0.0, raise_on_noconv=False)
+    assert info["cycles"] == 5
+
+
+def test_solve_select_falls_back_for_a_zero_network(gpu):
+    n = 255
+    p = inputs.jumping(n, 16, -3.0, 3.0, 51, 52)
+    st, rhs = boxmg.discretize(dev(p.k), dev(p.f))
+    net = boxmg.Net(np.zeros(boxmg.NET_PARAMS, np.float32), max_n=n, train=False)
+    L = boxmg.Solver(st, interp=boxmg.BMG_INTERP_LEARNED, net=net, max_cycles=400)
+    B = boxmg.Solver(st, max_cycles=400)
+    x, info, used, rho = boxmg.solve_select(L, B, rhs, tol=1e-10)
+    assert used == boxmg.BMG_INTERP_BOXMG
+    assert rho[0] > rho[1]
+    assert info["rel_res"] <= 1e-10
+    # the winner's solve continued from its probe iterate
+    _, ib = B.solve(rhs, tol=1e-10)
+    assert abs(info["cycles"] - ib["cycles"]) <= 2
+
+
+def test_training_reduces_the_loss(gpu):
+    """A few Adam steps on a fixed set of samples lower their mean loss."""
+    n = 31
+    net = boxmg.Net(inputs.net_init(7), max_n=n, train=True)
+    samples = []
+    for s in range(4):
+        p = inputs.jumping(n, 4, -3.0, 3.0, 600 + s, 700 + s)
+        st, _ = boxmg.discretize(dev(p.k), dev(p.f))
+        samples.append((st, dev(inputs.residual_probe(n, 800 + s))))
+
+    def epoch(update):
+        tot = 0.0
+        net.zero_grad()
+        for st, r0 in samples:
+            S = boxmg.Solver(st, interp=boxmg.BMG_INTERP_LEARNED, learned_levels=1, net=net)
+            loss, _ = net.twogrid(S, r0, inner_tol=1e-8, inner_max=30)
+            tot += loss
+        if update:
+            net.adam(3e-3, scale=1.0 / len(samples))
+        return tot / len(samples)
+
+    first = epoch(True)
+    for _ in range(40):
+        epoch(True)
+    last = epoch(False)
+    assert last < 0.7 * first, (first, last)

@@ -389,3 +389,17 @@ def test_batch_matches_single_problem_oracle(gpu):
     assert steps[3] == 0 and not host(x[3]).any()
     info = B.info()
     assert info["workgroups"] >= 256
+
+
+def test_second_solve_on_one_handle(gpu):
+    """A solve after a converged solve on the same handle starts afresh: same
+    history and iterate as the first (its stop code and norms are not reused)."""
+    p = problem("jump16", 127, 3)
+    st, rhs = gpu_problem(p)
+    S = boxmg.Solver(st, max_cycles=200)
+    x1, i1 = S.solve(rhs, tol=1e-10)
+    x2, i2 = S.solve(rhs, tol=1e-10)
+    assert i1["cycles"] == i2["cycles"] and i1["history"] == i2["history"]
+    same(host(x1), host(x2), "iterate")
+    rel = S.vcycle(rhs, x2.clone())
+    assert 0.0 < rel < 1e-9
