@@ -61,10 +61,11 @@ def lib():
     """The loaded ``libbmg.so``; raises if it has not been built."""
     global _lib
     if _lib is None:
-        if not os.path.exists(_build.LIB):
-            raise RuntimeError(f"{_build.LIB} is not built; run "
+        path = os.environ.get("BMG_LIBRARY", _build.LIB)   # a tuning variant of the same sources
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is not built; run "
                                "`python -m paper_2502_05279_amd.build` first")
-        L = C.CDLL(_build.LIB)
+        L = C.CDLL(path)
         vp, i, d, sz = C.c_void_p, C.c_int, C.c_double, C.c_size_t
         sig = {
             "bmg_default_options": ([C.POINTER(Options)], i),

@@ -27,9 +27,10 @@ def _deps():
     return [p for p in out if os.path.isfile(p)]
 
 
-def command(out: str) -> list[str]:
+def command(out: str, defines=()) -> list[str]:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     return [hipcc, f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+            *[f"-D{d}" for d in defines],
             "-ffp-contract=off", "-fno-fast-math",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
@@ -37,15 +38,17 @@ def command(out: str) -> list[str]:
             *[os.path.join(CSRC, s) for s in SOURCES], "-o", out]
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(OUT_DIR, exist_ok=True)
-    tmp = LIB + ".tmp"
-    cmd = command(tmp)
+def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
+    """Compiles the library to ``out`` (with extra -D definitions, e.g. a
+    tuning variant such as BMG_PREFETCH_STEPS=1)."""
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    tmp = out + ".tmp"
+    cmd = command(tmp, defines)
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 def needs_build() -> bool:

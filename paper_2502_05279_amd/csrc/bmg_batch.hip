@@ -34,7 +34,11 @@ namespace {
 
 constexpr int BT = FW;              // threads per workgroup (one fused tile)
 constexpr int CHUNK_ROWS = 16;      // fine rows per item of the FP64 phases
-constexpr int MAXD = 8;             // tiled levels per problem (n >= 127)
+constexpr int MAXD = 8;             // tiled levels per problem (n > SMALL_BATCH)
+// Levels of at most this many points per side run in the per-problem
+// LDS-resident sub-cycle; keeping it at 31 keeps the kernel's LDS at the size
+// of one nine-point FP32 tile, so that four workgroups fit on a CU.
+constexpr int SMALL_BATCH = 31;
 
 struct BProb {
     int n0, nlev, sdepth;           // finest size, levels, first small level
@@ -125,7 +129,7 @@ __device__ __forceinline__ void phase_barrier(cg::grid_group &grid)
     __threadfence();
 }
 
-__global__ __launch_bounds__(BT) void k_batch(BArgs A, int mode, int steps)
+__global__ __launch_bounds__(BT, 4) void k_batch(BArgs A, int mode, int steps)
 {
     extern __shared__ unsigned char smem[];
     cg::grid_group grid = cg::this_grid();
@@ -266,10 +270,10 @@ __global__ __launch_bounds__(BT) void k_batch(BArgs A, int mode, int steps)
                 BProb &q = P[items[it].x];
                 if (q.done) continue;
                 if (d == 0)
-                    pre_tile<float, false, 2>(q.L[0], q.ualt[0], q.C[0], q.L[1], q.gpre[0], items[it].y,
+                    pre_tile<float, false, 2, 1>(q.L[0], q.ualt[0], q.C[0], q.L[1], q.gpre[0], items[it].y,
                                               *reinterpret_cast<TileLds<float, false, 2> *>(smem));
                 else
-                    pre_tile<float, true, 2>(q.L[d], q.ualt[d], q.C[d], q.L[d + 1], q.gpre[d], items[it].y,
+                    pre_tile<float, true, 2, 1>(q.L[d], q.ualt[d], q.C[d], q.L[d + 1], q.gpre[d], items[it].y,
                                              *reinterpret_cast<TileLds<float, true, 2> *>(smem));
                 __syncthreads();
             }
@@ -293,10 +297,10 @@ __global__ __launch_bounds__(BT) void k_batch(BArgs A, int mode, int steps)
                 float *out = L.u;
                 L.u = q.ualt[d];
                 if (d == 0)
-                    post_tile<float, false, 1, false>(L, out, q.C[0], q.L[1].u, q.gpost[0], items[it].y, nullptr,
+                    post_tile<float, false, 1, false, 1>(L, out, q.C[0], q.L[1].u, q.gpost[0], items[it].y, nullptr,
                                                       *reinterpret_cast<TileLds<float, false, 1> *>(smem));
                 else
-                    post_tile<float, true, 1, false>(L, out, q.C[d], q.L[d + 1].u, q.gpost[d], items[it].y, nullptr,
+                    post_tile<float, true, 1, false, 1>(L, out, q.C[d], q.L[d + 1].u, q.gpost[d], items[it].y, nullptr,
                                                      *reinterpret_cast<TileLds<float, true, 1> *>(smem));
                 __syncthreads();
             }
@@ -470,7 +474,7 @@ bmg_status bmg_batch_setup(bmg_batch **out, int nprob, const int *n, const doubl
         q.n0 = n[p];
         q.nlev = h->nlev;
         q.sdepth = 0;
-        while (q.sdepth < h->nlev - 1 && h->L32[q.sdepth].n > 63) ++q.sdepth;
+        while (q.sdepth < h->nlev - 1 && h->L32[q.sdepth].n > SMALL_BATCH) ++q.sdepth;
         if (q.sdepth > MAXD) return bail(fail(BMG_EINVAL, "problem %d is too large for the batch", p));
         ndepth = std::max(ndepth, q.sdepth);
         for (int l = 0; l < h->nlev; ++l) {

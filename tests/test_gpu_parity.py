@@ -306,7 +306,8 @@ def test_breakdown_is_reported(gpu):
 
 # ------------------------------------------------------------ fused passes
 @pytest.mark.parametrize("kind,n,tile_rows", [("jump16", 15, 0), ("lognormal", 127, 6),
-                                              ("jump64", 511, 32), ("lognormal", 1023, 64)])
+                                              ("jump16", 255, 2), ("jump64", 511, 32),
+                                              ("lognormal", 1023, 64)])
 @pytest.mark.parametrize("fp32", [False, True])
 def test_fused_passes_bitwise(gpu, kind, n, tile_rows, fp32):
     """The fused pre pass (nu sweeps + residual + restriction) and post pass
