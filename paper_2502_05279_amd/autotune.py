@@ -16,7 +16,7 @@ import torch
 
 from . import boxmg, inputs
 
-DEFAULT_CANDIDATES = (8, 16, 32, 64, 128)
+DEFAULT_CANDIDATES = (2, 4, 8, 16, 32, 64, 128)
 
 # timings (ms per pre+post pass pair, by tile height) of the last tune() call
 LAST: dict = {}

@@ -270,10 +270,10 @@ __global__ __launch_bounds__(BT, 4) void k_batch(BArgs A, int mode, int steps)
                 BProb &q = P[items[it].x];
                 if (q.done) continue;
                 if (d == 0)
-                    pre_tile<float, false, 2, 1>(q.L[0], q.ualt[0], q.C[0], q.L[1], q.gpre[0], items[it].y,
+                    pre_tile<float, false, 2>(q.L[0], q.ualt[0], q.C[0], q.L[1], q.gpre[0], items[it].y,
                                               *reinterpret_cast<TileLds<float, false, 2> *>(smem));
                 else
-                    pre_tile<float, true, 2, 1>(q.L[d], q.ualt[d], q.C[d], q.L[d + 1], q.gpre[d], items[it].y,
+                    pre_tile<float, true, 2>(q.L[d], q.ualt[d], q.C[d], q.L[d + 1], q.gpre[d], items[it].y,
                                              *reinterpret_cast<TileLds<float, true, 2> *>(smem));
                 __syncthreads();
             }
@@ -297,10 +297,10 @@ __global__ __launch_bounds__(BT, 4) void k_batch(BArgs A, int mode, int steps)
                 float *out = L.u;
                 L.u = q.ualt[d];
                 if (d == 0)
-                    post_tile<float, false, 1, false, 1>(L, out, q.C[0], q.L[1].u, q.gpost[0], items[it].y, nullptr,
+                    post_tile<float, false, 1, false>(L, out, q.C[0], q.L[1].u, q.gpost[0], items[it].y, nullptr,
                                                       *reinterpret_cast<TileLds<float, false, 1> *>(smem));
                 else
-                    post_tile<float, true, 1, false, 1>(L, out, q.C[d], q.L[d + 1].u, q.gpost[d], items[it].y, nullptr,
+                    post_tile<float, true, 1, false>(L, out, q.C[d], q.L[d + 1].u, q.gpost[d], items[it].y, nullptr,
                                                      *reinterpret_cast<TileLds<float, true, 1> *>(smem));
                 __syncthreads();
             }
@@ -334,6 +334,20 @@ __global__ __launch_bounds__(BT, 4) void k_batch(BArgs A, int mode, int steps)
 }
 
 size_t align_up(size_t v) { return (v + ALIGN - 1) & ~(ALIGN - 1); }
+
+// Work items of one problem of size n, an upper bound for any tile height:
+// row chunks of the FP64 phases (three lists), one item per problem in two
+// lists, and the pre and post tiles of every tiled level with two-row tiles
+// and the widest halo (nine-point, nu = 2).
+size_t max_items(int n)
+{
+    const size_t nch = (n + CHUNK_ROWS - 1) / CHUNK_ROWS;
+    size_t t = 3 * nch + 2;
+    const int useful = FW - 2 * (4 * 2 + 2);
+    for (int m = n; m > SMALL_BATCH; m = (m - 1) / 2)
+        t += 2 * (size_t)((m + useful - 1) / useful) * (size_t)((m + 1) / 2);
+    return t;
+}
 
 }  // namespace
 
@@ -386,7 +400,7 @@ size_t batch_layout(int nprob, const int *n, const bmg_options &op, std::vector<
     size_t items = 0, parts = 0;
     for (int p = 0; p < nprob; ++p) {
         const int nch = (n[p] + CHUNK_ROWS - 1) / CHUNK_ROWS;
-        items += 3 * (size_t)nch + 2 + 4 * (size_t)(n[p] / 4) + 64;  // generous bound on tiles
+        items += max_items(n[p]);
         parts += 2 * (size_t)nch;
     }
     off = align_up(off + (size_t)nprob * sizeof(BProb));
@@ -453,7 +467,7 @@ bmg_status bmg_batch_setup(bmg_batch **out, int nprob, const int *n, const doubl
     size_t items_cap = 0, parts = 0;
     for (int p = 0; p < nprob; ++p) {
         const int nch = (n[p] + CHUNK_ROWS - 1) / CHUNK_ROWS;
-        items_cap += 3 * (size_t)nch + 2 + 4 * (size_t)(n[p] / 4) + 64;
+        items_cap += max_items(n[p]);
         parts += 2 * (size_t)nch;
     }
     off = align_up(off + items_cap * sizeof(int2));

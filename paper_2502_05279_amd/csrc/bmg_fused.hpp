@@ -25,13 +25,6 @@ namespace bmg {
 
 constexpr int FW = 256;  // lanes (= columns) per workgroup
 
-// Steps (of two rows) between the request of a row's data and its use in the
-// fused passes: 2 keeps twice the bytes in flight of 1 at the cost of
-// registers.
-#ifndef BMG_PREFETCH_STEPS
-#define BMG_PREFETCH_STEPS 2
-#endif
-
 // Ring-buffer slot of a row (rows may be slightly negative near the bottom).
 template <int R>
 __device__ __forceinline__ int slot(int row) { return (row + 64 * R) & (R - 1); }
@@ -109,22 +102,11 @@ struct TileLds {
     T sSW[NINE ? RU * FW : 1], sNW[NINE ? RU * FW : 1];
 };
 
-// Global data of one step (two rows and, for the pre pass, the weights of one
-// restriction row; for the post pass one coarse row and the interpolation
-// weights), held in registers from the time it is requested until its step.
-template <typename T>
-struct StepRows {
-    T u0, u1, W0, W1, O0, O1, S0, S1, B0, B1, SW0, SW1, NW0, NW1;
-    T w[8];
-    T ec;
-};
-
-template <typename T, bool NINE, int NU, int PD = BMG_PREFETCH_STEPS>
+template <typename T, bool NINE, int NU>
 __device__ __forceinline__ void pre_tile(const Lev<T> &L, T *__restrict__ uout, const Wts<T> &C,
                                          const Lev<T> &Cl, const TileGeo &G, int tid,
                                          TileLds<T, NINE, NU> &S)
 {
-    static_assert(PD == 1 || PD == 2, "prefetch distance of one or two steps");
     constexpr int RW = 2 * NU + 4;                 // window rows
     constexpr int RU = RW <= 8 ? 8 : 16;           // LDS ring rows (power of two)
     T *su = S.su, *sW = S.sW, *sr = S.sx, *sSW = S.sSW, *sNW = S.sNW;
@@ -178,39 +160,39 @@ __device__ __forceinline__ void pre_tile(const Lev<T> &L, T *__restrict__ uout, 
         rS[k] = ld_row(L.S, row);
         rB[k] = ld_row(L.b, row);
     }
-    // data of the first PD steps
-    T w[8];
-    auto fetch = [&](StepRows<T> &P, int e) {
-        P.u0 = ld_row(L.u, e); P.u1 = ld_row(L.u, e + 1);
-        P.W0 = ld_row(L.W, e); P.W1 = ld_row(L.W, e + 1);
-        P.O0 = ld_row(L.O, e); P.O1 = ld_row(L.O, e + 1);
-        P.S0 = ld_row(L.S, e); P.S1 = ld_row(L.S, e + 1);
-        P.B0 = ld_row(L.b, e); P.B1 = ld_row(L.b, e + 1);
+    // data of the first step
+    T pu0, pu1, pW0, pW1, pO0, pO1, pS0, pS1, pB0, pB1, pSW0 = 0, pSW1 = 0, pNW0 = 0, pNW1 = 0;
+    T pw[8], w[8];
+    auto fetch = [&](int e) {
+        pu0 = ld_row(L.u, e); pu1 = ld_row(L.u, e + 1);
+        pW0 = ld_row(L.W, e); pW1 = ld_row(L.W, e + 1);
+        pO0 = ld_row(L.O, e); pO1 = ld_row(L.O, e + 1);
+        pS0 = ld_row(L.S, e); pS1 = ld_row(L.S, e + 1);
+        pB0 = ld_row(L.b, e); pB1 = ld_row(L.b, e + 1);
         if (NINE) {
-            P.SW0 = ld_row(L.SW, e); P.SW1 = ld_row(L.SW, e + 1);
-            P.NW0 = ld_row(L.NW, e); P.NW1 = ld_row(L.NW, e + 1);
+            pSW0 = ld_row(L.SW, e); pSW1 = ld_row(L.SW, e + 1);
+            pNW0 = ld_row(L.NW, e); pNW1 = ld_row(L.NW, e + 1);
         }
-        ld_w((e - 2 * NU - 2) >> 1, P.w);
+        ld_w((e - 2 * NU - 2) >> 1, pw);
     };
-    // one step: rows e, e+1 join the window (their data in P, which is then
-    // refilled with the data of step e + 2 PD), NU pipelined sweeps, two
-    // residual rows, one restriction row
-    auto step = [&](int e, StepRows<T> &P) {
+    fetch(es);
+
+    for (int e = es; e <= elast; e += 2) {
         __syncthreads();  // the previous step is done with the slots reused below
         {
             const int s0 = slot<RU>(e) * FW + lane, s1 = slot<RU>(e + 1) * FW + lane;
-            su[s0] = P.u0; su[s1] = P.u1;
-            sW[s0] = P.W0; sW[s1] = P.W1;
-            if (NINE) { sSW[s0] = P.SW0; sSW[s1] = P.SW1; sNW[s0] = P.NW0; sNW[s1] = P.NW1; }
+            su[s0] = pu0; su[s1] = pu1;
+            sW[s0] = pW0; sW[s1] = pW1;
+            if (NINE) { sSW[s0] = pSW0; sSW[s1] = pSW1; sNW[s0] = pNW0; sNW[s1] = pNW1; }
 #pragma unroll
             for (int k = 0; k < RW - 2; ++k) { rO[k] = rO[k + 2]; rS[k] = rS[k + 2]; rB[k] = rB[k + 2]; }
-            rO[RW - 2] = P.O0; rO[RW - 1] = P.O1;
-            rS[RW - 2] = P.S0; rS[RW - 1] = P.S1;
-            rB[RW - 2] = P.B0; rB[RW - 1] = P.B1;
+            rO[RW - 2] = pO0; rO[RW - 1] = pO1;
+            rS[RW - 2] = pS0; rS[RW - 1] = pS1;
+            rB[RW - 2] = pB0; rB[RW - 1] = pB1;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) w[q] = P.w[q];
+            for (int q = 0; q < 8; ++q) w[q] = pw[q];
         }
-        if (e + 2 * PD <= elast) fetch(P, e + 2 * PD);
+        if (e + 2 <= elast) fetch(e + 2);
         __syncthreads();
         // NU sweeps, each over colours 0,1 (even row) then 2,3 (odd row)
 #pragma unroll
@@ -264,17 +246,6 @@ __device__ __forceinline__ void pre_tile(const Lev<T> &L, T *__restrict__ uout, 
                 Cl.u[c] = (T)0;
             }
         }
-    };
-    StepRows<T> PA, PB;
-    fetch(PA, es);
-    if (PD == 2) {
-        if (es + 2 <= elast) fetch(PB, es + 2);
-        for (int e = es; e <= elast; e += 4) {
-            step(e, PA);
-            if (e + 2 <= elast) step(e + 2, PB);
-        }
-    } else {
-        for (int e = es; e <= elast; e += 2) step(e, PA);
     }
 }
 
@@ -295,13 +266,12 @@ __global__ __launch_bounds__(FW) void k_pre(Lev<T> L, T *__restrict__ uout, Wts<
 // points into part[tile].  Window: rows e-2NU-2 .. e+1 at step e; the data of
 // step e+2 (rows, coarse row, interpolation weights) is requested while step
 // e computes.
-template <typename T, bool NINE, int NU, bool NORM, int PD = BMG_PREFETCH_STEPS>
+template <typename T, bool NINE, int NU, bool NORM>
 __device__ __forceinline__ void post_tile(const Lev<T> &L, T *__restrict__ uout, const Wts<T> &C,
                                           const T *__restrict__ ec, const TileGeo &G, int tid,
                                           double *__restrict__ part, TileLds<T, NINE, NU> &S)
 {
     static_assert(NU <= 2, "post pass supports up to two sweeps");
-    static_assert(PD == 1 || PD == 2, "prefetch distance of one or two steps");
     constexpr int RW = 2 * NU + 4;
     constexpr int RU = RW <= 8 ? 8 : 16;
     T *su = S.su, *sW = S.sW, *sec = S.sx, *sSW = S.sSW, *sNW = S.sNW;
@@ -405,41 +375,41 @@ __device__ __forceinline__ void post_tile(const Lev<T> &L, T *__restrict__ uout,
             rB[k + t] = ld_row(L.b, row + t);
         }
     }
-    auto fetch = [&](StepRows<T> &P, IW &Pw, int e) {
-        P.u0 = ld_row(L.u, e); P.u1 = ld_row(L.u, e + 1);
-        P.W0 = ld_row(L.W, e); P.W1 = ld_row(L.W, e + 1);
-        P.O0 = ld_row(L.O, e); P.O1 = ld_row(L.O, e + 1);
-        P.S0 = ld_row(L.S, e); P.S1 = ld_row(L.S, e + 1);
-        P.B0 = ld_row(L.b, e); P.B1 = ld_row(L.b, e + 1);
+    T pu0, pu1, pW0, pW1, pO0, pO1, pS0, pS1, pB0, pB1, pSW0 = 0, pSW1 = 0, pNW0 = 0, pNW1 = 0, pec;
+    IW pw;
+    auto fetch = [&](int e) {
+        pu0 = ld_row(L.u, e); pu1 = ld_row(L.u, e + 1);
+        pW0 = ld_row(L.W, e); pW1 = ld_row(L.W, e + 1);
+        pO0 = ld_row(L.O, e); pO1 = ld_row(L.O, e + 1);
+        pS0 = ld_row(L.S, e); pS1 = ld_row(L.S, e + 1);
+        pB0 = ld_row(L.b, e); pB1 = ld_row(L.b, e + 1);
         if (NINE) {
-            P.SW0 = ld_row(L.SW, e); P.SW1 = ld_row(L.SW, e + 1);
-            P.NW0 = ld_row(L.NW, e); P.NW1 = ld_row(L.NW, e + 1);
+            pSW0 = ld_row(L.SW, e); pSW1 = ld_row(L.SW, e + 1);
+            pNW0 = ld_row(L.NW, e); pNW1 = ld_row(L.NW, e + 1);
         }
-        P.ec = ld_crow((e >> 1) + 1);
-        Pw = ld_iw(e);
+        pec = ld_crow((e >> 1) + 1);
+        pw = ld_iw(e);
     };
+    fetch(es);
     double acc = 0.0;
-    // one step: coarse row e/2+1 and rows e, e+1 (interpolated) join the
-    // window, P is refilled with the data of step e + 2 PD, NU pipelined
-    // sweeps, the final rows are written and (NORM) their residual summed
-    auto step = [&](int e, StepRows<T> &P, IW &Pw) {
+    for (int e = es; e <= elast; e += 2) {
         __syncthreads();
         // coarse row e/2 + 1 joins the e_c ring (rows e/2 and e/2 + 1 are used)
-        sec[(((e >> 1) + 1) & 3) * FW + lane] = P.ec;
+        sec[(((e >> 1) + 1) & 3) * FW + lane] = pec;
 #pragma unroll
         for (int k = 0; k < RW - 2; ++k) { rO[k] = rO[k + 2]; rS[k] = rS[k + 2]; rB[k] = rB[k + 2]; }
-        rO[RW - 2] = P.O0; rO[RW - 1] = P.O1;
-        rS[RW - 2] = P.S0; rS[RW - 1] = P.S1;
-        rB[RW - 2] = P.B0; rB[RW - 1] = P.B1;
+        rO[RW - 2] = pO0; rO[RW - 1] = pO1;
+        rS[RW - 2] = pS0; rS[RW - 1] = pS1;
+        rB[RW - 2] = pB0; rB[RW - 1] = pB1;
         __syncthreads();
         {
             const int s0 = slot<RU>(e) * FW + lane, s1 = slot<RU>(e + 1) * FW + lane;
-            su[s0] = interp(e, P.u0, Pw);
-            su[s1] = interp(e + 1, P.u1, Pw);
-            sW[s0] = P.W0; sW[s1] = P.W1;
-            if (NINE) { sSW[s0] = P.SW0; sSW[s1] = P.SW1; sNW[s0] = P.NW0; sNW[s1] = P.NW1; }
+            su[s0] = interp(e, pu0, pw);
+            su[s1] = interp(e + 1, pu1, pw);
+            sW[s0] = pW0; sW[s1] = pW1;
+            if (NINE) { sSW[s0] = pSW0; sSW[s1] = pSW1; sNW[s0] = pNW0; sNW[s1] = pNW1; }
         }
-        if (e + 2 * PD <= elast) fetch(P, Pw, e + 2 * PD);
+        if (e + 2 <= elast) fetch(e + 2);
         __syncthreads();
 #pragma unroll
         for (int s = 0; s < NU; ++s) {
@@ -494,18 +464,6 @@ __device__ __forceinline__ void post_tile(const Lev<T> &L, T *__restrict__ uout,
                 }
             }
         }
-    };
-    StepRows<T> PA, PB;
-    IW WA, WB;
-    fetch(PA, WA, es);
-    if (PD == 2) {
-        if (es + 2 <= elast) fetch(PB, WB, es + 2);
-        for (int e = es; e <= elast; e += 4) {
-            step(e, PA, WA);
-            if (e + 2 <= elast) step(e + 2, PB, WB);
-        }
-    } else {
-        for (int e = es; e <= elast; e += 2) step(e, PA, WA);
     }
     if (NORM) {
         acc = block_sum(acc);

@@ -40,12 +40,14 @@ int tile_rows_for(const bmg_solver *h, int n)
     int m = 0;
     while ((1 << m) < n + 1 && m < 16) ++m;
     if (g_tile_rows[m] > 0) return g_tile_rows[m];
-    // measured defaults: enough tiles to fill the chip against the warm-up rows
-    // each tile re-reads
-    if (n >= 4095) return 128;
-    if (n >= 2047) return 64;
+    // measured defaults (FP64, V(2,1)): enough tiles to keep several
+    // workgroups on every CU against the warm-up rows each tile re-reads; on
+    // the levels below 1023 the shortest tiles win, their passes being bound
+    // by the latency of the row pipeline rather than by bandwidth
+    if (n >= 2047) return 32;
     if (n >= 1023) return 16;
-    return 8;
+    if (n >= 511) return 4;
+    return 2;
 }
 
 TileGeo tile_geo(int n, int hx, int ht)
