@@ -94,7 +94,16 @@ def bench_batch(args):
     from paper_2502_05279_amd import autotune, boxmg, inputs
 
     dev = torch.device("cuda:0")
-    tuned = autotune.tune(sizes=(127, 255, 511, 1023), precision=boxmg.BMG_FP32_IR)
+    if args.batch_tile_rows:
+        tuned = {n: args.batch_tile_rows for n in (63, 127, 255, 511, 1023)}
+        for n, r in tuned.items():
+            boxmg.tile_rows_set(n, r)
+    else:
+        # every problem's passes share the chip, so parallelism is plentiful:
+        # the tile heights are tuned among the taller candidates, whose tiles
+        # re-read fewer warm-up rows
+        tuned = autotune.tune(sizes=(63, 127, 255, 511, 1023), precision=boxmg.BMG_FP32_IR,
+                              candidates=(8, 16, 32, 64))
     probs = inputs.batch_512()
     sts, rhss = [], []
     for q in probs:
@@ -227,6 +236,8 @@ def main():
                          "calibrate hardware byte counters) and print the achieved GB/s")
     ap.add_argument("--params", default=None, help="learned_4095: network parameters (.npy)")
     ap.add_argument("--learned-n", type=int, default=4095)
+    ap.add_argument("--batch-tile-rows", type=int, default=0,
+                    help="batch_512: tile height of every level instead of the autotuner's")
     args = ap.parse_args()
 
     if args.gpus != 1:

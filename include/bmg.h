@@ -349,14 +349,21 @@ bmg_status bmg_net_twogrid(bmg_net *net, bmg_solver *h, const double *r0, double
 
 /* The fallback rule of the learned interpolation: both handles (set up on the
  * same operator, `learned` with BMG_INTERP_LEARNED, `boxmg` with the
- * operator-induced weights) run two probe V-cycles from x; the one whose
- * measured reduction factor rho = (r_2 / r_0)^(1/2) is smaller (the learned
- * one on a tie) continues from its own iterate with bmg_solve.  used (host)
- * receives BMG_INTERP_LEARNED or BMG_INTERP_BOXMG, rho (host, 2 entries) the
- * probe factors of the learned and the BoxMG hierarchy; info counts the
- * winner's probe cycles too. */
+ * operator-induced weights) run probe_cycles V-cycles (0 = 8) from x; the
+ * measured reduction factor of each is the mean per cycle over the second
+ * half of its probe, rho = (r_K / r_(K/2))^(2/K) with K = probe_cycles, and
+ * the hierarchy with the smaller one (the learned one on a tie) continues
+ * from its own iterate with bmg_solve.  The learned hierarchy is watched: it
+ * runs in chunks of 16 cycles, and a chunk whose mean factor exceeds the BoxMG
+ * probe's hands the current iterate (still valid) to the BoxMG hierarchy for
+ * the rest of the solve.  used (host) receives the hierarchy that finished,
+ * BMG_INTERP_LEARNED or BMG_INTERP_BOXMG; rho (host, 2 entries) the probe
+ * factors of the learned and the BoxMG hierarchy; info->cycles counts every
+ * cycle after the probes plus the finishing hierarchy's probe, the other
+ * fields describe the last bmg_solve call (info->history, if given, holds
+ * that call's history).  FP64 handles only. */
 bmg_status bmg_solve_select(bmg_solver *learned, bmg_solver *boxmg, const double *rhs, double *x, double tol,
-                            bmg_info *info, int *used, double *rho);
+                            int probe_cycles, bmg_info *info, int *used, double *rho);
 
 #ifdef __cplusplus
 }

@@ -105,7 +105,7 @@ def lib():
             "bmg_net_adam": ([vp, C.c_float, C.c_float, C.c_float, C.c_float, d], i),
             "bmg_net_export": ([vp, i, vp, C.POINTER(sz)], i),
             "bmg_net_twogrid": ([vp, vp, vp, d, i, C.POINTER(d), vp], i),
-            "bmg_solve_select": ([vp, vp, vp, vp, d, C.POINTER(Info), C.POINTER(i), C.POINTER(d)], i),
+            "bmg_solve_select": ([vp, vp, vp, vp, d, i, C.POINTER(Info), C.POINTER(i), C.POINTER(d)], i),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -435,9 +435,12 @@ class Net:
 
 
 def solve_select(learned: Solver, boxmg: Solver, rhs: torch.Tensor, x: torch.Tensor | None = None,
-                 tol: float = 1e-10, raise_on_noconv: bool = True):
-    """Probe both hierarchies for two cycles and finish with the faster one;
-    returns (x, info, used, (rho_learned, rho_boxmg))."""
+                 tol: float = 1e-10, probe_cycles: int = 8, raise_on_noconv: bool = True):
+    """Probe both hierarchies (probe_cycles V-cycles each), continue with the
+    one whose factor over the probe's second half is smaller (a learned
+    hierarchy is watched every 16 cycles and hands over to BoxMG if it falls
+    behind); returns (x, info, used, (rho_learned, rho_boxmg)), info with the
+    total cycles, the final relative residual and the last call's rho."""
     if x is None:
         x = torch.zeros_like(rhs)
     cap = max(learned.options.max_cycles, boxmg.options.max_cycles) + 2
@@ -445,10 +448,9 @@ def solve_select(learned: Solver, boxmg: Solver, rhs: torch.Tensor, x: torch.Ten
     info = Info(0, 0.0, 0.0, C.cast(hist, C.POINTER(C.c_double)))
     used = C.c_int(0)
     rho = (C.c_double * 2)()
-    st = lib().bmg_solve_select(learned._h, boxmg._h, _ptr(rhs), _ptr(x), float(tol), C.byref(info),
-                                C.byref(used), rho)
+    st = lib().bmg_solve_select(learned._h, boxmg._h, _ptr(rhs), _ptr(x), float(tol), int(probe_cycles),
+                                C.byref(info), C.byref(used), rho)
     if st not in (BMG_OK, BMG_ENOCONV) or (st == BMG_ENOCONV and raise_on_noconv):
         _check(st, "bmg_solve_select")
-    out = {"cycles": info.cycles, "rel_res": info.rel_res, "rho": info.rho,
-           "history": [hist[t] for t in range(max(info.cycles - 2, 0))], "status": st}
+    out = {"cycles": info.cycles, "rel_res": info.rel_res, "rho": info.rho, "status": st}
     return x, out, used.value, (rho[0], rho[1])

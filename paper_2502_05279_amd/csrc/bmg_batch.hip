@@ -36,9 +36,13 @@ constexpr int BT = FW;              // threads per workgroup (one fused tile)
 constexpr int CHUNK_ROWS = 16;      // fine rows per item of the FP64 phases
 constexpr int MAXD = 8;             // tiled levels per problem (n > SMALL_BATCH)
 // Levels of at most this many points per side run in the per-problem
-// LDS-resident sub-cycle; keeping it at 31 keeps the kernel's LDS at the size
-// of one nine-point FP32 tile, so that four workgroups fit on a CU.
-constexpr int SMALL_BATCH = 31;
+// LDS-resident sub-cycle.  31 keeps the kernel's LDS at the size of one
+// nine-point FP32 tile (four workgroups per CU); 63 runs one more level per
+// problem in LDS (two workgroups per CU, two fewer grid barriers per step).
+#ifndef BMG_BATCH_SMALL_N
+#define BMG_BATCH_SMALL_N 31
+#endif
+constexpr int SMALL_BATCH = BMG_BATCH_SMALL_N;
 
 struct BProb {
     int n0, nlev, sdepth;           // finest size, levels, first small level

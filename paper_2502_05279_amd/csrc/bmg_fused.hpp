@@ -486,6 +486,407 @@ __global__ __launch_bounds__(FW) void k_post(Lev<T> L, T *__restrict__ uout, Wts
 
 namespace bmg {
 
+// ------------------------------------ four-row steps (five-point levels)
+// The same pipelines as pre_tile and post_tile with four new rows per step:
+// sweep s updates the even rows e-2s and e-2s+2 (colours 0, 1) and then the
+// odd rows e-2s-1 and e-2s+1 (colours 2, 3).  This is the two-row schedule of
+// steps e and e+2 with their phases merged; every point sees the same
+// neighbour values in the same order, so the results are the same bits, and
+// each workgroup barrier now separates twice the work.  Window: rows
+// e-2NU-2 .. e+3 (RW = 2NU+6), LDS rings of RW rows.
+template <int R>
+__device__ __forceinline__ int qslot(int row) { return (row + 64 * R) % R; }
+
+template <typename T, int NU>
+struct TileLds4 {
+    static constexpr int RW = 2 * NU + 6;
+    T su[RW * FW], sW[RW * FW], sx[8 * FW];
+};
+
+// five-point Gauss-Seidel update and residual from the rings (the terms of
+// gs_point / residual_point in their order)
+template <typename T, int R>
+__device__ __forceinline__ T gs5(const T *su, const T *sW, int lane, int row, T b, T O, T S, T Sn)
+{
+    const int r0 = qslot<R>(row) * FW + lane;
+    const int rd = qslot<R>(row - 1) * FW + lane;
+    const int ru = qslot<R>(row + 1) * FW + lane;
+    T s = b;
+    s -= S * su[rd];
+    s -= sW[r0] * su[r0 - 1];
+    s -= sW[r0 + 1] * su[r0 + 1];
+    s -= Sn * su[ru];
+    return s / O;
+}
+
+template <typename T, int R>
+__device__ __forceinline__ T res5(const T *su, const T *sW, int lane, int row, T b, T O, T S, T Sn)
+{
+    const int r0 = qslot<R>(row) * FW + lane;
+    const int rd = qslot<R>(row - 1) * FW + lane;
+    const int ru = qslot<R>(row + 1) * FW + lane;
+    T s = b;
+    s -= S * su[rd];
+    s -= sW[r0] * su[r0 - 1];
+    s -= sW[r0 + 1] * su[r0 + 1];
+    s -= Sn * su[ru];
+    s -= O * su[r0];
+    return s;
+}
+
+template <typename T, int NU>
+__device__ __forceinline__ void pre_tile4(const Lev<T> &L, T *__restrict__ uout, const Wts<T> &C,
+                                          const Lev<T> &Cl, const TileGeo &G, int tid, TileLds4<T, NU> &S)
+{
+    constexpr int RW = 2 * NU + 6;
+    T *su = S.su, *sW = S.sW, *sr = S.sx;
+
+    const int n = L.n, ld = L.ld, lane = threadIdx.x, nc = Cl.n;
+    const int useful = FW - 2 * G.hx;
+    const int tx = tid % G.tiles_x, ty = tid / G.tiles_x;
+    const int x0 = 1 + tx * useful;
+    const int i = x0 - G.hx + lane;
+    const bool col_in = i >= 0 && i <= n + 1;
+    const bool col_upd = i >= 1 && i <= n && lane >= 1 && lane < FW - 1;
+    const bool col_own = i >= x0 && i < x0 + useful && i <= n;
+    const int y0 = 1 + ty * G.ht;
+    const int y1 = min(y0 + G.ht, n + 1);
+    const int es = (y0 - 2 * NU) & ~1;
+    const int jlast = (y1 - 1) >> 1;
+    const int elast = 2 * jlast + 2 * NU + 2;
+    const int I = i >> 1;
+    const bool restrictor = !(i & 1) && col_own && I >= 1 && I <= nc;
+
+    T rO[RW], rS[RW], rB[RW];
+    auto ld_row = [&](const T *a, int row) -> T {
+        return (col_in && row >= 0 && row <= n + 1) ? a[(size_t)row * ld + i] : (T)0;
+    };
+    auto ld_w = [&](int J, T *w) {
+        const bool ok = restrictor && J >= 1 && J <= nc;
+        const size_t c = ok ? (size_t)J * C.ld + I : 0, cn = c + C.ld;
+        w[0] = ok ? C.at(LNE, c) : (T)0;
+        w[1] = ok ? C.at(LA, c) : (T)0;
+        w[2] = ok ? C.at(LNW, c + 1) : (T)0;
+        w[3] = ok ? C.at(LR, c) : (T)0;
+        w[4] = ok ? C.at(LL, c + 1) : (T)0;
+        w[5] = ok ? C.at(LSE, cn) : (T)0;
+        w[6] = ok ? C.at(LB, cn) : (T)0;
+        w[7] = ok ? C.at(LSW, cn + 1) : (T)0;
+    };
+    // window of step es without its own four rows: rows es-2NU-2 .. es-1 at
+    // positions 4..RW-1 (the first shift by four aligns them)
+#pragma unroll
+    for (int k = 4; k < RW; ++k) {
+        const int row = es - 2 * NU - 6 + k;
+        su[qslot<RW>(row) * FW + lane] = ld_row(L.u, row);
+        sW[qslot<RW>(row) * FW + lane] = ld_row(L.W, row);
+        rO[k] = ld_row(L.O, row);
+        rS[k] = ld_row(L.S, row);
+        rB[k] = ld_row(L.b, row);
+    }
+    T pu[4], pW[4], pO[4], pS[4], pB[4], pw[16], w[16];
+    auto fetch = [&](int e) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            pu[q] = ld_row(L.u, e + q);
+            pW[q] = ld_row(L.W, e + q);
+            pO[q] = ld_row(L.O, e + q);
+            pS[q] = ld_row(L.S, e + q);
+            pB[q] = ld_row(L.b, e + q);
+        }
+        ld_w((e - 2 * NU - 2) >> 1, pw);
+        ld_w(((e - 2 * NU - 2) >> 1) + 1, pw + 8);
+    };
+    fetch(es);
+
+    for (int e = es; e <= elast; e += 4) {
+        __syncthreads();  // the previous step is done with the slots reused below
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int sq = qslot<RW>(e + q) * FW + lane;
+            su[sq] = pu[q];
+            sW[sq] = pW[q];
+        }
+#pragma unroll
+        for (int k = 0; k < RW - 4; ++k) { rO[k] = rO[k + 4]; rS[k] = rS[k + 4]; rB[k] = rB[k + 4]; }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) { rO[RW - 4 + q] = pO[q]; rS[RW - 4 + q] = pS[q]; rB[RW - 4 + q] = pB[q]; }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) w[q] = pw[q];
+        if (e + 4 <= elast) fetch(e + 4);
+        __syncthreads();
+        // NU sweeps, each over colours 0,1 (two even rows) then 2,3 (two odd rows)
+#pragma unroll
+        for (int s = 0; s < NU; ++s) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    const int row = (c < 2 ? e - 2 * s : e - 2 * s - 1) + 2 * t;
+                    const int k = row - (e - 2 * NU - 2);
+                    if (col_upd && (i & 1) == (c & 1) && row >= 1 && row <= n)
+                        su[qslot<RW>(row) * FW + lane] =
+                            gs5<T, RW>(su, sW, lane, row, rB[k], rO[k], rS[k], rS[k + 1]);
+                }
+                __syncthreads();
+            }
+        }
+        // the last sweep's four rows are final: write the owned ones
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int row = e - 2 * NU + 1 + t;
+            if (col_own && row >= y0 && row < y1) uout[(size_t)row * ld + i] = su[qslot<RW>(row) * FW + lane];
+        }
+        // residual of rows e-2NU-1 .. e-2NU+2
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int row = e - 2 * NU - 1 + t;
+            const int k = 1 + t;
+            T r = 0;
+            if (col_upd && row >= 1 && row <= n) r = res5<T, RW>(su, sW, lane, row, rB[k], rO[k], rS[k], rS[k + 1]);
+            sr[(row & 7) * FW + lane] = r;
+        }
+        __syncthreads();
+        // restriction of coarse rows (e-2NU-2)/2 and (e-2NU)/2 by the even columns
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const int f = e - 2 * NU - 2 + 2 * t, J = f >> 1;
+            if (restrictor && J >= 1 && J <= nc && f >= y0 && f < y1) {
+                const T *wt = w + 8 * t;
+                const size_t c = (size_t)J * C.ld + I;
+                const T *rd = sr + ((f - 1) & 7) * FW + lane, *r0 = sr + (f & 7) * FW + lane,
+                        *ru = sr + ((f + 1) & 7) * FW + lane;
+                T sum = wt[0] * rd[-1];
+                sum = sum + wt[1] * rd[0];
+                sum = sum + wt[2] * rd[1];
+                sum = sum + wt[3] * r0[-1];
+                sum = sum + r0[0];
+                sum = sum + wt[4] * r0[1];
+                sum = sum + wt[5] * ru[-1];
+                sum = sum + wt[6] * ru[0];
+                sum = sum + wt[7] * ru[1];
+                Cl.b[c] = sum;
+                Cl.u[c] = (T)0;
+            }
+        }
+    }
+}
+
+template <typename T, int NU>
+__global__ __launch_bounds__(FW) void k_pre4(Lev<T> L, T *__restrict__ uout, Wts<T> C, Lev<T> Cl, TileGeo G,
+                                              const int *stop)
+{
+    if (stopped(stop)) return;
+    const int tid = tile_id(G.ntiles);
+    if (tid < 0) return;
+    __shared__ TileLds4<T, NU> S;
+    pre_tile4<T, NU>(L, uout, C, Cl, G, tid, S);
+}
+
+template <typename T, int NU, bool NORM>
+__device__ __forceinline__ void post_tile4(const Lev<T> &L, T *__restrict__ uout, const Wts<T> &C,
+                                           const T *__restrict__ ec, const TileGeo &G, int tid,
+                                           double *__restrict__ part, TileLds4<T, NU> &S)
+{
+    static_assert(NU <= 2, "post pass supports up to two sweeps");
+    constexpr int RW = 2 * NU + 6;
+    T *su = S.su, *sW = S.sW, *sec = S.sx;
+
+    const int n = L.n, ld = L.ld, lane = threadIdx.x, ldc = C.ld, nc = (n - 1) >> 1;
+    const int useful = FW - 2 * G.hx;
+    const int tx = tid % G.tiles_x, ty = tid / G.tiles_x;
+    const int x0 = 1 + tx * useful;
+    const int i = x0 - G.hx + lane;
+    const bool col_in = i >= 0 && i <= n + 1;
+    const bool col_upd = i >= 1 && i <= n && lane >= 1 && lane < FW - 1;
+    const bool col_own = i >= x0 && i < x0 + useful && i <= n;
+    const int y0 = 1 + ty * G.ht;
+    const int y1 = min(y0 + G.ht, n + 1);
+    const int es = (y0 - 2 * NU + 1) & ~1;
+    const int elast = ((y1 + 2 * NU) + 1) & ~1;
+    const int ib = (x0 - G.hx) >> 1;
+    const int Ie = ib + lane;
+    const bool ccol_in = lane < FW / 2 + 2 && Ie >= 0 && Ie <= nc + 1;
+    const bool odd_i = i & 1;
+    const int Ix = (i + 1) >> 1;
+
+    T rO[RW], rS[RW], rB[RW];
+    auto ld_row = [&](const T *a, int row) -> T {
+        return (col_in && row >= 0 && row <= n + 1) ? a[(size_t)row * ld + i] : (T)0;
+    };
+    auto ld_crow = [&](int J) -> T {
+        return (ccol_in && J >= 0 && J <= nc + 1) ? ec[(size_t)J * ldc + Ie] : (T)0;
+    };
+    struct IW { T w[6]; };
+    auto ld_iw = [&](int e) -> IW {
+        IW r;
+        T *w = r.w;
+        const int J0 = e >> 1, J1 = J0 + 1;
+        const bool ok0 = col_upd && odd_i && e >= 1 && e <= n;
+        const bool ok1 = col_upd && e + 1 >= 1 && e + 1 <= n;
+        const size_t c0 = ok0 ? (size_t)J0 * ldc + Ix : 0;
+        const size_t c1 = ok1 ? (size_t)J1 * ldc + (odd_i ? Ix : (i >> 1)) : 0;
+        w[0] = ok0 ? C.at(LL, c0) : (T)0;
+        w[1] = ok0 ? C.at(LR, c0) : (T)0;
+        if (odd_i) {
+            w[2] = ok1 ? C.at(LSW, c1) : (T)0;
+            w[3] = ok1 ? C.at(LSE, c1) : (T)0;
+            w[4] = ok1 ? C.at(LNW, c1) : (T)0;
+            w[5] = ok1 ? C.at(LNE, c1) : (T)0;
+        } else {
+            w[2] = ok1 ? C.at(LB, c1) : (T)0;
+            w[3] = ok1 ? C.at(LA, c1) : (T)0;
+            w[4] = w[5] = (T)0;
+        }
+        return r;
+    };
+    // u + P e_c (the expression of post_tile's interp)
+    auto interp = [&](int row, T u, const IW &iw) -> T {
+        const T *w = iw.w;
+        if (!col_upd || row < 1 || row > n) return u;
+        T e;
+        if (!(row & 1)) {
+            const T *er = sec + ((row >> 1) & 3) * FW;
+            if (!odd_i) e = er[(i >> 1) - ib];
+            else e = w[0] * er[Ix - 1 - ib] + w[1] * er[Ix - ib];
+        } else {
+            const int J = (row + 1) >> 1;
+            const T *es_ = sec + ((J - 1) & 3) * FW, *en = sec + (J & 3) * FW;
+            if (!odd_i) {
+                e = w[2] * es_[(i >> 1) - ib] + w[3] * en[(i >> 1) - ib];
+            } else {
+                e = w[2] * es_[Ix - 1 - ib] + w[3] * es_[Ix - ib];
+                e = e + w[4] * en[Ix - 1 - ib];
+                e = e + w[5] * en[Ix - ib];
+            }
+        }
+        return u + e;
+    };
+
+    // window of step es without its own four rows: rows es-2NU-2 .. es-1,
+    // interpolated, at positions 4..RW-1; their coarse rows
+    // (es-2NU-2)/2 .. es/2 (at most four) fill the e_c ring
+    for (int J = (es - 2 * NU - 2) >> 1; J <= (es >> 1); ++J) sec[(J & 3) * FW + lane] = ld_crow(J);
+    __syncthreads();
+#pragma unroll
+    for (int k = 4; k < RW; k += 2) {
+        const int row = es - 2 * NU - 6 + k;      // even
+        const IW wk = ld_iw(row);
+        su[qslot<RW>(row) * FW + lane] = interp(row, ld_row(L.u, row), wk);
+        su[qslot<RW>(row + 1) * FW + lane] = interp(row + 1, ld_row(L.u, row + 1), wk);
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            sW[qslot<RW>(row + t) * FW + lane] = ld_row(L.W, row + t);
+            rO[k + t] = ld_row(L.O, row + t);
+            rS[k + t] = ld_row(L.S, row + t);
+            rB[k + t] = ld_row(L.b, row + t);
+        }
+    }
+    T pu[4], pW[4], pO[4], pS[4], pB[4], pec[2];
+    IW pw[2];
+    auto fetch = [&](int e) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            pu[q] = ld_row(L.u, e + q);
+            pW[q] = ld_row(L.W, e + q);
+            pO[q] = ld_row(L.O, e + q);
+            pS[q] = ld_row(L.S, e + q);
+            pB[q] = ld_row(L.b, e + q);
+        }
+        pec[0] = ld_crow((e >> 1) + 1);
+        pec[1] = ld_crow((e >> 1) + 2);
+        pw[0] = ld_iw(e);
+        pw[1] = ld_iw(e + 2);
+    };
+    fetch(es);
+    double acc = 0.0;
+    for (int e = es; e <= elast; e += 4) {
+        __syncthreads();
+        // coarse rows e/2+1 and e/2+2 join the e_c ring
+        sec[(((e >> 1) + 1) & 3) * FW + lane] = pec[0];
+        sec[(((e >> 1) + 2) & 3) * FW + lane] = pec[1];
+#pragma unroll
+        for (int k = 0; k < RW - 4; ++k) { rO[k] = rO[k + 4]; rS[k] = rS[k + 4]; rB[k] = rB[k + 4]; }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) { rO[RW - 4 + q] = pO[q]; rS[RW - 4 + q] = pS[q]; rB[RW - 4 + q] = pB[q]; }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int sq = qslot<RW>(e + q) * FW + lane;
+            su[sq] = interp(e + q, pu[q], pw[q >> 1]);
+            sW[sq] = pW[q];
+        }
+        if (e + 4 <= elast) fetch(e + 4);
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < NU; ++s) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    const int row = (c < 2 ? e - 2 * s : e - 2 * s - 1) + 2 * t;
+                    const int k = row - (e - 2 * NU - 2);
+                    if (col_upd && (i & 1) == (c & 1) && row >= 1 && row <= n)
+                        su[qslot<RW>(row) * FW + lane] =
+                            gs5<T, RW>(su, sW, lane, row, rB[k], rO[k], rS[k], rS[k + 1]);
+                }
+                __syncthreads();
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int row = e - 2 * NU + 1 + t;
+            if (col_own && row >= y0 && row < y1) uout[(size_t)row * ld + i] = su[qslot<RW>(row) * FW + lane];
+        }
+        if (NORM) {
+            // accurate residual of the final rows e-2NU-1 .. e-2NU+2
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int row = e - 2 * NU - 1 + t;
+                const int k = 1 + t;
+                if (col_own && row >= y0 && row < y1 && row >= 1) {
+                    const int r0 = qslot<RW>(row) * FW + lane, rd = qslot<RW>(row - 1) * FW + lane,
+                              ru = qslot<RW>(row + 1) * FW + lane;
+                    const double a[5] = {(double)rS[k], (double)sW[r0], (double)sW[r0 + 1], (double)rS[k + 1],
+                                         (double)rO[k]};
+                    const double x[5] = {(double)su[rd], (double)su[r0 - 1], (double)su[r0 + 1], (double)su[ru],
+                                         (double)su[r0]};
+                    double sacc = rB[k], cc = 0.0, ns, se;
+#pragma unroll
+                    for (int q = 0; q < 5; ++q) {
+                        const double pr = a[q] * x[q];
+                        const double pe = fma(a[q], x[q], -pr);
+                        two_sum(sacc, -pr, ns, se);
+                        sacc = ns;
+                        cc = cc + (se - pe);
+                    }
+                    const double r = sacc + cc;
+                    acc += r * r;
+                }
+            }
+        }
+    }
+    if (NORM) {
+        acc = block_sum(acc);
+        if (threadIdx.x == 0) part[tid] = acc;
+    }
+}
+
+template <typename T, int NU, bool NORM>
+__global__ __launch_bounds__(FW) void k_post4(Lev<T> L, T *__restrict__ uout, Wts<T> C, const T *__restrict__ ec,
+                                               TileGeo G, double *__restrict__ part, const int *stop)
+{
+    if (stopped(stop)) return;
+    const int tid = tile_id(G.ntiles);
+    if (tid < 0) return;
+    __shared__ TileLds4<T, NU> S;
+    post_tile4<T, NU, NORM>(L, uout, C, ec, G, tid, part, S);
+}
+
+}  // namespace bmg
+
+namespace bmg {
+
 // ---------------------------------------------- persistent small levels
 // The whole V-cycle below (and including) a small level runs in one workgroup:
 // the iterates, right-hand sides and the residual of these levels stay in LDS

@@ -330,6 +330,12 @@ int level_tile_rows(const bmg_solver *h, int n) { return tile_rows_for(h, n); }
 
 dim3 tile_grid(const TileGeo &g) { return dim3(((g.ntiles + 7) / 8) * 8); }
 
+// Rows per step of the fused passes on five-point levels: 4 (k_pre4, k_post4)
+// or 2 (the general k_pre, k_post).
+#ifndef BMG_FIVE_POINT_STEP_ROWS
+#define BMG_FIVE_POINT_STEP_ROWS 2
+#endif
+
 // nu sweeps, residual and restriction in one pass (results as SMOOTH,
 // RESIDUAL, RESTRICT in turn); the level's iterate moves to the other buffer.
 template <typename T>
@@ -350,14 +356,18 @@ bmg_status fused_pre(bmg_solver *h, int l, int nu, const int *stop)
     T *out = ualt<T>(h, l);
     const dim3 grid = tile_grid(g), blk(FW);
 #define PRE(NINE, NU) hipLaunchKernelGGL((k_pre<T, NINE, NU>), grid, blk, 0, h->st, F, out, C, Cl, g, stop)
+#define PRE4(NU) hipLaunchKernelGGL((k_pre4<T, NU>), grid, blk, 0, h->st, F, out, C, Cl, g, stop)
     trace_begin(h, BMG_TRACE_PRE, l);
     if (nine) {
         if (nu == 1) PRE(true, 1); else if (nu == 2) PRE(true, 2); else PRE(true, 3);
+    } else if (BMG_FIVE_POINT_STEP_ROWS == 4) {
+        if (nu == 1) PRE4(1); else if (nu == 2) PRE4(2); else PRE4(3);
     } else {
         if (nu == 1) PRE(false, 1); else if (nu == 2) PRE(false, 2); else PRE(false, 3);
     }
     trace_end(h, BMG_TRACE_PRE, l);
 #undef PRE
+#undef PRE4
     LAUNCHCHK();
     std::swap(F.u, ualt<T>(h, l));
     return BMG_OK;
@@ -387,8 +397,13 @@ bmg_status fused_post(bmg_solver *h, int l, int nu, const int *stop, bool norm =
     const dim3 grid = tile_grid(g), blk(FW);
 #define POST(NINE, NU, NORM) \
     hipLaunchKernelGGL((k_post<T, NINE, NU, NORM>), grid, blk, 0, h->st, F, out, C, (const T *)Cl.u, g, h->part, stop)
+#define POST4(NU, NORM) \
+    hipLaunchKernelGGL((k_post4<T, NU, NORM>), grid, blk, 0, h->st, F, out, C, (const T *)Cl.u, g, h->part, stop)
     trace_begin(h, BMG_TRACE_POST, l);
-    if (norm) {
+    if (!nine && BMG_FIVE_POINT_STEP_ROWS == 4) {
+        if (norm) { if (nu == 1) POST4(1, true); else POST4(2, true); }
+        else { if (nu == 1) POST4(1, false); else POST4(2, false); }
+    } else if (norm) {
         if (nine) { if (nu == 1) POST(true, 1, true); else POST(true, 2, true); }
         else { if (nu == 1) POST(false, 1, true); else POST(false, 2, true); }
     } else {
@@ -397,6 +412,7 @@ bmg_status fused_post(bmg_solver *h, int l, int nu, const int *stop, bool norm =
     }
     trace_end(h, BMG_TRACE_POST, l);
 #undef POST
+#undef POST4
     LAUNCHCHK();
     std::swap(F.u, ualt<T>(h, l));
     if (norm) h->norm_parts = g.ntiles;
@@ -905,29 +921,33 @@ bmg_status bmg_solve(bmg_solver *h, const double *rhs, double *x, double tol, bm
 }
 
 // --------------------------------------------------------- level access
-// Two FP64 V-cycles from x (tight n x n) on h; rho = (r2 / r0)^(1/2) with the
-// relative residuals before and after; the iterate goes to xout (tight).
-static bmg_status probe2(bmg_solver *h, const double *rhs, const double *x, double *xout, double *rho)
+// `cycles` FP64 V-cycles from x (tight n x n) on h; rho is the mean factor per
+// cycle over the second half of the probe, (r_cycles / r_(cycles/2))^(2/cycles),
+// which leaves out the first cycles' fast decay of the components an initial
+// guess makes easy; the iterate goes to xout (tight).
+static bmg_status probe(bmg_solver *h, const double *rhs, const double *x, double *xout, int cycles, double *rho)
 {
     const Lev<double> &L = h->L[0];
     TRY(pack_in(h, rhs, L.b));
     TRY(pack_in(h, x, L.u));
-    double v[S_NSCAL];
-    TRY(sumsq<double>(h, L, h->nine[0], false, L.b, S_TMP, false, 0.0, 0));
-    TRY(resnorm_dd(h, L.b, L.u, nullptr, 0, nullptr, S_SUMSQ, false, 0.0, 0, 0.0));
-    TRY(read_scalars(h, v, 0, 4));
-    const double r0 = v[S_SUMSQ];
-    TRY(cycle64(h, nullptr));
-    TRY(cycle64(h, nullptr));
-    TRY(resnorm_dd(h, L.b, L.u, nullptr, 0, nullptr, S_SUMSQ, false, 0.0, 0, 0.0));
-    TRY(read_scalars(h, v, 0, 4));
-    *rho = r0 > 0.0 ? sqrt(sqrt(v[S_SUMSQ] / r0)) : 0.0;
+    double v[S_NSCAL], rmid = 0.0;
+    const int half = cycles / 2;
+    for (int k = 1; k <= cycles; ++k) {
+        TRY(cycle64(h, nullptr));
+        if (k == half || k == cycles) {
+            TRY(resnorm_dd(h, L.b, L.u, nullptr, 0, nullptr, S_SUMSQ, false, 0.0, 0, 0.0));
+            TRY(read_scalars(h, v, 0, 4));
+            if (k == half) rmid = v[S_SUMSQ];
+        }
+    }
+    *rho = rmid > 0.0 ? pow(v[S_SUMSQ] / rmid, 1.0 / (cycles - half)) : 0.0;
+    *rho = sqrt(*rho);   // the sums are of squares
     TRY(pack_out(h, L.u, xout));
     return BMG_OK;
 }
 
 bmg_status bmg_solve_select(bmg_solver *learned, bmg_solver *boxmg, const double *rhs, double *x, double tol,
-                            bmg_info *info, int *used, double *rho)
+                            int probe_cycles, bmg_info *info, int *used, double *rho)
 {
     if (!learned || !boxmg || !rhs || !x || !used || !rho) return fail(BMG_EINVAL, "NULL argument");
     if (learned->n != boxmg->n) return fail(BMG_EINVAL, "the two hierarchies have different sizes");
@@ -935,23 +955,53 @@ bmg_status bmg_solve_select(bmg_solver *learned, bmg_solver *boxmg, const double
         return fail(BMG_EINVAL, "the probe compares FP64 hierarchies");
     if (learned->opt.interp != BMG_INTERP_LEARNED || boxmg->opt.interp != BMG_INTERP_BOXMG)
         return fail(BMG_EINVAL, "expected a learned and an operator-induced hierarchy");
+    if (probe_cycles == 0) probe_cycles = 8;
+    if (probe_cycles < 2 || probe_cycles > 1000) return fail(BMG_EINVAL, "probe_cycles=%d out of range", probe_cycles);
     // the BoxMG probe reads x first and leaves its iterate in its XH buffer
     // (tight n x n); the learned probe then overwrites x with its own
     double *scratch = boxmg->XH;
-    TRY(probe2(boxmg, rhs, x, scratch, &rho[1]));
+    TRY(probe(boxmg, rhs, x, scratch, probe_cycles, &rho[1]));
     HIPCHK(hipStreamSynchronize(boxmg->st));
-    TRY(probe2(learned, rhs, x, x, &rho[0]));
-    bmg_solver *w = learned;
-    *used = BMG_INTERP_LEARNED;
+    TRY(probe(learned, rhs, x, x, probe_cycles, &rho[0]));
     if (rho[0] > rho[1]) {
-        w = boxmg;
         *used = BMG_INTERP_BOXMG;
         HIPCHK(hipMemcpyAsync(x, scratch, (size_t)boxmg->n * boxmg->n * sizeof(double), hipMemcpyDeviceToDevice,
                               boxmg->st));
         HIPCHK(hipStreamSynchronize(boxmg->st));
+        const bmg_status s = bmg_solve(boxmg, rhs, x, tol, info);
+        if (info) info->cycles += probe_cycles;
+        return s;
     }
-    const bmg_status s = bmg_solve(w, rhs, x, tol, info);
-    if (info) info->cycles += 2;
+    // the learned hierarchy continues in chunks of WATCH cycles; a chunk whose
+    // factor exceeds the BoxMG probe's hands the iterate to BoxMG
+    constexpr int WATCH = 16;
+    *used = BMG_INTERP_LEARNED;
+    const int maxc = learned->opt.max_cycles;
+    int done = probe_cycles;
+    bmg_status s = BMG_ENOCONV;
+    double *hist = info ? info->history : nullptr;
+    bmg_info ci{};
+    while (done < maxc + probe_cycles) {
+        learned->opt.max_cycles = std::min(WATCH, maxc + probe_cycles - done);
+        ci = bmg_info{};
+        ci.history = hist;
+        s = bmg_solve(learned, rhs, x, tol, &ci);
+        learned->opt.max_cycles = maxc;
+        done += ci.cycles;
+        if (s != BMG_ENOCONV) break;
+        if (ci.rho > rho[1]) {
+            *used = BMG_INTERP_BOXMG;
+            ci = bmg_info{};
+            ci.history = hist;
+            s = bmg_solve(boxmg, rhs, x, tol, &ci);
+            done += ci.cycles;
+            break;
+        }
+    }
+    if (info) {
+        *info = ci;
+        info->cycles = done;
+    }
     return s;
 }
 

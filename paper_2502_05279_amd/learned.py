@@ -56,29 +56,41 @@ class Trainer:
         self.inner_max = inner_max
         self._ws = None
 
-    def sample_loss(self, st: torch.Tensor, seed: int) -> float:
+        self.skipped = 0
+
+    def sample_loss(self, st: torch.Tensor, seed: int):
+        """Loss of one sample (its gradient added to the network's sum), or
+        None when the operator-induced weights of the levels below the learned
+        one break down on the coarse operator (the sample is skipped)."""
         n = st.shape[0]
-        need = boxmg.workspace_bytes(n, st.shape[2], interp=boxmg.BMG_INTERP_LEARNED)
+        need = boxmg.workspace_bytes(n, st.shape[2])   # the layout does not depend on the weights
         if self._ws is None or self._ws.numel() < need:
             self._ws = torch.empty(max(need, 1 << 20), dtype=torch.uint8, device=st.device)
-        S = boxmg.Solver(st, workspace=self._ws, interp=boxmg.BMG_INTERP_LEARNED, learned_levels=1,
-                         net=self.net)
+        try:
+            S = boxmg.Solver(st, workspace=self._ws, interp=boxmg.BMG_INTERP_LEARNED, learned_levels=1,
+                             net=self.net)
+        except boxmg.BoxMGError as e:
+            if e.status != boxmg.BMG_EBREAKDOWN:
+                raise
+            self.skipped += 1
+            return None
         r0 = torch.from_numpy(inputs.residual_probe(n, seed)).to(st.device)
         loss, _ = self.net.twogrid(S, r0, self.inner_tol, self.inner_max)
         S.close()
         return loss
 
-    def step(self, batch, seeds, lr: float) -> float:
+    def step(self, batch, seeds, lr: float):
         self.net.zero_grad()
-        tot = 0.0
-        for st, sd in zip(batch, seeds):
-            tot += self.sample_loss(st, sd)
-        self.net.adam(lr, scale=1.0 / len(batch))
-        return tot / len(batch)
+        losses = [v for v in (self.sample_loss(st, sd) for st, sd in zip(batch, seeds)) if v is not None]
+        if not losses:
+            return None
+        self.net.adam(lr, scale=1.0 / len(losses))
+        return float(np.mean(losses))
 
     def mean_loss(self, samples, seed0: int) -> float:
         self.net.zero_grad()
-        return float(np.mean([self.sample_loss(st, seed0 + t) for t, st in enumerate(samples)]))
+        v = [x for x in (self.sample_loss(st, seed0 + t) for t, st in enumerate(samples)) if x is not None]
+        return float(np.mean(v)) if v else float("nan")
 
 
 def train(fields: int = 2000, epochs: int = 1, batch: int = 16, lr: float = 1e-3, n: int = 255,
@@ -97,11 +109,12 @@ def train(fields: int = 2000, epochs: int = 1, batch: int = 16, lr: float = 1e-3
         for b0 in range(0, len(order), batch):
             idx = order[b0:b0 + batch]
             loss = tr.step([samples[t] for t in idx], [1_000_000 * (ep + 1) + int(t) for t in idx], lr)
-            hist["train"].append(loss)
+            if loss is not None:
+                hist["train"].append(loss)
             step += 1
             if step % 50 == 0:
                 log(json.dumps({"epoch": ep, "step": step, "loss": float(np.mean(hist["train"][-50:])),
-                                "s": round(time.perf_counter() - t0, 1)}))
+                                "skipped": tr.skipped, "s": round(time.perf_counter() - t0, 1)}))
             if max_minutes and time.perf_counter() - t0 > 60 * max_minutes:
                 break
         hist["held_out"].append(tr.mean_loss(held, 123_000))
