@@ -29,15 +29,12 @@ if ROOT not in sys.path:
 METRIC = "fine DOF/s solved to 1e-10 rel. residual (4095^2); smoother HBM GB/s vs peak"
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic bytes per fine point of one pass of each traced kernel class
-# (FP64, symmetric compact stencil, each array read or written once):
-#   smoothing sweep on the five-point fine level: A_O, A_W, A_S, b, u read, u
-#   written = 48 B; fused pre pass (nu1 sweeps + residual + restriction):
-#   stencil 24, b 8, u 8 read, u 8 written, weights 16/4 and b_c 8/4 per fine
-#   point = 66 B; fused post pass (interpolation + nu2 sweeps + residual norm):
-#   e_c 8/4, weights 16/4... see the design notes; the figure below is what the
-#   traced class moves per fine point.
-BYTES_PER_POINT = {"smooth": 48.0, "pre": 66.0, "post": 66.0, "resnorm": 56.0}
+# The algorithmic bytes of the timed launches come from the library, which
+# counts each array a launch needs once (read or written) for the variant that
+# ran: a five-point FP64 pre pass reads A_O, A_W, A_S, b, u and writes u (48 B
+# per fine point) and writes b_c, u_c (16 B per coarse point: 4 per fine point),
+# 52 B per fine point, as it computes the interpolation weights itself; with
+# stored weights their 8 planes add 16 B per fine point.
 
 
 def workload(name: str):
@@ -294,12 +291,13 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     infos = []
-    launches, kms = 0, 0.0
+    launches, kms, kbytes = 0, 0.0, 0.0
     for _ in range(args.steps):
         S, x, info = step(True)
-        nl, ms = S.trace_read()
+        nl, ms, nb = S.trace_read()
         launches += nl
         kms += ms
+        kbytes += nb
         infos.append(info)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -307,8 +305,8 @@ def main():
     info = infos[-1]
     ms_step = dt * 1e3 / args.steps
     avg_ms = kms / max(launches, 1)
-    bpp = BYTES_PER_POINT.get(tclass, 64.0)
-    achieved = bpp * n * n / (avg_ms * 1e-3) / 1e9 if launches else None
+    bpl = kbytes / max(launches, 1)                     # algorithmic bytes per launch
+    achieved = bpl / (avg_ms * 1e-3) / 1e9 if launches else None
     metric = METRIC
     extra = {}
     if prec == boxmg.BMG_FP32_IR:
@@ -348,7 +346,7 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS if achieved else None,
                      "traffic": None, "launches": launches, "avg_launch_ms": avg_ms,
-                     "bytes_per_point": bpp},
+                     "bytes_per_launch": bpl, "bytes_per_point": bpl / (n * n)},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, info["cycles"], args.cpu_sample_cycles)

@@ -218,11 +218,14 @@ bmg_status bmg_step(bmg_solver *h, int level, int step, int arg, int fp32);
 /* Kernel timing with HIP events on the handle's stream.  While enabled, every
  * launch of the kernels of class `kclass` on level `level` is bracketed by an
  * event pair (at most 65536 pairs are kept).  bmg_trace_read synchronises the
- * stream and returns the number of launches timed and their total duration in
- * milliseconds, then clears the record.  Classes: */
+ * stream and returns the number of launches timed, their total duration in
+ * milliseconds and (bytes, may be NULL) their algorithmic HBM bytes: each
+ * array the launch needs counted once, read or written, for the variant that
+ * ran (a fused pre pass that computes its weights does not count them).  It
+ * then clears the record.  Classes: */
 enum { BMG_TRACE_SMOOTH = 0, BMG_TRACE_PRE = 1, BMG_TRACE_POST = 2, BMG_TRACE_RESNORM = 3 };
 bmg_status bmg_trace_enable(bmg_solver *h, int kclass, int level, int on);
-bmg_status bmg_trace_read(bmg_solver *h, int *launches, double *total_ms);
+bmg_status bmg_trace_read(bmg_solver *h, int *launches, double *total_ms, double *bytes);
 
 /* ------------------------------------------------------------------------
  * Tile shapes of the fused passes.  A process-wide table of rows per tile for

@@ -44,7 +44,7 @@ def _time_level(stencil, rhs, level: int, rows: int, precision: int, cycles: int
         S.trace_enable(cls, level)
         for _ in range(cycles):
             S.vcycle(rhs, x, want_residual=False)
-        nl, ms = S.trace_read()
+        nl, ms, _ = S.trace_read()
         S.trace_enable(cls, level, on=False)
         total += ms / max(nl, 1)
     S.close()

@@ -83,7 +83,7 @@ def lib():
             "bmg_import": ([vp, i, i, vp], i),
             "bmg_step": ([vp, i, i, i, i], i),
             "bmg_trace_enable": ([vp, i, i, i], i),
-            "bmg_trace_read": ([vp, C.POINTER(i), C.POINTER(d)], i),
+            "bmg_trace_read": ([vp, C.POINTER(i), C.POINTER(d), C.POINTER(d)], i),
             "bmg_tile_rows_set": ([i, i], i),
             "bmg_tile_rows_get": ([i, C.POINTER(i)], i),
             "bmg_batch_workspace_bytes": ([i, C.POINTER(i), C.POINTER(Options), C.POINTER(sz)], i),
@@ -264,9 +264,10 @@ class Solver:
         _check(lib().bmg_trace_enable(self._h, TRACE[kclass], level, int(on)), "bmg_trace_enable")
 
     def trace_read(self):
-        n, ms = C.c_int(0), C.c_double(0.0)
-        _check(lib().bmg_trace_read(self._h, C.byref(n), C.byref(ms)), "bmg_trace_read")
-        return n.value, ms.value
+        """(launches, total ms, algorithmic bytes) of the timed launches."""
+        n, ms, nb = C.c_int(0), C.c_double(0.0), C.c_double(0.0)
+        _check(lib().bmg_trace_read(self._h, C.byref(n), C.byref(ms), C.byref(nb)), "bmg_trace_read")
+        return n.value, ms.value, nb.value
 
 
 def tile_rows_set(n: int, rows: int) -> None:

@@ -94,18 +94,30 @@ __device__ __forceinline__ T res_lds(const T *su, const T *sW, const T *sSW, con
 // global data of step e+2 (rows e+2, e+3 and the weights of its restriction
 // row) is requested before step e computes, so the loads overlap the compute.
 // LDS of one pre/post tile (ring rows RU, nine-point rings only if NINE)
-template <typename T, bool NINE, int NU>
+template <typename T, bool NINE, int NU, bool WREC = false>
 struct TileLds {
     static constexpr int RW = 2 * NU + 4;
     static constexpr int RU = RW <= 8 ? 8 : 16;
     T su[RU * FW], sW[RU * FW], sx[4 * FW];
-    T sSW[NINE ? RU * FW : 1], sNW[NINE ? RU * FW : 1];
+    // unused parts have length zero: four five-point FP64 tiles of 40 KiB
+    // then share one CU's 160 KiB
+    T sSW[NINE ? RU * FW : 0], sNW[NINE ? RU * FW : 0];
+    // weights computed in the pass (WREC): y-edge LB, LA of the even columns
+    // and six values of the odd columns, each indexed by lane / 2
+    T wy[WREC ? FW : 0], wx[WREC ? 3 * FW : 0];
 };
 
-template <typename T, bool NINE, int NU>
+// With WREC the restriction weights are not read: each column computes the
+// operator-induced weights of its own F-points from the stencil rows in the
+// window (the expressions of k_weights_edges / k_weights_corners in their
+// order, so the same bits), and the restricting columns collect their
+// neighbours' through LDS.  Step e computes the y-edges and cell centres of
+// row e-2NU-1 and the x-edges of row e-2NU; the weights of the rows below come
+// from the previous step.
+template <typename T, bool NINE, int NU, bool WREC = false>
 __device__ __forceinline__ void pre_tile(const Lev<T> &L, T *__restrict__ uout, const Wts<T> &C,
                                          const Lev<T> &Cl, const TileGeo &G, int tid,
-                                         TileLds<T, NINE, NU> &S)
+                                         TileLds<T, NINE, NU, WREC> &S)
 {
     constexpr int RW = 2 * NU + 4;                 // window rows
     constexpr int RU = RW <= 8 ? 8 : 16;           // LDS ring rows (power of two)
@@ -160,6 +172,36 @@ __device__ __forceinline__ void pre_tile(const Lev<T> &L, T *__restrict__ uout, 
         rS[k] = ld_row(L.S, row);
         rB[k] = ld_row(L.b, row);
     }
+    // the lumped nine-point row of this column at window row k (WREC)
+    auto row9 = [&](int k, int row, T a[9]) {
+        const int r0 = slot<RU>(row) * FW + lane;
+        a[0] = NINE ? sSW[r0] : (T)0;
+        a[1] = rS[k];
+        a[2] = NINE ? sNW[slot<RU>(row - 1) * FW + lane + 1] : (T)0;
+        a[3] = sW[r0];
+        a[4] = rO[k];
+        a[5] = sW[r0 + 1];
+        a[6] = NINE ? sNW[r0] : (T)0;
+        a[7] = rS[k + 1];
+        a[8] = NINE ? sSW[slot<RU>(row + 1) * FW + lane + 1] : (T)0;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            if (q == 4) continue;
+            if (a[q] > (T)0) {
+                a[4] = a[4] + a[q];
+                a[q] = (T)0;
+            }
+        }
+    };
+    // exchange index of this column: lanes and columns have opposite parity
+    // (x0 - hx is odd: x0 = 1 + tx * useful with useful even, hx even), so the
+    // odd columns' indices lane/2 are distinct, and so are the even columns'
+    const int wl = lane >> 1;
+    const bool odd_col = i & 1;
+    // weights of the previous step (rows below) kept by their columns: odd
+    // columns LNE, LNW of the centre and LR, LL of the x-edge, even columns LA
+    T pLNE = 0, pLNW = 0, pLR = 0, pLL = 0, pLA = 0, yLB = 0, yLA = 0;
+
     // data of the first step
     T pu0, pu1, pW0, pW1, pO0, pO1, pS0, pS1, pB0, pB1, pSW0 = 0, pSW1 = 0, pNW0 = 0, pNW1 = 0;
     T pw[8], w[8];
@@ -173,7 +215,7 @@ __device__ __forceinline__ void pre_tile(const Lev<T> &L, T *__restrict__ uout, 
             pSW0 = ld_row(L.SW, e); pSW1 = ld_row(L.SW, e + 1);
             pNW0 = ld_row(L.NW, e); pNW1 = ld_row(L.NW, e + 1);
         }
-        ld_w((e - 2 * NU - 2) >> 1, pw);
+        if (!WREC) ld_w((e - 2 * NU - 2) >> 1, pw);
     };
     fetch(es);
 
@@ -189,11 +231,30 @@ __device__ __forceinline__ void pre_tile(const Lev<T> &L, T *__restrict__ uout, 
             rO[RW - 2] = pO0; rO[RW - 1] = pO1;
             rS[RW - 2] = pS0; rS[RW - 1] = pS1;
             rB[RW - 2] = pB0; rB[RW - 1] = pB1;
+            if (!WREC) {
 #pragma unroll
-            for (int q = 0; q < 8; ++q) w[q] = pw[q];
+                for (int q = 0; q < 8; ++q) w[q] = pw[q];
+            }
         }
         if (e + 2 <= elast) fetch(e + 2);
         __syncthreads();
+        if (WREC && !odd_col) {
+            // y-edge of row f+1 (f = e-2NU-2, window row 1): collapse along x;
+            // zero where the F-point does not exist (the ring), as in the
+            // stored planes
+            const int row = e - 2 * NU - 1;
+            yLB = yLA = (T)0;
+            if (col_upd && row >= 1 && row <= n) {
+                T a[9];
+                row9(1, row, a);
+                const T D = (a[4] + a[3]) + a[5];
+                yLB = -((a[1] + a[0]) + a[2]) / D;
+                yLA = -((a[7] + a[6]) + a[8]) / D;
+            }
+            S.wy[wl] = yLB;
+            S.wy[FW / 2 + wl] = yLA;
+        }
+        // (the colour barriers below publish wy)
         // NU sweeps, each over colours 0,1 (even row) then 2,3 (odd row)
 #pragma unroll
         for (int s = 0; s < NU; ++s) {
@@ -215,6 +276,32 @@ __device__ __forceinline__ void pre_tile(const Lev<T> &L, T *__restrict__ uout, 
             if (col_own && row >= y0 && row < y1)
                 uout[(size_t)row * ld + i] = su[slot<RU>(row) * FW + lane];
         }
+        if (WREC && col_upd && odd_col) {
+            // x-edge of row f+2 (window row 2): collapse along y (zero on the ring)
+            T a[9];
+            T xLL = (T)0, xLR = (T)0;
+            if (e - 2 * NU >= 1 && e - 2 * NU <= n) {
+                row9(2, e - 2 * NU, a);
+                const T D = (a[4] + a[7]) + a[1];
+                xLL = -((a[3] + a[6]) + a[0]) / D;
+                xLR = -((a[5] + a[8]) + a[2]) / D;
+            }
+            // cell centre of row f+1 from its own row and the edges around it
+            row9(1, e - 2 * NU - 1, a);
+            const T lbw = S.wy[wl - 1], law = S.wy[FW / 2 + wl - 1];
+            const T lbe = S.wy[wl], lae = S.wy[FW / 2 + wl];
+            const T cLNE = -((a[8] + a[7] * xLR) + a[5] * lae) / a[4];
+            const T cLNW = -((a[6] + a[7] * xLL) + a[3] * law) / a[4];
+            const T cLSE = -((a[2] + a[1] * pLR) + a[5] * lbe) / a[4];
+            const T cLSW = -((a[0] + a[1] * pLL) + a[3] * lbw) / a[4];
+            S.wx[wl] = pLNE;
+            S.wx[FW / 2 + wl] = pLNW;
+            S.wx[FW + wl] = pLR;
+            S.wx[3 * FW / 2 + wl] = pLL;
+            S.wx[2 * FW + wl] = cLSE;
+            S.wx[5 * FW / 2 + wl] = cLSW;
+            pLNE = cLNE; pLNW = cLNW; pLR = xLR; pLL = xLL;
+        }
         // residual of rows e-2NU and e-2NU-1
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
@@ -226,6 +313,18 @@ __device__ __forceinline__ void pre_tile(const Lev<T> &L, T *__restrict__ uout, 
             sr[(row & 3) * FW + lane] = r;
         }
         __syncthreads();
+        if (WREC && restrictor) {
+            // odd neighbours: i-1 at exchange index wl, i+1 at wl+1
+            w[0] = S.wx[wl];                  // LNE of the centre (i-1, f-1)
+            w[1] = pLA;                       // LA of the y-edge (i, f-1)
+            w[2] = S.wx[FW / 2 + wl + 1];     // LNW of the centre (i+1, f-1)
+            w[3] = S.wx[FW + wl];             // LR of the x-edge (i-1, f)
+            w[4] = S.wx[3 * FW / 2 + wl + 1]; // LL of the x-edge (i+1, f)
+            w[5] = S.wx[2 * FW + wl];         // LSE of the centre (i-1, f+1)
+            w[6] = yLB;                       // LB of the y-edge (i, f+1)
+            w[7] = S.wx[5 * FW / 2 + wl + 1]; // LSW of the centre (i+1, f+1)
+        }
+        if (WREC && !odd_col) pLA = yLA;
         // restriction of coarse row J = (e - 2NU - 2) / 2 by the even columns
         {
             const int f = e - 2 * NU - 2, J = f >> 1;
@@ -249,15 +348,15 @@ __device__ __forceinline__ void pre_tile(const Lev<T> &L, T *__restrict__ uout, 
     }
 }
 
-template <typename T, bool NINE, int NU>
+template <typename T, bool NINE, int NU, bool WREC = false>
 __global__ __launch_bounds__(FW) void k_pre(Lev<T> L, T *__restrict__ uout, Wts<T> C, Lev<T> Cl,
                                              TileGeo G, const int *stop)
 {
     if (stopped(stop)) return;
     const int tid = tile_id(G.ntiles);
     if (tid < 0) return;
-    __shared__ TileLds<T, NINE, NU> S;
-    pre_tile<T, NINE, NU>(L, uout, C, Cl, G, tid, S);
+    __shared__ TileLds<T, NINE, NU, WREC> S;
+    pre_tile<T, NINE, NU, WREC>(L, uout, C, Cl, G, tid, S);
 }
 
 // ---------------------------------------------------------- post pass
@@ -306,26 +405,24 @@ __device__ __forceinline__ void post_tile(const Lev<T> &L, T *__restrict__ uout,
     // odd columns: LL, LR at (Ix, e/2), then LSW, LSE, LNW, LNE at (Ix, e/2+1);
     // even columns: LB, LA at (i/2, e/2+1)
     struct IW { T w[6]; };
+    // the planes this column reads for its odd row: LSW, LSE, LNW, LNE (odd
+    // columns) or LB, LA (even columns); every lane issues the same six loads
+    const int p2 = odd_i ? LSW : LB, p3 = odd_i ? LSE : LA;
     auto ld_iw = [&](int e) -> IW {
         IW r;
         T *w = r.w;
         const int J0 = e >> 1, J1 = J0 + 1;
         const bool ok0 = col_upd && odd_i && e >= 1 && e <= n;
         const bool ok1 = col_upd && e + 1 >= 1 && e + 1 <= n;
+        const bool ok2 = ok1 && odd_i;
         const size_t c0 = ok0 ? (size_t)J0 * ldc + Ix : 0;
         const size_t c1 = ok1 ? (size_t)J1 * ldc + (odd_i ? Ix : (i >> 1)) : 0;
         w[0] = ok0 ? C.at(LL, c0) : (T)0;
         w[1] = ok0 ? C.at(LR, c0) : (T)0;
-        if (odd_i) {
-            w[2] = ok1 ? C.at(LSW, c1) : (T)0;
-            w[3] = ok1 ? C.at(LSE, c1) : (T)0;
-            w[4] = ok1 ? C.at(LNW, c1) : (T)0;
-            w[5] = ok1 ? C.at(LNE, c1) : (T)0;
-        } else {
-            w[2] = ok1 ? C.at(LB, c1) : (T)0;
-            w[3] = ok1 ? C.at(LA, c1) : (T)0;
-            w[4] = w[5] = (T)0;
-        }
+        w[2] = ok1 ? C.at(p2, c1) : (T)0;
+        w[3] = ok1 ? C.at(p3, c1) : (T)0;
+        w[4] = ok2 ? C.at(LNW, c1) : (T)0;
+        w[5] = ok2 ? C.at(LNE, c1) : (T)0;
         return r;
     };
     // u + P e_c at (i, row) for an even (row = e) or odd (row = e+1) row, with
@@ -466,7 +563,8 @@ __device__ __forceinline__ void post_tile(const Lev<T> &L, T *__restrict__ uout,
         }
     }
     if (NORM) {
-        acc = block_sum(acc);
+        __syncthreads();  // the residual ring is free again: reduce through it
+        acc = block_sum(acc, reinterpret_cast<double *>(S.sx));
         if (threadIdx.x == 0) part[tid] = acc;
     }
 }
@@ -718,26 +816,24 @@ __device__ __forceinline__ void post_tile4(const Lev<T> &L, T *__restrict__ uout
         return (ccol_in && J >= 0 && J <= nc + 1) ? ec[(size_t)J * ldc + Ie] : (T)0;
     };
     struct IW { T w[6]; };
+    // the planes this column reads for its odd row: LSW, LSE, LNW, LNE (odd
+    // columns) or LB, LA (even columns); every lane issues the same six loads
+    const int p2 = odd_i ? LSW : LB, p3 = odd_i ? LSE : LA;
     auto ld_iw = [&](int e) -> IW {
         IW r;
         T *w = r.w;
         const int J0 = e >> 1, J1 = J0 + 1;
         const bool ok0 = col_upd && odd_i && e >= 1 && e <= n;
         const bool ok1 = col_upd && e + 1 >= 1 && e + 1 <= n;
+        const bool ok2 = ok1 && odd_i;
         const size_t c0 = ok0 ? (size_t)J0 * ldc + Ix : 0;
         const size_t c1 = ok1 ? (size_t)J1 * ldc + (odd_i ? Ix : (i >> 1)) : 0;
         w[0] = ok0 ? C.at(LL, c0) : (T)0;
         w[1] = ok0 ? C.at(LR, c0) : (T)0;
-        if (odd_i) {
-            w[2] = ok1 ? C.at(LSW, c1) : (T)0;
-            w[3] = ok1 ? C.at(LSE, c1) : (T)0;
-            w[4] = ok1 ? C.at(LNW, c1) : (T)0;
-            w[5] = ok1 ? C.at(LNE, c1) : (T)0;
-        } else {
-            w[2] = ok1 ? C.at(LB, c1) : (T)0;
-            w[3] = ok1 ? C.at(LA, c1) : (T)0;
-            w[4] = w[5] = (T)0;
-        }
+        w[2] = ok1 ? C.at(p2, c1) : (T)0;
+        w[3] = ok1 ? C.at(p3, c1) : (T)0;
+        w[4] = ok2 ? C.at(LNW, c1) : (T)0;
+        w[5] = ok2 ? C.at(LNE, c1) : (T)0;
         return r;
     };
     // u + P e_c (the expression of post_tile's interp)

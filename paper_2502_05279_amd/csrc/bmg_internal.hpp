@@ -85,6 +85,7 @@ struct bmg_solver {
     int tr_class = -1, tr_level = -1;
     std::vector<hipEvent_t> tr_ev;
     int tr_used = 0;
+    double tr_bytes = 0.0, tr_pending = 0.0;   // algorithmic bytes of the timed launches
 };
 
 namespace bmgi {

@@ -473,10 +473,10 @@ static __global__ void k_interp_add(Lev<T> L, Wts<T> C, const T *__restrict__ ec
 }
 
 // ------------------------------------------------------------ reductions
-// Wave64 + LDS block reduction of a double; result valid in thread 0.
-__device__ __forceinline__ double block_sum(double v)
+// Wave64 + LDS block reduction of a double (up to 16 waves) through 16
+// doubles of LDS at `part`; result valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double *part)
 {
-    __shared__ double part[16];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -489,6 +489,12 @@ __device__ __forceinline__ double block_sum(double v)
         for (int o = 8; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
     }
     return v;
+}
+
+__device__ __forceinline__ double block_sum(double v)
+{
+    __shared__ double part[16];
+    return block_sum(v, part);
 }
 
 // Per-block partial sums of squares of the residual (r_mode = 1: recompute

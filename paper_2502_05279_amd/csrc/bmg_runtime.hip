@@ -204,9 +204,12 @@ bmg_status check_options(const bmg_options &o)
 }
 
 // ------------------------------------------------------------ tracing
-void trace_begin(bmg_solver *h, int kclass, int level)
+// `bytes`: the algorithmic bytes of the bracketed launches (each array the
+// kernels need read or written once), summed for bmg_trace_read.
+void trace_begin(bmg_solver *h, int kclass, int level, double bytes)
 {
     if (h->tr_class != kclass || h->tr_level != level) return;
+    h->tr_pending = bytes;
     if (h->tr_used + 2 > (int)h->tr_ev.size()) {
         if ((int)h->tr_ev.size() >= 2 * MAX_TRACE) return;
         const size_t grow = std::min<size_t>(2 * MAX_TRACE, std::max<size_t>(64, 2 * h->tr_ev.size()));
@@ -223,7 +226,12 @@ void trace_end(bmg_solver *h, int kclass, int level)
     if (h->tr_used + 2 > (int)h->tr_ev.size()) return;
     (void)hipEventRecord(h->tr_ev[h->tr_used + 1], h->st);
     h->tr_used += 2;
+    h->tr_bytes += h->tr_pending;
 }
+
+// Elements of the stencil planes stored per point: O, W, S (five-point) or
+// also SW, NW (nine-point).
+static inline double stencil_planes(bool nine) { return nine ? 5.0 : 3.0; }
 
 // -------------------------------------------------------- cycle steps
 const dim3 B2(64, 4);
@@ -232,7 +240,9 @@ template <typename T>
 bmg_status smooth(bmg_solver *h, const Lev<T> &L, bool nine, int sweeps, const int *stop, int level)
 {
     if (sweeps <= 0) return BMG_OK;
-    trace_begin(h, BMG_TRACE_SMOOTH, level);
+    // per sweep: stencil, b and u read, u written
+    trace_begin(h, BMG_TRACE_SMOOTH, level,
+                sweeps * (stencil_planes(nine) + 3.0) * sizeof(T) * (double)L.n * L.n);
     for (int s = 0; s < sweeps; ++s) {
         for (int c = 0; c < 4; ++c) {
             const int ni = (c & 1) ? (L.n + 1) / 2 : (L.n - 1) / 2;
@@ -330,6 +340,19 @@ int level_tile_rows(const bmg_solver *h, int n) { return tile_rows_for(h, n); }
 
 dim3 tile_grid(const TileGeo &g) { return dim3(((g.ntiles + 7) / 8) * 8); }
 
+// FP64 pre passes compute the restriction weights (1) or read them (0).
+#ifndef BMG_PRE_WEIGHTS_IN_PASS
+#define BMG_PRE_WEIGHTS_IN_PASS 1
+#endif
+
+template <typename T>
+static bool pre_weights_in_pass(const bmg_solver *h, int l, bool nine)
+{
+    const bool learned = h->opt.interp == BMG_INTERP_LEARNED &&
+                         (h->opt.learned_levels == 0 || l < h->opt.learned_levels);
+    return BMG_PRE_WEIGHTS_IN_PASS && std::is_same<T, double>::value && !nine && !learned;
+}
+
 // Rows per step of the fused passes on five-point levels: 4 (k_pre4, k_post4)
 // or 2 (the general k_pre, k_post).
 #ifndef BMG_FIVE_POINT_STEP_ROWS
@@ -356,9 +379,24 @@ bmg_status fused_pre(bmg_solver *h, int l, int nu, const int *stop)
     T *out = ualt<T>(h, l);
     const dim3 grid = tile_grid(g), blk(FW);
 #define PRE(NINE, NU) hipLaunchKernelGGL((k_pre<T, NINE, NU>), grid, blk, 0, h->st, F, out, C, Cl, g, stop)
+#define PREW(NINE, NU) hipLaunchKernelGGL((k_pre<T, NINE, NU, true>), grid, blk, 0, h->st, F, out, C, Cl, g, stop)
 #define PRE4(NU) hipLaunchKernelGGL((k_pre4<T, NU>), grid, blk, 0, h->st, F, out, C, Cl, g, stop)
-    trace_begin(h, BMG_TRACE_PRE, l);
-    if (nine) {
+    // Five-point FP64 levels with operator-induced weights compute them in the
+    // pass instead of reading the 8 planes (16 of 68 bytes per fine point).
+    // Not FP32 levels (their weights are the rounded FP64 ones), not learned
+    // weights (no formula), and not nine-point levels, whose divisions cost
+    // more time than the loads they replace.
+    const bool wrec = pre_weights_in_pass<T>(h, l, nine);
+    // stencil, b and u read, u written on the fine level; b and u (zero)
+    // written on the coarse level, and the 8 weight planes read unless computed
+    trace_begin(h, BMG_TRACE_PRE, l,
+                sizeof(T) * ((stencil_planes(nine) + 3.0) * (double)F.n * F.n +
+                             (wrec ? 2.0 : 10.0) * (double)Cl.n * Cl.n));
+    if (wrec) {
+        if constexpr (std::is_same<T, double>::value) {
+            if (nu == 1) PREW(false, 1); else if (nu == 2) PREW(false, 2); else PREW(false, 3);
+        }
+    } else if (nine) {
         if (nu == 1) PRE(true, 1); else if (nu == 2) PRE(true, 2); else PRE(true, 3);
     } else if (BMG_FIVE_POINT_STEP_ROWS == 4) {
         if (nu == 1) PRE4(1); else if (nu == 2) PRE4(2); else PRE4(3);
@@ -367,6 +405,7 @@ bmg_status fused_pre(bmg_solver *h, int l, int nu, const int *stop)
     }
     trace_end(h, BMG_TRACE_PRE, l);
 #undef PRE
+#undef PREW
 #undef PRE4
     LAUNCHCHK();
     std::swap(F.u, ualt<T>(h, l));
@@ -399,7 +438,10 @@ bmg_status fused_post(bmg_solver *h, int l, int nu, const int *stop, bool norm =
     hipLaunchKernelGGL((k_post<T, NINE, NU, NORM>), grid, blk, 0, h->st, F, out, C, (const T *)Cl.u, g, h->part, stop)
 #define POST4(NU, NORM) \
     hipLaunchKernelGGL((k_post4<T, NU, NORM>), grid, blk, 0, h->st, F, out, C, (const T *)Cl.u, g, h->part, stop)
-    trace_begin(h, BMG_TRACE_POST, l);
+    // stencil, b and u read, u written on the fine level; the coarse
+    // correction and the 8 weight planes read
+    trace_begin(h, BMG_TRACE_POST, l,
+                sizeof(T) * ((stencil_planes(nine) + 3.0) * (double)F.n * F.n + 9.0 * (double)Cl.n * Cl.n));
     if (!nine && BMG_FIVE_POINT_STEP_ROWS == 4) {
         if (norm) { if (nu == 1) POST4(1, true); else POST4(2, true); }
         else { if (nu == 1) POST4(1, false); else POST4(2, false); }
@@ -474,7 +516,8 @@ bmg_status sumsq(bmg_solver *h, const Lev<T> &L, bool nine, bool res, const T *x
 {
     const int nb = std::min(NPART_ROWS, L.n);
     const int *stop = record ? h->stop : nullptr;
-    trace_begin(h, BMG_TRACE_RESNORM, 0);
+    trace_begin(h, BMG_TRACE_RESNORM, 0,
+                sizeof(T) * (res ? stencil_planes(nine) + 2.0 : 1.0) * (double)L.n * L.n);
     if (res) {
         if (nine) hipLaunchKernelGGL((k_sumsq_partial<T, true, true>), dim3(nb), dim3(256), 0, h->st, L, x, h->part, stop);
         else hipLaunchKernelGGL((k_sumsq_partial<T, false, true>), dim3(nb), dim3(256), 0, h->st, L, x, h->part, stop);
@@ -501,7 +544,10 @@ bmg_status resnorm_dd(bmg_solver *h, const double *B, const double *XH, const do
     const int *stop = record ? h->stop : nullptr;
     const dim3 g(nb), b(256);
 #define RDD(NINE, MODE) hipLaunchKernelGGL((k_resid_dd<NINE, MODE>), g, b, 0, h->st, L, B, XH, XL, rout, h->part, stop)
-    trace_begin(h, BMG_TRACE_RESNORM, 0);
+    // stencil, B and XH (and XL) read; r (mode 1) or b and u (mode 2) written
+    trace_begin(h, BMG_TRACE_RESNORM, 0,
+                8.0 * (stencil_planes(h->nine[0]) + (XL ? 3.0 : 2.0) + (mode == 1 ? 1.0 : mode == 2 ? 2.0 : 0.0)) *
+                    (double)L.n * L.n);
     if (h->nine[0]) {
         if (mode == 0) RDD(true, 0); else if (mode == 1) RDD(true, 1); else RDD(true, 2);
     } else {
@@ -760,7 +806,7 @@ static bmg_status cycle_and_norm(bmg_solver *h, double tol, int maxc, double ref
     if (h->opt.kernels == BMG_KERNELS_FUSED) {
         TRY(fused_vcycle(h, h->stop, true));
         if (h->norm_parts > 0) {
-            trace_begin(h, BMG_TRACE_RESNORM, 0);
+            trace_begin(h, BMG_TRACE_RESNORM, 0, 8.0 * h->norm_parts);   // the partial sums
             hipLaunchKernelGGL(k_sumsq_final, dim3(1), dim3(1024), 0, h->st, (const double *)h->part,
                                h->norm_parts, h->scal + S_SUMSQ, h->hist, h->count, h->stop,
                                (const double *)(h->scal + S_BNORM), tol, maxc, refine);
@@ -1163,10 +1209,11 @@ bmg_status bmg_trace_enable(bmg_solver *h, int kclass, int level, int on)
     h->tr_class = on ? kclass : -1;
     h->tr_level = level;
     h->tr_used = 0;
+    h->tr_bytes = 0.0;
     return BMG_OK;
 }
 
-bmg_status bmg_trace_read(bmg_solver *h, int *launches, double *total_ms)
+bmg_status bmg_trace_read(bmg_solver *h, int *launches, double *total_ms, double *bytes)
 {
     if (!h || !launches || !total_ms) return fail(BMG_EINVAL, "NULL argument");
     HIPCHK(hipStreamSynchronize(h->st));
@@ -1178,7 +1225,9 @@ bmg_status bmg_trace_read(bmg_solver *h, int *launches, double *total_ms)
     }
     *launches = h->tr_used / 2;
     *total_ms = tot;
+    if (bytes) *bytes = h->tr_bytes;
     h->tr_used = 0;
+    h->tr_bytes = 0.0;
     return BMG_OK;
 }
 

@@ -404,3 +404,31 @@ def test_second_solve_on_one_handle(gpu):
     same(host(x1), host(x2), "iterate")
     rel = S.vcycle(rhs, x2.clone())
     assert 0.0 < rel < 1e-9
+
+
+def test_trace_counts_algorithmic_bytes(gpu):
+    """The timed launches' algorithmic bytes: the five-point FP64 pre pass
+    computes its weights (stencil 3 planes, b, u read, u written: 6 values per
+    fine point; b_c, u_c written: 2 per coarse point), the nine-point one reads
+    them (8 planes more per coarse point), and the FP32 hierarchy counts 4-byte
+    values."""
+    p = problem("jump16", 255, 5)
+    st, rhs = gpu_problem(p)
+    for prec, esz in ((boxmg.BMG_FP64, 8), (boxmg.BMG_FP32_IR, 4)):
+        S = boxmg.Solver(st, precision=prec)
+        n0, n1, n2 = S.level_n(0), S.level_n(1), S.level_n(2)
+        fp32 = prec == boxmg.BMG_FP32_IR
+        for lvl, want in ((0, esz * (6 * n0 * n0 + (10 if fp32 else 2) * n1 * n1)),
+                          (1, esz * (8 * n1 * n1 + 10 * n2 * n2))):
+            S.trace_enable("pre", lvl)
+            S.step(lvl, "pre", 2, fp32=fp32)
+            S.step(lvl, "pre", 2, fp32=fp32)
+            nl, ms, nb = S.trace_read()
+            S.trace_enable("pre", lvl, on=False)
+            assert nl == 2 and ms > 0.0
+            assert nb == 2 * want, (prec, lvl, nb, want)
+        S.trace_enable("post", 0)
+        S.step(0, "post", 1, fp32=fp32)
+        nl, ms, nb = S.trace_read()
+        assert nl == 1 and nb == esz * (6 * n0 * n0 + 9 * n1 * n1)
+        S.close()
