@@ -15,6 +15,7 @@ host on a bounded sample.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -35,6 +36,27 @@ HBM_PEAK_GBS = 8000.0
 # per fine point) and writes b_c, u_c (16 B per coarse point: 4 per fine point),
 # 52 B per fine point, as it computes the interpolation weights itself; with
 # stored weights their 8 planes add 16 B per fine point.
+
+
+def measured_traffic(key: str):
+    """HBM bytes per launch of the timed kernel from the committed counter
+    record (FETCH_SIZE and WRITE_SIZE, each scaled by what it reads for a copy
+    of known size), or None when there is none for this run or the kernel's
+    sources have changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        rec = json.load(open(path)).get(key)
+    except (OSError, ValueError):
+        return None
+    if not rec:
+        return None
+    h = hashlib.sha256()
+    for f in rec["sources"]:
+        try:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        except OSError:
+            return None
+    return rec["traffic_bytes_per_launch"] if h.hexdigest() == rec["sources_sha256"] else None
 
 
 def workload(name: str):
@@ -304,9 +326,18 @@ def main():
 
     info = infos[-1]
     ms_step = dt * 1e3 / args.steps
-    avg_ms = kms / max(launches, 1)
     bpl = kbytes / max(launches, 1)                     # algorithmic bytes per launch
-    achieved = bpl / (avg_ms * 1e-3) / 1e9 if launches else None
+    # a solve's last batch of cycles ends in launches that return at once (the
+    # stop flag is set); the fine pre pass runs once per cycle, so its working
+    # launches are the cycles, and their average includes those few microseconds
+    working = launches
+    if tclass == "pre":
+        working = min(launches, sum(i["cycles"] for i in infos))
+    avg_ms = kms / max(working, 1)
+    achieved = bpl / (avg_ms * 1e-3) / 1e9 if working else None
+    traffic = None
+    if tclass == "pre" and args.kernels == "fused":
+        traffic = measured_traffic(f"{args.workload} {args.precision} pre")
     metric = METRIC
     extra = {}
     if prec == boxmg.BMG_FP32_IR:
@@ -345,7 +376,8 @@ def main():
         "roofline": {"bound": "hbm", "kernel": tclass, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS if achieved else None,
-                     "traffic": None, "launches": launches, "avg_launch_ms": avg_ms,
+                     "traffic": traffic, "traffic_unit": "B/launch",
+                     "launches": launches, "working_launches": working, "avg_launch_ms": avg_ms,
                      "bytes_per_launch": bpl, "bytes_per_point": bpl / (n * n)},
     }
     if not args.no_cpu_baseline:

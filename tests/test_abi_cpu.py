@@ -129,3 +129,24 @@ def test_batch_and_tuning_validation(L):
     assert boxmg.tile_rows_get(4095) == default
     assert L.bmg_tile_rows_set(4095, 7) == boxmg.BMG_EINVAL
     assert L.bmg_tile_rows_set(100, 8) == boxmg.BMG_EINVAL
+
+
+def test_bench_traffic_record_is_tied_to_the_kernel_sources(tmp_path, monkeypatch):
+    """bench.py reports measured traffic only while the sources the counters
+    were taken on are unchanged: a record with another hash gives None."""
+    import json
+    import bench
+    root = tmp_path
+    (root / "profiles").mkdir()
+    (root / "k.hpp").write_text("kernel v1")
+    import hashlib
+    good = hashlib.sha256(b"kernel v1").hexdigest()
+    rec = {"w fp64 pre": {"sources": ["k.hpp"], "sources_sha256": good, "traffic_bytes_per_launch": 123},
+           "w fp64 post": {"sources": ["k.hpp"], "sources_sha256": "0" * 64, "traffic_bytes_per_launch": 5}}
+    (root / "profiles" / "traffic.json").write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "ROOT", str(root))
+    assert bench.measured_traffic("w fp64 pre") == 123
+    assert bench.measured_traffic("w fp64 post") is None
+    assert bench.measured_traffic("other") is None
+    (root / "k.hpp").write_text("kernel v2")
+    assert bench.measured_traffic("w fp64 pre") is None
