@@ -113,16 +113,7 @@ def bench_batch(args):
     from paper_2502_05279_amd import autotune, boxmg, inputs
 
     dev = torch.device("cuda:0")
-    if args.batch_tile_rows:
-        tuned = {n: args.batch_tile_rows for n in (63, 127, 255, 511, 1023)}
-        for n, r in tuned.items():
-            boxmg.tile_rows_set(n, r)
-    else:
-        # every problem's passes share the chip, so parallelism is plentiful:
-        # the tile heights are tuned among the taller candidates, whose tiles
-        # re-read fewer warm-up rows
-        tuned = autotune.tune(sizes=(63, 127, 255, 511, 1023), precision=boxmg.BMG_FP32_IR,
-                              candidates=(8, 16, 32, 64))
+    sizes = (63, 127, 255, 511, 1023)
     probs = inputs.batch_512()
     sts, rhss = [], []
     for q in probs:
@@ -139,6 +130,13 @@ def bench_batch(args):
         torch.cuda.synchronize()
         return B, x, steps, rel, status, time.perf_counter() - t1
 
+    if args.batch_tile_rows:
+        tuned = {n: args.batch_tile_rows for n in sizes}
+        for n, r in tuned.items():
+            boxmg.tile_rows_set(n, r)
+    else:
+        # untimed: one batched solve per candidate tile height
+        tuned = autotune.tune_batch(lambda: step()[-1], sizes)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -233,6 +231,79 @@ def bench_learned(args):
     print(json.dumps(out))
 
 
+def bench_block(args):
+    """k right-hand sides on the jumping_4095 operator solved as one block: the
+    fused passes run the tiles of all of them per launch and read the operator
+    and weights about once.  One step = set-up of the hierarchy + the block
+    solve of all k to the tolerance."""
+    import torch
+    from paper_2502_05279_amd import boxmg, inputs
+
+    dev = torch.device("cuda:0")
+    K = args.rhs
+    p = workload(args.workload)
+    n = p.n
+    kk = torch.from_numpy(p.k).to(dev)
+    stencil, _ = boxmg.discretize(kk, torch.from_numpy(p.f).to(dev))
+    rhs = torch.stack([boxmg.discretize(kk, torch.from_numpy(f).to(dev))[1]
+                       for f in inputs.extra_sources(n, K)])
+    opts = dict(max_cycles=args.max_cycles, check_every=16)
+    ws = {}
+
+    def step(trace: bool):
+        S = boxmg.Solver(stencil, workspace=ws.get("s"), **opts)
+        ws["s"] = S.workspace
+        B = boxmg.Block(S, K, workspace=ws.get("b"))
+        ws["b"] = B.workspace
+        if trace:
+            B.trace_enable("pre", 0)
+        x, infos = B.solve(rhs, tol=args.tol, raise_on_noconv=False)
+        return S, B, x, infos
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    launches, kms, kbytes, cyc, working = 0, 0.0, 0.0, 0, 0
+    for _ in range(args.steps):
+        S, B, x, infos = step(True)
+        nl, ms, nb = B.trace_read()
+        launches += nl
+        kms += ms
+        kbytes += nb
+        cyc += sum(i["cycles"] for i in infos)
+        working += max(i["cycles"] for i in infos)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    n1 = S.level_n(1)
+    # the library counts every launch with all k right-hand sides; launches
+    # where some have stopped move less: count the operator and weights once per
+    # working launch and the per-right-hand-side arrays once per cycle of each
+    shared = 8.0 * (3 * n * n + 8 * n1 * n1)
+    per_rhs = 8.0 * (3 * n * n + 2 * n1 * n1)
+    assert abs(kbytes - launches * (shared + K * per_rhs)) <= 1e-9 * kbytes
+    alg = working * shared + cyc * per_rhs
+    avg_ms = kms / max(working, 1)
+    achieved = alg / (kms * 1e-3) / 1e9
+    out = {
+        "metric": f"fine DOF/s solved to {args.tol:g} rel. residual ({n}^2, {K} right-hand sides "
+                  "on one hierarchy)",
+        "value": K * n * n / (dt / args.steps), "unit": "DOF/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt * 1e3 / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{args.workload}_rhs{K}", "n": n, "rhs": K, "tol": args.tol,
+                   "cycles": [i["cycles"] for i in infos], "final_rel_res": max(i["rel_res"] for i in infos),
+                   "converged": all(i["status"] == 0 for i in infos), "nu1": 2, "nu2": 1,
+                   "precision": "fp64"},
+        "roofline": {"bound": "hbm", "kernel": "pre", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "traffic_unit": "B/launch", "launches": launches, "working_launches": working,
+                     "avg_launch_ms": avg_ms, "bytes_per_launch": alg / max(working, 1),
+                     "bytes_per_point": alg / max(working, 1) / (n * n)},
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -255,6 +326,8 @@ def main():
                          "calibrate hardware byte counters) and print the achieved GB/s")
     ap.add_argument("--params", default=None, help="learned_4095: network parameters (.npy)")
     ap.add_argument("--learned-n", type=int, default=4095)
+    ap.add_argument("--rhs", type=int, default=1,
+                    help="right-hand sides solved as one block on the workload's operator")
     ap.add_argument("--batch-tile-rows", type=int, default=0,
                     help="batch_512: tile height of every level instead of the autotuner's")
     args = ap.parse_args()
@@ -275,6 +348,8 @@ def main():
         return bench_batch(args)
     if args.workload == "learned_4095":
         return bench_learned(args)
+    if args.rhs > 1:
+        return bench_block(args)
     if args.copy_probe:
         a = torch.ones(args.copy_probe << 17, dtype=torch.float64, device=dev)
         b = torch.empty_like(a)

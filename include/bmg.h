@@ -161,6 +161,51 @@ bmg_status bmg_solve(bmg_solver *h, const double *rhs, double *x, double tol,
 /* Releases the handle (host memory only; the workspace stays the caller's). */
 bmg_status bmg_destroy(bmg_solver *h);
 
+/* ------------------------------------------------------------------------
+ * Block solves: k right-hand sides on one hierarchy.  The solver is bandwidth
+ * bound and more data reuse and block solves are the further work Sec. 5
+ * names; here every fused pass runs the tiles of all k right-hand sides in one
+ * launch, the k workgroups of a tile side by side on one XCD, so the operator
+ * and weight rows they share are read from HBM about once for all of them.
+ * Each right-hand side follows its own bmg_solve exactly (the same cycles, the
+ * same switch to refinement at refine_factor * tol, the same stop rule), so
+ * its iterate, history and cycle count are the ones bmg_solve gives it alone.
+ * The hierarchy must be FP64 (precision BMG_FP64) with the fused kernels,
+ * 1 <= nu1 <= 3 and 1 <= nu2 <= 2.
+ * ---------------------------------------------------------------------- */
+typedef struct bmg_block bmg_block;
+
+/* Device workspace of a block of k >= 1 right-hand sides on h: per level
+ * 3k iterate/right-hand-side arrays, 3k fine-level refinement arrays, and
+ * per right-hand side its norm partials, scalars, history and stop flag.
+ * Errors: BMG_EINVAL (NULL, k < 1, a hierarchy the block cannot run). */
+bmg_status bmg_block_workspace_bytes(const bmg_solver *h, int k, size_t *bytes);
+
+/* A block of k right-hand sides on the hierarchy of h (which must outlive it;
+ * the block runs on h's stream and only reads h's operators, weights and
+ * coarsest factor).  workspace: device, >= bmg_block_workspace_bytes, owned
+ * by the caller, outliving the block.  Errors: BMG_EINVAL, BMG_EWORKSPACE. */
+bmg_status bmg_block_create(bmg_block **out, bmg_solver *h, int k, void *workspace, size_t bytes);
+
+/* bmg_solve for the k right-hand sides at once.
+ *   rhs: device, k planes of n x n (row-major, plane j = right-hand side j);
+ *   x:   device, the same layout: initial guesses in, solutions out;
+ *   info: host, k entries, nullable (each entry's history as in bmg_solve);
+ *   status: host, k entries, nullable: each right-hand side's bmg_solve status.
+ * Returns BMG_OK if every right-hand side converged, else the first failing
+ * one's status (all x and info entries still valid). */
+bmg_status bmg_block_solve(bmg_block *b, const double *rhs, double *x, double tol, bmg_info *info,
+                           bmg_status *status);
+
+/* Kernel timing of the block's fused passes, as bmg_trace_enable/read (the
+ * bytes count the operator and weights once and the per-right-hand-side
+ * arrays k times). */
+bmg_status bmg_block_trace_enable(bmg_block *b, int kclass, int level, int on);
+bmg_status bmg_block_trace_read(bmg_block *b, int *launches, double *total_ms, double *bytes);
+
+/* Releases the block (host memory only). */
+bmg_status bmg_block_destroy(bmg_block *b);
+
 const char *bmg_status_string(int status);
 const char *bmg_last_error(void);
 

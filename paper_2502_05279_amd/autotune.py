@@ -92,3 +92,23 @@ def tune(sizes=(127, 255, 511, 1023, 2047), precision: int = boxmg.BMG_FP64,
         with open(path, "w") as fh:
             json.dump(cache, fh, indent=1)
     return out
+
+
+def tune_batch(run, sizes, candidates=(16, 32, 64), verbose: bool = False) -> dict:
+    """Tile height for a batch: in a batch every problem's passes share the
+    chip, so the objective is the whole batched solve rather than one level's
+    passes.  ``run()`` performs one timed batched solve and returns its seconds;
+    each candidate height is installed for every size, the fastest is kept.
+    Returns {n: rows}; the timings (ms) go to ``LAST["batch"]``."""
+    timings = {}
+    for rows in candidates:
+        for n in sizes:
+            boxmg.tile_rows_set(n, rows)
+        timings[rows] = run() * 1e3
+        if verbose:
+            print(f"batch tile rows {rows}: {timings[rows]:.1f} ms", flush=True)
+    best = min(timings, key=timings.get)
+    for n in sizes:
+        boxmg.tile_rows_set(n, best)
+    LAST["batch"] = timings
+    return {n: best for n in sizes}

@@ -106,6 +106,12 @@ def lib():
             "bmg_net_export": ([vp, i, vp, C.POINTER(sz)], i),
             "bmg_net_twogrid": ([vp, vp, vp, d, i, C.POINTER(d), vp], i),
             "bmg_solve_select": ([vp, vp, vp, vp, d, i, C.POINTER(Info), C.POINTER(i), C.POINTER(d)], i),
+            "bmg_block_workspace_bytes": ([vp, i, C.POINTER(sz)], i),
+            "bmg_block_create": ([C.POINTER(vp), vp, i, vp, sz], i),
+            "bmg_block_solve": ([vp, vp, vp, d, C.POINTER(Info), C.POINTER(i)], i),
+            "bmg_block_trace_enable": ([vp, i, i, i], i),
+            "bmg_block_trace_read": ([vp, C.POINTER(i), C.POINTER(d), C.POINTER(d)], i),
+            "bmg_block_destroy": ([vp], i),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -267,6 +273,66 @@ class Solver:
         """(launches, total ms, algorithmic bytes) of the timed launches."""
         n, ms, nb = C.c_int(0), C.c_double(0.0), C.c_double(0.0)
         _check(lib().bmg_trace_read(self._h, C.byref(n), C.byref(ms), C.byref(nb)), "bmg_trace_read")
+        return n.value, ms.value, nb.value
+
+
+class Block:
+    """k right-hand sides solved together on the hierarchy of ``solver`` (which
+    must stay open while the block is used)."""
+
+    def __init__(self, solver: Solver, k: int, workspace: torch.Tensor | None = None):
+        self.solver, self.k, self.n = solver, k, solver.n
+        need = C.c_size_t(0)
+        _check(lib().bmg_block_workspace_bytes(solver._h, k, C.byref(need)), "bmg_block_workspace_bytes")
+        if workspace is not None and workspace.numel() >= need.value:
+            self.workspace = workspace
+        else:
+            self.workspace = torch.empty(need.value, dtype=torch.uint8, device=solver.device)
+        b = C.c_void_p(None)
+        _check(lib().bmg_block_create(C.byref(b), solver._h, k, self.workspace.data_ptr(), need.value),
+               "bmg_block_create")
+        self._b = b
+
+    def close(self) -> None:
+        if getattr(self, "_b", None):
+            lib().bmg_block_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, rhs: torch.Tensor, x: torch.Tensor | None = None, tol: float = 1e-10,
+              raise_on_noconv: bool = True):
+        """rhs, x: ``[k][n][n]``.  Returns ``(x, infos)``, one dict per right-hand
+        side as ``Solver.solve`` gives."""
+        if rhs.shape != (self.k, self.n, self.n):
+            raise ValueError(f"rhs must be [{self.k}][{self.n}][{self.n}]")
+        if x is None:
+            x = torch.zeros_like(rhs)
+        cap = self.solver.options.max_cycles + 2
+        hists = [(C.c_double * cap)() for _ in range(self.k)]
+        infos = (Info * self.k)()
+        for j in range(self.k):
+            infos[j].history = C.cast(hists[j], C.POINTER(C.c_double))
+        status = (C.c_int * self.k)()
+        st = lib().bmg_block_solve(self._b, _ptr(rhs), _ptr(x), float(tol), infos, status)
+        if st not in (BMG_OK, BMG_ENOCONV) or (st == BMG_ENOCONV and raise_on_noconv):
+            _check(st, "bmg_block_solve")
+        out = [{"cycles": infos[j].cycles, "rel_res": infos[j].rel_res, "rho": infos[j].rho,
+                "history": [hists[j][t] for t in range(infos[j].cycles)], "status": status[j]}
+               for j in range(self.k)]
+        return x, out
+
+    def trace_enable(self, kclass: str, level: int = 0, on: bool = True) -> None:
+        _check(lib().bmg_block_trace_enable(self._b, TRACE[kclass], level, int(on)), "bmg_block_trace_enable")
+
+    def trace_read(self):
+        """(launches, total ms, algorithmic bytes) of the timed launches."""
+        n, ms, nb = C.c_int(0), C.c_double(0.0), C.c_double(0.0)
+        _check(lib().bmg_block_trace_read(self._b, C.byref(n), C.byref(ms), C.byref(nb)), "bmg_block_trace_read")
         return n.value, ms.value, nb.value
 
 

@@ -287,8 +287,8 @@ __global__ __launch_bounds__(BT, 4) void k_batch(BArgs A, int mode, int steps)
         for (int it = A.li.prob0 + bid; it < A.li.prob1; it += nb) {
             BProb &q = P[items[it].x];
             if (q.done) continue;
-            if (q.sdepth == 0) small_vcycle_body<float, false>(q.small, reinterpret_cast<float *>(smem));
-            else small_vcycle_body<float, true>(q.small, reinterpret_cast<float *>(smem));
+            if (q.sdepth == 0) small_vcycle_body<float, false>(q.small, reinterpret_cast<float *>(smem), 0);
+            else small_vcycle_body<float, true>(q.small, reinterpret_cast<float *>(smem), 0);
             __syncthreads();
         }
         phase_barrier(grid);

@@ -45,7 +45,26 @@ struct TileGeo {
     int ht;       // owned rows per tile
     int tiles_x;  // strips
     int ntiles;
+    // several right-hand sides on one hierarchy: right-hand side k's u, b (and
+    // the output) start k*ksf elements after the first's, its coarse-level u, b
+    // k*ksc after, its stop flag k*kstop ints after and its norm partials
+    // k*kpart doubles after
+    int nrhs = 1, kstop = 0, kpart = 0;
+    size_t ksf = 0, ksc = 0;
 };
+
+// Work item of this workgroup: tile `tid` of right-hand side `k`.  The nrhs
+// workgroups of a tile get consecutive ids, so they run on the same XCD at
+// about the same time and the stencil and weight rows they share are fetched
+// into its L2 once.
+__device__ __forceinline__ bool tile_work(const TileGeo &G, int &tid, int &k)
+{
+    const int w = tile_id(G.ntiles * G.nrhs);
+    if (w < 0) return false;
+    tid = w / G.nrhs;
+    k = w - tid * G.nrhs;
+    return true;
+}
 
 // Gauss-Seidel update of point (lane, row) from the LDS rings: the same terms in
 // the same order as gs_point.
@@ -352,9 +371,11 @@ template <typename T, bool NINE, int NU, bool WREC = false>
 __global__ __launch_bounds__(FW) void k_pre(Lev<T> L, T *__restrict__ uout, Wts<T> C, Lev<T> Cl,
                                              TileGeo G, const int *stop)
 {
-    if (stopped(stop)) return;
-    const int tid = tile_id(G.ntiles);
-    if (tid < 0) return;
+    int tid, k;
+    if (!tile_work(G, tid, k)) return;
+    if (stopped(stop ? stop + k * G.kstop : stop)) return;
+    L.u += k * G.ksf; L.b += k * G.ksf; uout += k * G.ksf;
+    Cl.u += k * G.ksc; Cl.b += k * G.ksc;
     __shared__ TileLds<T, NINE, NU, WREC> S;
     pre_tile<T, NINE, NU, WREC>(L, uout, C, Cl, G, tid, S);
 }
@@ -573,9 +594,12 @@ template <typename T, bool NINE, int NU, bool NORM>
 __global__ __launch_bounds__(FW) void k_post(Lev<T> L, T *__restrict__ uout, Wts<T> C, const T *__restrict__ ec,
                                               TileGeo G, double *__restrict__ part, const int *stop)
 {
-    if (stopped(stop)) return;
-    const int tid = tile_id(G.ntiles);
-    if (tid < 0) return;
+    int tid, k;
+    if (!tile_work(G, tid, k)) return;
+    if (stopped(stop ? stop + k * G.kstop : stop)) return;
+    L.u += k * G.ksf; L.b += k * G.ksf; uout += k * G.ksf;
+    ec += k * G.ksc;
+    if (NORM) part += k * G.kpart;
     __shared__ TileLds<T, NINE, NU> S;
     post_tile<T, NINE, NU, NORM>(L, uout, C, ec, G, tid, part, S);
 }
@@ -774,9 +798,11 @@ template <typename T, int NU>
 __global__ __launch_bounds__(FW) void k_pre4(Lev<T> L, T *__restrict__ uout, Wts<T> C, Lev<T> Cl, TileGeo G,
                                               const int *stop)
 {
-    if (stopped(stop)) return;
-    const int tid = tile_id(G.ntiles);
-    if (tid < 0) return;
+    int tid, k;
+    if (!tile_work(G, tid, k)) return;
+    if (stopped(stop ? stop + k * G.kstop : stop)) return;
+    L.u += k * G.ksf; L.b += k * G.ksf; uout += k * G.ksf;
+    Cl.u += k * G.ksc; Cl.b += k * G.ksc;
     __shared__ TileLds4<T, NU> S;
     pre_tile4<T, NU>(L, uout, C, Cl, G, tid, S);
 }
@@ -972,9 +998,12 @@ template <typename T, int NU, bool NORM>
 __global__ __launch_bounds__(FW) void k_post4(Lev<T> L, T *__restrict__ uout, Wts<T> C, const T *__restrict__ ec,
                                                TileGeo G, double *__restrict__ part, const int *stop)
 {
-    if (stopped(stop)) return;
-    const int tid = tile_id(G.ntiles);
-    if (tid < 0) return;
+    int tid, k;
+    if (!tile_work(G, tid, k)) return;
+    if (stopped(stop ? stop + k * G.kstop : stop)) return;
+    L.u += k * G.ksf; L.b += k * G.ksf; uout += k * G.ksf;
+    ec += k * G.ksc;
+    if (NORM) part += k * G.kpart;
     __shared__ TileLds4<T, NU> S;
     post_tile4<T, NU, NORM>(L, uout, C, ec, G, tid, part, S);
 }
@@ -1001,6 +1030,10 @@ struct SmallH {
     int off_u[SMALL_MAXL], off_b[SMALL_MAXL], off_r;
     const double *LD;          // coarsest LDL^T factor
     int nu1, nu2;
+    // workgroup k runs right-hand side k: the first level's u and b start
+    // k*ks0 elements after the first's, its stop flag k*kstop ints after
+    size_t ks0;
+    int kstop;
 };
 
 template <typename T, bool NINE>
@@ -1077,7 +1110,7 @@ __host__ __device__ inline int small_layout(SmallH<T> &H)
 }
 
 template <typename T, bool NINE0>
-__device__ void small_vcycle_body(const SmallH<T> &H, T *sm)
+__device__ void small_vcycle_body(const SmallH<T> &H, T *sm, size_t rhs_off)
 {
     const int nl = H.nl, last = nl - 1;
     // fetch b of the first level, zero every iterate and the coarser b
@@ -1087,7 +1120,8 @@ __device__ void small_vcycle_body(const SmallH<T> &H, T *sm)
         for (int t = threadIdx.x; t < p * p; t += blockDim.x) {
             const int i = t % p, j = t / p;
             u[t] = (T)0;
-            b[t] = (l == 0 && i >= 1 && i <= n && j >= 1 && j <= n) ? H.L[0].b[(size_t)j * H.L[0].ld + i] : (T)0;
+            b[t] = (l == 0 && i >= 1 && i <= n && j >= 1 && j <= n) ? H.L[0].b[rhs_off + (size_t)j * H.L[0].ld + i]
+                                                                     : (T)0;
         }
     }
     T *r = sm + H.off_r;
@@ -1181,7 +1215,7 @@ __device__ void small_vcycle_body(const SmallH<T> &H, T *sm)
         const T *u = sm + H.off_u[0];
         for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
             const int i = 1 + t % n, j = 1 + t / n;
-            L.u[(size_t)j * L.ld + i] = u[j * p + i];
+            L.u[rhs_off + (size_t)j * L.ld + i] = u[j * p + i];
         }
     }
 }
@@ -1189,9 +1223,10 @@ __device__ void small_vcycle_body(const SmallH<T> &H, T *sm)
 template <typename T, bool NINE0>
 __global__ __launch_bounds__(SMALL_THREADS) void k_small_vcycle(SmallH<T> H, const int *stop)
 {
-    if (stopped(stop)) return;
+    const int k = blockIdx.x;
+    if (stopped(stop ? stop + k * H.kstop : stop)) return;
     extern __shared__ unsigned char smem_raw[];
-    small_vcycle_body<T, NINE0>(H, reinterpret_cast<T *>(smem_raw));
+    small_vcycle_body<T, NINE0>(H, reinterpret_cast<T *>(smem_raw), k * H.ks0);
 }
 
 }  // namespace bmg

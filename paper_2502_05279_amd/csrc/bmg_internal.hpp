@@ -70,6 +70,12 @@ struct bmg_solver {
     double *ualt[MAXL];         // second iterate buffer of each level (fused passes)
     float *ualt32[MAXL];
     int norm_parts = 0;         // partial sums left by the last fused norm
+    // several right-hand sides on this hierarchy (a block solve's view; 1
+    // otherwise): right-hand side k's level-l arrays start k*ks[l] elements
+    // after the first's, its stop flag k*kstop ints and its norm partials
+    // k*kpart doubles after
+    int nrhs = 1, kstop = 0, kpart = 0;
+    size_t ks[MAXL] = {};
     double *B0 = nullptr;       // fine right-hand side during refinement
     double *XH = nullptr;       // double-FP64 iterate, high part
     double *XL = nullptr;       // double-FP64 iterate, low part

@@ -286,7 +286,14 @@ bmg_status interp(bmg_solver *h, const Lev<T> &F, const Wts<T> &C, const Lev<T> 
 template <typename T>
 bmg_status coarse(bmg_solver *h, const Lev<T> &Cl, const int *stop)
 {
-    hipLaunchKernelGGL((k_coarse_solve<T>), dim3(1), dim3(64), 0, h->st, Cl, (const double *)h->LD, stop);
+    const size_t ks = h->ks[h->nlev - 1];
+    for (int k = 0; k < h->nrhs; ++k) {
+        Lev<T> Ck = Cl;
+        Ck.u += k * ks;
+        Ck.b += k * ks;
+        hipLaunchKernelGGL((k_coarse_solve<T>), dim3(1), dim3(64), 0, h->st, Ck, (const double *)h->LD,
+                           stop ? stop + k * h->kstop : stop);
+    }
     LAUNCHCHK();
     return BMG_OK;
 }
@@ -338,7 +345,19 @@ float *&ualt<float>(bmg_solver *h, int l) { return h->ualt32[l]; }
 
 int level_tile_rows(const bmg_solver *h, int n) { return tile_rows_for(h, n); }
 
-dim3 tile_grid(const TileGeo &g) { return dim3(((g.ntiles + 7) / 8) * 8); }
+dim3 tile_grid(const TileGeo &g) { return dim3(((g.ntiles * g.nrhs + 7) / 8) * 8); }
+
+// The tiles of level l of every right-hand side of the handle.
+TileGeo level_tiles(const bmg_solver *h, int l, int hx)
+{
+    TileGeo g = tile_geo(h->L[l].n, hx, level_tile_rows(h, h->L[l].n));
+    g.nrhs = h->nrhs;
+    g.kstop = h->kstop;
+    g.kpart = h->kpart;
+    g.ksf = h->ks[l];
+    g.ksc = l + 1 < h->nlev ? h->ks[l + 1] : 0;
+    return g;
+}
 
 // FP64 pre passes compute the restriction weights (1) or read them (0).
 #ifndef BMG_PRE_WEIGHTS_IN_PASS
@@ -350,7 +369,9 @@ static bool pre_weights_in_pass(const bmg_solver *h, int l, bool nine)
 {
     const bool learned = h->opt.interp == BMG_INTERP_LEARNED &&
                          (h->opt.learned_levels == 0 || l < h->opt.learned_levels);
-    return BMG_PRE_WEIGHTS_IN_PASS && std::is_same<T, double>::value && !nine && !learned;
+    // with several right-hand sides the weight rows are shared through L2,
+    // while computing them would repeat the divisions for each
+    return BMG_PRE_WEIGHTS_IN_PASS && std::is_same<T, double>::value && !nine && !learned && h->nrhs == 1;
 }
 
 // Rows per step of the fused passes on five-point levels: 4 (k_pre4, k_post4)
@@ -375,7 +396,7 @@ bmg_status fused_pre(bmg_solver *h, int l, int nu, const int *stop)
     }
     // halo: each sweep invalidates 2 (five-point) or 4 (nine-point) columns at
     // each edge of the strip, the residual and the restriction one more each
-    const TileGeo g = tile_geo(F.n, nine ? 4 * nu + 2 : 2 * nu + 2, level_tile_rows(h, F.n));
+    const TileGeo g = level_tiles(h, l, nine ? 4 * nu + 2 : 2 * nu + 2);
     T *out = ualt<T>(h, l);
     const dim3 grid = tile_grid(g), blk(FW);
 #define PRE(NINE, NU) hipLaunchKernelGGL((k_pre<T, NINE, NU>), grid, blk, 0, h->st, F, out, C, Cl, g, stop)
@@ -387,11 +408,13 @@ bmg_status fused_pre(bmg_solver *h, int l, int nu, const int *stop)
     // weights (no formula), and not nine-point levels, whose divisions cost
     // more time than the loads they replace.
     const bool wrec = pre_weights_in_pass<T>(h, l, nine);
-    // stencil, b and u read, u written on the fine level; b and u (zero)
-    // written on the coarse level, and the 8 weight planes read unless computed
+    // stencil once and b, u read, u written for each right-hand side on the
+    // fine level; b and u (zero) written for each on the coarse level, and the
+    // 8 weight planes read once unless computed
+    const double K = h->nrhs;
     trace_begin(h, BMG_TRACE_PRE, l,
-                sizeof(T) * ((stencil_planes(nine) + 3.0) * (double)F.n * F.n +
-                             (wrec ? 2.0 : 10.0) * (double)Cl.n * Cl.n));
+                sizeof(T) * ((stencil_planes(nine) + 3.0 * K) * (double)F.n * F.n +
+                             (2.0 * K + (wrec ? 0.0 : 8.0)) * (double)Cl.n * Cl.n));
     if (wrec) {
         if constexpr (std::is_same<T, double>::value) {
             if (nu == 1) PREW(false, 1); else if (nu == 2) PREW(false, 2); else PREW(false, 3);
@@ -430,7 +453,7 @@ bmg_status fused_post(bmg_solver *h, int l, int nu, const int *stop, bool norm =
     // halo: the edge lanes are never interpolated (stale from the start), then
     // each sweep invalidates 2 (five-point) or 4 (nine-point) more columns and
     // the fused residual one more
-    const TileGeo g = tile_geo(F.n, nine ? 4 * nu + 2 : 2 * nu + 2, level_tile_rows(h, F.n));
+    const TileGeo g = level_tiles(h, l, nine ? 4 * nu + 2 : 2 * nu + 2);
     norm = norm && std::is_same<T, double>::value && g.ntiles <= NPART;
     T *out = ualt<T>(h, l);
     const dim3 grid = tile_grid(g), blk(FW);
@@ -438,10 +461,11 @@ bmg_status fused_post(bmg_solver *h, int l, int nu, const int *stop, bool norm =
     hipLaunchKernelGGL((k_post<T, NINE, NU, NORM>), grid, blk, 0, h->st, F, out, C, (const T *)Cl.u, g, h->part, stop)
 #define POST4(NU, NORM) \
     hipLaunchKernelGGL((k_post4<T, NU, NORM>), grid, blk, 0, h->st, F, out, C, (const T *)Cl.u, g, h->part, stop)
-    // stencil, b and u read, u written on the fine level; the coarse
-    // correction and the 8 weight planes read
+    // stencil once and b, u read, u written for each right-hand side on the
+    // fine level; the coarse correction of each and the 8 weight planes read
+    const double K = h->nrhs;
     trace_begin(h, BMG_TRACE_POST, l,
-                sizeof(T) * ((stencil_planes(nine) + 3.0) * (double)F.n * F.n + 9.0 * (double)Cl.n * Cl.n));
+                sizeof(T) * ((stencil_planes(nine) + 3.0 * K) * (double)F.n * F.n + (K + 8.0) * (double)Cl.n * Cl.n));
     if (!nine && BMG_FIVE_POINT_STEP_ROWS == 4) {
         if (norm) { if (nu == 1) POST4(1, true); else POST4(2, true); }
         else { if (nu == 1) POST4(1, false); else POST4(2, false); }
@@ -479,6 +503,8 @@ bmg_status small_cycle(bmg_solver *h, int l, const int *stop)
     S.LD = h->LD;
     S.nu1 = h->opt.nu1;
     S.nu2 = h->opt.nu2;
+    S.ks0 = h->ks[l];
+    S.kstop = h->kstop;
     const size_t shmem = (size_t)off * sizeof(T);
     static bool attr_set[2] = {false, false};
     const int which = sizeof(T) == 8 ? 0 : 1;
@@ -487,7 +513,7 @@ bmg_status small_cycle(bmg_solver *h, int l, const int *stop)
                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
         attr_set[which] = true;
     }
-    hipLaunchKernelGGL((k_small_vcycle<T, true>), dim3(1), dim3(SMALL_THREADS), shmem, h->st, S, stop);
+    hipLaunchKernelGGL((k_small_vcycle<T, true>), dim3(h->nrhs), dim3(SMALL_THREADS), shmem, h->st, S, stop);
     LAUNCHCHK();
     return BMG_OK;
 }
@@ -1229,6 +1255,288 @@ bmg_status bmg_trace_read(bmg_solver *h, int *launches, double *total_ms, double
     h->tr_used = 0;
     h->tr_bytes = 0.0;
     return BMG_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ block solves
+// A block is a second view of a hierarchy: `hb` shares the operators, weights
+// and coarsest factor of the parent handle and points its iterate and
+// right-hand-side arrays at k planes per level (nrhs = k), so the fused cycle
+// code runs all of them in each launch; view[j] is right-hand side j alone
+// (nrhs = 1), on which the per-right-hand-side steps of bmg_solve run
+// unchanged.  Each fused pass swaps a level's iterate buffers, twice per cycle,
+// so between cycles every view's pointers are the block's again.
+struct bmg_block {
+    bmg_solver *parent = nullptr;
+    int k = 0;
+    bmg_solver hb;
+    std::vector<bmg_solver> view;
+};
+
+namespace {
+
+bmg_status block_check(const bmg_solver *h, int k)
+{
+    if (!h) return fail(BMG_EINVAL, "NULL handle");
+    if (k < 1 || k > 4096) return fail(BMG_EINVAL, "k=%d right-hand sides must be in [1, 4096]", k);
+    if (h->opt.precision != BMG_FP64) return fail(BMG_EINVAL, "block solves run FP64 hierarchies");
+    if (h->opt.kernels != BMG_KERNELS_FUSED) return fail(BMG_EINVAL, "block solves need the fused kernels");
+    if (h->opt.nu1 < 1 || h->opt.nu1 > 3 || h->opt.nu2 < 1 || h->opt.nu2 > 2)
+        return fail(BMG_EINVAL, "block solves need 1 <= nu1 <= 3 and 1 <= nu2 <= 2");
+    return BMG_OK;
+}
+
+// Walks the block's workspace; with base == nullptr it only measures.
+size_t block_plan(const bmg_solver *h, int k, char *base, bmg_block *B)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char * {
+        off = (off + ALIGN - 1) & ~(ALIGN - 1);
+        char *p = base ? base + off : nullptr;
+        off += bytes;
+        return p;
+    };
+    // planes rounded to ALIGN so that every right-hand side's plane is aligned
+    auto plane = [&](int l) { return (((size_t)(h->L[l].n + 2) * h->L[l].ld * 8 + ALIGN - 1) & ~(ALIGN - 1)) / 8; };
+    double *u[MAXL], *ua[MAXL], *b[MAXL];
+    for (int l = 0; l < h->nlev; ++l) {
+        u[l] = (double *)take(k * plane(l) * 8);
+        ua[l] = (double *)take(k * plane(l) * 8);
+        b[l] = (double *)take(k * plane(l) * 8);
+    }
+    const size_t p0 = plane(0);
+    double *B0 = (double *)take(k * p0 * 8);
+    double *XH = (double *)take(k * p0 * 8);
+    double *XL = (double *)take(k * p0 * 8);
+    double *part = (double *)take((size_t)k * NPART * 8);
+    double *scal = (double *)take((size_t)k * S_NSCAL * 8);
+    double *hist = (double *)take((size_t)k * h->hist_cap * 8);
+    int *cnt = (int *)take((size_t)k * 2 * sizeof(int));
+    if (B) {
+        bmg_solver &v = B->hb;
+        v = *h;
+        v.tr_ev.clear();
+        v.tr_class = v.tr_level = -1;
+        v.tr_used = 0;
+        v.tr_bytes = v.tr_pending = 0.0;
+        v.ws = nullptr;
+        v.ws_bytes = 0;
+        v.nrhs = k;
+        v.kstop = 2;
+        v.kpart = NPART;
+        for (int l = 0; l < h->nlev; ++l) {
+            v.ks[l] = plane(l);
+            v.L[l].u = u[l];
+            v.L[l].b = b[l];
+            v.L[l].r = nullptr;   // the fused passes keep residuals on chip
+            v.ualt[l] = ua[l];
+        }
+        v.B0 = B0;
+        v.XH = XH;
+        v.XL = XL;
+        v.part = part;
+        v.scal = scal;
+        v.hist = hist;
+        v.count = cnt;
+        v.stop = cnt + 1;
+        B->view.assign(k, v);
+        for (int j = 0; j < k; ++j) {
+            bmg_solver &w = B->view[j];
+            w.nrhs = 1;
+            w.kstop = w.kpart = 0;
+            for (int l = 0; l < h->nlev; ++l) {
+                w.ks[l] = 0;
+                w.L[l].u = u[l] + j * v.ks[l];
+                w.L[l].b = b[l] + j * v.ks[l];
+                w.ualt[l] = ua[l] + j * v.ks[l];
+            }
+            w.B0 = B0 + j * p0;
+            w.XH = XH + j * p0;
+            w.XL = XL + j * p0;
+            w.part = part + (size_t)j * NPART;
+            w.scal = scal + (size_t)j * S_NSCAL;
+            w.hist = hist + (size_t)j * h->hist_cap;
+            w.count = cnt + 2 * j;
+            w.stop = cnt + 2 * j + 1;
+        }
+    }
+    return (off + ALIGN - 1) & ~(ALIGN - 1);
+}
+
+}  // namespace
+
+extern "C" {
+
+bmg_status bmg_block_workspace_bytes(const bmg_solver *h, int k, size_t *bytes)
+{
+    TRY(block_check(h, k));
+    if (!bytes) return fail(BMG_EINVAL, "NULL argument");
+    *bytes = block_plan(h, k, nullptr, nullptr);
+    return BMG_OK;
+}
+
+bmg_status bmg_block_create(bmg_block **out, bmg_solver *h, int k, void *workspace, size_t bytes)
+{
+    if (!out) return fail(BMG_EINVAL, "NULL argument");
+    *out = nullptr;
+    TRY(block_check(h, k));
+    if (!workspace) return fail(BMG_EINVAL, "NULL workspace");
+    if ((uintptr_t)workspace % ALIGN) return fail(BMG_EINVAL, "workspace not %zu-byte aligned", ALIGN);
+    const size_t need = block_plan(h, k, nullptr, nullptr);
+    if (bytes < need) return fail(BMG_EWORKSPACE, "block workspace %zu < %zu bytes", bytes, need);
+    bmg_block *B = new bmg_block;
+    B->parent = h;
+    B->k = k;
+    block_plan(h, k, (char *)workspace, B);
+    *out = B;
+    return BMG_OK;
+}
+
+bmg_status bmg_block_destroy(bmg_block *B)
+{
+    if (!B) return BMG_OK;
+    for (hipEvent_t e : B->hb.tr_ev) (void)hipEventDestroy(e);
+    delete B;
+    return BMG_OK;
+}
+
+bmg_status bmg_block_trace_enable(bmg_block *B, int kclass, int level, int on)
+{
+    if (!B) return fail(BMG_EINVAL, "NULL handle");
+    return bmg_trace_enable(&B->hb, kclass, level, on);
+}
+
+bmg_status bmg_block_trace_read(bmg_block *B, int *launches, double *total_ms, double *bytes)
+{
+    if (!B) return fail(BMG_EINVAL, "NULL handle");
+    return bmg_trace_read(&B->hb, launches, total_ms, bytes);
+}
+
+bmg_status bmg_block_solve(bmg_block *B, const double *rhs, double *x, double tol, bmg_info *info,
+                           bmg_status *status)
+{
+    if (!B || !rhs || !x) return fail(BMG_EINVAL, "NULL argument");
+    if (!(tol >= 0.0)) return fail(BMG_EINVAL, "tol must be >= 0");
+    bmg_solver *hb = &B->hb;
+    const int K = B->k;
+    const Lev<double> &L = hb->L[0];
+    const size_t n2 = (size_t)L.n * L.n;
+    const size_t pl0 = (size_t)(L.n + 2) * L.ld * sizeof(double);
+    const int maxc = hb->opt.max_cycles;
+    const double refine = hb->opt.refine_factor > 0 ? hb->opt.refine_factor * tol : 0.0;
+    enum { PLAIN, REFINING, ZERO };
+    std::vector<int> mode(K, PLAIN), cs(2 * K, 0);
+    std::vector<double> sc((size_t)K * S_NSCAL), init(2 * (size_t)K, 0.0);
+    // each right-hand side's ||b|| and initial residual, as bmg_solve starts
+    HIPCHK(hipMemsetAsync(hb->count, 0, 2 * K * sizeof(int), hb->st));
+    for (int j = 0; j < K; ++j) {
+        bmg_solver *v = &B->view[j];
+        TRY(pack_in(v, rhs + j * n2, v->B0));
+        TRY(pack_in(v, x + j * n2, v->XH));
+        HIPCHK(hipMemsetAsync(v->XL, 0, pl0, hb->st));
+        TRY(sumsq<double>(v, v->L[0], false, false, v->B0, S_TMP, false, 0.0, 0));
+        TRY(resnorm_dd(v, v->B0, v->XH, nullptr, 0, nullptr, S_SUMSQ, false, 0.0, 0, 0.0));
+    }
+    TRY(read_scalars(hb, sc.data(), 0, K * S_NSCAL));
+    for (int j = 0; j < K; ++j) {
+        bmg_solver *v = &B->view[j];
+        const double *s = &sc[(size_t)j * S_NSCAL];
+        if (s[S_TMP] == 0.0) {
+            // a zero right-hand side: x = 0 after 0 cycles; its stop flag keeps
+            // every launch of the block from touching it
+            mode[j] = ZERO;
+            cs[2 * j + 1] = 1;
+            HIPCHK(hipMemsetAsync(v->XH, 0, pl0, hb->st));
+            continue;
+        }
+        init[2 * j] = sqrt(s[S_TMP]);
+        init[2 * j + 1] = sqrt(s[S_SUMSQ]) / sqrt(s[S_TMP]);
+        HIPCHK(hipMemcpyAsync(v->scal + S_BNORM, &init[2 * j], 2 * sizeof(double), hipMemcpyHostToDevice, hb->st));
+        HIPCHK(hipMemcpyAsync(v->L[0].b, v->B0, pl0, hipMemcpyDeviceToDevice, hb->st));
+        HIPCHK(hipMemcpyAsync(v->L[0].u, v->XH, pl0, hipMemcpyDeviceToDevice, hb->st));
+    }
+    HIPCHK(hipMemcpyAsync(hb->count, cs.data(), 2 * K * sizeof(int), hipMemcpyHostToDevice, hb->st));
+    HIPCHK(hipStreamSynchronize(hb->st));   // init[] and cs[] are read by the copies above
+    const int every = hb->opt.check_every;
+    while (true) {
+        for (int t = 0; t < every; ++t) {
+            // one V-cycle of every running right-hand side (plain: on (b, u);
+            // refining: on (r, 0)); stopped ones return at once
+            TRY(fused_vcycle(hb, hb->stop, true));
+            for (int j = 0; j < K; ++j) {
+                bmg_solver *v = &B->view[j];
+                if (mode[j] == PLAIN) {
+                    if (hb->norm_parts > 0) {
+                        hipLaunchKernelGGL(k_sumsq_final, dim3(1), dim3(1024), 0, hb->st, (const double *)v->part,
+                                           hb->norm_parts, v->scal + S_SUMSQ, v->hist, v->count, v->stop,
+                                           (const double *)(v->scal + S_BNORM), tol, maxc, refine);
+                        LAUNCHCHK();
+                    } else {
+                        TRY(resnorm_dd(v, v->L[0].b, v->L[0].u, nullptr, 0, nullptr, S_SUMSQ, true, tol, maxc,
+                                       refine));
+                    }
+                } else if (mode[j] == REFINING) {
+                    hipLaunchKernelGGL(k_dd_update, grid2(L.n, L.n, B2), B2, 0, hb->st, v->L[0], v->XH, v->XL,
+                                       (const float *)nullptr, (const double *)nullptr, v->stop);
+                    LAUNCHCHK();
+                    TRY(resnorm_dd(v, v->B0, v->XH, v->XL, 2, nullptr, S_SUMSQ, true, tol, maxc, 0.0));
+                }
+            }
+        }
+        HIPCHK(hipMemcpyAsync(cs.data(), hb->count, 2 * K * sizeof(int), hipMemcpyDeviceToHost, hb->st));
+        HIPCHK(hipStreamSynchronize(hb->st));
+        bool running = false;
+        for (int j = 0; j < K; ++j) {
+            bmg_solver *v = &B->view[j];
+            if (mode[j] == PLAIN && cs[2 * j + 1] == 4) {
+                // as bmg_solve: (XH, XL) = (u, 0), the next cycle starts from
+                // zero on r = B0 - A XH
+                mode[j] = REFINING;
+                HIPCHK(hipMemcpyAsync(v->XH, v->L[0].u, pl0, hipMemcpyDeviceToDevice, hb->st));
+                HIPCHK(hipMemsetAsync(v->XL, 0, pl0, hb->st));
+                TRY(resnorm_dd(v, v->B0, v->XH, v->XL, 2, nullptr, S_TMP, false, 0.0, 0, 0.0));
+                HIPCHK(hipMemsetAsync(v->stop, 0, sizeof(int), hb->st));
+                running = true;
+            } else if (mode[j] != ZERO && cs[2 * j + 1] == 0) {
+                running = true;
+            }
+        }
+        if (!running) break;
+    }
+    bmg_status first = BMG_OK;
+    std::vector<double> hist((size_t)hb->hist_cap);
+    for (int j = 0; j < K; ++j) {
+        bmg_solver *v = &B->view[j];
+        if (mode[j] == PLAIN) {
+            HIPCHK(hipMemcpyAsync(v->XH, v->L[0].u, pl0, hipMemcpyDeviceToDevice, hb->st));
+            HIPCHK(hipMemsetAsync(v->XL, 0, pl0, hb->st));
+        }
+        TRY(pack_out(v, v->XH, x + j * n2));
+        bmg_status sj = BMG_OK;
+        if (mode[j] == ZERO) {
+            if (info) { info[j].cycles = 0; info[j].rel_res = 0.0; info[j].rho = 0.0; }
+        } else {
+            const int c = cs[2 * j];
+            HIPCHK(hipMemcpyAsync(hist.data(), v->hist, c * sizeof(double), hipMemcpyDeviceToHost, hb->st));
+            HIPCHK(hipStreamSynchronize(hb->st));
+            if (info) {
+                info[j].cycles = c;
+                info[j].rel_res = c > 0 ? hist[c - 1] : init[2 * j + 1];
+                info[j].rho = c > 0 ? pow(info[j].rel_res / init[2 * j + 1], 1.0 / c) : 0.0;
+                if (info[j].history) memcpy(info[j].history, hist.data(), c * sizeof(double));
+            }
+            if (cs[2 * j + 1] == 2) sj = BMG_EDIVERGED;
+            if (cs[2 * j + 1] == 3) sj = BMG_ENOCONV;
+            if (sj != BMG_OK && first == BMG_OK) {
+                first = sj;
+                fail(sj, "right-hand side %d: relative residual %.3e after %d cycles", j, c > 0 ? hist[c - 1] : 0.0, c);
+            }
+        }
+        if (status) status[j] = sj;
+    }
+    HIPCHK(hipStreamSynchronize(hb->st));
+    return first;
 }
 
 }  // extern "C"

@@ -121,6 +121,12 @@ def jumping_4095(seed_k: int = 201, seed_f: int = 202, n: int = 4095) -> Problem
     return jumping(n, 64, -4.0, 4.0, seed_k, seed_f, f"jumping_{n}_c1e8")
 
 
+def extra_sources(n: int, k: int, seed0: int = 202):
+    """k right-hand-side fields on one operator: ``f_j ~ U[-1, 1]`` drawn with
+    seed ``seed0 + j`` (so f_0 is the single-problem workload's own source)."""
+    return [uniform_source(n, seed0 + j) for j in range(k)]
+
+
 def jumping_8191(seed_k: int = 301, seed_f: int = 302, n: int = 8191) -> Problem:
     """8191^2 interior, 128x128-cell blocks, ``log10 k ~ U[-3, 3]``."""
     return jumping(n, 128, -3.0, 3.0, seed_k, seed_f, f"jumping_{n}_c1e6")

@@ -150,3 +150,18 @@ def test_bench_traffic_record_is_tied_to_the_kernel_sources(tmp_path, monkeypatc
     assert bench.measured_traffic("other") is None
     (root / "k.hpp").write_text("kernel v2")
     assert bench.measured_traffic("w fp64 pre") is None
+
+
+def test_block_entry_points_validate_on_the_host(L):
+    """Block entry points reject NULL handles and arguments before any device
+    call."""
+    sz = C.c_size_t(0)
+    assert L.bmg_block_workspace_bytes(None, 2, C.byref(sz)) == boxmg.BMG_EINVAL
+    out = C.c_void_p(None)
+    assert L.bmg_block_create(C.byref(out), None, 2, None, 0) == boxmg.BMG_EINVAL
+    assert L.bmg_block_create(None, None, 2, None, 0) == boxmg.BMG_EINVAL
+    assert L.bmg_block_solve(None, None, None, 1e-10, None, None) == boxmg.BMG_EINVAL
+    assert L.bmg_block_trace_enable(None, 1, 0, 1) == boxmg.BMG_EINVAL
+    n, ms = C.c_int(0), C.c_double(0)
+    assert L.bmg_block_trace_read(None, C.byref(n), C.byref(ms), None) == boxmg.BMG_EINVAL
+    assert L.bmg_block_destroy(None) == boxmg.BMG_OK
