@@ -40,11 +40,14 @@ int tile_rows_for(const bmg_solver *h, int n)
     int m = 0;
     while ((1 << m) < n + 1 && m < 16) ++m;
     if (g_tile_rows[m] > 0) return g_tile_rows[m];
-    // measured defaults (FP64, V(2,1)): enough tiles to keep several
-    // workgroups on every CU against the warm-up rows each tile re-reads; on
-    // the levels below 1023 the shortest tiles win, their passes being bound
-    // by the latency of the row pipeline rather than by bandwidth
-    if (n >= 2047) return 32;
+    // measured defaults (FP64, V(2,1)): the fewest warm-up rows re-read while
+    // the tiles still fill the chip in whole rounds (at 4095^2, 96 rows give
+    // 731 tiles, one round of four 40 KiB workgroups per CU, where 64 rows
+    // give 1088 and a second round of 64); on the levels below 1023 the
+    // shortest tiles win, their passes being bound by the latency of the row
+    // pipeline rather than by bandwidth
+    if (n >= 4095) return 96;
+    if (n >= 2047) return 48;
     if (n >= 1023) return 16;
     if (n >= 511) return 4;
     return 2;
