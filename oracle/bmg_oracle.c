@@ -43,6 +43,140 @@
 #undef REAL
 #undef SFX
 
+static int valid_n(int n);
+
+/* ------------------------------------------------------- line relaxation
+ * The "Line" relaxation of Fig. vcycle_flowchart, read as BoxMG's alternating
+ * zebra line Gauss-Seidel (FP64): x-lines (rows) with odd index, then even,
+ * then y-lines (columns) with odd index, then even.  Each line's equations are
+ * solved exactly for its own unknowns with every other unknown at its current
+ * value.  A line is a tridiagonal system:
+ *   x-line j: a_i = A_W(i,j), b_i = A_O(i,j), c_i = A_E(i,j), i = 1..n;
+ *   y-line i: a_j = A_S(i,j), b_j = A_O(i,j), c_j = A_N(i,j), j = 1..n;
+ * right-hand side d = b minus the couplings to the two neighbouring lines,
+ * the lower (x-line: SW, S, SE) or left (y-line: SW, W, NW) one first, then
+ * the upper (NW, N, NE) or right (SE, E, NE) one, each in increasing
+ * position.  With this order an x-line is the y-line of the transposed grid.
+ *
+ * Each line matrix is factored once per level, T = L U (Thomas): m_1 = b_1,
+ * l_k = a_k / m_{k-1}, m_k = b_k - l_k c_{k-1}; stored are l_k and the
+ * reciprocal pivots r_k = 1 / m_k.  A solve is y_1 = d_1, y_k = d_k - l_k
+ * y_{k-1}, then x_n = y_n r_n, x_k = (y_k - c_k x_{k+1}) r_k.  */
+
+/* Factor of every x-line (dir 0) or y-line (dir 1) of a level into the planes
+ * l, r ((n+2)^2, entry of unknown k of the line at its grid point).  Returns
+ * ORC_EBREAKDOWN if a pivot is not positive and finite. */
+static int line_factor_dir(int n, const double *O, const double *W, const double *S, int dir,
+                           double *lf, double *rf)
+{
+    const size_t ld = (size_t)n + 2;
+    /* point k of line t, and the strides to the previous / next point */
+    const size_t step = dir == 0 ? 1 : ld;
+    int bad = 0;
+    for (int t = 1; t <= n; ++t) {
+        const size_t p0 = dir == 0 ? (size_t)t * ld + 1 : ld + (size_t)t;
+        double m_prev = 0.0;
+        for (int k = 1; k <= n; ++k) {
+            const size_t p = p0 + (size_t)(k - 1) * step;
+            /* a_k: the coupling to the previous point; c_{k-1}: the previous
+             * point's coupling to this one (the same entry, symmetric) */
+            const double a = dir == 0 ? W[p] : S[p];
+            double m;
+            if (k == 1) {
+                lf[p] = 0.0;
+                m = O[p];
+            } else {
+                const double l = a / m_prev;
+                lf[p] = l;
+                m = O[p] - l * a;
+            }
+            if (!(m > 0.0) || !isfinite(m)) bad = 1;
+            rf[p] = 1.0 / m;
+            m_prev = m;
+        }
+    }
+    return bad ? ORC_EBREAKDOWN : ORC_OK;
+}
+
+int orc_line_factor(int n, const double *O, const double *W, const double *S,
+                    double *lx, double *rx, double *ly, double *ry)
+{
+    if (!valid_n(n)) return ORC_EINVAL;
+    const int a = line_factor_dir(n, O, W, S, 0, lx, rx);
+    const int b = line_factor_dir(n, O, W, S, 1, ly, ry);
+    return a != ORC_OK ? a : b;
+}
+
+/* Solve line t of direction dir (its right-hand side from the current u) and
+ * store it into u. */
+static void line_solve(int n, const double *O, const double *W, const double *S,
+                       const double *SW, const double *NW, const double *lf,
+                       const double *rf, const double *b, double *u, int dir, int t,
+                       double *y)
+{
+    (void)O;
+    const size_t ld = (size_t)n + 2;
+    const size_t step = dir == 0 ? 1 : ld;
+    const size_t p0 = dir == 0 ? (size_t)t * ld + 1 : ld + (size_t)t;
+    for (int k = 1; k <= n; ++k) {
+        const size_t p = p0 + (size_t)(k - 1) * step;
+        double d = b[p];
+        if (dir == 0) {
+            if (SW) d -= SW[p] * u[p - ld - 1];
+            d -= S[p] * u[p - ld];
+            if (NW) d -= NW[p + 1 - ld] * u[p - ld + 1];   /* A_SE */
+            if (NW) d -= NW[p] * u[p + ld - 1];
+            d -= S[p + ld] * u[p + ld];                   /* A_N  */
+            if (SW) d -= SW[p + ld + 1] * u[p + ld + 1];  /* A_NE */
+        } else {
+            if (SW) d -= SW[p] * u[p - ld - 1];
+            d -= W[p] * u[p - 1];
+            if (NW) d -= NW[p] * u[p + ld - 1];
+            if (NW) d -= NW[p + 1 - ld] * u[p - ld + 1];   /* A_SE */
+            d -= W[p + 1] * u[p + 1];                     /* A_E  */
+            if (SW) d -= SW[p + ld + 1] * u[p + ld + 1];  /* A_NE */
+        }
+        y[k] = k == 1 ? d : d - lf[p] * y[k - 1];
+    }
+    double x = 0.0;
+    for (int k = n; k >= 1; --k) {
+        const size_t p = p0 + (size_t)(k - 1) * step;
+        const double c = dir == 0 ? W[p + 1] : S[p + ld];   /* A_E or A_N */
+        x = k == n ? y[k] * rf[p] : (y[k] - c * x) * rf[p];
+        u[p] = x;
+    }
+}
+
+/* `sweeps` alternating zebra line relaxations of u. */
+static void line_relax_sweeps(int n, const double *O, const double *W, const double *S,
+                              const double *SW, const double *NW, const double *lx,
+                              const double *rx, const double *ly, const double *ry,
+                              const double *b, double *u, int sweeps)
+{
+    for (int sweep = 0; sweep < sweeps; ++sweep) {
+        for (int dir = 0; dir < 2; ++dir) {
+            for (int parity = 1; parity >= 0; --parity) {   /* odd lines, then even */
+#pragma omp parallel
+                {
+                    double *y = (double *)malloc(((size_t)n + 1) * sizeof(double));
+#pragma omp for schedule(static)
+                    for (int t = 2 - parity; t <= n; t += 2)
+                        line_solve(n, O, W, S, SW, NW, dir == 0 ? lx : ly, dir == 0 ? rx : ry,
+                                   b, u, dir, t, y);
+                    free(y);
+                }
+            }
+        }
+    }
+}
+
+void orc_line_relax(int n, const double *O, const double *W, const double *S, const double *SW,
+                    const double *NW, const double *lx, const double *rx, const double *ly,
+                    const double *ry, const double *b, double *u, int sweeps)
+{
+    line_relax_sweeps(n, O, W, S, SW, NW, lx, rx, ly, ry, b, u, sweeps);
+}
+
 /* Error-free transformations: Knuth's TwoSum and the fma TwoProduct. */
 static inline void two_sum_(double a, double b, double *s, double *e)
 {
@@ -488,6 +622,9 @@ typedef struct {
     int have_f32;
     double Lc[81], Dc[9];
     int nu1, nu2;
+    /* line relaxation instead of point Gauss-Seidel: factors of every line */
+    int line;
+    double *lx[ORC_MAXL], *rx[ORC_MAXL], *ly[ORC_MAXL], *ry[ORC_MAXL];
 } orc_hier;
 
 static double *zalloc(size_t count)
@@ -503,6 +640,7 @@ void orc_destroy(orc_hier *H)
         free(H->Ci[l]); free(H->u[l]); free(H->b[l]); free(H->r[l]);
         free(H->fO[l]); free(H->fW[l]); free(H->fS[l]); free(H->fSW[l]); free(H->fNW[l]);
         free(H->fCi[l]); free(H->fu[l]); free(H->fb[l]); free(H->fr[l]);
+        free(H->lx[l]); free(H->rx[l]); free(H->ly[l]); free(H->ry[l]);
     }
     free(H);
 }
@@ -588,6 +726,34 @@ orc_hier *orc_setup(int n, int K, const double *st, int nu1, int nu2, int *statu
     return H;
 }
 
+/* Relax with alternating zebra line Gauss-Seidel on every level above the
+ * coarsest (the FP64 cycle): factor every line of those levels. */
+int orc_set_line_relax(orc_hier *H)
+{
+    for (int l = 0; l + 1 < H->nlev; ++l) {
+        const size_t sz = (size_t)(H->n[l] + 2) * (size_t)(H->n[l] + 2);
+        if (!H->lx[l]) {
+            H->lx[l] = zalloc(sz); H->rx[l] = zalloc(sz); H->ly[l] = zalloc(sz); H->ry[l] = zalloc(sz);
+        }
+        const int st = orc_line_factor(H->n[l], H->O[l], H->W[l], H->S[l], H->lx[l], H->rx[l],
+                                       H->ly[l], H->ry[l]);
+        if (st != ORC_OK) return st;
+    }
+    H->line = 1;
+    return ORC_OK;
+}
+
+/* The relaxation of level l: point or line Gauss-Seidel. */
+static void relax_d(orc_hier *H, int l, int sweeps)
+{
+    const int n = H->n[l];
+    if (H->line)
+        line_relax_sweeps(n, H->O[l], H->W[l], H->S[l], H->SW[l], H->NW[l], H->lx[l], H->rx[l],
+                          H->ly[l], H->ry[l], H->b[l], H->u[l], sweeps);
+    else
+        gs_sweeps_d(n, H->O[l], H->W[l], H->S[l], H->SW[l], H->NW[l], H->b[l], H->u[l], sweeps);
+}
+
 /* Round the FP64 hierarchy to an FP32 copy (round to nearest even). */
 int orc_make_f32(orc_hier *H)
 {
@@ -646,13 +812,13 @@ static void vcycle_d(orc_hier *H, int l)
 {
     if (l == H->nlev - 1) { coarse_solve_d(H); return; }
     const int n = H->n[l];
-    gs_sweeps_d(n, H->O[l], H->W[l], H->S[l], H->SW[l], H->NW[l], H->b[l], H->u[l], H->nu1);
+    relax_d(H, l, H->nu1);
     residual_d(n, H->O[l], H->W[l], H->S[l], H->SW[l], H->NW[l], H->b[l], H->u[l], H->r[l]);
     restrict__d(n, H->Ci[l], H->r[l], H->b[l + 1]);
     memset(H->u[l + 1], 0, (size_t)(H->n[l + 1] + 2) * (H->n[l + 1] + 2) * sizeof(double));
     vcycle_d(H, l + 1);
     interp_add_d(n, H->Ci[l], H->u[l + 1], H->u[l]);
-    gs_sweeps_d(n, H->O[l], H->W[l], H->S[l], H->SW[l], H->NW[l], H->b[l], H->u[l], H->nu2);
+    relax_d(H, l, H->nu2);
 }
 
 static void vcycle_f(orc_hier *H, int l)
@@ -678,14 +844,14 @@ void orc_vcycle(orc_hier *H, const double *b, double *u)
     memcpy(u, H->u[0], sz * sizeof(double));
 }
 
-/* One level-l step, on the hierarchy's own arrays: 0 = nu sweeps of GS (arg =
- * sweeps), 1 = residual into r, 2 = restriction of r into b_{l+1} and zero
+/* One level-l step, on the hierarchy's own arrays: 0 = nu relaxation sweeps
+ * (point or line Gauss-Seidel as set; arg = sweeps), 1 = residual into r, 2 = restriction of r into b_{l+1} and zero
  * u_{l+1}, 3 = u += P u_{l+1}, 4 = coarsest direct solve. */
 void orc_step(orc_hier *H, int l, int op, int arg)
 {
     const int n = H->n[l];
     switch (op) {
-    case 0: gs_sweeps_d(n, H->O[l], H->W[l], H->S[l], H->SW[l], H->NW[l], H->b[l], H->u[l], arg); break;
+    case 0: relax_d(H, l, arg); break;
     case 1: residual_d(n, H->O[l], H->W[l], H->S[l], H->SW[l], H->NW[l], H->b[l], H->u[l], H->r[l]); break;
     case 2:
         restrict__d(n, H->Ci[l], H->r[l], H->b[l + 1]);

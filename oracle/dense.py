@@ -14,7 +14,11 @@ that the C tier can be checked against them:
   neighbours, cell centres four);
 * ``colour_gs``: one four-colour Gauss-Seidel sweep as the triangular solve
   (D + L) u_new = b - U u_old in colour order, done by SciPy;
-* ``two_grid``: the explicit two-grid map S^nu2 (I - P A_c^-1 P^T A) S^nu1.
+* ``two_grid``: the explicit two-grid map S^nu2 (I - P A_c^-1 P^T A) S^nu1;
+* ``zebra_line_gs``: one alternating zebra line relaxation as four block
+  Gauss-Seidel steps over the unknown sets odd rows, even rows, odd columns,
+  even columns, each solved exactly (A restricted to a set is block diagonal
+  with one tridiagonal block per line) by SciPy.
 
 Unknowns are numbered k = (i-1) + n (j-1) over the interior.
 """
@@ -205,3 +209,24 @@ def padded(v: np.ndarray, n: int) -> np.ndarray:
     out = np.zeros((n + 2, n + 2))
     out[1:-1, 1:-1] = v.reshape(n, n)
     return out
+
+
+def line_sets(n: int):
+    """Unknown index sets of the zebra line relaxation, in its order: rows
+    j = 1, 3, ..., rows j = 2, 4, ..., columns i = 1, 3, ..., columns 2, 4, ..."""
+    i, j = np.meshgrid(np.arange(1, n + 1), np.arange(1, n + 1))
+    k = (i - 1) + n * (j - 1)
+    return [k[(j % 2) == 1], k[(j % 2) == 0], k[(i % 2) == 1], k[(i % 2) == 0]]
+
+
+def zebra_line_gs(A: sp.spmatrix, b: np.ndarray, u: np.ndarray, n: int) -> np.ndarray:
+    """u_S <- A_SS^-1 (b_S - A_S,rest u_rest) for each set S of line_sets."""
+    import scipy.sparse.linalg as spla
+    A = sp.csr_matrix(A)
+    u = np.array(u, dtype=np.float64, copy=True)
+    for S in line_sets(n):
+        S = np.sort(S.reshape(-1))
+        rest = np.setdiff1d(np.arange(n * n), S)
+        rhs = b[S] - A[S][:, rest] @ u[rest]
+        u[S] = spla.spsolve(sp.csc_matrix(A[S][:, S]), rhs)
+    return u

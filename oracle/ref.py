@@ -89,6 +89,12 @@ def lib():
         L.orc_solve_ir.restype = C.c_int
         L.orc_make_f32.argtypes = [C.c_void_p]
         L.orc_make_f32.restype = C.c_int
+        L.orc_line_factor.argtypes = [C.c_int] + [_dp] * 7
+        L.orc_line_factor.restype = C.c_int
+        L.orc_line_relax.argtypes = [C.c_int] + [_dp] * 11 + [C.c_int]
+        L.orc_line_relax.restype = None
+        L.orc_set_line_relax.argtypes = [C.c_void_p]
+        L.orc_set_line_relax.restype = C.c_int
         _lib = L
     return _lib
 
@@ -177,6 +183,27 @@ def ldlt_solve(L, D, b):
     return x
 
 
+def line_factor(O, W, S):
+    """Factors of every x-line and y-line of a level: ``(lx, rx, ly, ry)``,
+    the multipliers and reciprocal pivots of each line's tridiagonal matrix at
+    its grid points."""
+    n = O.shape[0] - 2
+    out = [np.zeros((n + 2, n + 2)) for _ in range(4)]
+    s = lib().orc_line_factor(n, _p(_c(O)), _p(_c(W)), _p(_c(S)), *[_p(o) for o in out])
+    if s:
+        raise OracleError(s, "line_factor")
+    return tuple(out)
+
+
+def line_relax(O, W, S, SW, NW, factors, b, u, sweeps=1):
+    """Alternating zebra line Gauss-Seidel sweeps; returns the updated copy of u."""
+    n = O.shape[0] - 2
+    u = np.array(u, dtype=np.float64, copy=True)
+    lib().orc_line_relax(n, *[_p(_c(a)) for a in (O, W, S, SW, NW)], *[_p(_c(f)) for f in factors],
+                         _p(_c(b)), _p(u), sweeps)
+    return u
+
+
 def sumsq(r: np.ndarray) -> float:
     """Accurately rounded sum of squares over the interior of a padded array."""
     return lib().orc_sumsq(r.shape[0] - 2, _p(_c(r)))
@@ -219,7 +246,7 @@ def interp_add(Ci, ec, u, dtype=np.float64):
 class Hierarchy:
     """FP64 BoxMG hierarchy built from a ``[n][n][K]`` stencil."""
 
-    def __init__(self, stencil: np.ndarray, nu1: int = 2, nu2: int = 1):
+    def __init__(self, stencil: np.ndarray, nu1: int = 2, nu2: int = 1, smoother: str = "point"):
         st = _c(stencil)
         n, _, K = st.shape
         status = C.c_int(0)
@@ -227,6 +254,13 @@ class Hierarchy:
         if not h:
             raise OracleError(status.value, "setup")
         self._h = h
+        if smoother == "line":
+            s = lib().orc_set_line_relax(h)
+            if s:
+                self.close()
+                raise OracleError(s, "line factor")
+        elif smoother != "point":
+            raise ValueError(smoother)
         self.n = n
         self.K = K
         self.nu1, self.nu2 = nu1, nu2
