@@ -326,6 +326,8 @@ def main():
                          "calibrate hardware byte counters) and print the achieved GB/s")
     ap.add_argument("--params", default=None, help="learned_4095: network parameters (.npy)")
     ap.add_argument("--learned-n", type=int, default=4095)
+    ap.add_argument("--smoother", choices=("point", "line"), default="point",
+                    help="line: alternating zebra line relaxation (unfused cycle)")
     ap.add_argument("--rhs", type=int, default=1,
                     help="right-hand sides solved as one block on the workload's operator")
     ap.add_argument("--batch-tile-rows", type=int, default=0,
@@ -371,8 +373,10 @@ def main():
     stencil, rhs = boxmg.discretize(k, f)
     kern = boxmg.BMG_KERNELS_FUSED if args.kernels == "fused" else boxmg.BMG_KERNELS_BASIC
     prec = boxmg.BMG_FP32_IR if args.precision == "fp32ir" else boxmg.BMG_FP64
-    opts = dict(max_cycles=args.max_cycles, kernels=kern, check_every=16, precision=prec)
-    tclass = "pre" if args.kernels == "fused" else "smooth"
+    line = args.smoother == "line"
+    opts = dict(max_cycles=args.max_cycles, kernels=kern, check_every=16, precision=prec,
+                smoother=boxmg.BMG_SMOOTH_LINE if line else boxmg.BMG_SMOOTH_POINT)
+    tclass = "pre" if args.kernels == "fused" and not line else "smooth"
     if prec == boxmg.BMG_FP32_IR:
         tclass = "resnorm"     # the FP64 outer residual (accurate, 64 B per point)
 
@@ -415,6 +419,8 @@ def main():
         traffic = measured_traffic(f"{args.workload} {args.precision} pre")
     metric = METRIC
     extra = {}
+    if line:
+        metric = f"fine DOF/s solved to {args.tol:g} rel. residual ({n}^2, line relaxation)"
     if prec == boxmg.BMG_FP32_IR:
         metric = f"fine DOF/s solved to {args.tol:g} rel. residual ({n}^2, FP32 V-cycle in FP64 refinement)"
         if args.compare_fp64:
@@ -446,7 +452,8 @@ def main():
         "config": {"workload": args.workload, "n": n, "dof": n * n, "tol": args.tol,
                    "cycles": info["cycles"], "final_rel_res": info["rel_res"],
                    "converged": info["status"] == 0, "rho": info["rho"],
-                   "kernels": args.kernels, "nu1": 2, "nu2": 1, "precision": args.precision,
+                   "kernels": "basic" if line else args.kernels, "smoother": args.smoother,
+                   "nu1": 2, "nu2": 1, "precision": args.precision,
                    **extra},
         "roofline": {"bound": "hbm", "kernel": tclass, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -50,6 +50,7 @@ enum { BMG_STENCIL_5PT = 5, BMG_STENCIL_9PT = 9 };
 enum { BMG_FP64 = 0, BMG_FP32_IR = 1 };
 enum { BMG_KERNELS_BASIC = 0, BMG_KERNELS_FUSED = 1 };
 enum { BMG_INTERP_BOXMG = 0, BMG_INTERP_LEARNED = 1 };
+enum { BMG_SMOOTH_POINT = 0, BMG_SMOOTH_LINE = 1 };
 
 typedef struct bmg_net bmg_net;   /* learned interpolation network, see below */
 
@@ -70,14 +71,22 @@ typedef struct {
                         residual, which converges below the residual floor of
                         FP64 vectors; 0 = never (default 16) */
     int tile_rows;   /* grid rows per workgroup tile of the fused passes
-                        (even, 0 = the default of 128) */
+                        (even, 0 = a measured default for each level size) */
     int interp;      /* BMG_INTERP_BOXMG (default): operator-induced weights on
                         every level; BMG_INTERP_LEARNED: the weights of levels
                         l < learned_levels come from the network `net` */
     int learned_levels; /* levels with learned weights (0 = all) */
     bmg_net *net;    /* network of BMG_INTERP_LEARNED (not owned); it must
                         outlive the set-up call only */
-    int reserved[4];
+    int smoother;    /* BMG_SMOOTH_POINT (default): four-colour point
+                        Gauss-Seidel; BMG_SMOOTH_LINE: alternating zebra line
+                        Gauss-Seidel (the "Line" relaxation of Fig.
+                        vcycle_flowchart): x-lines odd then even, then y-lines
+                        odd then even, each line's tridiagonal system solved
+                        exactly with a factor formed at set-up.  FP64 only; the
+                        cycle then runs one launch per step (kernels is
+                        ignored) */
+    int reserved[3];
 } bmg_options;
 
 typedef struct {

@@ -726,11 +726,11 @@ orc_hier *orc_setup(int n, int K, const double *st, int nu1, int nu2, int *statu
     return H;
 }
 
-/* Relax with alternating zebra line Gauss-Seidel on every level above the
- * coarsest (the FP64 cycle): factor every line of those levels. */
+/* Relax with alternating zebra line Gauss-Seidel on every level (the FP64
+ * cycle): factor every line of every level. */
 int orc_set_line_relax(orc_hier *H)
 {
-    for (int l = 0; l + 1 < H->nlev; ++l) {
+    for (int l = 0; l < H->nlev; ++l) {
         const size_t sz = (size_t)(H->n[l] + 2) * (size_t)(H->n[l] + 2);
         if (!H->lx[l]) {
             H->lx[l] = zalloc(sz); H->rx[l] = zalloc(sz); H->ly[l] = zalloc(sz); H->ry[l] = zalloc(sz);

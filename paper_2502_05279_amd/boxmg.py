@@ -14,15 +14,16 @@ import torch
 
 from . import build as _build
 
-__all__ = ["BoxMGError", "Options", "Solver", "Batch", "Net", "discretize", "lib", "FIELDS", "STEPS",
+__all__ = ["BoxMGError", "Options", "Solver", "Block", "Batch", "Net", "discretize", "lib", "FIELDS", "STEPS",
            "tile_rows_set", "tile_rows_get", "solve_select", "NET_PARAMS", "NET_ARRAYS",
-           "BMG_INTERP_BOXMG", "BMG_INTERP_LEARNED",
+           "BMG_INTERP_BOXMG", "BMG_INTERP_LEARNED", "BMG_SMOOTH_POINT", "BMG_SMOOTH_LINE",
            "TRACE", "BMG_FP64", "BMG_FP32_IR", "BMG_KERNELS_BASIC", "BMG_KERNELS_FUSED"]
 
 BMG_OK, BMG_EINVAL, BMG_EBREAKDOWN, BMG_ENOCONV, BMG_EDIVERGED, BMG_EDEVICE, BMG_EWORKSPACE = \
     0, -1, -2, -3, -4, -5, -6
 BMG_FP64, BMG_FP32_IR = 0, 1
 BMG_KERNELS_BASIC, BMG_KERNELS_FUSED = 0, 1
+BMG_SMOOTH_POINT, BMG_SMOOTH_LINE = 0, 1
 BMG_INTERP_BOXMG, BMG_INTERP_LEARNED = 0, 1
 NET_PARAMS = 14184
 NET_ARRAYS = {"X": 0, "H1": 1, "H2": 2, "D3": 3, "D2": 4, "D1": 5}
@@ -39,7 +40,8 @@ class Options(C.Structure):
     _fields_ = [("nu1", C.c_int), ("nu2", C.c_int), ("max_cycles", C.c_int),
                 ("precision", C.c_int), ("kernels", C.c_int), ("check_every", C.c_int),
                 ("refine_factor", C.c_int), ("tile_rows", C.c_int), ("interp", C.c_int),
-                ("learned_levels", C.c_int), ("net", C.c_void_p), ("reserved", C.c_int * 4)]
+                ("learned_levels", C.c_int), ("net", C.c_void_p), ("smoother", C.c_int),
+                ("reserved", C.c_int * 3)]
 
 
 class Info(C.Structure):

@@ -4,6 +4,7 @@
 
 #include "bmg.h"
 #include "bmg_fused.hpp"
+#include "bmg_line.hpp"
 
 #include <vector>
 
@@ -76,6 +77,10 @@ struct bmg_solver {
     // k*kpart doubles after
     int nrhs = 1, kstop = 0, kpart = 0;
     size_t ks[MAXL] = {};
+    // line relaxation: factors of the y-lines (lfy, rfy) and, transposed, of
+    // the x-lines (lfx, rfx) with the transposed W; one scratch plane
+    double *lfy[MAXL] = {}, *rfy[MAXL] = {}, *lfx[MAXL] = {}, *rfx[MAXL] = {}, *WT[MAXL] = {};
+    double *lineD = nullptr;
     double *B0 = nullptr;       // fine right-hand side during refinement
     double *XH = nullptr;       // double-FP64 iterate, high part
     double *XL = nullptr;       // double-FP64 iterate, low part

@@ -44,7 +44,7 @@ enum : int { LNE = 0, LA = 1, LNW = 2, LR = 3, LL = 4, LSE = 5, LB = 6, LSW = 7 
 // validation / breakdown flag bits
 enum : int {
     F_NONFINITE = 1, F_DIAG = 2, F_BOUNDARY = 4, F_ASYM = 8,
-    F_BREAK_INTERP = 16, F_BREAK_COARSE = 32
+    F_BREAK_INTERP = 16, F_BREAK_COARSE = 32, F_BREAK_LINE = 64
 };
 
 __device__ __forceinline__ bool stopped(const int *stop) { return stop && *stop; }

@@ -144,7 +144,15 @@ size_t plan(bmg_solver *h, int n, int kind, const bmg_options &o, char *base)
                 FW.p = (float *)take(8 * W.ps * 4);
             }
         }
+        double *lf[5] = {};
+        if (o.smoother == BMG_SMOOTH_LINE)
+            for (int q = 0; q < 5; ++q) lf[q] = (double *)take(pl * 8);
         if (h) {
+            h->lfy[l] = lf[0];
+            h->rfy[l] = lf[1];
+            h->lfx[l] = lf[2];
+            h->rfx[l] = lf[3];
+            h->WT[l] = lf[4];
             h->L[l] = D;
             h->C[l] = W;
             h->nine[l] = nine;
@@ -155,6 +163,7 @@ size_t plan(bmg_solver *h, int n, int kind, const bmg_options &o, char *base)
         }
     }
     const size_t pl0 = (size_t)(ns[0] + 2) * pitch_of(ns[0]);
+    double *lineD = o.smoother == BMG_SMOOTH_LINE ? (double *)take(pl0 * 8) : nullptr;
     double *B0 = (double *)take(pl0 * 8);
     double *XH = (double *)take(pl0 * 8);
     double *XL = (double *)take(pl0 * 8);
@@ -167,6 +176,7 @@ size_t plan(bmg_solver *h, int n, int kind, const bmg_options &o, char *base)
     int *cnt = (int *)take(64);
     if (h) {
         h->nlev = nl;
+        h->lineD = lineD;
         h->B0 = B0;
         h->XH = XH;
         h->XL = XL;
@@ -203,6 +213,10 @@ bmg_status check_options(const bmg_options &o)
         return fail(BMG_EINVAL, "unknown interpolation %d", o.interp);
     if (o.interp == BMG_INTERP_LEARNED && !o.net) return fail(BMG_EINVAL, "learned interpolation without a network");
     if (o.learned_levels < 0) return fail(BMG_EINVAL, "learned_levels=%d must be >= 0", o.learned_levels);
+    if (o.smoother != BMG_SMOOTH_POINT && o.smoother != BMG_SMOOTH_LINE)
+        return fail(BMG_EINVAL, "unknown smoother %d", o.smoother);
+    if (o.smoother == BMG_SMOOTH_LINE && o.precision != BMG_FP64)
+        return fail(BMG_EINVAL, "line relaxation runs FP64 hierarchies");
     return BMG_OK;
 }
 
@@ -239,10 +253,47 @@ static inline double stencil_planes(bool nine) { return nine ? 5.0 : 3.0; }
 // -------------------------------------------------------- cycle steps
 const dim3 B2(64, 4);
 
+// `sweeps` alternating zebra line relaxations of level l (FP64).
+bmg_status line_smooth(bmg_solver *h, const Lev<double> &L, bool nine, int sweeps, const int *stop, int l)
+{
+    const int n = L.n, ld = L.ld;
+    const dim3 tb(LT, 8), tg((n + 2 + LT - 1) / LT, (n + 2 + LT - 1) / LT);
+    double *D = h->lineD;
+    // per relaxation and direction: b, u, the line coupling, the off-line
+    // couplings (S or W; also SW, NW) and the factor l, r read, u written
+    trace_begin(h, BMG_TRACE_SMOOTH, l, sweeps * 2.0 * 8.0 * (nine ? 9.0 : 7.0) * (double)n * n);
+    for (int s = 0; s < sweeps; ++s) {
+        for (int par = 1; par >= 0; --par) {   // x-lines: odd rows, then even
+            const int nl = par ? (n + 1) / 2 : (n - 1) / 2;
+            if (nine) hipLaunchKernelGGL((k_line_rhs_x<true>), tg, tb, 0, h->st, L, par, D, stop);
+            else hipLaunchKernelGGL((k_line_rhs_x<false>), tg, tb, 0, h->st, L, par, D, stop);
+            hipLaunchKernelGGL(k_line_solve, dim3((nl + 63) / 64), dim3(64), 0, h->st, n, ld, par, D,
+                               (const double *)h->lfx[l], (const double *)h->rfx[l], (const double *)h->WT[l], D,
+                               stop);
+            hipLaunchKernelGGL(k_line_put_x, tg, tb, 0, h->st, n, ld, par, (const double *)D, L.u, stop);
+        }
+        for (int par = 1; par >= 0; --par) {   // y-lines: odd columns, then even
+            const int nl = par ? (n + 1) / 2 : (n - 1) / 2;
+            const dim3 rb(64, 4), rg((nl + 63) / 64, (n + 3) / 4);
+            if (nine) hipLaunchKernelGGL((k_line_rhs_y<true>), rg, rb, 0, h->st, L, par, D, stop);
+            else hipLaunchKernelGGL((k_line_rhs_y<false>), rg, rb, 0, h->st, L, par, D, stop);
+            hipLaunchKernelGGL(k_line_solve, dim3((nl + 63) / 64), dim3(64), 0, h->st, n, ld, par, D,
+                               (const double *)h->lfy[l], (const double *)h->rfy[l], (const double *)L.S, L.u,
+                               stop);
+        }
+    }
+    trace_end(h, BMG_TRACE_SMOOTH, l);
+    LAUNCHCHK();
+    return BMG_OK;
+}
+
 template <typename T>
 bmg_status smooth(bmg_solver *h, const Lev<T> &L, bool nine, int sweeps, const int *stop, int level)
 {
     if (sweeps <= 0) return BMG_OK;
+    if constexpr (std::is_same<T, double>::value) {
+        if (h->opt.smoother == BMG_SMOOTH_LINE) return line_smooth(h, L, nine, sweeps, stop, level);
+    }
     // per sweep: stencil, b and u read, u written
     trace_begin(h, BMG_TRACE_SMOOTH, level,
                 sweeps * (stencil_planes(nine) + 3.0) * sizeof(T) * (double)L.n * L.n);
@@ -755,6 +806,20 @@ bmg_status bmg_setup(bmg_solver **out, const double *stencil, int n, int kind, c
         hipLaunchKernelGGL(k_rap, grid2(nc, nc, dim3(32, 4)), dim3(32, 4), 0, h->st, h->L[l], h->C[l], h->L[l + 1]);
     }
     hipLaunchKernelGGL(k_coarse_factor, dim3(1), dim3(64), 0, h->st, h->L[h->nlev - 1], h->LD, h->flags);
+    if (op.smoother == BMG_SMOOTH_LINE) {
+        // y-lines in the grid's frame; x-lines on the transposed O (in the
+        // scratch plane) and W
+        for (int l = 0; l < h->nlev; ++l) {
+            const Lev<double> &L = h->L[l];
+            const dim3 fb(64), fg((L.n + 63) / 64), tb(LT, 8), tg((L.n + 2 + LT - 1) / LT, (L.n + 2 + LT - 1) / LT);
+            hipLaunchKernelGGL(k_line_factor, fg, fb, 0, h->st, L.n, L.ld, (const double *)L.O, (const double *)L.S,
+                               h->lfy[l], h->rfy[l], h->flags);
+            hipLaunchKernelGGL(k_transpose, tg, tb, 0, h->st, L.n, L.ld, (const double *)L.O, h->lineD);
+            hipLaunchKernelGGL(k_transpose, tg, tb, 0, h->st, L.n, L.ld, (const double *)L.W, h->WT[l]);
+            hipLaunchKernelGGL(k_line_factor, fg, fb, 0, h->st, L.n, L.ld, (const double *)h->lineD,
+                               (const double *)h->WT[l], h->lfx[l], h->rfx[l], h->flags);
+        }
+    }
     if (h->f32) {
         for (int l = 0; l < h->nlev; ++l) {
             const size_t pl = (size_t)(h->L[l].n + 2) * h->L[l].ld;
@@ -782,9 +847,10 @@ bmg_status bmg_setup(bmg_solver **out, const double *stencil, int n, int kind, c
         return bail(fail(BMG_EINVAL, "stencil rejected:%s%s%s%s", (flags & F_NONFINITE) ? " non-finite entry" : "",
                          (flags & F_DIAG) ? " centre <= 0" : "", (flags & F_BOUNDARY) ? " coupling to the boundary" : "",
                          (flags & F_ASYM) ? " not symmetric" : ""));
-    if (flags & (F_BREAK_INTERP | F_BREAK_COARSE))
-        return bail(fail(BMG_EBREAKDOWN, "%s", (flags & F_BREAK_INTERP) ? "interpolation denominator <= 0"
-                                                                         : "coarsest pivot <= 0"));
+    if (flags & (F_BREAK_INTERP | F_BREAK_COARSE | F_BREAK_LINE))
+        return bail(fail(BMG_EBREAKDOWN, "%s", (flags & F_BREAK_INTERP)   ? "interpolation denominator <= 0"
+                                               : (flags & F_BREAK_COARSE) ? "coarsest pivot <= 0"
+                                                                          : "line factor pivot <= 0"));
 #undef SCHK
     *out = h;
     return BMG_OK;
@@ -798,10 +864,16 @@ bmg_status bmg_destroy(bmg_solver *h)
     return BMG_OK;
 }
 
+// The fused passes relax pointwise: line relaxation runs the unfused cycle.
+static bool fused(const bmg_solver *h)
+{
+    return h->opt.kernels == BMG_KERNELS_FUSED && h->opt.smoother == BMG_SMOOTH_POINT;
+}
+
 // One FP64 V-cycle on the level-0 arrays (b, u already set).
 static bmg_status cycle64(bmg_solver *h, const int *stop)
 {
-    if (h->opt.kernels == BMG_KERNELS_FUSED) return fused_vcycle(h, stop);
+    if (fused(h)) return fused_vcycle(h, stop);
     return vcycle_from<double>(h, 0, stop);
 }
 
@@ -818,7 +890,7 @@ static bmg_status ir_correct(bmg_solver *h, const int *stop)
     hipLaunchKernelGGL(k_ir_scale, grid2(L.n, L.n, B2), B2, 0, h->st, L, F, (const double *)(h->scal + S_RMAX),
                        h->scal + S_SCALE, stop);
     LAUNCHCHK();
-    if (h->opt.kernels == BMG_KERNELS_FUSED) TRY(fused_vcycle32(h, stop));
+    if (fused(h)) TRY(fused_vcycle32(h, stop));
     else TRY(vcycle_from<float>(h, 0, stop));
     hipLaunchKernelGGL(k_dd_update, grid2(L.n, L.n, B2), B2, 0, h->st, L, h->XH, h->XL, (const float *)F.u,
                        (const double *)(h->scal + S_SCALE), stop);
@@ -832,7 +904,7 @@ static bmg_status ir_correct(bmg_solver *h, const int *stop)
 static bmg_status cycle_and_norm(bmg_solver *h, double tol, int maxc, double refine)
 {
     const Lev<double> &L = h->L[0];
-    if (h->opt.kernels == BMG_KERNELS_FUSED) {
+    if (fused(h)) {
         TRY(fused_vcycle(h, h->stop, true));
         if (h->norm_parts > 0) {
             trace_begin(h, BMG_TRACE_RESNORM, 0, 8.0 * h->norm_parts);   // the partial sums
@@ -1211,8 +1283,10 @@ static bmg_status step_t(bmg_solver *h, int l, int step, int arg)
     case BMG_STEP_COARSE:
         if (!last) return fail(BMG_EINVAL, "the direct solve runs on the coarsest level only");
         return coarse<T>(h, F, nullptr);
-    case BMG_STEP_PRE: return fused_pre<T>(h, l, arg, nullptr);
-    case BMG_STEP_POST: return fused_post<T>(h, l, arg, nullptr);
+    case BMG_STEP_PRE:
+    case BMG_STEP_POST:
+        if (h->opt.smoother != BMG_SMOOTH_POINT) return fail(BMG_EINVAL, "the fused passes relax pointwise");
+        return step == BMG_STEP_PRE ? fused_pre<T>(h, l, arg, nullptr) : fused_post<T>(h, l, arg, nullptr);
     default: return fail(BMG_EINVAL, "unknown step %d", step);
     }
 }
@@ -1284,7 +1358,8 @@ bmg_status block_check(const bmg_solver *h, int k)
     if (!h) return fail(BMG_EINVAL, "NULL handle");
     if (k < 1 || k > 4096) return fail(BMG_EINVAL, "k=%d right-hand sides must be in [1, 4096]", k);
     if (h->opt.precision != BMG_FP64) return fail(BMG_EINVAL, "block solves run FP64 hierarchies");
-    if (h->opt.kernels != BMG_KERNELS_FUSED) return fail(BMG_EINVAL, "block solves need the fused kernels");
+    if (h->opt.kernels != BMG_KERNELS_FUSED || h->opt.smoother != BMG_SMOOTH_POINT)
+        return fail(BMG_EINVAL, "block solves need the fused kernels (point relaxation)");
     if (h->opt.nu1 < 1 || h->opt.nu1 > 3 || h->opt.nu2 < 1 || h->opt.nu2 > 2)
         return fail(BMG_EINVAL, "block solves need 1 <= nu1 <= 3 and 1 <= nu2 <= 2");
     return BMG_OK;
