@@ -38,17 +38,19 @@ HBM_PEAK_GBS = 8000.0
 # stored weights their 8 planes add 16 B per fine point.
 
 
-def measured_traffic(key: str):
+def measured_traffic(key: str, tile_rows: int | None = None):
     """HBM bytes per launch of the timed kernel from the committed counter
     record (FETCH_SIZE and WRITE_SIZE, each scaled by what it reads for a copy
-    of known size), or None when there is none for this run or the kernel's
-    sources have changed since it was taken."""
+    of known size), or None when there is none for this run, or the kernel's
+    sources or its launch geometry (rows per tile) have changed since."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         rec = json.load(open(path)).get(key)
     except (OSError, ValueError):
         return None
     if not rec:
+        return None
+    if tile_rows is not None and rec.get("tile_rows") not in (None, tile_rows):
         return None
     h = hashlib.sha256()
     for f in rec["sources"]:
@@ -416,7 +418,7 @@ def main():
     achieved = bpl / (avg_ms * 1e-3) / 1e9 if working else None
     traffic = None
     if tclass == "pre" and args.kernels == "fused":
-        traffic = measured_traffic(f"{args.workload} {args.precision} pre")
+        traffic = measured_traffic(f"{args.workload} {args.precision} pre", boxmg.tile_rows_get(n))
     metric = METRIC
     extra = {}
     if line:

@@ -147,6 +147,10 @@ def test_bench_traffic_record_is_tied_to_the_kernel_sources(tmp_path, monkeypatc
     (root / "profiles" / "traffic.json").write_text(json.dumps(rec))
     monkeypatch.setattr(bench, "ROOT", str(root))
     assert bench.measured_traffic("w fp64 pre") == 123
+    rec["w fp64 pre"]["tile_rows"] = 96
+    (root / "profiles" / "traffic.json").write_text(json.dumps(rec))
+    assert bench.measured_traffic("w fp64 pre", 96) == 123
+    assert bench.measured_traffic("w fp64 pre", 32) is None
     assert bench.measured_traffic("w fp64 post") is None
     assert bench.measured_traffic("other") is None
     (root / "k.hpp").write_text("kernel v2")
