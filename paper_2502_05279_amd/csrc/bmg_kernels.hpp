@@ -517,16 +517,28 @@ static __global__ void k_sumsq_partial(Lev<T> L, const T *__restrict__ x, double
     if (threadIdx.x == 0) part[blockIdx.x] = acc;
 }
 
+// Several right-hand sides in one launch (block solves): the launch serves
+// those whose mode[] equals `want`; right-hand side z's level-0 u, b are kl
+// elements after the first's, its B, XH, XL planes kx after, its partial sums
+// kpart doubles, scalars kscal doubles, history khist doubles and (count, stop)
+// pair kcnt ints after.
+struct RhsFan {
+    int nrhs;
+    const int *mode;
+    int want;
+    size_t kl, kx;
+    int kpart, kscal, khist, kcnt;
+};
+
 // Final sum of the partials (fixed order) -> out[0].  With `hist` given (and
 // the solve not stopped), this also records rel = sqrt(sum)/bnorm[0] into hist[*count], advances the count,
 // and raises *stop: 1 once rel <= tol, 2 if rel is not finite or exceeds
 // 1e3 times the initial relative residual bnorm[1], 3 when maxc entries exist,
 // 4 once rel <= refine (refine > 0): the solve switches to refinement.
-static __global__ void k_sumsq_final(const double *__restrict__ part, int np, double *__restrict__ out,
-                              double *hist, int *count, int *stop, const double *bnorm,
-                              double tol, int maxc, double refine)
+__device__ __forceinline__ void sumsq_final_body(const double *__restrict__ part, int np, double *__restrict__ out,
+                                                 double *hist, int *count, int *stop, const double *bnorm,
+                                                 double tol, int maxc, double refine)
 {
-    if (hist && stopped(stop)) return;   // a finished solve records nothing more
     double v = 0.0;
     for (int t = threadIdx.x; t < np; t += blockDim.x) v += part[t];
     v = block_sum(v);
@@ -545,6 +557,27 @@ static __global__ void k_sumsq_final(const double *__restrict__ part, int np, do
             if (s) *stop = s;
         }
     }
+}
+
+static __global__ void k_sumsq_final(const double *__restrict__ part, int np, double *__restrict__ out,
+                              double *hist, int *count, int *stop, const double *bnorm,
+                              double tol, int maxc, double refine)
+{
+    if (hist && stopped(stop)) return;   // a finished solve records nothing more
+    sumsq_final_body(part, np, out, hist, count, stop, bnorm, tol, maxc, refine);
+}
+
+// The same for the right-hand sides F selects (one workgroup each): out and
+// bnorm are the first right-hand side's, count its (count, stop) pair.
+static __global__ void k_sumsq_final_fan(const double *__restrict__ part, int np, double *out, double *hist,
+                                         int *count, const double *bnorm, double tol, int maxc, double refine,
+                                         RhsFan F)
+{
+    const int z = blockIdx.x;
+    int *cz = count + z * F.kcnt;
+    if (F.mode[z] != F.want || stopped(cz + 1)) return;
+    sumsq_final_body(part + (size_t)z * F.kpart, np, out + z * F.kscal, hist + (size_t)z * F.khist, cz, cz + 1,
+                     bnorm + z * F.kscal, tol, maxc, refine);
 }
 
 // ---------------------------------------------------- layout conversions
@@ -638,16 +671,17 @@ __device__ __forceinline__ void two_sum(double a, double b, double &s, double &e
 // TwoSum, the errors summed apart, then the XL products, one final rounding.
 // MODE 0: sum of squares only; 1: also r -> rout; 2: also r -> L.b and 0 -> L.u
 // (the next refinement cycle starts from zero on the right-hand side r).
+
+// Row block rb of nrb (rows 1 + rb, 1 + rb + nrb, ...) into part[rb].
 template <bool NINE, int MODE>
-static __global__ void k_resid_dd(Lev<double> L, const double *__restrict__ B, const double *__restrict__ XH,
-                           const double *__restrict__ XL, double *__restrict__ rout,
-                           double *__restrict__ part, const int *stop)
+__device__ __forceinline__ void resid_dd_rows(Lev<double> L, const double *__restrict__ B,
+                                              const double *__restrict__ XH, const double *__restrict__ XL,
+                                              double *__restrict__ rout, double *__restrict__ part, int rb, int nrb)
 {
-    if (stopped(stop)) return;
     const size_t ld = L.ld;
     const int n = L.n;
     double acc = 0.0;
-    for (int j = 1 + blockIdx.x; j <= n; j += gridDim.x) {
+    for (int j = 1 + rb; j <= n; j += nrb) {
         for (int i = 1 + threadIdx.x; i <= n; i += blockDim.x) {
             const size_t p = (size_t)j * ld + i;
             double a[9];
@@ -691,17 +725,45 @@ static __global__ void k_resid_dd(Lev<double> L, const double *__restrict__ B, c
         }
     }
     acc = block_sum(acc);
-    if (threadIdx.x == 0) part[blockIdx.x] = acc;
+    if (threadIdx.x == 0) part[rb] = acc;
+}
+
+template <bool NINE, int MODE>
+static __global__ void k_resid_dd(Lev<double> L, const double *__restrict__ B, const double *__restrict__ XH,
+                           const double *__restrict__ XL, double *__restrict__ rout,
+                           double *__restrict__ part, const int *stop)
+{
+    if (stopped(stop)) return;
+    resid_dd_rows<NINE, MODE>(L, B, XH, XL, rout, part, blockIdx.x, gridDim.x);
+}
+
+// The same for the right-hand sides F selects: work item w serves right-hand
+// side w % nrhs and row block w / nrhs.  Consecutive workgroups are dealt
+// round-robin to the 8 XCDs, so w regroups them (grids that are a multiple of
+// 8) to give each XCD a contiguous run: the right-hand sides of a row block run
+// side by side on one XCD and share its operator rows through that L2.
+template <bool NINE, int MODE>
+static __global__ void k_resid_dd_fan(Lev<double> L, const double *__restrict__ B, const double *__restrict__ XH,
+                                      const double *__restrict__ XL, double *__restrict__ part, const int *stop,
+                                      RhsFan F)
+{
+    const int g = gridDim.x;
+    const int w = (g & 7) ? (int)blockIdx.x : (int)(blockIdx.x & 7) * (g >> 3) + (int)(blockIdx.x >> 3);
+    const int z = w % F.nrhs;
+    if (F.mode[z] != F.want || stopped(stop + z * F.kcnt)) return;
+    L.u += z * F.kl;
+    L.b += z * F.kl;
+    resid_dd_rows<NINE, MODE>(L, B + z * F.kx, XH + z * F.kx, XL ? XL + z * F.kx : XL, nullptr,
+                              part + (size_t)z * F.kpart, w / F.nrhs, g / F.nrhs);
 }
 
 // (XH, XL) += d in double-FP64 with d = L.u (FP64 inner cycle) or
 // d = scale * (double)U32 (FP32 inner cycle): TwoSum, add the low part,
 // renormalise with Dekker's fast TwoSum.
-static __global__ void k_dd_update(Lev<double> L, double *__restrict__ XH, double *__restrict__ XL,
-                            const float *__restrict__ U32, const double *__restrict__ scale,
-                            const int *stop)
+__device__ __forceinline__ void dd_update_point(const Lev<double> &L, double *__restrict__ XH,
+                                                double *__restrict__ XL, const float *__restrict__ U32,
+                                                const double *__restrict__ scale)
 {
-    if (stopped(stop)) return;
     const int i = 1 + blockIdx.x * blockDim.x + threadIdx.x;
     const int j = 1 + blockIdx.y * blockDim.y + threadIdx.y;
     if (i > L.n || j > L.n) return;
@@ -713,6 +775,24 @@ static __global__ void k_dd_update(Lev<double> L, double *__restrict__ XH, doubl
     const double hi = s + e;
     XL[p] = e - (hi - s);
     XH[p] = hi;
+}
+
+static __global__ void k_dd_update(Lev<double> L, double *__restrict__ XH, double *__restrict__ XL,
+                            const float *__restrict__ U32, const double *__restrict__ scale,
+                            const int *stop)
+{
+    if (stopped(stop)) return;
+    dd_update_point(L, XH, XL, U32, scale);
+}
+
+// FP64 inner cycle, the right-hand sides F selects (blockIdx.z).
+static __global__ void k_dd_update_fan(Lev<double> L, double *__restrict__ XH, double *__restrict__ XL,
+                                       const int *stop, RhsFan F)
+{
+    const int z = blockIdx.z;
+    if (F.mode[z] != F.want || stopped(stop + z * F.kcnt)) return;
+    L.u += z * F.kl;
+    dd_update_point(L, XH + z * F.kx, XL + z * F.kx, nullptr, nullptr);
 }
 
 }  // namespace bmg

@@ -1349,6 +1349,7 @@ struct bmg_block {
     int k = 0;
     bmg_solver hb;
     std::vector<bmg_solver> view;
+    int *mode = nullptr;        // device: each right-hand side's state in the solve
 };
 
 namespace {
@@ -1391,7 +1392,9 @@ size_t block_plan(const bmg_solver *h, int k, char *base, bmg_block *B)
     double *scal = (double *)take((size_t)k * S_NSCAL * 8);
     double *hist = (double *)take((size_t)k * h->hist_cap * 8);
     int *cnt = (int *)take((size_t)k * 2 * sizeof(int));
+    int *mode = (int *)take((size_t)k * sizeof(int));
     if (B) {
+        B->mode = mode;
         bmg_solver &v = B->hb;
         v = *h;
         v.tr_ev.clear();
@@ -1535,36 +1538,71 @@ bmg_status bmg_block_solve(bmg_block *B, const double *rhs, double *x, double to
         HIPCHK(hipMemcpyAsync(v->L[0].u, v->XH, pl0, hipMemcpyDeviceToDevice, hb->st));
     }
     HIPCHK(hipMemcpyAsync(hb->count, cs.data(), 2 * K * sizeof(int), hipMemcpyHostToDevice, hb->st));
-    HIPCHK(hipStreamSynchronize(hb->st));   // init[] and cs[] are read by the copies above
+    HIPCHK(hipMemcpyAsync(B->mode, mode.data(), K * sizeof(int), hipMemcpyHostToDevice, hb->st));
+    HIPCHK(hipStreamSynchronize(hb->st));   // init[], cs[] and mode[] are read by the copies above
+    // the per-right-hand-side steps of a cycle run as one launch each over the
+    // right-hand sides in the state they apply to
+    const size_t p0 = hb->ks[0];            // elements between right-hand sides' fine planes
+    auto fan = [&](int want) {
+        RhsFan F;
+        F.nrhs = K;
+        F.mode = B->mode;
+        F.want = want;
+        F.kl = hb->ks[0];
+        F.kx = p0;
+        F.kpart = NPART;
+        F.kscal = S_NSCAL;
+        F.khist = hb->hist_cap;
+        F.kcnt = 2;
+        return F;
+    };
+    const int nb = std::min(NPART_ROWS, L.n);
     const int every = hb->opt.check_every;
     while (true) {
+        const bool any_plain = std::count(mode.begin(), mode.end(), (int)PLAIN) > 0;
+        const bool any_ref = std::count(mode.begin(), mode.end(), (int)REFINING) > 0;
         for (int t = 0; t < every; ++t) {
             // one V-cycle of every running right-hand side (plain: on (b, u);
             // refining: on (r, 0)); stopped ones return at once
             TRY(fused_vcycle(hb, hb->stop, true));
-            for (int j = 0; j < K; ++j) {
-                bmg_solver *v = &B->view[j];
-                if (mode[j] == PLAIN) {
-                    if (hb->norm_parts > 0) {
-                        hipLaunchKernelGGL(k_sumsq_final, dim3(1), dim3(1024), 0, hb->st, (const double *)v->part,
-                                           hb->norm_parts, v->scal + S_SUMSQ, v->hist, v->count, v->stop,
-                                           (const double *)(v->scal + S_BNORM), tol, maxc, refine);
-                        LAUNCHCHK();
-                    } else {
-                        TRY(resnorm_dd(v, v->L[0].b, v->L[0].u, nullptr, 0, nullptr, S_SUMSQ, true, tol, maxc,
-                                       refine));
-                    }
-                } else if (mode[j] == REFINING) {
-                    hipLaunchKernelGGL(k_dd_update, grid2(L.n, L.n, B2), B2, 0, hb->st, v->L[0], v->XH, v->XL,
-                                       (const float *)nullptr, (const double *)nullptr, v->stop);
+            if (any_plain) {
+                if (hb->norm_parts > 0) {
+                    hipLaunchKernelGGL(k_sumsq_final_fan, dim3(K), dim3(1024), 0, hb->st, (const double *)hb->part,
+                                       hb->norm_parts, hb->scal + S_SUMSQ, hb->hist, hb->count,
+                                       (const double *)(hb->scal + S_BNORM), tol, maxc, refine, fan(PLAIN));
                     LAUNCHCHK();
-                    TRY(resnorm_dd(v, v->B0, v->XH, v->XL, 2, nullptr, S_SUMSQ, true, tol, maxc, 0.0));
+                } else {
+                    for (int j = 0; j < K; ++j) {
+                        bmg_solver *v = &B->view[j];
+                        if (mode[j] == PLAIN)
+                            TRY(resnorm_dd(v, v->L[0].b, v->L[0].u, nullptr, 0, nullptr, S_SUMSQ, true, tol, maxc,
+                                           refine));
+                    }
                 }
+            }
+            if (any_ref) {
+                // (XH, XL) += u, then r = B0 - A (XH + XL) -> b and 0 -> u
+                dim3 g = grid2(L.n, L.n, B2);
+                g.z = K;
+                hipLaunchKernelGGL(k_dd_update_fan, g, B2, 0, hb->st, L, hb->XH, hb->XL, (const int *)hb->stop,
+                                   fan(REFINING));
+                if (hb->nine[0])
+                    hipLaunchKernelGGL((k_resid_dd_fan<true, 2>), dim3(nb * K), dim3(256), 0, hb->st, L,
+                                       (const double *)hb->B0, (const double *)hb->XH, (const double *)hb->XL,
+                                       hb->part, (const int *)hb->stop, fan(REFINING));
+                else
+                    hipLaunchKernelGGL((k_resid_dd_fan<false, 2>), dim3(nb * K), dim3(256), 0, hb->st, L,
+                                       (const double *)hb->B0, (const double *)hb->XH, (const double *)hb->XL,
+                                       hb->part, (const int *)hb->stop, fan(REFINING));
+                hipLaunchKernelGGL(k_sumsq_final_fan, dim3(K), dim3(1024), 0, hb->st, (const double *)hb->part, nb,
+                                   hb->scal + S_SUMSQ, hb->hist, hb->count, (const double *)(hb->scal + S_BNORM),
+                                   tol, maxc, 0.0, fan(REFINING));
+                LAUNCHCHK();
             }
         }
         HIPCHK(hipMemcpyAsync(cs.data(), hb->count, 2 * K * sizeof(int), hipMemcpyDeviceToHost, hb->st));
         HIPCHK(hipStreamSynchronize(hb->st));
-        bool running = false;
+        bool running = false, switched = false;
         for (int j = 0; j < K; ++j) {
             bmg_solver *v = &B->view[j];
             if (mode[j] == PLAIN && cs[2 * j + 1] == 4) {
@@ -1575,10 +1613,14 @@ bmg_status bmg_block_solve(bmg_block *B, const double *rhs, double *x, double to
                 HIPCHK(hipMemsetAsync(v->XL, 0, pl0, hb->st));
                 TRY(resnorm_dd(v, v->B0, v->XH, v->XL, 2, nullptr, S_TMP, false, 0.0, 0, 0.0));
                 HIPCHK(hipMemsetAsync(v->stop, 0, sizeof(int), hb->st));
-                running = true;
+                running = switched = true;
             } else if (mode[j] != ZERO && cs[2 * j + 1] == 0) {
                 running = true;
             }
+        }
+        if (switched) {
+            HIPCHK(hipMemcpyAsync(B->mode, mode.data(), K * sizeof(int), hipMemcpyHostToDevice, hb->st));
+            HIPCHK(hipStreamSynchronize(hb->st));
         }
         if (!running) break;
     }
