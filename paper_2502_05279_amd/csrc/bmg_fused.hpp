@@ -126,6 +126,56 @@ struct TileLds {
     T wy[WREC ? FW : 0], wx[WREC ? 3 * FW : 0];
 };
 
+// The NU sweeps of a step on a five-point level, colours merged across rows.
+// Colour c updates the columns with parity c & 1, colours 0, 1 on the step's
+// even row e - 2s, colours 2, 3 on its odd row e - 2s - 1.  With five-point
+// couplings colour 1 (odd i, even j) and colour 2 (even i, odd j) do not
+// touch, nor do colour 3 of sweep s and colour 0 of sweep s + 1 (which trails
+// two rows lower): each pair runs as one phase, every column busy, and every
+// point still sees the neighbour values of the order 0, 1, 2, 3, so the
+// result is the same to the bit.  Phases: c0(s=0); then per sweep
+// {c1, c2(s)} and {c3(s), c0(s+1)}: 2 NU + 1 barriers instead of 4 NU.
+// The window rows are compile-time positions k = row - (e - 2NU - 2); a lane
+// picks its row's entries by its column parity.
+template <typename T, int NU, int RU>
+__device__ __forceinline__ void five_point_sweeps(T *su, const T *sW, int lane, int i, bool col_upd, int n, int e,
+                                                  const T *rB, const T *rO, const T *rS)
+{
+    const bool odd = i & 1;
+    const int base = e - 2 * NU - 2;
+    // the update of the point of this lane's column in window row k (if any)
+    auto upd = [&](bool on, int k) {
+        const int row = base + k;
+        if (on && col_upd && row >= 1 && row <= n) {
+            const T v = gs_lds<T, false, RU>(su, sW, nullptr, nullptr, lane, row, rB[k], rO[k], rS[k], rS[k + 1]);
+            su[slot<RU>(row) * FW + lane] = v;
+        }
+    };
+    // a phase where odd columns update window row ko and even columns row ke
+    auto pair = [&](bool on_odd, int ko, bool on_even, int ke) {
+        const bool on = odd ? on_odd : on_even;
+        const int row = base + (odd ? ko : ke);
+        if (on && col_upd && row >= 1 && row <= n) {
+            const T b = odd ? rB[ko] : rB[ke];
+            const T o = odd ? rO[ko] : rO[ke];
+            const T s0 = odd ? rS[ko] : rS[ke];
+            const T s1 = odd ? rS[ko + 1] : rS[ke + 1];
+            const T v = gs_lds<T, false, RU>(su, sW, nullptr, nullptr, lane, row, b, o, s0, s1);
+            su[slot<RU>(row) * FW + lane] = v;
+        }
+    };
+    upd(!odd, 2 * NU + 2);                                  // c0 of sweep 0 on row e
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < NU; ++s) {
+        const int ke = 2 * NU + 2 - 2 * s;                  // even row e - 2s
+        pair(true, ke, true, ke - 1);                       // c1 on e - 2s, c2 on e - 2s - 1
+        __syncthreads();
+        pair(true, ke - 1, s + 1 < NU, ke - 2);             // c3 on e - 2s - 1, c0 of s + 1 on e - 2s - 2
+        __syncthreads();
+    }
+}
+
 // With WREC the restriction weights are not read: each column computes the
 // operator-induced weights of its own F-points from the stencil rows in the
 // window (the expressions of k_weights_edges / k_weights_corners in their
@@ -275,18 +325,22 @@ __device__ __forceinline__ void pre_tile(const Lev<T> &L, T *__restrict__ uout, 
         }
         // (the colour barriers below publish wy)
         // NU sweeps, each over colours 0,1 (even row) then 2,3 (odd row)
+        if constexpr (NINE) {
 #pragma unroll
-        for (int s = 0; s < NU; ++s) {
+            for (int s = 0; s < NU; ++s) {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const int row = c < 2 ? e - 2 * s : e - 2 * s - 1;
-                const int k = row - (e - 2 * NU - 2);
-                if (col_upd && (i & 1) == (c & 1) && row >= 1 && row <= n) {
-                    const T v = gs_lds<T, NINE, RU>(su, sW, sSW, sNW, lane, row, rB[k], rO[k], rS[k], rS[k + 1]);
-                    su[slot<RU>(row) * FW + lane] = v;
+                for (int c = 0; c < 4; ++c) {
+                    const int row = c < 2 ? e - 2 * s : e - 2 * s - 1;
+                    const int k = row - (e - 2 * NU - 2);
+                    if (col_upd && (i & 1) == (c & 1) && row >= 1 && row <= n) {
+                        const T v = gs_lds<T, NINE, RU>(su, sW, sSW, sNW, lane, row, rB[k], rO[k], rS[k], rS[k + 1]);
+                        su[slot<RU>(row) * FW + lane] = v;
+                    }
+                    __syncthreads();
                 }
-                __syncthreads();
             }
+        } else {
+            five_point_sweeps<T, NU, RU>(su, sW, lane, i, col_upd, n, e, rB, rO, rS);
         }
         // the last sweep's two rows are final: write the owned ones
 #pragma unroll
@@ -529,18 +583,22 @@ __device__ __forceinline__ void post_tile(const Lev<T> &L, T *__restrict__ uout,
         }
         if (e + 2 <= elast) fetch(e + 2);
         __syncthreads();
+        if constexpr (NINE) {
 #pragma unroll
-        for (int s = 0; s < NU; ++s) {
+            for (int s = 0; s < NU; ++s) {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const int row = c < 2 ? e - 2 * s : e - 2 * s - 1;
-                const int k = row - (e - 2 * NU - 2);
-                if (col_upd && (i & 1) == (c & 1) && row >= 1 && row <= n) {
-                    const T v = gs_lds<T, NINE, RU>(su, sW, sSW, sNW, lane, row, rB[k], rO[k], rS[k], rS[k + 1]);
-                    su[slot<RU>(row) * FW + lane] = v;
+                for (int c = 0; c < 4; ++c) {
+                    const int row = c < 2 ? e - 2 * s : e - 2 * s - 1;
+                    const int k = row - (e - 2 * NU - 2);
+                    if (col_upd && (i & 1) == (c & 1) && row >= 1 && row <= n) {
+                        const T v = gs_lds<T, NINE, RU>(su, sW, sSW, sNW, lane, row, rB[k], rO[k], rS[k], rS[k + 1]);
+                        su[slot<RU>(row) * FW + lane] = v;
+                    }
+                    __syncthreads();
                 }
-                __syncthreads();
             }
+        } else {
+            five_point_sweeps<T, NU, RU>(su, sW, lane, i, col_upd, n, e, rB, rO, rS);
         }
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
