@@ -501,7 +501,7 @@ bmg_status bmg_batch_setup(bmg_batch **out, int nprob, const int *n, const doubl
             q.ualt[l] = h->ualt32[l];
         }
         for (int d = 0; d < q.sdepth; ++d) {
-            const int nl = h->L32[d].n, rows = tile_rows_for(h, nl);
+            const int nl = h->L32[d].n, rows = tile_rows_for(h, nl, h->nine[d]);
             q.gpre[d] = tile_geo(nl, d == 0 ? 6 : 10, rows);
             q.gpost[d] = tile_geo(nl, d == 0 ? 4 : 6, rows);
             for (int t = 0; t < q.gpre[d].ntiles; ++t) pre[d].push_back(make_int2(p, t));

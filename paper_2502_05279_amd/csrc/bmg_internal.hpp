@@ -102,7 +102,7 @@ struct bmg_solver {
 namespace bmgi {
 // Rows per tile of a fused pass on a level of size n: the handle's option, the
 // autotuned table (bmg_tile_rows_set), else a measured default.
-int tile_rows_for(const bmg_solver *h, int n);
+int tile_rows_for(const bmg_solver *h, int n, bool nine);
 TileGeo tile_geo(int n, int hx, int ht);
 }  // namespace bmgi
 

@@ -609,24 +609,7 @@ static __global__ void k_round_f32(const double *__restrict__ src, float *__rest
 }
 
 // -------------------------------------------- FP64 iterative refinement
-// Per-block max |r| over the interior of the FP64 level-0 residual.
-static __global__ void k_absmax_partial(Lev<double> L, double *__restrict__ part, const int *stop)
-{
-    if (stopped(stop)) return;
-    __shared__ double sm[16];
-    double m = 0.0;
-    for (int j = 1 + blockIdx.x; j <= L.n; j += gridDim.x)
-        for (int i = 1 + threadIdx.x; i <= L.n; i += blockDim.x) m = fmax(m, fabs(L.r[(size_t)j * L.ld + i]));
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_down(m, o, 64));
-    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, sm[w]);
-        part[blockIdx.x] = m;
-    }
-}
-
+// Largest of np partial maxima of |r| -> out[0].
 static __global__ void k_absmax_final(const double *__restrict__ part, int np, double *__restrict__ out,
                                const int *stop)
 {
@@ -672,7 +655,22 @@ __device__ __forceinline__ void two_sum(double a, double b, double &s, double &e
 // MODE 0: sum of squares only; 1: also r -> rout; 2: also r -> L.b and 0 -> L.u
 // (the next refinement cycle starts from zero on the right-hand side r).
 
-// Row block rb of nrb (rows 1 + rb, 1 + rb + nrb, ...) into part[rb].
+// Maximum over the block (up to 16 waves); result valid in thread 0.
+__device__ __forceinline__ double block_max(double m)
+{
+    __shared__ double sm[16];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_down(m, o, 64));
+    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, sm[w]);
+    return m;
+}
+
+// Row block rb of nrb (rows 1 + rb, 1 + rb + nrb, ...): the sum of squares of
+// r into part[rb] and, with MODE 1 (the refinement of the FP32 cycle, which
+// scales r by its largest magnitude next), max |r| into part[nrb + rb].
 template <bool NINE, int MODE>
 __device__ __forceinline__ void resid_dd_rows(Lev<double> L, const double *__restrict__ B,
                                               const double *__restrict__ XH, const double *__restrict__ XL,
@@ -680,7 +678,7 @@ __device__ __forceinline__ void resid_dd_rows(Lev<double> L, const double *__res
 {
     const size_t ld = L.ld;
     const int n = L.n;
-    double acc = 0.0;
+    double acc = 0.0, mx = 0.0;
     for (int j = 1 + rb; j <= n; j += nrb) {
         for (int i = 1 + threadIdx.x; i <= n; i += blockDim.x) {
             const size_t p = (size_t)j * ld + i;
@@ -716,7 +714,10 @@ __device__ __forceinline__ void resid_dd_rows(Lev<double> L, const double *__res
                 }
             }
             const double r = s + c;
-            if (MODE == 1) rout[p] = r;
+            if (MODE == 1) {
+                rout[p] = r;
+                mx = fmax(mx, fabs(r));
+            }
             if (MODE == 2) {
                 L.b[p] = r;
                 L.u[p] = 0.0;
@@ -726,6 +727,10 @@ __device__ __forceinline__ void resid_dd_rows(Lev<double> L, const double *__res
     }
     acc = block_sum(acc);
     if (threadIdx.x == 0) part[rb] = acc;
+    if (MODE == 1) {
+        mx = block_max(mx);
+        if (threadIdx.x == 0) part[nrb + rb] = mx;
+    }
 }
 
 template <bool NINE, int MODE>

@@ -34,7 +34,7 @@ bmg_status fail(bmg_status s, const char *fmt, ...)
 // Tile rows chosen by the autotuner, per level size n = 2^m - 1 (0 = unset).
 static int g_tile_rows[17];
 
-int tile_rows_for(const bmg_solver *h, int n)
+int tile_rows_for(const bmg_solver *h, int n, bool nine)
 {
     if (h && h->opt.tile_rows > 0) return h->opt.tile_rows;
     int m = 0;
@@ -42,12 +42,15 @@ int tile_rows_for(const bmg_solver *h, int n)
     if (g_tile_rows[m] > 0) return g_tile_rows[m];
     // measured defaults (FP64, V(2,1)): the fewest warm-up rows re-read while
     // the tiles still fill the chip in whole rounds (at 4095^2, 96 rows give
-    // 731 tiles, one round of four 40 KiB workgroups per CU, where 64 rows
-    // give 1088 and a second round of 64); on the levels below 1023 the
+    // 731 tiles, one round of three 48 KiB pre-pass or four 40 KiB post-pass
+    // workgroups per CU, where 64 rows give 1088 and a second round of 64, and
+    // a second round costs more than the rows it saves); on the levels below 1023 the
     // shortest tiles win, their passes being bound by the latency of the row
     // pipeline rather than by bandwidth
     if (n >= 4095) return 96;
-    if (n >= 2047) return 48;
+    // nine-point tiles take 72 KiB of LDS, two per CU: 40 rows give 468
+    // tiles at 2047^2, one round of 512 (36 rows give 513)
+    if (n >= 2047) return nine ? 40 : 48;
     if (n >= 1023) return 16;
     if (n >= 511) return 4;
     return 2;
@@ -79,7 +82,7 @@ extern "C" bmg_status bmg_tile_rows_set(int n, int rows)
 extern "C" bmg_status bmg_tile_rows_get(int n, int *rows)
 {
     if (!valid_n(n) || !rows) return fail(BMG_EINVAL, "bad arguments");
-    *rows = tile_rows_for(nullptr, n);
+    *rows = tile_rows_for(nullptr, n, false);
     return BMG_OK;
 }
 
@@ -397,14 +400,14 @@ double *&ualt<double>(bmg_solver *h, int l) { return h->ualt[l]; }
 template <>
 float *&ualt<float>(bmg_solver *h, int l) { return h->ualt32[l]; }
 
-int level_tile_rows(const bmg_solver *h, int n) { return tile_rows_for(h, n); }
+int level_tile_rows(const bmg_solver *h, int l) { return tile_rows_for(h, h->L[l].n, h->nine[l]); }
 
 dim3 tile_grid(const TileGeo &g) { return dim3(((g.ntiles * g.nrhs + 7) / 8) * 8); }
 
 // The tiles of level l of every right-hand side of the handle.
 TileGeo level_tiles(const bmg_solver *h, int l, int hx)
 {
-    TileGeo g = tile_geo(h->L[l].n, hx, level_tile_rows(h, h->L[l].n));
+    TileGeo g = tile_geo(h->L[l].n, hx, level_tile_rows(h, l));
     g.nrhs = h->nrhs;
     g.kstop = h->kstop;
     g.kpart = h->kpart;
@@ -877,15 +880,15 @@ static bmg_status cycle64(bmg_solver *h, const int *stop)
     return vcycle_from<double>(h, 0, stop);
 }
 
-// One FP32 refinement step: r = B0 - A (XH + XL) is in L0.r; scale to the
+// One FP32 refinement step: r = B0 - A (XH + XL) is in L0.r and the residual
+// pass left the partial maxima of |r| after its partial sums; scale to the
 // power of two s >= ||r||_inf, round to FP32, V32 from zero, (XH, XL) += s d32.
 static bmg_status ir_correct(bmg_solver *h, const int *stop)
 {
     const Lev<double> &L = h->L[0];
     const Lev<float> &F = h->L32[0];
     const int nb = std::min(NPART_ROWS, L.n);
-    hipLaunchKernelGGL(k_absmax_partial, dim3(nb), dim3(256), 0, h->st, L, h->part, stop);
-    hipLaunchKernelGGL(k_absmax_final, dim3(1), dim3(1024), 0, h->st, (const double *)h->part, nb,
+    hipLaunchKernelGGL(k_absmax_final, dim3(1), dim3(1024), 0, h->st, (const double *)h->part + nb, nb,
                        h->scal + S_RMAX, stop);
     hipLaunchKernelGGL(k_ir_scale, grid2(L.n, L.n, B2), B2, 0, h->st, L, F, (const double *)(h->scal + S_RMAX),
                        h->scal + S_SCALE, stop);
