@@ -47,11 +47,15 @@ int tile_rows_for(const bmg_solver *h, int n, bool nine)
     // a second round costs more than the rows it saves); on the levels below 1023 the
     // shortest tiles win, their passes being bound by the latency of the row
     // pipeline rather than by bandwidth
+    // at 8191^2 (the FP32 refinement's fine level, five 20 KiB workgroups
+    // per CU) 224 rows give 1258 tiles, one round of 1280
+    if (n >= 8191) return 224;
     if (n >= 4095) return 96;
     // nine-point tiles take 72 KiB of LDS, two per CU: 40 rows give 468
-    // tiles at 2047^2, one round of 512 (36 rows give 513)
+    // tiles at 2047^2 and 12 rows 430 at 1023^2, each one round of 512 (36
+    // and 10 rows give 513 and 515)
     if (n >= 2047) return nine ? 40 : 48;
-    if (n >= 1023) return 16;
+    if (n >= 1023) return nine ? 12 : 16;
     if (n >= 511) return 4;
     return 2;
 }
