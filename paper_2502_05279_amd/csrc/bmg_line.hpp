@@ -124,10 +124,13 @@ static __global__ void k_line_rhs_x(Lev<double> L, int par, double *__restrict__
 // Solve of the columns of parity `par` in the frame of the arrays given: the
 // right-hand side in D (overwritten by y), the factor lf, rf, the coupling
 // C(c, k) = c_k (A_N, or the transposed A_E); the solution into X (which may
-// be D).  One lane per column; the rows stream in order, coalesced, in blocks
-// of LINE_BLK whose loads are requested while the previous block computes (a
-// half-sweep has only n/2 lines, so each lane must keep many loads in flight).
-constexpr int LINE_BLK = 16;
+// be D).  A half-sweep has only n/2 lines and each line is a sequential
+// recurrence, so the loads, not the arithmetic, set the pace: one wave serves
+// LINE_G lines, all 64 lanes stream chunks of LINE_R rows of them into LDS (the next
+// chunk requested while the current one computes), LINE_G lanes run the
+// recurrences from LDS, and all lanes write the results back.
+constexpr int LINE_G = 8;     // lines per wave
+constexpr int LINE_R = 128;   // rows per chunk
 
 static __global__ __launch_bounds__(64) void k_line_solve(int n, int ld, int par, double *__restrict__ D,
                                                           const double *__restrict__ lf,
@@ -136,61 +139,129 @@ static __global__ __launch_bounds__(64) void k_line_solve(int n, int ld, int par
                                                           const int *stop)
 {
     if (stopped(stop)) return;
-    const int c = 2 * (blockIdx.x * blockDim.x + threadIdx.x) + (par ? 1 : 2);
-    if (c > n) return;
+    __shared__ double buf[2][3][LINE_R][LINE_G];
+    constexpr int PL = LINE_R / (64 / LINE_G);               // rows each lane moves per chunk
+    const int lane = threadIdx.x;
+    const int t = lane % LINE_G, q = lane / LINE_G;          // moving: line t, rows q, q + 8, ...
+    const int nlines = par ? (n + 1) / 2 : (n - 1) / 2;
+    const int line0 = blockIdx.x * LINE_G;
+    const bool lok = line0 + t < nlines;
+    const size_t col = (size_t)((par ? 1 : 2) + 2 * (line0 + t));
     const size_t sld = ld;
-    // forward: y_1 = d_1, y_k = d_k - l_k y_{k-1}, over rows 1..n
-    double dv[LINE_BLK], lv[LINE_BLK], dn[LINE_BLK], ln[LINE_BLK];
-    auto fload = [&](int k0, double *d, double *l) {
+    const bool comp = lane < LINE_G && line0 + lane < nlines;   // computing: line `lane`
+    const int nch = (n + LINE_R - 1) / LINE_R;
+
+    // forward over rows 1..n: y_1 = d_1, y_k = d_k - l_k y_{k-1}
+    double rd[PL], rl[PL];
+    auto fload = [&](int ch) {
 #pragma unroll
-        for (int t = 0; t < LINE_BLK; ++t) {
-            const int k = k0 + t;
-            const size_t p = (size_t)(k <= n ? k : n) * sld + c;
-            d[t] = D[p];
-            l[t] = lf[p];
+        for (int s = 0; s < PL; ++s) {
+            const int k = 1 + ch * LINE_R + q + (64 / LINE_G) * s;
+            const bool ok = lok && k <= n;
+            const size_t p = ok ? (size_t)k * sld + col : 0;
+            rd[s] = ok ? D[p] : 0.0;
+            rl[s] = ok ? lf[p] : 0.0;
         }
     };
-    fload(1, dv, lv);
+    auto fput = [&](int b) {
+#pragma unroll
+        for (int s = 0; s < PL; ++s) {
+            buf[b][0][q + (64 / LINE_G) * s][t] = rd[s];
+            buf[b][1][q + (64 / LINE_G) * s][t] = rl[s];
+        }
+    };
+    fload(0);
+    fput(0);
+    __syncthreads();
     double y = 0.0;
-    for (int k0 = 1; k0 <= n; k0 += LINE_BLK) {
-        if (k0 + LINE_BLK <= n) fload(k0 + LINE_BLK, dn, ln);
+    for (int ch = 0; ch < nch; ++ch) {
+        const int b = ch & 1;
+        if (ch + 1 < nch) fload(ch + 1);
+        if (comp) {
+            // sub-blocks of 16 rows: their LDS reads are issued together, so
+            // only the recurrence's own arithmetic is sequential
+            for (int r0 = 0; r0 < LINE_R && 1 + ch * LINE_R + r0 <= n; r0 += 16) {
+                double dv[16], lv[16];
 #pragma unroll
-        for (int t = 0; t < LINE_BLK; ++t) {
-            const int k = k0 + t;
-            if (k <= n) {
-                y = k == 1 ? dv[t] : dv[t] - lv[t] * y;
-                D[(size_t)k * sld + c] = y;
+                for (int u = 0; u < 16; ++u) {
+                    dv[u] = buf[b][0][r0 + u][lane];
+                    lv[u] = buf[b][1][r0 + u][lane];
+                }
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    const int k = 1 + ch * LINE_R + r0 + u;
+                    if (k <= n) {
+                        y = k == 1 ? dv[u] : dv[u] - lv[u] * y;
+                        buf[b][0][r0 + u][lane] = y;
+                    }
+                }
             }
         }
+        __syncthreads();
 #pragma unroll
-        for (int t = 0; t < LINE_BLK; ++t) { dv[t] = dn[t]; lv[t] = ln[t]; }
+        for (int s = 0; s < PL; ++s) {
+            const int k = 1 + ch * LINE_R + q + (64 / LINE_G) * s;
+            if (lok && k <= n) D[(size_t)k * sld + col] = buf[b][0][q + (64 / LINE_G) * s][t];
+        }
+        if (ch + 1 < nch) fput(b ^ 1);
+        __syncthreads();
     }
-    // back: x_n = y_n r_n, x_k = (y_k - c_k x_{k+1}) r_k, over rows n..1
-    double yv[LINE_BLK], rv[LINE_BLK], cv[LINE_BLK], yn[LINE_BLK], rn[LINE_BLK], cn[LINE_BLK];
-    auto bload = [&](int k0, double *yy, double *r, double *cc) {   // rows k0, k0-1, ...
+
+    // back over rows n..1: x_n = y_n r_n, x_k = (y_k - c_k x_{k+1}) r_k
+    double ry[PL], rr[PL], rc[PL];
+    auto bload = [&](int ch) {   // chunk ch from the top: rows n - ch LINE_R - (0 .. LINE_R-1)
 #pragma unroll
-        for (int t = 0; t < LINE_BLK; ++t) {
-            const int k = k0 - t;
-            const size_t p = (size_t)(k >= 1 ? k : 1) * sld + c;
-            yy[t] = D[p];
-            r[t] = rf[p];
-            cc[t] = C[p + sld];
+        for (int s = 0; s < PL; ++s) {
+            const int k = n - ch * LINE_R - q - (64 / LINE_G) * s;
+            const bool ok = lok && k >= 1;
+            const size_t p = ok ? (size_t)k * sld + col : 0;
+            ry[s] = ok ? D[p] : 0.0;
+            rr[s] = ok ? rf[p] : 0.0;
+            rc[s] = ok ? C[p + sld] : 0.0;
         }
     };
-    bload(n, yv, rv, cv);
-    double x = 0.0;
-    for (int k0 = n; k0 >= 1; k0 -= LINE_BLK) {
-        if (k0 - LINE_BLK >= 1) bload(k0 - LINE_BLK, yn, rn, cn);
+    auto bput = [&](int b) {
 #pragma unroll
-        for (int t = 0; t < LINE_BLK; ++t) {
-            const int k = k0 - t;
-            if (k >= 1) {
-                x = k == n ? yv[t] * rv[t] : (yv[t] - cv[t] * x) * rv[t];
-                X[(size_t)k * sld + c] = x;
+        for (int s = 0; s < PL; ++s) {
+            buf[b][0][q + (64 / LINE_G) * s][t] = ry[s];
+            buf[b][1][q + (64 / LINE_G) * s][t] = rr[s];
+            buf[b][2][q + (64 / LINE_G) * s][t] = rc[s];
+        }
+    };
+    bload(0);
+    bput(0);
+    __syncthreads();
+    double x = 0.0;
+    for (int ch = 0; ch < nch; ++ch) {
+        const int b = ch & 1;
+        if (ch + 1 < nch) bload(ch + 1);
+        if (comp) {
+            for (int r0 = 0; r0 < LINE_R && n - ch * LINE_R - r0 >= 1; r0 += 16) {
+                double yv[16], rv[16], cv[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    yv[u] = buf[b][0][r0 + u][lane];
+                    rv[u] = buf[b][1][r0 + u][lane];
+                    cv[u] = buf[b][2][r0 + u][lane];
+                }
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    const int k = n - ch * LINE_R - r0 - u;
+                    if (k >= 1) {
+                        x = k == n ? yv[u] * rv[u] : (yv[u] - cv[u] * x) * rv[u];
+                        buf[b][0][r0 + u][lane] = x;
+                    }
+                }
             }
         }
+        __syncthreads();
 #pragma unroll
-        for (int t = 0; t < LINE_BLK; ++t) { yv[t] = yn[t]; rv[t] = rn[t]; cv[t] = cn[t]; }
+        for (int s = 0; s < PL; ++s) {
+            const int k = n - ch * LINE_R - q - (64 / LINE_G) * s;
+            if (lok && k >= 1) X[(size_t)k * sld + col] = buf[b][0][q + (64 / LINE_G) * s][t];
+        }
+        if (ch + 1 < nch) bput(b ^ 1);
+        __syncthreads();
     }
 }
 

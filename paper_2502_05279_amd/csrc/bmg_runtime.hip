@@ -274,7 +274,7 @@ bmg_status line_smooth(bmg_solver *h, const Lev<double> &L, bool nine, int sweep
             const int nl = par ? (n + 1) / 2 : (n - 1) / 2;
             if (nine) hipLaunchKernelGGL((k_line_rhs_x<true>), tg, tb, 0, h->st, L, par, D, stop);
             else hipLaunchKernelGGL((k_line_rhs_x<false>), tg, tb, 0, h->st, L, par, D, stop);
-            hipLaunchKernelGGL(k_line_solve, dim3((nl + 63) / 64), dim3(64), 0, h->st, n, ld, par, D,
+            hipLaunchKernelGGL(k_line_solve, dim3((nl + LINE_G - 1) / LINE_G), dim3(64), 0, h->st, n, ld, par, D,
                                (const double *)h->lfx[l], (const double *)h->rfx[l], (const double *)h->WT[l], D,
                                stop);
             hipLaunchKernelGGL(k_line_put_x, tg, tb, 0, h->st, n, ld, par, (const double *)D, L.u, stop);
@@ -284,7 +284,7 @@ bmg_status line_smooth(bmg_solver *h, const Lev<double> &L, bool nine, int sweep
             const dim3 rb(64, 4), rg((nl + 63) / 64, (n + 3) / 4);
             if (nine) hipLaunchKernelGGL((k_line_rhs_y<true>), rg, rb, 0, h->st, L, par, D, stop);
             else hipLaunchKernelGGL((k_line_rhs_y<false>), rg, rb, 0, h->st, L, par, D, stop);
-            hipLaunchKernelGGL(k_line_solve, dim3((nl + 63) / 64), dim3(64), 0, h->st, n, ld, par, D,
+            hipLaunchKernelGGL(k_line_solve, dim3((nl + LINE_G - 1) / LINE_G), dim3(64), 0, h->st, n, ld, par, D,
                                (const double *)h->lfy[l], (const double *)h->rfy[l], (const double *)L.S, L.u,
                                stop);
         }
