@@ -129,7 +129,7 @@ static __global__ void k_line_rhs_x(Lev<double> L, int par, double *__restrict__
 // LINE_G lines, all 64 lanes stream chunks of LINE_R rows of them into LDS (the next
 // chunk requested while the current one computes), LINE_G lanes run the
 // recurrences from LDS, and all lanes write the results back.
-constexpr int LINE_G = 8;     // lines per wave
+constexpr int LINE_G = 4;     // lines per wave
 constexpr int LINE_R = 128;   // rows per chunk
 
 static __global__ __launch_bounds__(64) void k_line_solve(int n, int ld, int par, double *__restrict__ D,
