@@ -230,6 +230,29 @@ def bench_learned(args):
                    "learned_ms": tl * 1e3, "learned_cycles": il["cycles"], "learned_rho": il["rho"],
                    "learned_final_rel_res": il["rel_res"]},
     }
+    # the network's forward pass on the fine operator, the learned set-up's
+    # dominant work: conv1 (9 -> 32 channels, 3x3) at every fine point, conv2
+    # (32 -> 32, stride 2) and conv3 (32 -> 8) at the (nc+1)^2 coarse points,
+    # 2 flop per multiply-add, on bfloat16 MFMA
+    S0 = boxmg.Solver(st, **opts)
+    planes = [S0.export(0, f) for f in ("O", "W", "S")]
+    nc = (n - 1) // 2
+    Ci = torch.zeros((8, nc + 2, nc + 2), dtype=torch.float64, device=dev)
+    net.forward(*planes, out=Ci)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 5
+    e0.record()
+    for _ in range(reps):
+        net.forward(*planes, out=Ci)
+    e1.record()
+    torch.cuda.synchronize()
+    fwd_ms = e0.elapsed_time(e1) / reps
+    flop = 2.0 * (9 * 9 * 32) * n * n + 2.0 * (32 * 9 * 32 + 32 * 9 * 8) * (nc + 1) ** 2
+    tflops = flop / (fwd_ms * 1e-3) / 1e12
+    out["roofline"] = {"bound": "mfma", "kernel": "network forward (k_net_features, k_conv x 3)",
+                       "achieved": tflops, "peak": 2500.0, "unit": "TFLOP/s", "frac": tflops / 2500.0,
+                       "traffic": None, "flop_per_launch": flop, "avg_launch_ms": fwd_ms,
+                       "dtype": "bf16 (fp32 accumulate)"}
     print(json.dumps(out))
 
 

@@ -454,11 +454,12 @@ class Net:
         _check(lib().bmg_net_get_params(self._h, p.ctypes.data), "bmg_net_get_params")
         return p
 
-    def forward(self, O, W, S, SW=None, NW=None) -> torch.Tensor:
-        """Weight planes (8, nc+2, nc+2) of a level given as padded planes."""
+    def forward(self, O, W, S, SW=None, NW=None, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Weight planes (8, nc+2, nc+2) of a level given as padded planes
+        (into `out` if given)."""
         n = O.shape[0] - 2
         nc = (n - 1) // 2
-        Ci = torch.zeros((8, nc + 2, nc + 2), dtype=torch.float64, device=O.device)
+        Ci = torch.zeros((8, nc + 2, nc + 2), dtype=torch.float64, device=O.device) if out is None else out
         _check(lib().bmg_net_forward(self._h, n, n + 2, _ptr(O), _ptr(W), _ptr(S), _ptr(SW), _ptr(NW),
                                      _ptr(Ci), nc + 2, (nc + 2) * (nc + 2)), "bmg_net_forward")
         return Ci
