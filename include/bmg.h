@@ -235,7 +235,9 @@ const char *bmg_last_error(void);
  *   n_l x n_l x K with K = 5 (S, W, O, E, N) on a five-point level and K = 9
  *   (SW, S, SE, W, O, E, NW, N, NE) otherwise.
  * The *32 fields are the FP32 hierarchy (precision BMG_FP32_IR only) and
- * transfer float data. */
+ * transfer float data.  A solve or V-cycle leaves the level-0 u32 unspecified:
+ * the fused fine-level pass of a refinement step adds each FP32 correction to
+ * the double-FP64 iterate in place of storing it. */
 enum {
     BMG_F_U = 0, BMG_F_B = 1, BMG_F_R = 2,
     BMG_F_AO = 3, BMG_F_AW = 4, BMG_F_AS = 5, BMG_F_ASW = 6, BMG_F_ANW = 7,

@@ -126,6 +126,21 @@ struct TileLds {
     T wy[WREC ? FW : 0], wx[WREC ? 3 * FW : 0];
 };
 
+// An FP32 refinement step folded into the fine level's passes (five-point
+// level, one right-hand side).  The pre pass starts from u = 0 and reads the
+// FP64 residual r in place of b: b = fl32(r / s) with s = 2^e the least power
+// of two >= ||r||_inf (the scaling of k_ir_scale), which it also stores as the
+// FP32 right-hand side for the post pass and, from one lane, into scale[0].
+// The post pass adds s * u to the double-FP64 iterate (XH, XL) as each owned
+// point's final value is produced, with the arithmetic of dd_update_point, in
+// place of storing u.
+struct IrArgs {
+    const double *r;     // FP64 residual, the level's pitch
+    const double *rmax;  // ||r||_inf
+    double *scale;       // s, written by the pre pass
+    double *XH, *XL;     // double-FP64 iterate
+};
+
 // The NU sweeps of a step on a five-point level, colours merged across rows.
 // Colour c updates the columns with parity c & 1, colours 0, 1 on the step's
 // even row e - 2s, colours 2, 3 on its odd row e - 2s - 1.  With five-point
@@ -183,10 +198,10 @@ __device__ __forceinline__ void five_point_sweeps(T *su, const T *sW, int lane, 
 // neighbours' through LDS.  Step e computes the y-edges and cell centres of
 // row e-2NU-1 and the x-edges of row e-2NU; the weights of the rows below come
 // from the previous step.
-template <typename T, bool NINE, int NU, bool WREC = false>
+template <typename T, bool NINE, int NU, bool WREC = false, bool IRIN = false>
 __device__ __forceinline__ void pre_tile(const Lev<T> &L, T *__restrict__ uout, const Wts<T> &C,
                                          const Lev<T> &Cl, const TileGeo &G, int tid,
-                                         TileLds<T, NINE, NU, WREC> &S)
+                                         TileLds<T, NINE, NU, WREC> &S, IrArgs ir = {})
 {
     constexpr int RW = 2 * NU + 4;                 // window rows
     constexpr int RU = RW <= 8 ? 8 : 16;           // LDS ring rows (power of two)
@@ -213,6 +228,21 @@ __device__ __forceinline__ void pre_tile(const Lev<T> &L, T *__restrict__ uout, 
     auto ld_row = [&](const T *a, int row) -> T {
         return (col_in && row >= 0 && row <= n + 1) ? a[(size_t)row * ld + i] : (T)0;
     };
+    // the iterate and the right-hand side as the pass reads them (IRIN: zero,
+    // and the scaled FP64 residual at interior points)
+    double inv = 1.0;
+    if constexpr (IRIN) {
+        const int ex = ir_exponent(*ir.rmax);
+        inv = ldexp(1.0, -ex);
+        if (tid == 0 && lane == 0) ir.scale[0] = ldexp(1.0, ex);
+    }
+    auto ld_u = [&](int row) -> T { return IRIN ? (T)0 : ld_row(L.u, row); };
+    auto ld_b = [&](int row) -> T {
+        if constexpr (IRIN)
+            return (i >= 1 && i <= n && row >= 1 && row <= n) ? (T)(ir.r[(size_t)row * ld + i] * inv) : (T)0;
+        else
+            return ld_row(L.b, row);
+    };
     // the eight weights of coarse point (I, J) in the order the restriction uses
     auto ld_w = [&](int J, T w[8]) {
         const bool ok = restrictor && J >= 1 && J <= nc;
@@ -231,7 +261,7 @@ __device__ __forceinline__ void pre_tile(const Lev<T> &L, T *__restrict__ uout, 
 #pragma unroll
     for (int k = 2; k < RW; ++k) {
         const int row = es - 2 * NU - 4 + k;
-        su[slot<RU>(row) * FW + lane] = ld_row(L.u, row);
+        su[slot<RU>(row) * FW + lane] = ld_u(row);
         sW[slot<RU>(row) * FW + lane] = ld_row(L.W, row);
         if (NINE) {
             sSW[slot<RU>(row) * FW + lane] = ld_row(L.SW, row);
@@ -239,7 +269,7 @@ __device__ __forceinline__ void pre_tile(const Lev<T> &L, T *__restrict__ uout, 
         }
         rO[k] = ld_row(L.O, row);
         rS[k] = ld_row(L.S, row);
-        rB[k] = ld_row(L.b, row);
+        rB[k] = ld_b(row);
     }
     // the lumped nine-point row of this column at window row k (WREC)
     auto row9 = [&](int k, int row, T a[9]) {
@@ -275,16 +305,21 @@ __device__ __forceinline__ void pre_tile(const Lev<T> &L, T *__restrict__ uout, 
     T pu0, pu1, pW0, pW1, pO0, pO1, pS0, pS1, pB0, pB1, pSW0 = 0, pSW1 = 0, pNW0 = 0, pNW1 = 0;
     T pw[8], w[8];
     auto fetch = [&](int e) {
-        pu0 = ld_row(L.u, e); pu1 = ld_row(L.u, e + 1);
+        pu0 = ld_u(e); pu1 = ld_u(e + 1);
         pW0 = ld_row(L.W, e); pW1 = ld_row(L.W, e + 1);
         pO0 = ld_row(L.O, e); pO1 = ld_row(L.O, e + 1);
         pS0 = ld_row(L.S, e); pS1 = ld_row(L.S, e + 1);
-        pB0 = ld_row(L.b, e); pB1 = ld_row(L.b, e + 1);
+        pB0 = ld_b(e); pB1 = ld_b(e + 1);
         if (NINE) {
             pSW0 = ld_row(L.SW, e); pSW1 = ld_row(L.SW, e + 1);
             pNW0 = ld_row(L.NW, e); pNW1 = ld_row(L.NW, e + 1);
         }
         if (!WREC) ld_w((e - 2 * NU - 2) >> 1, pw);
+        if (IRIN && col_own) {
+            // every owned row is fetched once: keep its FP32 right-hand side
+            if (e >= y0 && e < y1) L.b[(size_t)e * ld + i] = pB0;
+            if (e + 1 >= y0 && e + 1 < y1) L.b[(size_t)(e + 1) * ld + i] = pB1;
+        }
     };
     fetch(es);
 
@@ -440,10 +475,10 @@ __global__ __launch_bounds__(FW) void k_pre(Lev<T> L, T *__restrict__ uout, Wts<
 // points into part[tile].  Window: rows e-2NU-2 .. e+1 at step e; the data of
 // step e+2 (rows, coarse row, interpolation weights) is requested while step
 // e computes.
-template <typename T, bool NINE, int NU, bool NORM>
+template <typename T, bool NINE, int NU, bool NORM, bool IRUP = false>
 __device__ __forceinline__ void post_tile(const Lev<T> &L, T *__restrict__ uout, const Wts<T> &C,
                                           const T *__restrict__ ec, const TileGeo &G, int tid,
-                                          double *__restrict__ part, TileLds<T, NINE, NU> &S)
+                                          double *__restrict__ part, TileLds<T, NINE, NU> &S, IrArgs ir = {})
 {
     static_assert(NU <= 2, "post pass supports up to two sweeps");
     constexpr int RW = 2 * NU + 4;
@@ -549,7 +584,21 @@ __device__ __forceinline__ void post_tile(const Lev<T> &L, T *__restrict__ uout,
     }
     T pu0, pu1, pW0, pW1, pO0, pO1, pS0, pS1, pB0, pB1, pSW0 = 0, pSW1 = 0, pNW0 = 0, pNW1 = 0, pec;
     IW pw;
+    // IRUP: the double-FP64 iterate at the two rows a step finalises (rows
+    // e-2NU+2 and e-2NU+1 at step e), requested one step ahead
+    const double sc = IRUP ? *ir.scale : 0.0;
+    auto owned = [&](int row) { return col_own && row >= y0 && row < y1; };
+    double xh[2] = {0.0, 0.0}, xl[2] = {0.0, 0.0}, pxh[2] = {0.0, 0.0}, pxl[2] = {0.0, 0.0};
     auto fetch = [&](int e) {
+        if (IRUP) {
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const int row = e - 2 * NU + 2 - t;
+                const size_t p = (size_t)row * ld + i;
+                pxh[t] = owned(row) ? ir.XH[p] : 0.0;
+                pxl[t] = owned(row) ? ir.XL[p] : 0.0;
+            }
+        }
         pu0 = ld_row(L.u, e); pu1 = ld_row(L.u, e + 1);
         pW0 = ld_row(L.W, e); pW1 = ld_row(L.W, e + 1);
         pO0 = ld_row(L.O, e); pO1 = ld_row(L.O, e + 1);
@@ -573,6 +622,10 @@ __device__ __forceinline__ void post_tile(const Lev<T> &L, T *__restrict__ uout,
         rO[RW - 2] = pO0; rO[RW - 1] = pO1;
         rS[RW - 2] = pS0; rS[RW - 1] = pS1;
         rB[RW - 2] = pB0; rB[RW - 1] = pB1;
+        if (IRUP) {
+#pragma unroll
+            for (int t = 0; t < 2; ++t) { xh[t] = pxh[t]; xl[t] = pxl[t]; }
+        }
         __syncthreads();
         {
             const int s0 = slot<RU>(e) * FW + lane, s1 = slot<RU>(e + 1) * FW + lane;
@@ -603,8 +656,22 @@ __device__ __forceinline__ void post_tile(const Lev<T> &L, T *__restrict__ uout,
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
             const int row = e - 2 * NU + 2 - t;
-            if (col_own && row >= y0 && row < y1)
-                uout[(size_t)row * ld + i] = su[slot<RU>(row) * FW + lane];
+            if (owned(row)) {
+                const size_t p = (size_t)row * ld + i;
+                const T v = su[slot<RU>(row) * FW + lane];
+                if constexpr (IRUP) {
+                    // (XH, XL) += s v: TwoSum, add the low part, renormalise
+                    const double d = sc * (double)v;
+                    double hs, he;
+                    two_sum(xh[t], d, hs, he);
+                    he = he + xl[t];
+                    const double hi = hs + he;
+                    ir.XL[p] = he - (hi - hs);
+                    ir.XH[p] = hi;
+                } else {
+                    uout[p] = v;
+                }
+            }
         }
         if (NORM) {
             // accurate residual of the final rows e-2NU and e-2NU-1
@@ -660,6 +727,30 @@ __global__ __launch_bounds__(FW) void k_post(Lev<T> L, T *__restrict__ uout, Wts
     if (NORM) part += k * G.kpart;
     __shared__ TileLds<T, NINE, NU> S;
     post_tile<T, NINE, NU, NORM>(L, uout, C, ec, G, tid, part, S);
+}
+
+// The fine-level passes of an FP32 refinement step (IrArgs).  The post pass
+// leaves u itself unwritten: the iterate takes the correction directly.
+template <int NU>
+__global__ __launch_bounds__(FW) void k_pre_ir(Lev<float> L, float *__restrict__ uout, Wts<float> C,
+                                                Lev<float> Cl, TileGeo G, const int *stop, IrArgs ir)
+{
+    int tid, k;
+    if (!tile_work(G, tid, k)) return;
+    if (stopped(stop)) return;
+    __shared__ TileLds<float, false, NU> S;
+    pre_tile<float, false, NU, false, true>(L, uout, C, Cl, G, tid, S, ir);
+}
+
+template <int NU>
+__global__ __launch_bounds__(FW) void k_post_ir(Lev<float> L, Wts<float> C, const float *__restrict__ ec,
+                                                 TileGeo G, const int *stop, IrArgs ir)
+{
+    int tid, k;
+    if (!tile_work(G, tid, k)) return;
+    if (stopped(stop)) return;
+    __shared__ TileLds<float, false, NU> S;
+    post_tile<float, false, NU, false, true>(L, nullptr, C, ec, G, tid, nullptr, S, ir);
 }
 
 }  // namespace bmg

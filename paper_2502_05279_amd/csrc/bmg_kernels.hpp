@@ -620,16 +620,23 @@ static __global__ void k_absmax_final(const double *__restrict__ part, int np, d
     out[0] = m;
 }
 
+// Exponent e of the scale 2^e: the least power of two >= rmax (1 for rmax = 0).
+__device__ __forceinline__ int ir_exponent(double rmax)
+{
+    int e = 0;
+    const double fr = frexp(rmax, &e);  // rmax = fr 2^e, fr in [1/2, 1)
+    if (fr == 0.5) e -= 1;
+    if (fr == 0.0) e = 0;
+    return e;
+}
+
 // s = the smallest power of two >= ||r||_inf (1 if r = 0); the FP32 right-hand
 // side is fl32(r / s) (an exact scaling, then one rounding) and u32 = 0.
 static __global__ void k_ir_scale(Lev<double> L, Lev<float> F, const double *__restrict__ rmax,
                            double *__restrict__ scale, const int *stop)
 {
     if (stopped(stop)) return;
-    int e = 0;
-    const double fr = frexp(*rmax, &e);  // rmax = fr 2^e, fr in [1/2, 1)
-    if (fr == 0.5) e -= 1;
-    if (fr == 0.0) e = 0;
+    const int e = ir_exponent(*rmax);
     const double inv = ldexp(1.0, -e);
     const int i = 1 + blockIdx.x * blockDim.x + threadIdx.x;
     const int j = 1 + blockIdx.y * blockDim.y + threadIdx.y;

@@ -595,6 +595,51 @@ bmg_status fused_vcycle(bmg_solver *h, const int *stop, bool norm = false)
 }
 bmg_status fused_vcycle32(bmg_solver *h, const int *stop) { return fused_cycle_from<float>(h, 0, stop, false); }
 
+// The FP32 cycle of a refinement step with the fine level's passes taking the
+// scaled residual and adding the correction to (XH, XL) themselves (k_pre_ir,
+// k_post_ir): a five-point fine level, pass sweep counts, one right-hand side.
+static bool ir_fusable(const bmg_solver *h)
+{
+    return h->opt.kernels == BMG_KERNELS_FUSED && h->opt.smoother == BMG_SMOOTH_POINT && !h->nine[0] &&
+           BMG_FIVE_POINT_STEP_ROWS == 2 && h->nrhs == 1 && h->nlev >= 2 && h->opt.nu1 >= 1 &&
+           h->opt.nu1 <= 3 && h->opt.nu2 >= 1 && h->opt.nu2 <= 2 && h->L32[0].ld == h->L[0].ld;
+}
+
+static bmg_status ir_fused_cycle(bmg_solver *h, const int *stop, const IrArgs &ir)
+{
+    Lev<float> &F = h->L32[0];
+    const Lev<float> &Cl = h->L32[1];
+    const Wts<float> &C = h->C32[0];
+    const int nu1 = h->opt.nu1, nu2 = h->opt.nu2;
+    const double nf = (double)F.n * F.n, ncc = (double)Cl.n * Cl.n;
+    {
+        const TileGeo g = level_tiles(h, 0, 2 * nu1 + 2);
+        const dim3 grid = tile_grid(g), blk(FW);
+        // stencil and the FP64 residual read, u and b written; b and u (zero)
+        // written on the coarse level and the 8 weight planes read
+        trace_begin(h, BMG_TRACE_PRE, 0, 4.0 * ((stencil_planes(false) + 2.0) * nf + 10.0 * ncc) + 8.0 * nf);
+#define PREI(NU) hipLaunchKernelGGL((k_pre_ir<NU>), grid, blk, 0, h->st, F, h->ualt32[0], C, Cl, g, stop, ir)
+        if (nu1 == 1) PREI(1); else if (nu1 == 2) PREI(2); else PREI(3);
+#undef PREI
+        trace_end(h, BMG_TRACE_PRE, 0);
+        LAUNCHCHK();
+        std::swap(F.u, h->ualt32[0]);
+    }
+    TRY(fused_cycle_from<float>(h, 1, stop, false));
+    const TileGeo g = level_tiles(h, 0, 2 * nu2 + 2);
+    const dim3 grid = tile_grid(g), blk(FW);
+    // stencil, b and u read, (XH, XL) read and written; the coarse correction
+    // and the 8 weight planes read
+    trace_begin(h, BMG_TRACE_POST, 0, 4.0 * ((stencil_planes(false) + 2.0) * nf + 9.0 * ncc) + 32.0 * nf);
+    if (nu2 == 1)
+        hipLaunchKernelGGL((k_post_ir<1>), grid, blk, 0, h->st, F, C, (const float *)Cl.u, g, stop, ir);
+    else
+        hipLaunchKernelGGL((k_post_ir<2>), grid, blk, 0, h->st, F, C, (const float *)Cl.u, g, stop, ir);
+    trace_end(h, BMG_TRACE_POST, 0);
+    LAUNCHCHK();
+    return BMG_OK;
+}
+
 // Sum of squares of r = b - A u (res) or of the array x, into scal[slot]; with
 // record, also the history / stop bookkeeping of the running solve.
 template <typename T>
@@ -887,6 +932,8 @@ static bmg_status cycle64(bmg_solver *h, const int *stop)
 // One FP32 refinement step: r = B0 - A (XH + XL) is in L0.r and the residual
 // pass left the partial maxima of |r| after its partial sums; scale to the
 // power of two s >= ||r||_inf, round to FP32, V32 from zero, (XH, XL) += s d32.
+// The scaling and the update run inside the fine level's passes where the
+// cycle allows (the same values), else as passes of their own.
 static bmg_status ir_correct(bmg_solver *h, const int *stop)
 {
     const Lev<double> &L = h->L[0];
@@ -894,6 +941,11 @@ static bmg_status ir_correct(bmg_solver *h, const int *stop)
     const int nb = std::min(NPART_ROWS, L.n);
     hipLaunchKernelGGL(k_absmax_final, dim3(1), dim3(1024), 0, h->st, (const double *)h->part + nb, nb,
                        h->scal + S_RMAX, stop);
+    if (ir_fusable(h)) {
+        LAUNCHCHK();
+        const IrArgs ir{L.r, h->scal + S_RMAX, h->scal + S_SCALE, h->XH, h->XL};
+        return ir_fused_cycle(h, stop, ir);
+    }
     hipLaunchKernelGGL(k_ir_scale, grid2(L.n, L.n, B2), B2, 0, h->st, L, F, (const double *)(h->scal + S_RMAX),
                        h->scal + S_SCALE, stop);
     LAUNCHCHK();

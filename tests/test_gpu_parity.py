@@ -197,12 +197,16 @@ def test_solve_matches_oracle(gpu, kind, n, tol, rf):
 
 
 @pytest.mark.parametrize("kind,n", [("lognormal", 127), ("jump16", 255)])
-def test_fp32_refinement_matches_oracle(gpu, kind, n):
+@pytest.mark.parametrize("kernels", ["fused", "basic"])
+def test_fp32_refinement_matches_oracle(gpu, kind, n, kernels):
     """FP32 V-cycles inside double-FP64 refinement: the FP32 hierarchy is the
-    rounded FP64 one, and every refinement iterate matches the oracle bitwise."""
+    rounded FP64 one, and every refinement iterate matches the oracle bitwise,
+    with the scaling and the iterate update inside the fine level's fused passes
+    and as passes of their own."""
     p = problem(kind, n, 5)
     st, rhs = gpu_problem(p)
-    S = boxmg.Solver(st, max_cycles=300, precision=boxmg.BMG_FP32_IR)
+    kern = boxmg.BMG_KERNELS_FUSED if kernels == "fused" else boxmg.BMG_KERNELS_BASIC
+    S = boxmg.Solver(st, max_cycles=300, precision=boxmg.BMG_FP32_IR, kernels=kern)
     H = ref.Hierarchy(host(st))
     H.solve_ir(ref.pad(host(rhs)), tol=1.0, max_iter=0)     # builds the FP32 copy
     for l in range(H.nlev):
@@ -431,4 +435,15 @@ def test_trace_counts_algorithmic_bytes(gpu):
         S.step(0, "post", 1, fp32=fp32)
         nl, ms, nb = S.trace_read()
         assert nl == 1 and nb == esz * (6 * n0 * n0 + 9 * n1 * n1)
+        if fp32:
+            # a refinement step's fine passes: the pre pass reads the FP64
+            # residual (8 bytes) in place of b and u and writes b; the post
+            # pass reads and writes (XH, XL) (32 bytes) in place of writing u
+            for cls, want in (("pre", 4 * (5 * n0 * n0 + 10 * n1 * n1) + 8 * n0 * n0),
+                              ("post", 4 * (5 * n0 * n0 + 9 * n1 * n1) + 32 * n0 * n0)):
+                S.trace_enable(cls, 0)
+                S.vcycle(rhs, torch.zeros_like(rhs))
+                nl, ms, nb = S.trace_read()
+                S.trace_enable(cls, 0, on=False)
+                assert nl == 1 and nb == want, (cls, nb, want)
         S.close()
