@@ -1166,8 +1166,13 @@ namespace bmg {
 // the iterates, right-hand sides and the residual of these levels stay in LDS
 // (tight pitch n+2), the stencils and weights are read from global memory (they
 // are a few hundred KB and stay in L2), and every phase of the cycle is
-// separated by a workgroup barrier instead of a kernel launch.  The arithmetic
-// per point is the same expression as in the single-step kernels.
+// separated by a workgroup barrier instead of a kernel launch.  On a level of
+// at most 63 points per side each colour has at most 32 x 32 = SMALL_THREADS
+// points, so every thread owns at most one point of each colour; it loads the
+// stencil of its four points once per visit of the level and keeps it in
+// registers through the sweeps and the residual (one round trip to L2 per
+// visit instead of one per phase).  The arithmetic per point is the same
+// expression as in the single-step kernels.
 constexpr int SMALL_MAXL = 6;
 constexpr int SMALL_THREADS = 1024;
 
@@ -1185,58 +1190,84 @@ struct SmallH {
     int kstop;
 };
 
+constexpr int SMALL_MAX_N = 63;
+
+// The stencil rows of this thread's points, one per colour c (colour c: i odd
+// if c & 1, j odd if c & 2): a[c] holds SW, S, SE (the NW entry of the point
+// below-right), W, E, NW, N, NE (the SW entry of the point above-right), O in
+// the order the update subtracts them; q[c] is the point's LDS index, -1 if
+// the thread has no point of that colour.
+template <typename T>
+struct SmallPts {
+    T a[4][9];
+    int q[4];
+};
+
 template <typename T, bool NINE>
-__device__ __forceinline__ void small_gs_colour(const Lev<T> &L, T *u, const T *b, int c)
+__device__ __forceinline__ void small_load(const Lev<T> &L, SmallPts<T> &P)
 {
-    const int n = L.n, p = n + 2;
-    const int i0 = (c & 1) ? 1 : 2, j0 = (c >> 1) ? 1 : 2;
-    const int ni = (c & 1) ? (n + 1) / 2 : (n - 1) / 2, nj = (c >> 1) ? (n + 1) / 2 : (n - 1) / 2;
-    for (int t = threadIdx.x; t < ni * nj; t += blockDim.x) {
-        const int i = i0 + 2 * (t % ni), j = j0 + 2 * (t / ni);
+    const int n = L.n, p = n + 2, t = threadIdx.x;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int i0 = (c & 1) ? 1 : 2, j0 = (c >> 1) ? 1 : 2;
+        const int ni = (c & 1) ? (n + 1) / 2 : (n - 1) / 2, nj = (c >> 1) ? (n + 1) / 2 : (n - 1) / 2;
+        const bool ok = t < ni * nj;
+        const int i = ok ? i0 + 2 * (t % ni) : 1, j = ok ? j0 + 2 * (t / ni) : 1;
         const size_t g = (size_t)j * L.ld + i;
-        const int q = j * p + i;
-        T s = b[q];
-        if (NINE) s -= L.SW[g] * u[q - p - 1];
-        s -= L.S[g] * u[q - p];
-        if (NINE) s -= L.NW[g + 1 - L.ld] * u[q - p + 1];
-        s -= L.W[g] * u[q - 1];
-        s -= L.W[g + 1] * u[q + 1];
-        if (NINE) s -= L.NW[g] * u[q + p - 1];
-        s -= L.S[g + L.ld] * u[q + p];
-        if (NINE) s -= L.SW[g + L.ld + 1] * u[q + p + 1];
-        u[q] = s / L.O[g];
+        P.q[c] = ok ? j * p + i : -1;
+        T *a = P.a[c];
+        a[0] = NINE && ok ? L.SW[g] : (T)0;
+        a[1] = ok ? L.S[g] : (T)0;
+        a[2] = NINE && ok ? L.NW[g + 1 - L.ld] : (T)0;
+        a[3] = ok ? L.W[g] : (T)0;
+        a[4] = ok ? L.W[g + 1] : (T)0;
+        a[5] = NINE && ok ? L.NW[g] : (T)0;
+        a[6] = ok ? L.S[g + L.ld] : (T)0;
+        a[7] = NINE && ok ? L.SW[g + L.ld + 1] : (T)0;
+        a[8] = ok ? L.O[g] : (T)1;
+    }
+}
+
+// sum of the off-diagonal couplings of point q subtracted from s, in the
+// order of the single-step kernels
+template <typename T, bool NINE>
+__device__ __forceinline__ T small_offdiag(const T *a, const T *u, int q, int p, T s)
+{
+    if (NINE) s -= a[0] * u[q - p - 1];
+    s -= a[1] * u[q - p];
+    if (NINE) s -= a[2] * u[q - p + 1];
+    s -= a[3] * u[q - 1];
+    s -= a[4] * u[q + 1];
+    if (NINE) s -= a[5] * u[q + p - 1];
+    s -= a[6] * u[q + p];
+    if (NINE) s -= a[7] * u[q + p + 1];
+    return s;
+}
+
+template <typename T, bool NINE>
+__device__ __forceinline__ void small_relax(const SmallPts<T> &P, int p, T *u, const T *b, int sweeps)
+{
+    for (int s = 0; s < sweeps; ++s) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int q = P.q[c];
+            if (q >= 0) u[q] = small_offdiag<T, NINE>(P.a[c], u, q, p, b[q]) / P.a[c][8];
+            __syncthreads();
+        }
     }
 }
 
 template <typename T, bool NINE>
-__device__ __forceinline__ void small_smooth(const Lev<T> &L, T *u, const T *b, int sweeps)
+__device__ __forceinline__ void small_resid(const SmallPts<T> &P, int p, const T *u, const T *b, T *r)
 {
-    for (int s = 0; s < sweeps; ++s)
-        for (int c = 0; c < 4; ++c) {
-            small_gs_colour<T, NINE>(L, u, b, c);
-            __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int q = P.q[c];
+        if (q >= 0) {
+            T s = small_offdiag<T, NINE>(P.a[c], u, q, p, b[q]);
+            s -= P.a[c][8] * u[q];
+            r[q] = s;
         }
-}
-
-template <typename T, bool NINE>
-__device__ __forceinline__ void small_residual(const Lev<T> &L, const T *u, const T *b, T *r)
-{
-    const int n = L.n, p = n + 2;
-    for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
-        const int i = 1 + t % n, j = 1 + t / n;
-        const size_t g = (size_t)j * L.ld + i;
-        const int q = j * p + i;
-        T s = b[q];
-        if (NINE) s -= L.SW[g] * u[q - p - 1];
-        s -= L.S[g] * u[q - p];
-        if (NINE) s -= L.NW[g + 1 - L.ld] * u[q - p + 1];
-        s -= L.W[g] * u[q - 1];
-        s -= L.W[g + 1] * u[q + 1];
-        if (NINE) s -= L.NW[g] * u[q + p - 1];
-        s -= L.S[g + L.ld] * u[q + p];
-        if (NINE) s -= L.SW[g + L.ld + 1] * u[q + p + 1];
-        s -= L.O[g] * u[q];
-        r[q] = s;
     }
 }
 
@@ -1277,12 +1308,20 @@ __device__ void small_vcycle_body(const SmallH<T> &H, T *sm, size_t rhs_off)
     for (int t = threadIdx.x; t < (H.L[0].n + 2) * (H.L[0].n + 2); t += blockDim.x) r[t] = (T)0;
     __syncthreads();
     // down: relax, residual, restrict
+    SmallPts<T> P;
     for (int l = 0; l < last; ++l) {
         const Lev<T> &L = H.L[l];
         T *u = sm + H.off_u[l], *b = sm + H.off_b[l];
-        const bool nine = (l > 0) || NINE0;
-        if (nine) small_smooth<T, true>(L, u, b, H.nu1); else small_smooth<T, false>(L, u, b, H.nu1);
-        if (nine) small_residual<T, true>(L, u, b, r); else small_residual<T, false>(L, u, b, r);
+        const int p = L.n + 2;
+        if (l > 0 || NINE0) {
+            small_load<T, true>(L, P);
+            small_relax<T, true>(P, p, u, b, H.nu1);
+            small_resid<T, true>(P, p, u, b, r);
+        } else {
+            small_load<T, false>(L, P);
+            small_relax<T, false>(P, p, u, b, H.nu1);
+            small_resid<T, false>(P, p, u, b, r);
+        }
         __syncthreads();
         const int nf = L.n, pf = nf + 2, nc = H.L[l + 1].n, pc = nc + 2;
         const Wts<T> &C = H.C[l];
@@ -1331,6 +1370,9 @@ __device__ void small_vcycle_body(const SmallH<T> &H, T *sm, size_t rhs_off)
         const T *ec = sm + H.off_u[l + 1];
         const int n = L.n, p = n + 2, pc = H.L[l + 1].n + 2;
         const Wts<T> &C = H.C[l];
+        const bool nine = (l > 0) || NINE0;
+        // the sweeps' stencil is requested before the interpolation runs
+        if (nine) small_load<T, true>(L, P); else small_load<T, false>(L, P);
         for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
             const int i = 1 + t % n, j = 1 + t / n;
             T e;
@@ -1354,8 +1396,7 @@ __device__ void small_vcycle_body(const SmallH<T> &H, T *sm, size_t rhs_off)
             u[j * p + i] = u[j * p + i] + e;
         }
         __syncthreads();
-        const bool nine = (l > 0) || NINE0;
-        if (nine) small_smooth<T, true>(L, u, b, H.nu2); else small_smooth<T, false>(L, u, b, H.nu2);
+        if (nine) small_relax<T, true>(P, p, u, b, H.nu2); else small_relax<T, false>(P, p, u, b, H.nu2);
     }
     // the first level's iterate back to global memory
     {

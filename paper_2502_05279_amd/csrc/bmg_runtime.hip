@@ -548,7 +548,7 @@ bmg_status fused_post(bmg_solver *h, int l, int nu, const int *stop, bool norm =
 
 // Coarse levels of at most SMALL_N points per side: their whole sub-cycle in
 // one workgroup (k_small_vcycle), iterates and right-hand sides in LDS.
-constexpr int SMALL_N = 63;
+constexpr int SMALL_N = SMALL_MAX_N;
 
 template <typename T>
 bmg_status small_cycle(bmg_solver *h, int l, const int *stop)
@@ -556,6 +556,7 @@ bmg_status small_cycle(bmg_solver *h, int l, const int *stop)
     SmallH<T> S{};
     S.nl = h->nlev - l;
     if (S.nl > SMALL_MAXL) return fail(BMG_EINVAL, "too many small levels");
+    if (lev<T>(h, l).n > SMALL_MAX_N) return fail(BMG_EINVAL, "level %d too large for one workgroup", l);
     for (int k = 0; k < S.nl; ++k) {
         S.L[k] = lev<T>(h, l + k);
         if (k + 1 < S.nl) S.C[k] = wts<T>(h, l + k);
