@@ -126,18 +126,19 @@ struct TileLds {
     T wy[WREC ? FW : 0], wx[WREC ? 3 * FW : 0];
 };
 
-// An FP32 refinement step folded into the fine level's passes (five-point
-// level, one right-hand side).  The pre pass starts from u = 0 and reads the
-// FP64 residual r in place of b: b = fl32(r / s) with s = 2^e the least power
-// of two >= ||r||_inf (the scaling of k_ir_scale), which it also stores as the
-// FP32 right-hand side for the post pass and, from one lane, into scale[0].
-// The post pass adds s * u to the double-FP64 iterate (XH, XL) as each owned
-// point's final value is produced, with the arithmetic of dd_update_point, in
-// place of storing u.
+// A refinement step folded into the fine level's passes (five-point level,
+// one right-hand side).  FP32 inner cycle: the pre pass starts from u = 0 and
+// reads the FP64 residual r in place of b: b = fl32(r / s) with s = 2^e the
+// least power of two >= ||r||_inf (the scaling of k_ir_scale), which it also
+// stores as the FP32 right-hand side for the post pass and, from one lane,
+// into scale[0].  The post pass (FP32 or FP64 inner cycle) adds s * u to the
+// double-FP64 iterate (XH, XL) as each owned point's final value is produced,
+// with the arithmetic of dd_update_point, in place of storing u; s = 1 when
+// scale is null (FP64 inner cycle, where 1 * u = u exactly).
 struct IrArgs {
     const double *r;     // FP64 residual, the level's pitch
     const double *rmax;  // ||r||_inf
-    double *scale;       // s, written by the pre pass
+    double *scale;       // s, written by the pre pass; null: s = 1
     double *XH, *XL;     // double-FP64 iterate
 };
 
@@ -586,7 +587,7 @@ __device__ __forceinline__ void post_tile(const Lev<T> &L, T *__restrict__ uout,
     IW pw;
     // IRUP: the double-FP64 iterate at the two rows a step finalises (rows
     // e-2NU+2 and e-2NU+1 at step e), requested one step ahead
-    const double sc = IRUP ? *ir.scale : 0.0;
+    const double sc = IRUP ? (ir.scale ? *ir.scale : 1.0) : 0.0;
     auto owned = [&](int row) { return col_own && row >= y0 && row < y1; };
     double xh[2] = {0.0, 0.0}, xl[2] = {0.0, 0.0}, pxh[2] = {0.0, 0.0}, pxl[2] = {0.0, 0.0};
     auto fetch = [&](int e) {
@@ -742,15 +743,15 @@ __global__ __launch_bounds__(FW) void k_pre_ir(Lev<float> L, float *__restrict__
     pre_tile<float, false, NU, false, true>(L, uout, C, Cl, G, tid, S, ir);
 }
 
-template <int NU>
-__global__ __launch_bounds__(FW) void k_post_ir(Lev<float> L, Wts<float> C, const float *__restrict__ ec,
-                                                 TileGeo G, const int *stop, IrArgs ir)
+template <typename T, int NU>
+__global__ __launch_bounds__(FW) void k_post_ir(Lev<T> L, Wts<T> C, const T *__restrict__ ec, TileGeo G,
+                                                 const int *stop, IrArgs ir)
 {
     int tid, k;
     if (!tile_work(G, tid, k)) return;
     if (stopped(stop)) return;
-    __shared__ TileLds<float, false, NU> S;
-    post_tile<float, false, NU, false, true>(L, nullptr, C, ec, G, tid, nullptr, S, ir);
+    __shared__ TileLds<T, false, NU> S;
+    post_tile<T, false, NU, false, true>(L, nullptr, C, ec, G, tid, nullptr, S, ir);
 }
 
 }  // namespace bmg

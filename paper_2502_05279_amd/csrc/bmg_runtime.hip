@@ -596,14 +596,43 @@ bmg_status fused_vcycle(bmg_solver *h, const int *stop, bool norm = false)
 }
 bmg_status fused_vcycle32(bmg_solver *h, const int *stop) { return fused_cycle_from<float>(h, 0, stop, false); }
 
-// The FP32 cycle of a refinement step with the fine level's passes taking the
-// scaled residual and adding the correction to (XH, XL) themselves (k_pre_ir,
-// k_post_ir): a five-point fine level, pass sweep counts, one right-hand side.
-static bool ir_fusable(const bmg_solver *h)
+// A refinement step's cycle with the fine post pass adding the correction to
+// (XH, XL) itself (k_post_ir): a five-point fine level, a post sweep count the
+// pass takes, one right-hand side.  With an FP32 inner cycle the fine pre pass
+// also takes the scaled residual itself (k_pre_ir).
+static bool post_update_fusable(const bmg_solver *h)
 {
     return h->opt.kernels == BMG_KERNELS_FUSED && h->opt.smoother == BMG_SMOOTH_POINT && !h->nine[0] &&
-           BMG_FIVE_POINT_STEP_ROWS == 2 && h->nrhs == 1 && h->nlev >= 2 && h->opt.nu1 >= 1 &&
-           h->opt.nu1 <= 3 && h->opt.nu2 >= 1 && h->opt.nu2 <= 2 && h->L32[0].ld == h->L[0].ld;
+           BMG_FIVE_POINT_STEP_ROWS == 2 && h->nrhs == 1 && h->nlev >= 2 && h->opt.nu2 >= 1 && h->opt.nu2 <= 2;
+}
+
+static bool ir_fusable(const bmg_solver *h)
+{
+    return post_update_fusable(h) && h->opt.nu1 >= 1 && h->opt.nu1 <= 3 && h->L32[0].ld == h->L[0].ld;
+}
+
+// The fine post pass of such a step: interpolation and sweeps, then
+// (XH, XL) += s u at every owned point.
+template <typename T>
+static bmg_status post_update(bmg_solver *h, const int *stop, const IrArgs &ir)
+{
+    const Lev<T> &F = lev<T>(h, 0);
+    const Lev<T> &Cl = lev<T>(h, 1);
+    const Wts<T> &C = wts<T>(h, 0);
+    const int nu2 = h->opt.nu2;
+    const double nf = (double)F.n * F.n, ncc = (double)Cl.n * Cl.n;
+    const TileGeo g = level_tiles(h, 0, 2 * nu2 + 2);
+    const dim3 grid = tile_grid(g), blk(FW);
+    // stencil, b and u read, (XH, XL) read and written; the coarse correction
+    // and the 8 weight planes read
+    trace_begin(h, BMG_TRACE_POST, 0, sizeof(T) * ((stencil_planes(false) + 2.0) * nf + 9.0 * ncc) + 32.0 * nf);
+    if (nu2 == 1)
+        hipLaunchKernelGGL((k_post_ir<T, 1>), grid, blk, 0, h->st, F, C, (const T *)Cl.u, g, stop, ir);
+    else
+        hipLaunchKernelGGL((k_post_ir<T, 2>), grid, blk, 0, h->st, F, C, (const T *)Cl.u, g, stop, ir);
+    trace_end(h, BMG_TRACE_POST, 0);
+    LAUNCHCHK();
+    return BMG_OK;
 }
 
 static bmg_status ir_fused_cycle(bmg_solver *h, const int *stop, const IrArgs &ir)
@@ -611,34 +640,21 @@ static bmg_status ir_fused_cycle(bmg_solver *h, const int *stop, const IrArgs &i
     Lev<float> &F = h->L32[0];
     const Lev<float> &Cl = h->L32[1];
     const Wts<float> &C = h->C32[0];
-    const int nu1 = h->opt.nu1, nu2 = h->opt.nu2;
+    const int nu1 = h->opt.nu1;
     const double nf = (double)F.n * F.n, ncc = (double)Cl.n * Cl.n;
-    {
-        const TileGeo g = level_tiles(h, 0, 2 * nu1 + 2);
-        const dim3 grid = tile_grid(g), blk(FW);
-        // stencil and the FP64 residual read, u and b written; b and u (zero)
-        // written on the coarse level and the 8 weight planes read
-        trace_begin(h, BMG_TRACE_PRE, 0, 4.0 * ((stencil_planes(false) + 2.0) * nf + 10.0 * ncc) + 8.0 * nf);
-#define PREI(NU) hipLaunchKernelGGL((k_pre_ir<NU>), grid, blk, 0, h->st, F, h->ualt32[0], C, Cl, g, stop, ir)
-        if (nu1 == 1) PREI(1); else if (nu1 == 2) PREI(2); else PREI(3);
-#undef PREI
-        trace_end(h, BMG_TRACE_PRE, 0);
-        LAUNCHCHK();
-        std::swap(F.u, h->ualt32[0]);
-    }
-    TRY(fused_cycle_from<float>(h, 1, stop, false));
-    const TileGeo g = level_tiles(h, 0, 2 * nu2 + 2);
+    const TileGeo g = level_tiles(h, 0, 2 * nu1 + 2);
     const dim3 grid = tile_grid(g), blk(FW);
-    // stencil, b and u read, (XH, XL) read and written; the coarse correction
-    // and the 8 weight planes read
-    trace_begin(h, BMG_TRACE_POST, 0, 4.0 * ((stencil_planes(false) + 2.0) * nf + 9.0 * ncc) + 32.0 * nf);
-    if (nu2 == 1)
-        hipLaunchKernelGGL((k_post_ir<1>), grid, blk, 0, h->st, F, C, (const float *)Cl.u, g, stop, ir);
-    else
-        hipLaunchKernelGGL((k_post_ir<2>), grid, blk, 0, h->st, F, C, (const float *)Cl.u, g, stop, ir);
-    trace_end(h, BMG_TRACE_POST, 0);
+    // stencil and the FP64 residual read, u and b written; b and u (zero)
+    // written on the coarse level and the 8 weight planes read
+    trace_begin(h, BMG_TRACE_PRE, 0, 4.0 * ((stencil_planes(false) + 2.0) * nf + 10.0 * ncc) + 8.0 * nf);
+#define PREI(NU) hipLaunchKernelGGL((k_pre_ir<NU>), grid, blk, 0, h->st, F, h->ualt32[0], C, Cl, g, stop, ir)
+    if (nu1 == 1) PREI(1); else if (nu1 == 2) PREI(2); else PREI(3);
+#undef PREI
+    trace_end(h, BMG_TRACE_PRE, 0);
     LAUNCHCHK();
-    return BMG_OK;
+    std::swap(F.u, h->ualt32[0]);
+    TRY(fused_cycle_from<float>(h, 1, stop, false));
+    return post_update<float>(h, stop, ir);
 }
 
 // Sum of squares of r = b - A u (res) or of the array x, into scal[slot]; with
@@ -981,10 +997,17 @@ static bmg_status cycle_and_norm(bmg_solver *h, double tol, int maxc, double ref
     return resnorm_dd(h, L.b, L.u, nullptr, 0, nullptr, S_SUMSQ, true, tol, maxc, refine);
 }
 
-// One FP64 refinement step: L0.b holds r, L0.u = 0; V-cycle, (XH, XL) += u.
+// One FP64 refinement step: L0.b holds r, L0.u = 0; V-cycle, (XH, XL) += u
+// (inside the fine post pass where the cycle allows).
 static bmg_status refine_step64(bmg_solver *h, const int *stop)
 {
     const Lev<double> &L = h->L[0];
+    if (post_update_fusable(h)) {
+        TRY(fused_pre<double>(h, 0, h->opt.nu1, stop));
+        TRY(fused_cycle_from<double>(h, 1, stop, false));
+        const IrArgs ir{nullptr, nullptr, nullptr, h->XH, h->XL};
+        return post_update<double>(h, stop, ir);
+    }
     TRY(cycle64(h, stop));
     hipLaunchKernelGGL(k_dd_update, grid2(L.n, L.n, B2), B2, 0, h->st, L, h->XH, h->XL, (const float *)nullptr,
                        (const double *)nullptr, stop);

@@ -175,15 +175,21 @@ def test_poisson_127_ten_cycles_bitwise(gpu):
         assert abs(rel - rel_o) <= 1e-12 * rel_o, (k, rel, rel_o)
 
 
-@pytest.mark.parametrize("kind,n,tol,rf", [("lognormal", 255, 1e-10, 16), ("jump16", 127, 1e-10, 16),
-                                           ("poisson", 1023, 1e-10, 16), ("jump64", 255, 1e-16, 10**5),
-                                           ("jump64", 255, 1e-16, 0)])
-def test_solve_matches_oracle(gpu, kind, n, tol, rf):
+@pytest.mark.parametrize("kind,n,tol,rf,kernels", [("lognormal", 255, 1e-10, 16, "fused"),
+                                                   ("jump16", 127, 1e-10, 16, "fused"),
+                                                   ("poisson", 1023, 1e-10, 16, "fused"),
+                                                   ("jump64", 255, 1e-16, 10**5, "fused"),
+                                                   ("jump64", 255, 1e-16, 10**5, "basic"),
+                                                   ("jump64", 255, 1e-16, 0, "fused")])
+def test_solve_matches_oracle(gpu, kind, n, tol, rf, kernels):
     """Whole solves: cycle count, both parts of the iterate bitwise, history to
-    1e-12; including the double-FP64 refinement phase below the FP64 floor."""
+    1e-12; including the double-FP64 refinement phase below the FP64 floor,
+    whose iterate update runs inside the fine post pass (fused kernels) or as
+    a pass of its own (basic kernels)."""
     p = problem(kind, n, 11)
     st, rhs = gpu_problem(p)
-    S = boxmg.Solver(st, max_cycles=300, refine_factor=rf)
+    kern = boxmg.BMG_KERNELS_FUSED if kernels == "fused" else boxmg.BMG_KERNELS_BASIC
+    S = boxmg.Solver(st, max_cycles=300, refine_factor=rf, kernels=kern)
     x, info = S.solve(rhs, tol=tol, raise_on_noconv=False)
     H = ref.Hierarchy(host(st))
     u, hist = H.solve(ref.pad(host(rhs)), tol=tol, max_cycles=300, refine_factor=rf)
