@@ -40,7 +40,7 @@ def command(out: str, defines=()) -> list[str]:
 
 def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
     """Compiles the library to ``out`` (with extra -D definitions, e.g. a
-    tuning variant such as BMG_PREFETCH_STEPS=1)."""
+    tuning variant such as BMG_FIVE_POINT_STEP_ROWS=4)."""
     os.makedirs(os.path.dirname(out), exist_ok=True)
     tmp = out + ".tmp"
     cmd = command(tmp, defines)
