@@ -279,7 +279,8 @@ bmg_status bmg_step(bmg_solver *h, int level, int step, int arg, int fp32);
  * array the launch needs counted once, read or written, for the variant that
  * ran (a fused pre pass that computes its weights does not count them).  It
  * then clears the record.  Classes: */
-enum { BMG_TRACE_SMOOTH = 0, BMG_TRACE_PRE = 1, BMG_TRACE_POST = 2, BMG_TRACE_RESNORM = 3 };
+enum { BMG_TRACE_SMOOTH = 0, BMG_TRACE_PRE = 1, BMG_TRACE_POST = 2, BMG_TRACE_RESNORM = 3,
+       BMG_TRACE_POSTPRE = 4 /* fine post pass fused with the next cycle's fine pre pass */ };
 bmg_status bmg_trace_enable(bmg_solver *h, int kclass, int level, int on);
 bmg_status bmg_trace_read(bmg_solver *h, int *launches, double *total_ms, double *bytes);
 

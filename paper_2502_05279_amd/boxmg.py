@@ -33,7 +33,7 @@ FIELDS = {"u": 0, "b": 1, "r": 2, "O": 3, "W": 4, "S": 5, "SW": 6, "NW": 7, "Ci"
           "u32": 16, "b32": 17, "r32": 18, "O32": 19, "W32": 20, "S32": 21, "SW32": 22,
           "NW32": 23, "Ci32": 24}
 STEPS = {"smooth": 0, "residual": 1, "restrict": 2, "interp": 3, "coarse": 4, "pre": 5, "post": 6}
-TRACE = {"smooth": 0, "pre": 1, "post": 2, "resnorm": 3}
+TRACE = {"smooth": 0, "pre": 1, "post": 2, "resnorm": 3, "postpre": 4}
 
 
 class Options(C.Structure):

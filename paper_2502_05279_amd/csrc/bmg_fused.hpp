@@ -27,7 +27,13 @@ constexpr int FW = 256;  // lanes (= columns) per workgroup
 
 // Ring-buffer slot of a row (rows may be slightly negative near the bottom).
 template <int R>
-__device__ __forceinline__ int slot(int row) { return (row + 64 * R) & (R - 1); }
+__device__ __forceinline__ int slot(int row)
+{
+    if constexpr ((R & (R - 1)) == 0)
+        return (row + 64 * R) & (R - 1);
+    else
+        return (row + 64 * R) % R;
+}
 
 // Tile of the XCD-aware launch: consecutive workgroup ids are dealt round-robin
 // to the 8 XCDs, so ids are regrouped to give each XCD a contiguous run of
@@ -153,9 +159,11 @@ struct IrArgs {
 // {c1, c2(s)} and {c3(s), c0(s+1)}: 2 NU + 1 barriers instead of 4 NU.
 // The window rows are compile-time positions k = row - (e - 2NU - 2); a lane
 // picks its row's entries by its column parity.
-template <typename T, int NU, int RU>
+// done(s) runs after the phase that completes sweep s (all lanes past the
+// barrier that follows it).
+template <typename T, int NU, int RU, typename Done>
 __device__ __forceinline__ void five_point_sweeps(T *su, const T *sW, int lane, int i, bool col_upd, int n, int e,
-                                                  const T *rB, const T *rO, const T *rS)
+                                                  const T *rB, const T *rO, const T *rS, Done &&done)
 {
     const bool odd = i & 1;
     const int base = e - 2 * NU - 2;
@@ -189,7 +197,15 @@ __device__ __forceinline__ void five_point_sweeps(T *su, const T *sW, int lane, 
         __syncthreads();
         pair(true, ke - 1, s + 1 < NU, ke - 2);             // c3 on e - 2s - 1, c0 of s + 1 on e - 2s - 2
         __syncthreads();
+        done(s);
     }
+}
+
+template <typename T, int NU, int RU>
+__device__ __forceinline__ void five_point_sweeps(T *su, const T *sW, int lane, int i, bool col_upd, int n, int e,
+                                                  const T *rB, const T *rO, const T *rS)
+{
+    five_point_sweeps<T, NU, RU>(su, sW, lane, i, col_upd, n, e, rB, rO, rS, [](int) {});
 }
 
 // With WREC the restriction weights are not read: each column computes the
@@ -728,6 +744,341 @@ __global__ __launch_bounds__(FW) void k_post(Lev<T> L, T *__restrict__ uout, Wts
     if (NORM) part += k * G.kpart;
     __shared__ TileLds<T, NINE, NU> S;
     post_tile<T, NINE, NU, NORM>(L, uout, C, ec, G, tid, part, S);
+}
+
+// --------------------------------- post pass and the next cycle's pre pass
+// The fine level's post pass of cycle k and its pre pass of cycle k+1 as one
+// pass (FP64, five-point level, one right-hand side, one post sweep, NB pre
+// sweeps).  Rows enter as u' + P e_c; sweep 0 gives the cycle's result u_k,
+// which is written (a stop decided by its norm finds it) and copied to a
+// four-row LDS ring, from which the per-tile sum of squares of its accurate
+// residual goes to part[tile]; sweeps 1..NB give the next cycle's
+// pre-smoothed iterate u'' (written), whose residual is restricted with the
+// operator-induced weights computed in the pass, as in pre_tile.  Every value
+// is the one the two separate passes give.  u_c = 0 goes to a separate coarse
+// buffer (ucz), since the coarse correction e_c is still read by other tiles.
+template <int NB>
+struct PostPreLds {
+    static constexpr int NS = NB + 1;
+    static constexpr int RW = 2 * NS + 4;
+    static constexpr int CW = FW / 2 + 2;  // coarse columns of a strip
+    double su[RW * FW], sW[RW * FW], sx[4 * FW];
+    double wy[FW], wx[3 * FW];
+    double sec[8 * CW];                    // e_c rows, ring of 8
+    double uk[4 * FW];                     // u_k rows, ring of 4
+};
+
+template <int NB>
+__device__ __forceinline__ void postpre_tile(const Lev<double> &L, double *__restrict__ ukout,
+                                             double *__restrict__ uout, const Wts<double> &C,
+                                             const double *__restrict__ ec, const Lev<double> &Cl,
+                                             double *__restrict__ ucz, const TileGeo &G, int tid,
+                                             double *__restrict__ part, PostPreLds<NB> &S)
+{
+    using T = double;
+    constexpr int NS = NB + 1;                     // sweeps: one post, NB pre
+    constexpr int RW = 2 * NS + 4;                 // window rows e-2NS-2 .. e+1
+    constexpr int RU = RW;                         // LDS ring rows
+    constexpr int CW = PostPreLds<NB>::CW;
+    T *su = S.su, *sW = S.sW, *sr = S.sx, *sec = S.sec, *suk = S.uk;
+
+    const int n = L.n, ld = L.ld, lane = threadIdx.x, nc = Cl.n, ldc = C.ld;
+    const int useful = FW - 2 * G.hx;
+    const int tx = tid % G.tiles_x, ty = tid / G.tiles_x;
+    const int x0 = 1 + tx * useful;
+    const int i = x0 - G.hx + lane;
+    const bool col_in = i >= 0 && i <= n + 1;
+    const bool col_upd = i >= 1 && i <= n && lane >= 1 && lane < FW - 1;
+    const bool col_own = i >= x0 && i < x0 + useful && i <= n;
+    const int y0 = 1 + ty * G.ht;
+    const int y1 = min(y0 + G.ht, n + 1);
+    const int es = (y0 - 2 * NS) & ~1;
+    const int jlast = (y1 - 1) >> 1;
+    const int elast = 2 * jlast + 2 * NS + 2;
+    const int I = i >> 1;
+    const bool restrictor = !(i & 1) && col_own && I >= 1 && I <= nc;
+    const int ib = (x0 - G.hx) >> 1;               // coarse column of ring entry 0
+    const int Ie = ib + lane;
+    const bool ccol_in = lane < CW && Ie >= 0 && Ie <= nc + 1;
+    const bool odd_i = i & 1;
+    const int Ix = (i + 1) >> 1;
+
+    T rO[RW], rS[RW], rB[RW];
+    auto ld_row = [&](const T *a, int row) -> T {
+        return (col_in && row >= 0 && row <= n + 1) ? a[(size_t)row * ld + i] : (T)0;
+    };
+    auto ld_crow = [&](int J) -> T {
+        return (ccol_in && J >= 0 && J <= nc + 1) ? ec[(size_t)J * ldc + Ie] : (T)0;
+    };
+    // interpolation weights of this column for rows e (even) and e+1 (odd),
+    // as in post_tile
+    struct IW { T w[6]; };
+    const int p2 = odd_i ? LSW : LB, p3 = odd_i ? LSE : LA;
+    auto ld_iw = [&](int e) -> IW {
+        IW r;
+        T *w = r.w;
+        const int J0 = e >> 1, J1 = J0 + 1;
+        const bool ok0 = col_upd && odd_i && e >= 1 && e <= n;
+        const bool ok1 = col_upd && e + 1 >= 1 && e + 1 <= n;
+        const bool ok2 = ok1 && odd_i;
+        const size_t c0 = ok0 ? (size_t)J0 * ldc + Ix : 0;
+        const size_t c1 = ok1 ? (size_t)J1 * ldc + (odd_i ? Ix : (i >> 1)) : 0;
+        w[0] = ok0 ? C.at(LL, c0) : (T)0;
+        w[1] = ok0 ? C.at(LR, c0) : (T)0;
+        w[2] = ok1 ? C.at(p2, c1) : (T)0;
+        w[3] = ok1 ? C.at(p3, c1) : (T)0;
+        w[4] = ok2 ? C.at(LNW, c1) : (T)0;
+        w[5] = ok2 ? C.at(LNE, c1) : (T)0;
+        return r;
+    };
+    // u' + P e_c at (i, row), e_c from the ring (the terms of post_tile)
+    auto interp = [&](int row, T u, const IW &iw) -> T {
+        const T *w = iw.w;
+        if (!col_upd || row < 1 || row > n) return u;
+        T e;
+        if (!(row & 1)) {
+            const T *er = sec + ((row >> 1) & 7) * CW;
+            if (!odd_i) e = er[(i >> 1) - ib];
+            else e = w[0] * er[Ix - 1 - ib] + w[1] * er[Ix - ib];
+        } else {
+            const int J = (row + 1) >> 1;
+            const T *es_ = sec + ((J - 1) & 7) * CW, *en = sec + (J & 7) * CW;
+            if (!odd_i) {
+                e = w[2] * es_[(i >> 1) - ib] + w[3] * en[(i >> 1) - ib];
+            } else {
+                e = w[2] * es_[Ix - 1 - ib] + w[3] * es_[Ix - ib];
+                e = e + w[4] * en[Ix - 1 - ib];
+                e = e + w[5] * en[Ix - ib];
+            }
+        }
+        return u + e;
+    };
+
+    // coarse rows of the first step's window and of the first two steps:
+    // (es-2NS-2)/2 .. es/2 + 1 (NS + 3 <= 8 rows)
+    for (int J = (es - 2 * NS - 2) >> 1; J <= (es >> 1) + 1; ++J) {
+        const T v = ld_crow(J);
+        if (lane < CW) sec[(J & 7) * CW + lane] = v;
+    }
+    __syncthreads();
+    // window of step es without its own two rows: rows es-2NS-2 .. es-1,
+    // interpolated, at positions 2..RW-1 (aligned by the first shift)
+#pragma unroll
+    for (int k = 2; k < RW; k += 2) {
+        const int row = es - 2 * NS - 4 + k;       // even
+        const IW wk = ld_iw(row);
+        su[slot<RU>(row) * FW + lane] = interp(row, ld_row(L.u, row), wk);
+        su[slot<RU>(row + 1) * FW + lane] = interp(row + 1, ld_row(L.u, row + 1), wk);
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            sW[slot<RU>(row + t) * FW + lane] = ld_row(L.W, row + t);
+            rO[k + t] = ld_row(L.O, row + t);
+            rS[k + t] = ld_row(L.S, row + t);
+            rB[k + t] = ld_row(L.b, row + t);
+        }
+    }
+    // the lumped row of this column at window row k (in-pass weights)
+    auto row9 = [&](int k, int row, T a[9]) {
+        const int r0 = slot<RU>(row) * FW + lane;
+        a[0] = (T)0;
+        a[1] = rS[k];
+        a[2] = (T)0;
+        a[3] = sW[r0];
+        a[4] = rO[k];
+        a[5] = sW[r0 + 1];
+        a[6] = (T)0;
+        a[7] = rS[k + 1];
+        a[8] = (T)0;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            if (q == 4) continue;
+            if (a[q] > (T)0) {
+                a[4] = a[4] + a[q];
+                a[q] = (T)0;
+            }
+        }
+    };
+    const int wl = lane >> 1;
+    const bool odd_col = i & 1;
+    T pLNE = 0, pLNW = 0, pLR = 0, pLL = 0, pLA = 0, yLB = 0, yLA = 0;
+    T w[8];
+
+    T pu0, pu1, pW0, pW1, pO0, pO1, pS0, pS1, pB0, pB1, pec;
+    IW pw;
+    // data of step e; the e_c row it adds is the one step e + 2 needs
+    auto fetch = [&](int e) {
+        pu0 = ld_row(L.u, e); pu1 = ld_row(L.u, e + 1);
+        pW0 = ld_row(L.W, e); pW1 = ld_row(L.W, e + 1);
+        pO0 = ld_row(L.O, e); pO1 = ld_row(L.O, e + 1);
+        pS0 = ld_row(L.S, e); pS1 = ld_row(L.S, e + 1);
+        pB0 = ld_row(L.b, e); pB1 = ld_row(L.b, e + 1);
+        pec = ld_crow((e >> 1) + 2);
+        pw = ld_iw(e);
+    };
+    fetch(es);
+    double acc = 0.0;
+
+    for (int e = es; e <= elast; e += 2) {
+        __syncthreads();  // the previous step is done with the slots reused below
+        if (lane < CW) sec[(((e >> 1) + 2) & 7) * CW + lane] = pec;
+#pragma unroll
+        for (int k = 0; k < RW - 2; ++k) { rO[k] = rO[k + 2]; rS[k] = rS[k + 2]; rB[k] = rB[k + 2]; }
+        rO[RW - 2] = pO0; rO[RW - 1] = pO1;
+        rS[RW - 2] = pS0; rS[RW - 1] = pS1;
+        rB[RW - 2] = pB0; rB[RW - 1] = pB1;
+        {
+            const int s0 = slot<RU>(e) * FW + lane, s1 = slot<RU>(e + 1) * FW + lane;
+            su[s0] = interp(e, pu0, pw);
+            su[s1] = interp(e + 1, pu1, pw);
+            sW[s0] = pW0; sW[s1] = pW1;
+        }
+        if (e + 2 <= elast) fetch(e + 2);
+        __syncthreads();
+        if (!odd_col) {
+            // y-edge of row e-2NS-1 (window row 1), as in pre_tile
+            const int row = e - 2 * NS - 1;
+            yLB = yLA = (T)0;
+            if (col_upd && row >= 1 && row <= n) {
+                T a[9];
+                row9(1, row, a);
+                const T D = (a[4] + a[3]) + a[5];
+                yLB = -((a[1] + a[0]) + a[2]) / D;
+                yLA = -((a[7] + a[6]) + a[8]) / D;
+            }
+            S.wy[wl] = yLB;
+            S.wy[FW / 2 + wl] = yLA;
+        }
+        // sweep 0 completes rows e and e-1 of u_k: written, and kept for the norm
+        five_point_sweeps<T, NS, RU>(su, sW, lane, i, col_upd, n, e, rB, rO, rS, [&](int s) {
+            if (s == 0) {
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    const int row = e - t;
+                    const T v = su[slot<RU>(row) * FW + lane];
+                    suk[(row & 3) * FW + lane] = v;
+                    if (col_own && row >= y0 && row < y1) ukout[(size_t)row * ld + i] = v;
+                }
+            }
+        });
+        // the last sweep's two rows are final: write the owned ones
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const int row = e - 2 * NS + 2 - t;
+            if (col_own && row >= y0 && row < y1)
+                uout[(size_t)row * ld + i] = su[slot<RU>(row) * FW + lane];
+        }
+        if (col_upd && odd_col) {
+            // x-edge of window row 2 and cell centre of window row 1
+            T a[9];
+            T xLL = (T)0, xLR = (T)0;
+            if (e - 2 * NS >= 1 && e - 2 * NS <= n) {
+                row9(2, e - 2 * NS, a);
+                const T D = (a[4] + a[7]) + a[1];
+                xLL = -((a[3] + a[6]) + a[0]) / D;
+                xLR = -((a[5] + a[8]) + a[2]) / D;
+            }
+            row9(1, e - 2 * NS - 1, a);
+            const T lbw = S.wy[wl - 1], law = S.wy[FW / 2 + wl - 1];
+            const T lbe = S.wy[wl], lae = S.wy[FW / 2 + wl];
+            const T cLNE = -((a[8] + a[7] * xLR) + a[5] * lae) / a[4];
+            const T cLNW = -((a[6] + a[7] * xLL) + a[3] * law) / a[4];
+            const T cLSE = -((a[2] + a[1] * pLR) + a[5] * lbe) / a[4];
+            const T cLSW = -((a[0] + a[1] * pLL) + a[3] * lbw) / a[4];
+            S.wx[wl] = pLNE;
+            S.wx[FW / 2 + wl] = pLNW;
+            S.wx[FW + wl] = pLR;
+            S.wx[3 * FW / 2 + wl] = pLL;
+            S.wx[2 * FW + wl] = cLSE;
+            S.wx[5 * FW / 2 + wl] = cLSW;
+            pLNE = cLNE; pLNW = cLNW; pLR = xLR; pLL = xLL;
+        }
+        // residual of rows e-2NS and e-2NS-1
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const int row = e - 2 * NS - t;
+            const int k = row - (e - 2 * NS - 2);
+            T r = 0;
+            if (col_upd && row >= 1 && row <= n)
+                r = res_lds<T, false, RU>(su, sW, nullptr, nullptr, lane, row, rB[k], rO[k], rS[k], rS[k + 1]);
+            sr[(row & 3) * FW + lane] = r;
+        }
+        __syncthreads();
+        if (restrictor) {
+            w[0] = S.wx[wl];
+            w[1] = pLA;
+            w[2] = S.wx[FW / 2 + wl + 1];
+            w[3] = S.wx[FW + wl];
+            w[4] = S.wx[3 * FW / 2 + wl + 1];
+            w[5] = S.wx[2 * FW + wl];
+            w[6] = yLB;
+            w[7] = S.wx[5 * FW / 2 + wl + 1];
+        }
+        if (!odd_col) pLA = yLA;
+        // restriction of coarse row J = (e - 2NS - 2) / 2 by the even columns
+        {
+            const int f = e - 2 * NS - 2, J = f >> 1;
+            if (restrictor && J >= 1 && J <= nc && f >= y0 && f < y1) {
+                const size_t c = (size_t)J * Cl.ld + I;
+                const T *rd = sr + ((f - 1) & 3) * FW + lane, *r0 = sr + (f & 3) * FW + lane,
+                        *ru = sr + ((f + 1) & 3) * FW + lane;
+                T s = w[0] * rd[-1];
+                s = s + w[1] * rd[0];
+                s = s + w[2] * rd[1];
+                s = s + w[3] * r0[-1];
+                s = s + r0[0];
+                s = s + w[4] * r0[1];
+                s = s + w[5] * ru[-1];
+                s = s + w[6] * ru[0];
+                s = s + w[7] * ru[1];
+                Cl.b[c] = s;
+                ucz[c] = (T)0;
+            }
+        }
+        // accurate residual of u_k at rows e-1 and e-2 (the terms of post_tile)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const int row = e - 1 - t;
+            const int k = row - (e - 2 * NS - 2);
+            if (col_own && row >= y0 && row < y1 && row >= 1) {
+                const int r0 = slot<RU>(row) * FW + lane;
+                const T *xd = suk + ((row - 1) & 3) * FW + lane, *x0_ = suk + (row & 3) * FW + lane,
+                        *xu = suk + ((row + 1) & 3) * FW + lane;
+                double a[5], x[5];
+                a[0] = rS[k];       x[0] = xd[0];
+                a[1] = sW[r0];      x[1] = x0_[-1];
+                a[2] = sW[r0 + 1];  x[2] = x0_[1];
+                a[3] = rS[k + 1];   x[3] = xu[0];
+                a[4] = rO[k];       x[4] = x0_[0];
+                double s = rB[k], cc = 0.0, ns, se;
+#pragma unroll
+                for (int q = 0; q < 5; ++q) {
+                    const double pr = a[q] * x[q];
+                    const double pe = fma(a[q], x[q], -pr);
+                    two_sum(s, -pr, ns, se);
+                    s = ns;
+                    cc = cc + (se - pe);
+                }
+                const double r = s + cc;
+                acc += r * r;
+            }
+        }
+    }
+    __syncthreads();  // the residual ring is free again: reduce through it
+    acc = block_sum(acc, reinterpret_cast<double *>(S.sx));
+    if (threadIdx.x == 0) part[tid] = acc;
+}
+
+template <int NB>
+__global__ __launch_bounds__(FW) void k_postpre(Lev<double> L, double *__restrict__ ukout, double *__restrict__ uout,
+                                                 Wts<double> C, const double *__restrict__ ec, Lev<double> Cl,
+                                                 double *__restrict__ ucz, TileGeo G, double *__restrict__ part,
+                                                 const int *stop)
+{
+    int tid, k;
+    if (!tile_work(G, tid, k)) return;
+    if (stopped(stop)) return;
+    __shared__ PostPreLds<NB> S;
+    postpre_tile<NB>(L, ukout, uout, C, ec, Cl, ucz, G, tid, part, S);
 }
 
 // The fine-level passes of an FP32 refinement step (IrArgs).  The post pass

@@ -997,6 +997,80 @@ static bmg_status cycle_and_norm(bmg_solver *h, double tol, int maxc, double ref
     return resnorm_dd(h, L.b, L.u, nullptr, 0, nullptr, S_SUMSQ, true, tol, maxc, refine);
 }
 
+// Plain FP64 cycles where the fine post pass of each cycle runs together with
+// the fine pre pass of the next (k_postpre): a five-point fine level with the
+// in-pass restriction weights, one post sweep and one or two pre sweeps.
+static bool postpre_ok(const bmg_solver *h)
+{
+    return !h->f32 && h->opt.kernels == BMG_KERNELS_FUSED && h->opt.smoother == BMG_SMOOTH_POINT && !h->nine[0] &&
+           BMG_FIVE_POINT_STEP_ROWS == 2 && h->nlev >= 2 && h->opt.nu2 == 1 && (h->opt.nu1 == 1 || h->opt.nu1 == 2) &&
+           pre_weights_in_pass<double>(h, 0, false);
+}
+
+// Rows per tile of k_postpre: two of its 72 KiB workgroups share a CU, so
+// the fewest warm-up rows with all tiles in one round of 512 (148 rows at
+// 4095^2: 18 strips x 28 tiles).
+static int postpre_tile_rows(const bmg_solver *h, int n, int hx)
+{
+    if (h->opt.tile_rows > 0) return h->opt.tile_rows;
+    const int useful = FW - 2 * hx;
+    const int strips = (n + useful - 1) / useful;
+    const int rows = std::max(1, 512 / strips);
+    return ((n + rows - 1) / rows + 1) & ~1;
+}
+
+// One plain FP64 cycle and its recorded norm on the k_postpre schedule.
+// *pending: the fine pre pass of this cycle already ran inside the last
+// k_postpre, its iterate in L0.r (free on this schedule).  Level 0 rotates
+// three buffers: the pass reads u' and writes u_k and the next u''; level 1
+// takes u_c = 0 in its second buffer, since e_c is read until the pass ends.
+static bmg_status cycle_and_norm_pp(bmg_solver *h, double tol, int maxc, double refine, bool *pending)
+{
+    Lev<double> &F = h->L[0];
+    Lev<double> &C1 = h->L[1];
+    const int nb = h->opt.nu1;
+    if (!*pending) TRY(fused_pre<double>(h, 0, nb, h->stop));
+    TRY(fused_cycle_from<double>(h, 1, h->stop, false));
+    // u_k goes where L0.u points once a pre pass is pending, so that L0.u
+    // keeps the last result when the stop flag makes later passes return
+    double *in = *pending ? F.r : F.u;
+    double *const bufs[3] = {F.u, h->ualt[0], F.r};
+    double *out[2];
+    int m = 0;
+    for (double *b : bufs)
+        if (b != in) out[m++] = b;
+    Lev<double> Fin = F;
+    Fin.u = in;
+    const int hx = 2 * (nb + 1) + 4;   // interpolation edge, sweeps, residual, restriction
+    const TileGeo g = tile_geo(F.n, hx, postpre_tile_rows(h, F.n, hx));
+    if (g.ntiles > NPART) return fail(BMG_EINVAL, "too many tiles for the norm partials");
+    const dim3 grid = tile_grid(g), blk(FW);
+    const double nf = (double)F.n * F.n, ncc = (double)C1.n * C1.n;
+    // stencil, b and u' read, u_k and u'' written; e_c and the 8 weight planes
+    // read, b_c and u_c written
+    trace_begin(h, BMG_TRACE_POSTPRE, 0, 8.0 * ((stencil_planes(false) + 4.0) * nf + 11.0 * ncc));
+    if (nb == 1)
+        hipLaunchKernelGGL((k_postpre<1>), grid, blk, 0, h->st, Fin, out[0], out[1], h->C[0], (const double *)C1.u, C1,
+                           h->ualt[1], g, h->part, h->stop);
+    else
+        hipLaunchKernelGGL((k_postpre<2>), grid, blk, 0, h->st, Fin, out[0], out[1], h->C[0], (const double *)C1.u, C1,
+                           h->ualt[1], g, h->part, h->stop);
+    trace_end(h, BMG_TRACE_POSTPRE, 0);
+    LAUNCHCHK();
+    F.u = out[0];
+    F.r = out[1];
+    h->ualt[0] = in;
+    std::swap(C1.u, h->ualt[1]);
+    *pending = true;
+    trace_begin(h, BMG_TRACE_RESNORM, 0, 8.0 * g.ntiles);
+    hipLaunchKernelGGL(k_sumsq_final, dim3(1), dim3(1024), 0, h->st, (const double *)h->part, g.ntiles,
+                       h->scal + S_SUMSQ, h->hist, h->count, h->stop, (const double *)(h->scal + S_BNORM), tol, maxc,
+                       refine);
+    trace_end(h, BMG_TRACE_RESNORM, 0);
+    LAUNCHCHK();
+    return BMG_OK;
+}
+
 // One FP64 refinement step: L0.b holds r, L0.u = 0; V-cycle, (XH, XL) += u
 // (inside the fine post pass where the cycle allows).
 static bmg_status refine_step64(bmg_solver *h, const int *stop)
@@ -1092,10 +1166,13 @@ bmg_status bmg_solve(bmg_solver *h, const double *rhs, double *x, double tol, bm
         HIPCHK(hipMemcpyAsync(L.b, h->B0, pl0, hipMemcpyDeviceToDevice, h->st));
         HIPCHK(hipMemcpyAsync(L.u, h->XH, pl0, hipMemcpyDeviceToDevice, h->st));
         const double refine = h->opt.refine_factor > 0 ? h->opt.refine_factor * tol : 0.0;
+        const bool pp = postpre_ok(h);
+        bool pending = false;
         while (true) {
             for (int t = 0; t < every; ++t) {
                 if (!refining) {
-                    TRY(cycle_and_norm(h, tol, maxc, refine));
+                    if (pp) TRY(cycle_and_norm_pp(h, tol, maxc, refine, &pending));
+                    else TRY(cycle_and_norm(h, tol, maxc, refine));
                 } else {
                     TRY(refine_step64(h, h->stop));
                     TRY(resnorm_dd(h, h->B0, h->XH, h->XL, 2, nullptr, S_SUMSQ, true, tol, maxc, 0.0));
@@ -1391,7 +1468,7 @@ extern "C" {
 bmg_status bmg_trace_enable(bmg_solver *h, int kclass, int level, int on)
 {
     if (!h) return fail(BMG_EINVAL, "NULL handle");
-    if (kclass < BMG_TRACE_SMOOTH || kclass > BMG_TRACE_RESNORM) return fail(BMG_EINVAL, "unknown class");
+    if (kclass < BMG_TRACE_SMOOTH || kclass > BMG_TRACE_POSTPRE) return fail(BMG_EINVAL, "unknown class");
     h->tr_class = on ? kclass : -1;
     h->tr_level = level;
     h->tr_used = 0;

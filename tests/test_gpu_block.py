@@ -45,8 +45,10 @@ def block_problem(n, k, seed, zero=()):
 @pytest.mark.parametrize("n,k,tile_rows", [(255, 5, 0), (127, 3, 6), (7, 2, 0)])
 def test_block_equals_single_solves(gpu, n, k, tile_rows):
     """Every right-hand side of a block (one of them zero, one with a nonzero
-    initial guess) equals its own bmg_solve: cycles, history, both parts of the
-    iterate."""
+    initial guess) equals its own bmg_solve: cycles and both parts of the
+    iterate bit for bit, history to 1e-12 (the norm's per-tile partial sums
+    follow the tiling of the pass that takes it: the block's post pass, or the
+    single solve's fused post and next pre pass)."""
     st, rhs = block_problem(n, k, 7, zero=(1,))
     x0 = torch.zeros_like(rhs)
     x0[k - 1] = dev(np.random.default_rng(5).uniform(-1e-3, 1e-3, size=(n, n)))
@@ -56,7 +58,8 @@ def test_block_equals_single_solves(gpu, n, k, tile_rows):
     for j in range(k):
         x1, i1 = S.solve(rhs[j].contiguous(), x0[j].clone(), tol=1e-10, raise_on_noconv=False)
         assert infos[j]["cycles"] == i1["cycles"], (j, infos[j]["cycles"], i1["cycles"])
-        assert infos[j]["history"] == i1["history"], j
+        h, h1 = np.array(infos[j]["history"]), np.array(i1["history"])
+        assert np.all(np.abs(h - h1) <= 1e-12 * h1), j
         assert infos[j]["status"] == i1["status"], j
         same(host(xb[j]), host(x1), f"rhs {j}")
     assert all(i["status"] == 0 for i in infos), [i["rel_res"] for i in infos]

@@ -372,6 +372,33 @@ def test_cycle_variants_match_oracle(gpu, kernels, nu1, nu2):
     assert np.all(np.abs(np.array(info["history"]) - hist) <= 1e-12 * hist)
 
 
+@pytest.mark.parametrize("kind,n,tile_rows,nu1", [("jump16", 511, 14, 2), ("lognormal", 1023, 0, 2),
+                                                  ("jump64", 511, 6, 1), ("poisson", 127, 0, 2)])
+def test_post_and_next_pre_fused_match_oracle(gpu, kind, n, tile_rows, nu1):
+    """Plain cycles with the fine post pass of each cycle and the fine pre pass
+    of the next run as one pass (k_postpre): the history of every cycle, both
+    parts of the solution and a second solve on the same handle equal the
+    oracle bit for bit, across several strips and ragged row tiles, and the
+    fused pass is the one that ran (its trace counts 7 fine and 11 coarse
+    values per point)."""
+    p = problem(kind, n, 17)
+    st, rhs = gpu_problem(p)
+    S = boxmg.Solver(st, nu1=nu1, nu2=1, max_cycles=80, tile_rows=tile_rows)
+    H = ref.Hierarchy(host(st), nu1, 1)
+    u, hist = H.solve(ref.pad(host(rhs)), tol=1e-10, max_cycles=80)
+    n1 = S.level_n(1)
+    for rep in range(2):
+        S.trace_enable("postpre", 0)
+        x, info = S.solve(rhs, tol=1e-10, raise_on_noconv=False)
+        nl, ms, nb = S.trace_read()
+        S.trace_enable("postpre", 0, on=False)
+        assert nl >= 1 and nb == nl * 8 * (7 * n * n + 11 * n1 * n1), (nl, nb)
+        assert info["cycles"] == len(hist)
+        same(host(x), u[1:-1, 1:-1], f"solution, solve {rep}")
+        same(host(S.export(0, "xlo")), H.xl, f"low part, solve {rep}")
+        assert np.all(np.abs(np.array(info["history"]) - hist) <= 1e-12 * hist)
+
+
 # --------------------------------------------------------------- batched solves
 def test_batch_matches_single_problem_oracle(gpu):
     """Problems of uneven sizes (7 .. 511, per-cell log-normal coefficients, as the
