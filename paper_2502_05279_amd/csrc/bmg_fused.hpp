@@ -339,9 +339,45 @@ __device__ __forceinline__ void pre_tile(const Lev<T> &L, T *__restrict__ uout, 
         }
     };
     fetch(es);
+    // restriction of the coarse row of step e (J = (e - 2NU - 2) / 2) by the
+    // even columns, from the residual ring and the weights of step e (in w, or
+    // with WREC in LDS); it runs after the next step's first barrier (or after
+    // the last step), before anything overwrites them
+    auto restrict_step = [&](int e) {
+        if (WREC && restrictor) {
+            // odd neighbours: i-1 at exchange index wl, i+1 at wl+1
+            w[0] = S.wx[wl];                  // LNE of the centre (i-1, f-1)
+            w[1] = pLA;                       // LA of the y-edge (i, f-1)
+            w[2] = S.wx[FW / 2 + wl + 1];     // LNW of the centre (i+1, f-1)
+            w[3] = S.wx[FW + wl];             // LR of the x-edge (i-1, f)
+            w[4] = S.wx[3 * FW / 2 + wl + 1]; // LL of the x-edge (i+1, f)
+            w[5] = S.wx[2 * FW + wl];         // LSE of the centre (i-1, f+1)
+            w[6] = yLB;                       // LB of the y-edge (i, f+1)
+            w[7] = S.wx[5 * FW / 2 + wl + 1]; // LSW of the centre (i+1, f+1)
+        }
+        if (WREC && !odd_col) pLA = yLA;
+        const int f = e - 2 * NU - 2, J = f >> 1;
+        if (restrictor && J >= 1 && J <= nc && f >= y0 && f < y1) {
+            const size_t c = (size_t)J * C.ld + I;
+            const T *rd = sr + ((f - 1) & 3) * FW + lane, *r0 = sr + (f & 3) * FW + lane,
+                    *ru = sr + ((f + 1) & 3) * FW + lane;
+            T s = w[0] * rd[-1];
+            s = s + w[1] * rd[0];
+            s = s + w[2] * rd[1];
+            s = s + w[3] * r0[-1];
+            s = s + r0[0];
+            s = s + w[4] * r0[1];
+            s = s + w[5] * ru[-1];
+            s = s + w[6] * ru[0];
+            s = s + w[7] * ru[1];
+            Cl.b[c] = s;
+            Cl.u[c] = (T)0;
+        }
+    };
 
     for (int e = es; e <= elast; e += 2) {
         __syncthreads();  // the previous step is done with the slots reused below
+        if (e > es) restrict_step(e - 2);
         {
             const int s0 = slot<RU>(e) * FW + lane, s1 = slot<RU>(e + 1) * FW + lane;
             su[s0] = pu0; su[s1] = pu1;
@@ -437,40 +473,9 @@ __device__ __forceinline__ void pre_tile(const Lev<T> &L, T *__restrict__ uout, 
                 r = res_lds<T, NINE, RU>(su, sW, sSW, sNW, lane, row, rB[k], rO[k], rS[k], rS[k + 1]);
             sr[(row & 3) * FW + lane] = r;
         }
-        __syncthreads();
-        if (WREC && restrictor) {
-            // odd neighbours: i-1 at exchange index wl, i+1 at wl+1
-            w[0] = S.wx[wl];                  // LNE of the centre (i-1, f-1)
-            w[1] = pLA;                       // LA of the y-edge (i, f-1)
-            w[2] = S.wx[FW / 2 + wl + 1];     // LNW of the centre (i+1, f-1)
-            w[3] = S.wx[FW + wl];             // LR of the x-edge (i-1, f)
-            w[4] = S.wx[3 * FW / 2 + wl + 1]; // LL of the x-edge (i+1, f)
-            w[5] = S.wx[2 * FW + wl];         // LSE of the centre (i-1, f+1)
-            w[6] = yLB;                       // LB of the y-edge (i, f+1)
-            w[7] = S.wx[5 * FW / 2 + wl + 1]; // LSW of the centre (i+1, f+1)
-        }
-        if (WREC && !odd_col) pLA = yLA;
-        // restriction of coarse row J = (e - 2NU - 2) / 2 by the even columns
-        {
-            const int f = e - 2 * NU - 2, J = f >> 1;
-            if (restrictor && J >= 1 && J <= nc && f >= y0 && f < y1) {
-                const size_t c = (size_t)J * C.ld + I;
-                const T *rd = sr + ((f - 1) & 3) * FW + lane, *r0 = sr + (f & 3) * FW + lane,
-                        *ru = sr + ((f + 1) & 3) * FW + lane;
-                T s = w[0] * rd[-1];
-                s = s + w[1] * rd[0];
-                s = s + w[2] * rd[1];
-                s = s + w[3] * r0[-1];
-                s = s + r0[0];
-                s = s + w[4] * r0[1];
-                s = s + w[5] * ru[-1];
-                s = s + w[6] * ru[0];
-                s = s + w[7] * ru[1];
-                Cl.b[c] = s;
-                Cl.u[c] = (T)0;
-            }
-        }
     }
+    __syncthreads();
+    restrict_step(elast);
 }
 
 template <typename T, bool NINE, int NU, bool WREC = false>
@@ -917,9 +922,44 @@ __device__ __forceinline__ void postpre_tile(const Lev<double> &L, double *__res
     };
     fetch(es);
     double acc = 0.0;
+    // restriction of the coarse row of step e (J = (e - 2NS - 2) / 2) by the
+    // even columns, from the residual ring and the weights step e left in LDS;
+    // it runs after the next step's first barrier (or after the last step),
+    // before anything overwrites them
+    auto restrict_step = [&](int e) {
+        if (restrictor) {
+            w[0] = S.wx[wl];
+            w[1] = pLA;
+            w[2] = S.wx[FW / 2 + wl + 1];
+            w[3] = S.wx[FW + wl];
+            w[4] = S.wx[3 * FW / 2 + wl + 1];
+            w[5] = S.wx[2 * FW + wl];
+            w[6] = yLB;
+            w[7] = S.wx[5 * FW / 2 + wl + 1];
+        }
+        if (!odd_col) pLA = yLA;
+        const int f = e - 2 * NS - 2, J = f >> 1;
+        if (restrictor && J >= 1 && J <= nc && f >= y0 && f < y1) {
+            const size_t c = (size_t)J * Cl.ld + I;
+            const T *rd = sr + ((f - 1) & 3) * FW + lane, *r0 = sr + (f & 3) * FW + lane,
+                    *ru = sr + ((f + 1) & 3) * FW + lane;
+            T s = w[0] * rd[-1];
+            s = s + w[1] * rd[0];
+            s = s + w[2] * rd[1];
+            s = s + w[3] * r0[-1];
+            s = s + r0[0];
+            s = s + w[4] * r0[1];
+            s = s + w[5] * ru[-1];
+            s = s + w[6] * ru[0];
+            s = s + w[7] * ru[1];
+            Cl.b[c] = s;
+            ucz[c] = (T)0;
+        }
+    };
 
     for (int e = es; e <= elast; e += 2) {
         __syncthreads();  // the previous step is done with the slots reused below
+        if (e > es) restrict_step(e - 2);
         if (lane < CW) sec[(((e >> 1) + 2) & 7) * CW + lane] = pec;
 #pragma unroll
         for (int k = 0; k < RW - 2; ++k) { rO[k] = rO[k + 2]; rS[k] = rS[k + 2]; rB[k] = rB[k + 2]; }
@@ -1002,38 +1042,6 @@ __device__ __forceinline__ void postpre_tile(const Lev<double> &L, double *__res
                 r = res_lds<T, false, RU>(su, sW, nullptr, nullptr, lane, row, rB[k], rO[k], rS[k], rS[k + 1]);
             sr[(row & 3) * FW + lane] = r;
         }
-        __syncthreads();
-        if (restrictor) {
-            w[0] = S.wx[wl];
-            w[1] = pLA;
-            w[2] = S.wx[FW / 2 + wl + 1];
-            w[3] = S.wx[FW + wl];
-            w[4] = S.wx[3 * FW / 2 + wl + 1];
-            w[5] = S.wx[2 * FW + wl];
-            w[6] = yLB;
-            w[7] = S.wx[5 * FW / 2 + wl + 1];
-        }
-        if (!odd_col) pLA = yLA;
-        // restriction of coarse row J = (e - 2NS - 2) / 2 by the even columns
-        {
-            const int f = e - 2 * NS - 2, J = f >> 1;
-            if (restrictor && J >= 1 && J <= nc && f >= y0 && f < y1) {
-                const size_t c = (size_t)J * Cl.ld + I;
-                const T *rd = sr + ((f - 1) & 3) * FW + lane, *r0 = sr + (f & 3) * FW + lane,
-                        *ru = sr + ((f + 1) & 3) * FW + lane;
-                T s = w[0] * rd[-1];
-                s = s + w[1] * rd[0];
-                s = s + w[2] * rd[1];
-                s = s + w[3] * r0[-1];
-                s = s + r0[0];
-                s = s + w[4] * r0[1];
-                s = s + w[5] * ru[-1];
-                s = s + w[6] * ru[0];
-                s = s + w[7] * ru[1];
-                Cl.b[c] = s;
-                ucz[c] = (T)0;
-            }
-        }
         // accurate residual of u_k at rows e-1 and e-2 (the terms of post_tile)
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
@@ -1063,6 +1071,8 @@ __device__ __forceinline__ void postpre_tile(const Lev<double> &L, double *__res
             }
         }
     }
+    __syncthreads();
+    restrict_step(elast);
     __syncthreads();  // the residual ring is free again: reduce through it
     acc = block_sum(acc, reinterpret_cast<double *>(S.sx));
     if (threadIdx.x == 0) part[tid] = acc;
