@@ -74,7 +74,9 @@ def test_fused_passes_4095(gpu, jumping4095):
 
 def test_first_cycles_4095(gpu, jumping4095):
     """Three cycles of the benchmark's solve (every level, the small-level
-    kernel, the norm fused into the last pass) equal the oracle's."""
+    kernel, the fine post pass run with the next cycle's fine pre pass and
+    the norm inside it, in the benchmark's launch configuration) equal the
+    oracle's."""
     p, kk, st, rhs, H = jumping4095
     S = boxmg.Solver(st, max_cycles=3, check_every=16)
     x, info = S.solve(rhs, tol=1e-10, raise_on_noconv=False)
