@@ -759,9 +759,10 @@ __global__ __launch_bounds__(FW) void k_post(Lev<T> L, T *__restrict__ uout, Wts
 // four-row LDS ring, from which the per-tile sum of squares of its accurate
 // residual goes to part[tile]; sweeps 1..NB give the next cycle's
 // pre-smoothed iterate u'' (written), whose residual is restricted with the
-// operator-induced weights computed in the pass, as in pre_tile.  Every value
-// is the one the two separate passes give.  u_c = 0 goes to a separate coarse
-// buffer (ucz), since the coarse correction e_c is still read by other tiles.
+// operator-induced weights computed in the pass, as in pre_tile.  Every array
+// value is the one the two separate passes give (the norm's partial sums follow
+// this pass's tiles).  u_c = 0 goes to a separate coarse buffer (ucz), since the
+// coarse correction e_c is still read by other tiles.
 template <int NB>
 struct PostPreLds {
     static constexpr int NS = NB + 1;

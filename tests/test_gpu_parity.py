@@ -373,7 +373,8 @@ def test_cycle_variants_match_oracle(gpu, kernels, nu1, nu2):
 
 
 @pytest.mark.parametrize("kind,n,tile_rows,nu1", [("jump16", 511, 14, 2), ("lognormal", 1023, 0, 2),
-                                                  ("jump64", 511, 6, 1), ("poisson", 127, 0, 2)])
+                                                  ("jump64", 511, 6, 1), ("poisson", 127, 0, 2),
+                                                  ("poisson", 7, 0, 2), ("jump16", 15, 0, 1)])
 def test_post_and_next_pre_fused_match_oracle(gpu, kind, n, tile_rows, nu1):
     """Plain cycles with the fine post pass of each cycle and the fine pre pass
     of the next run as one pass (k_postpre): the history of every cycle, both
