@@ -997,16 +997,6 @@ static bmg_status cycle_and_norm(bmg_solver *h, double tol, int maxc, double ref
     return resnorm_dd(h, L.b, L.u, nullptr, 0, nullptr, S_SUMSQ, true, tol, maxc, refine);
 }
 
-// Plain FP64 cycles where the fine post pass of each cycle runs together with
-// the fine pre pass of the next (k_postpre): a five-point fine level with the
-// in-pass restriction weights, one post sweep and one or two pre sweeps.
-static bool postpre_ok(const bmg_solver *h)
-{
-    return !h->f32 && h->opt.kernels == BMG_KERNELS_FUSED && h->opt.smoother == BMG_SMOOTH_POINT && !h->nine[0] &&
-           BMG_FIVE_POINT_STEP_ROWS == 2 && h->nlev >= 2 && h->opt.nu2 == 1 && (h->opt.nu1 == 1 || h->opt.nu1 == 2) &&
-           pre_weights_in_pass<double>(h, 0, false);
-}
-
 // Rows per tile of k_postpre: two of its 72 KiB workgroups share a CU, so
 // the fewest warm-up rows with all tiles in one round of 512 (148 rows at
 // 4095^2: 18 strips x 28 tiles).
@@ -1017,6 +1007,25 @@ static int postpre_tile_rows(const bmg_solver *h, int n, int hx)
     const int strips = (n + useful - 1) / useful;
     const int rows = std::max(1, 512 / strips);
     return ((n + rows - 1) / rows + 1) & ~1;
+}
+
+// Tiles of k_postpre on the fine level: halo for the interpolation edge, the
+// sweeps, the residual and the restriction.
+static TileGeo postpre_geo(const bmg_solver *h)
+{
+    const int hx = 2 * (h->opt.nu1 + 1) + 4;
+    return tile_geo(h->L[0].n, hx, postpre_tile_rows(h, h->L[0].n, hx));
+}
+
+// Plain FP64 cycles where the fine post pass of each cycle runs together with
+// the fine pre pass of the next (k_postpre): a five-point fine level with the
+// in-pass restriction weights, one post sweep and one or two pre sweeps, and
+// at most NPART tiles (their norm partials).
+static bool postpre_ok(const bmg_solver *h)
+{
+    return !h->f32 && h->opt.kernels == BMG_KERNELS_FUSED && h->opt.smoother == BMG_SMOOTH_POINT && !h->nine[0] &&
+           BMG_FIVE_POINT_STEP_ROWS == 2 && h->nlev >= 2 && h->opt.nu2 == 1 && (h->opt.nu1 == 1 || h->opt.nu1 == 2) &&
+           pre_weights_in_pass<double>(h, 0, false) && postpre_geo(h).ntiles <= NPART;
 }
 
 // One plain FP64 cycle and its recorded norm on the k_postpre schedule.
@@ -1041,9 +1050,7 @@ static bmg_status cycle_and_norm_pp(bmg_solver *h, double tol, int maxc, double 
         if (b != in) out[m++] = b;
     Lev<double> Fin = F;
     Fin.u = in;
-    const int hx = 2 * (nb + 1) + 4;   // interpolation edge, sweeps, residual, restriction
-    const TileGeo g = tile_geo(F.n, hx, postpre_tile_rows(h, F.n, hx));
-    if (g.ntiles > NPART) return fail(BMG_EINVAL, "too many tiles for the norm partials");
+    const TileGeo g = postpre_geo(h);
     const dim3 grid = tile_grid(g), blk(FW);
     const double nf = (double)F.n * F.n, ncc = (double)C1.n * C1.n;
     // stencil, b and u' read, u_k and u'' written; e_c and the 8 weight planes
