@@ -609,15 +609,29 @@ static __global__ void k_round_f32(const double *__restrict__ src, float *__rest
 }
 
 // -------------------------------------------- FP64 iterative refinement
-// Largest of np partial maxima of |r| -> out[0].
+// Maximum over the block (up to 16 waves); result valid in thread 0.
+__device__ __forceinline__ double block_max(double m)
+{
+    __shared__ double sm[16];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_down(m, o, 64));
+    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, sm[w]);
+    return m;
+}
+
+// Largest of np partial maxima of |r| -> out[0] (a maximum: the same value in
+// any order of reduction).
 static __global__ void k_absmax_final(const double *__restrict__ part, int np, double *__restrict__ out,
                                const int *stop)
 {
     if (stopped(stop)) return;
-    if (threadIdx.x != 0) return;
     double m = 0.0;
-    for (int t = 0; t < np; ++t) m = fmax(m, part[t]);
-    out[0] = m;
+    for (int t = threadIdx.x; t < np; t += blockDim.x) m = fmax(m, part[t]);
+    m = block_max(m);
+    if (threadIdx.x == 0) out[0] = m;
 }
 
 // Exponent e of the scale 2^e: the least power of two >= rmax (1 for rmax = 0).
@@ -662,18 +676,6 @@ __device__ __forceinline__ void two_sum(double a, double b, double &s, double &e
 // MODE 0: sum of squares only; 1: also r -> rout; 2: also r -> L.b and 0 -> L.u
 // (the next refinement cycle starts from zero on the right-hand side r).
 
-// Maximum over the block (up to 16 waves); result valid in thread 0.
-__device__ __forceinline__ double block_max(double m)
-{
-    __shared__ double sm[16];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_down(m, o, 64));
-    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
-    __syncthreads();
-    if (threadIdx.x == 0)
-        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, sm[w]);
-    return m;
-}
 
 // Row block rb of nrb (rows 1 + rb, 1 + rb + nrb, ...): the sum of squares of
 // r into part[rb] and, with MODE 1 (the refinement of the FP32 cycle, which
