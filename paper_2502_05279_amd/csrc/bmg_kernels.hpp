@@ -608,6 +608,28 @@ static __global__ void k_round_f32(const double *__restrict__ src, float *__rest
         dst[t] = (float)src[t];
 }
 
+// Up to ROUND_MAX arrays rounded to FP32 in one launch (a hierarchy's
+// planes): blockIdx.y selects the array.
+constexpr int ROUND_MAX = 96;
+struct RoundList {
+    int n;
+    const double *src[ROUND_MAX];
+    float *dst[ROUND_MAX];
+    size_t count[ROUND_MAX];
+};
+
+static __global__ void k_round_f32_list(RoundList R)
+{
+    const int a = blockIdx.y;
+    if (a >= R.n) return;
+    const double *__restrict__ src = R.src[a];
+    float *__restrict__ dst = R.dst[a];
+    const size_t count = R.count[a];
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < count;
+         t += (size_t)gridDim.x * blockDim.x)
+        dst[t] = (float)src[t];
+}
+
 // -------------------------------------------- FP64 iterative refinement
 // Maximum over the block (up to 16 waves); result valid in thread 0.
 __device__ __forceinline__ double block_max(double m)

@@ -890,22 +890,38 @@ bmg_status bmg_setup(bmg_solver **out, const double *stencil, int n, int kind, c
         }
     }
     if (h->f32) {
+        // the FP32 hierarchy: every plane and weight array rounded, in one
+        // launch per list of arrays (the small levels would otherwise be
+        // dozens of launches of a few microseconds each)
+        RoundList R{};
+        size_t most = 0;
+        auto flush = [&]() {
+            if (R.n == 0) return;
+            const dim3 g((unsigned)std::min<size_t>((most + 255) / 256, 1024), (unsigned)R.n), b(256);
+            hipLaunchKernelGGL(k_round_f32_list, g, b, 0, h->st, R);
+            R.n = 0;
+            most = 0;
+        };
+        auto add = [&](const double *src, float *dst, size_t count) {
+            if (R.n == ROUND_MAX) flush();
+            R.src[R.n] = src;
+            R.dst[R.n] = dst;
+            R.count[R.n] = count;
+            ++R.n;
+            most = std::max(most, count);
+        };
         for (int l = 0; l < h->nlev; ++l) {
             const size_t pl = (size_t)(h->L[l].n + 2) * h->L[l].ld;
-            const dim3 g(std::min<size_t>((pl + 255) / 256, 4096)), b(256);
-            hipLaunchKernelGGL(k_round_f32, g, b, 0, h->st, h->L[l].O, h->L32[l].O, pl);
-            hipLaunchKernelGGL(k_round_f32, g, b, 0, h->st, h->L[l].W, h->L32[l].W, pl);
-            hipLaunchKernelGGL(k_round_f32, g, b, 0, h->st, h->L[l].S, h->L32[l].S, pl);
+            add(h->L[l].O, h->L32[l].O, pl);
+            add(h->L[l].W, h->L32[l].W, pl);
+            add(h->L[l].S, h->L32[l].S, pl);
             if (h->nine[l]) {
-                hipLaunchKernelGGL(k_round_f32, g, b, 0, h->st, h->L[l].SW, h->L32[l].SW, pl);
-                hipLaunchKernelGGL(k_round_f32, g, b, 0, h->st, h->L[l].NW, h->L32[l].NW, pl);
+                add(h->L[l].SW, h->L32[l].SW, pl);
+                add(h->L[l].NW, h->L32[l].NW, pl);
             }
-            if (l + 1 < h->nlev) {
-                const size_t cp = 8 * h->C[l].ps;
-                hipLaunchKernelGGL(k_round_f32, dim3(std::min<size_t>((cp + 255) / 256, 4096)), b, 0, h->st,
-                                   h->C[l].p, h->C32[l].p, cp);
-            }
+            if (l + 1 < h->nlev) add(h->C[l].p, h->C32[l].p, 8 * h->C[l].ps);
         }
+        flush();
     }
     if (hipGetLastError() != hipSuccess) return bail(fail(BMG_EDEVICE, "set-up kernel launch failed"));
     int flags = 0;
