@@ -9,7 +9,8 @@
  * listed in the design notes: vertex-centred five-point discretisation,
  * operator-induced (collapsed-stencil) interpolation, Galerkin coarse operators
  * P^T A P, four-colour Gauss-Seidel, and a square-root-free Cholesky (LDL^T)
- * on the coarsest 3x3 grid.
+ * of the band matrix of the coarsest grid (3x3 unless set-up asks for a larger
+ * one).
  *
  * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
  * benchmark's CPU-baseline leg load this library.  It shares no source with the
@@ -474,73 +475,94 @@ int orc_rap(int nf, const double *O, const double *W, const double *S,
 }
 
 /* ----------------------------------------- a3/a7: coarsest direct solve */
-/* Dense matrix of a 3x3-interior level (unknown k = (i-1) + 3(j-1)), built from
- * the compact stencil with the symmetric partners read from the neighbours. */
-static void dense_3x3(const double *O, const double *W, const double *S,
-                      const double *SW, const double *NW, double *A)
+/* The coarsest level is solved directly (Fig. vcycle_flowchart: a Cholesky
+ * factorisation; Section 2: a direct solve on a small system).  Its n_L x n_L
+ * interior unknowns are numbered lexicographically, k = (i-1) + n_L (j-1), so
+ * the nine-point matrix is a band matrix of half-bandwidth w = n_L + 1 and
+ * its Cholesky factor has no entries outside that band.
+ *
+ * Band storage of the lower triangle: row i keeps A_ik for k = i-w .. i at
+ * Ab[i (w+1) + (k - i + w)] (diagonal last), entries with k < 0 zero.  The
+ * factor keeps L_ik for k = i-w .. i-1 at Lb[i w + (k - i + w)] (the unit
+ * diagonal is implicit) and D_i at D[i]. */
+static void coarse_band_matrix(int nc, const double *O, const double *W, const double *S,
+                               const double *SW, const double *NW, double *Ab)
 {
-    const size_t ld = 5;
-    memset(A, 0, 81 * sizeof(double));
-    for (int j = 1; j <= 3; ++j) {
-        for (int i = 1; i <= 3; ++i) {
+    const size_t ld = (size_t)nc + 2;
+    const int w = nc + 1, m = nc * nc;
+    memset(Ab, 0, (size_t)m * (size_t)(w + 1) * sizeof(double));
+    for (int j = 1; j <= nc; ++j) {
+        for (int i = 1; i <= nc; ++i) {
             const size_t p = (size_t)j * ld + (size_t)i;
-            const int k = (i - 1) + 3 * (j - 1);
-            const double ent[9] = {
-                SW ? SW[p] : 0.0, S[p], NW ? NW[p + 1 - ld] : 0.0,
-                W[p], O[p], W[p + 1],
-                NW ? NW[p] : 0.0, S[p + ld], SW ? SW[p + ld + 1] : 0.0};
-            for (int e = 0; e < 9; ++e) {
-                const int qi = i + (e % 3) - 1, qj = j + (e / 3) - 1;
-                if (qi < 1 || qi > 3 || qj < 1 || qj > 3) continue;
-                A[k * 9 + (qi - 1) + 3 * (qj - 1)] = ent[e];
+            const int k = (i - 1) + nc * (j - 1);
+            /* the row's couplings to unknowns numbered before it, and A_kk:
+             * SW, S, SE (the NW entry of the point below-right), W, O */
+            const double ent[5] = {SW ? SW[p] : 0.0, S[p], NW ? NW[p + 1 - ld] : 0.0, W[p], O[p]};
+            const int di[5] = {-1, 0, 1, -1, 0}, dj[5] = {-1, -1, -1, 0, 0};
+            for (int e = 0; e < 5; ++e) {
+                const int qi = i + di[e], qj = j + dj[e];
+                if (qi < 1 || qi > nc || qj < 1 || qj > nc) continue;
+                const int q = (qi - 1) + nc * (qj - 1);
+                Ab[(size_t)k * (w + 1) + (size_t)(q - k + w)] = ent[e];
             }
         }
     }
 }
 
-/* Square-root-free Cholesky A = L D L^T of a dense SPD matrix (the coarsest
- * solve of Fig. vcycle_flowchart is a Cholesky factorisation; this form
- * needs only +, -, *, / so that it rounds identically everywhere).
- *   w_k = L_jk D_k;  D_j = A_jj - sum_{k<j} L_jk w_k;
- *   L_ij = (A_ij - sum_{k<j} L_ik w_k) / D_j,  sums in increasing k.
- * L is unit lower triangular, stored row-major with zeros above. */
-int orc_ldlt_factor(int m, const double *A, double *L, double *D)
+/* Square-root-free Cholesky A = L D L^T of an SPD band matrix (m unknowns,
+ * half-bandwidth w), column by column (the form needs only +, -, *, /, so it
+ * rounds identically everywhere):
+ *   v_k  = L_jk D_k                                   (k = j-w .. j-1)
+ *   D_j  = A_jj - sum_k L_jk v_k                      (k increasing)
+ *   L_ij = (A_ij - sum_k L_ik v_k) / D_j,  i = j+1 .. j+w, k = i-w .. j-1 increasing.
+ * Returns ORC_EBREAKDOWN if a pivot is not positive. */
+int orc_band_ldlt_factor(int m, int w, const double *Ab, double *Lb, double *D)
 {
-    double w[64];
-    if (m > 64) return ORC_EINVAL;
-    memset(L, 0, (size_t)m * m * sizeof(double));
-    for (int j = 0; j < m; ++j) {
-        for (int k = 0; k < j; ++k) w[k] = L[j * m + k] * D[k];
-        double s = A[j * m + j];
-        for (int k = 0; k < j; ++k) s = s - L[j * m + k] * w[k];
-        if (!(s > 0.0)) return ORC_EBREAKDOWN;
+    if (m < 1 || w < 1) return ORC_EINVAL;
+    double *v = (double *)malloc((size_t)m * sizeof(double));
+    if (!v) return ORC_ENOMEM;
+    memset(Lb, 0, (size_t)m * (size_t)w * sizeof(double));
+#define AB(i, k) Ab[(size_t)(i) * (w + 1) + (size_t)((k) - (i) + w)]
+#define LB(i, k) Lb[(size_t)(i) * w + (size_t)((k) - (i) + w)]
+    int st = ORC_OK;
+    for (int j = 0; j < m && st == ORC_OK; ++j) {
+        const int k0 = j - w > 0 ? j - w : 0;
+        for (int k = k0; k < j; ++k) v[k] = LB(j, k) * D[k];
+        double s = AB(j, j);
+        for (int k = k0; k < j; ++k) s = s - LB(j, k) * v[k];
+        if (!(s > 0.0)) st = ORC_EBREAKDOWN;
         D[j] = s;
-        L[j * m + j] = 1.0;
-        for (int i = j + 1; i < m; ++i) {
-            double t = A[i * m + j];
-            for (int k = 0; k < j; ++k) t = t - L[i * m + k] * w[k];
-            L[i * m + j] = t / s;
+        const int i1 = j + w < m - 1 ? j + w : m - 1;
+        for (int i = j + 1; i <= i1; ++i) {
+            double t = AB(i, j);
+            for (int k = i - w > 0 ? i - w : 0; k < j; ++k) t = t - LB(i, k) * v[k];
+            LB(i, j) = t / s;
         }
     }
-    return ORC_OK;
+    free(v);
+    return st;
 }
 
-/* Forward substitution y_i = b_i - sum_{k<i} L_ik y_k, scaling z_i = y_i / D_i,
- * back substitution x_i = z_i - sum_{k>i} L_ki x_k (k increasing). */
-void orc_ldlt_solve(int m, const double *L, const double *D, const double *b, double *x)
+/* Solve with the band factor, both triangles in column (axpy) form: once an
+ * unknown is final, its multiples are removed from the pending right-hand
+ * sides of the unknowns it couples to.
+ *   forward:  y = b; for j = 0 .. m-1: y_i -= L_ij y_j   (i = j+1 .. j+w)
+ *   scaling:  z_i = y_i / D_i
+ *   backward: x = z; for k = m-1 .. 0: x_i -= L_ki x_k   (i = k-w .. k-1)
+ * so y_i sums its terms with j increasing and x_i with k decreasing. */
+void orc_band_ldlt_solve(int m, int w, const double *Lb, const double *D, const double *b, double *x)
 {
-    double y[64];
-    for (int i = 0; i < m; ++i) {
-        double s = b[i];
-        for (int k = 0; k < i; ++k) s = s - L[i * m + k] * y[k];
-        y[i] = s;
+    for (int i = 0; i < m; ++i) x[i] = b[i];
+    for (int j = 0; j < m; ++j) {
+        const int i1 = j + w < m - 1 ? j + w : m - 1;
+        for (int i = j + 1; i <= i1; ++i) x[i] = x[i] - LB(i, j) * x[j];
     }
-    for (int i = 0; i < m; ++i) y[i] = y[i] / D[i];
-    for (int i = m - 1; i >= 0; --i) {
-        double s = y[i];
-        for (int k = i + 1; k < m; ++k) s = s - L[k * m + i] * x[k];
-        x[i] = s;
+    for (int i = 0; i < m; ++i) x[i] = x[i] / D[i];
+    for (int k = m - 1; k >= 0; --k) {
+        for (int i = k - w > 0 ? k - w : 0; i < k; ++i) x[i] = x[i] - LB(k, i) * x[k];
     }
+#undef AB
+#undef LB
 }
 
 /* ------------------------------------------------------------ a9: norms */
@@ -620,7 +642,10 @@ typedef struct {
     float *fO[ORC_MAXL], *fW[ORC_MAXL], *fS[ORC_MAXL], *fSW[ORC_MAXL], *fNW[ORC_MAXL];
     float *fCi[ORC_MAXL], *fu[ORC_MAXL], *fb[ORC_MAXL], *fr[ORC_MAXL];
     int have_f32;
-    double Lc[81], Dc[9];
+    /* band LDL^T factor of the coarsest level: m = n_L^2 unknowns,
+     * half-bandwidth w = n_L + 1 */
+    double *Lb, *Db;
+    int cm, cw;
     int nu1, nu2;
     /* line relaxation instead of point Gauss-Seidel: factors of every line */
     int line;
@@ -642,6 +667,8 @@ void orc_destroy(orc_hier *H)
         free(H->fCi[l]); free(H->fu[l]); free(H->fb[l]); free(H->fr[l]);
         free(H->lx[l]); free(H->rx[l]); free(H->ly[l]); free(H->ry[l]);
     }
+    free(H->Lb);
+    free(H->Db);
     free(H);
 }
 
@@ -667,25 +694,30 @@ double *orc_field(orc_hier *H, int l, int field)
     }
 }
 
-void orc_coarse_factor(const orc_hier *H, double *L81, double *D9)
+/* The coarsest factor: m w entries of L (band storage, see above), then m of
+ * D.  *m and *w (nullable) receive the sizes. */
+void orc_coarse_factor(const orc_hier *H, double *Lb, double *D, int *m, int *w)
 {
-    memcpy(L81, H->Lc, sizeof H->Lc);
-    memcpy(D9, H->Dc, sizeof H->Dc);
+    if (Lb) memcpy(Lb, H->Lb, (size_t)H->cm * (size_t)H->cw * sizeof(double));
+    if (D) memcpy(D, H->Db, (size_t)H->cm * sizeof(double));
+    if (m) *m = H->cm;
+    if (w) *w = H->cw;
 }
 
 /* Setup: copy the fine operator from the [n][n][K] stencil (K=5: S,W,O,E,N;
  * K=9: SW,S,SE,W,O,E,NW,N,NE) into compact form, then per level form the
- * interpolation weights and the Galerkin coarse operator, down to 3x3, and
+ * interpolation weights and the Galerkin coarse operator, down to the
+ * coarsest level of nc points per side (nc = 2^k - 1, 3 <= nc <= n), and
  * factor the coarsest matrix.  *status receives the first failure. */
-orc_hier *orc_setup(int n, int K, const double *st, int nu1, int nu2, int *status)
+orc_hier *orc_setup(int n, int K, const double *st, int nu1, int nu2, int nc, int *status)
 {
     *status = ORC_EINVAL;
-    if (!valid_n(n) || (K != 5 && K != 9)) return NULL;
+    if (!valid_n(n) || (K != 5 && K != 9) || !valid_n(nc) || nc > n) return NULL;
     orc_hier *H = (orc_hier *)calloc(1, sizeof(orc_hier));
     if (!H) { *status = ORC_ENOMEM; return NULL; }
     H->nu1 = nu1; H->nu2 = nu2;
     int nl = 0;
-    for (int m = n; m >= 3; m = (m - 1) / 2) H->n[nl++] = m;
+    for (int m = n; m >= nc; m = (m - 1) / 2) H->n[nl++] = m;
     H->nlev = nl;
     for (int l = 0; l < nl; ++l) {
         const size_t sz = (size_t)(H->n[l] + 2) * (size_t)(H->n[l] + 2);
@@ -717,10 +749,16 @@ orc_hier *orc_setup(int n, int K, const double *st, int nu1, int nu2, int *statu
         orc_rap(H->n[l], H->O[l], H->W[l], H->S[l], H->SW[l], H->NW[l], H->Ci[l],
                 H->O[l + 1], H->W[l + 1], H->S[l + 1], H->SW[l + 1], H->NW[l + 1]);
     }
-    double A[81];
     const int L = nl - 1;
-    dense_3x3(H->O[L], H->W[L], H->S[L], H->SW[L], H->NW[L], A);
-    int st_c = orc_ldlt_factor(9, A, H->Lc, H->Dc);
+    H->cm = nc * nc;
+    H->cw = nc + 1;
+    double *Ab = (double *)calloc((size_t)H->cm * (size_t)(H->cw + 1), sizeof(double));
+    H->Lb = zalloc((size_t)H->cm * (size_t)H->cw);
+    H->Db = zalloc((size_t)H->cm);
+    if (!Ab || !H->Lb || !H->Db) { free(Ab); *status = ORC_ENOMEM; orc_destroy(H); return NULL; }
+    coarse_band_matrix(nc, H->O[L], H->W[L], H->S[L], H->SW[L], H->NW[L], Ab);
+    int st_c = orc_band_ldlt_factor(H->cm, H->cw, Ab, H->Lb, H->Db);
+    free(Ab);
     if (st_c != ORC_OK) { *status = st_c; orc_destroy(H); return NULL; }
     *status = ORC_OK;
     return H;
@@ -780,28 +818,37 @@ int orc_make_f32(orc_hier *H)
     return ORC_OK;
 }
 
-/* Direct solve on the coarsest 3x3 level: u_L = A_L^{-1} b_L. */
+/* Direct solve on the coarsest level: u_L = A_L^{-1} b_L with the band factor. */
 static void coarse_solve_d(orc_hier *H)
 {
-    const int L = H->nlev - 1;
-    double rhs[9], x[9];
-    for (int j = 1; j <= 3; ++j)
-        for (int i = 1; i <= 3; ++i) rhs[(i - 1) + 3 * (j - 1)] = H->b[L][j * 5 + i];
-    orc_ldlt_solve(9, H->Lc, H->Dc, rhs, x);
-    for (int j = 1; j <= 3; ++j)
-        for (int i = 1; i <= 3; ++i) H->u[L][j * 5 + i] = x[(i - 1) + 3 * (j - 1)];
+    const int L = H->nlev - 1, nc = H->n[L];
+    const size_t ld = (size_t)nc + 2;
+    double *rhs = (double *)calloc((size_t)H->cm, sizeof(double));
+    double *x = (double *)calloc((size_t)H->cm, sizeof(double));
+    for (int j = 1; j <= nc; ++j)
+        for (int i = 1; i <= nc; ++i) rhs[(i - 1) + nc * (j - 1)] = H->b[L][(size_t)j * ld + (size_t)i];
+    orc_band_ldlt_solve(H->cm, H->cw, H->Lb, H->Db, rhs, x);
+    for (int j = 1; j <= nc; ++j)
+        for (int i = 1; i <= nc; ++i) H->u[L][(size_t)j * ld + (size_t)i] = x[(i - 1) + nc * (j - 1)];
+    free(rhs);
+    free(x);
 }
 
 /* The coarsest solve of the FP32 cycle stays in FP64: widen, solve, round. */
 static void coarse_solve_f(orc_hier *H)
 {
-    const int L = H->nlev - 1;
-    double rhs[9], x[9];
-    for (int j = 1; j <= 3; ++j)
-        for (int i = 1; i <= 3; ++i) rhs[(i - 1) + 3 * (j - 1)] = (double)H->fb[L][j * 5 + i];
-    orc_ldlt_solve(9, H->Lc, H->Dc, rhs, x);
-    for (int j = 1; j <= 3; ++j)
-        for (int i = 1; i <= 3; ++i) H->fu[L][j * 5 + i] = (float)x[(i - 1) + 3 * (j - 1)];
+    const int L = H->nlev - 1, nc = H->n[L];
+    const size_t ld = (size_t)nc + 2;
+    double *rhs = (double *)calloc((size_t)H->cm, sizeof(double));
+    double *x = (double *)calloc((size_t)H->cm, sizeof(double));
+    for (int j = 1; j <= nc; ++j)
+        for (int i = 1; i <= nc; ++i)
+            rhs[(i - 1) + nc * (j - 1)] = (double)H->fb[L][(size_t)j * ld + (size_t)i];
+    orc_band_ldlt_solve(H->cm, H->cw, H->Lb, H->Db, rhs, x);
+    for (int j = 1; j <= nc; ++j)
+        for (int i = 1; i <= nc; ++i) H->fu[L][(size_t)j * ld + (size_t)i] = (float)x[(i - 1) + nc * (j - 1)];
+    free(rhs);
+    free(x);
 }
 
 /* V(nu1,nu2) cycle from level l (Fig. vcycle_flowchart): relax, form the

@@ -46,10 +46,10 @@ def lib():
         L.orc_interp_weights.restype = C.c_int
         L.orc_rap.argtypes = [C.c_int] + [_dp] * 11
         L.orc_rap.restype = C.c_int
-        L.orc_ldlt_factor.argtypes = [C.c_int, _dp, _dp, _dp]
-        L.orc_ldlt_factor.restype = C.c_int
-        L.orc_ldlt_solve.argtypes = [C.c_int, _dp, _dp, _dp, _dp]
-        L.orc_ldlt_solve.restype = None
+        L.orc_band_ldlt_factor.argtypes = [C.c_int, C.c_int, _dp, _dp, _dp]
+        L.orc_band_ldlt_factor.restype = C.c_int
+        L.orc_band_ldlt_solve.argtypes = [C.c_int, C.c_int, _dp, _dp, _dp, _dp]
+        L.orc_band_ldlt_solve.restype = None
         L.orc_sumsq.argtypes = [C.c_int, _dp]
         L.orc_sumsq.restype = C.c_double
         for nm, p in (("orc_gs", _dp), ("orc_gs_f", _fp)):
@@ -65,7 +65,7 @@ def lib():
             fn = getattr(L, nm)
             fn.argtypes = [C.c_int, p, p, p]
             fn.restype = None
-        L.orc_setup.argtypes = [C.c_int, C.c_int, _dp, C.c_int, C.c_int, C.POINTER(C.c_int)]
+        L.orc_setup.argtypes = [C.c_int, C.c_int, _dp, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int)]
         L.orc_setup.restype = C.c_void_p
         L.orc_destroy.argtypes = [C.c_void_p]
         L.orc_destroy.restype = None
@@ -75,7 +75,7 @@ def lib():
         L.orc_level_n.restype = C.c_int
         L.orc_field.argtypes = [C.c_void_p, C.c_int, C.c_int]
         L.orc_field.restype = _dp
-        L.orc_coarse_factor.argtypes = [C.c_void_p, _dp, _dp]
+        L.orc_coarse_factor.argtypes = [C.c_void_p, _dp, _dp, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.orc_coarse_factor.restype = None
         L.orc_vcycle.argtypes = [C.c_void_p, _dp, _dp]
         L.orc_vcycle.restype = None
@@ -166,21 +166,62 @@ def rap(O, W, S, SW, NW, Ci):
     return tuple(out)
 
 
-def ldlt_factor(A: np.ndarray):
+def band_of(A: np.ndarray, w: int) -> np.ndarray:
+    """Lower band of a symmetric matrix in the oracle's band storage: row i holds
+    A[i, k] for k = i-w .. i at column k - i + w (zeros before the first row)."""
     m = A.shape[0]
-    L = np.zeros((m, m))
+    Ab = np.zeros((m, w + 1))
+    for i in range(m):
+        for k in range(max(0, i - w), i + 1):
+            Ab[i, k - i + w] = A[i, k]
+    return Ab
+
+
+def band_to_dense(Lb: np.ndarray) -> np.ndarray:
+    """Unit lower triangular L from its band storage ``Lb[i, k - i + w] = L[i, k]``."""
+    m, w = Lb.shape
+    L = np.eye(m)
+    for i in range(m):
+        for k in range(max(0, i - w), i):
+            L[i, k] = Lb[i, k - i + w]
+    return L
+
+
+def band_ldlt_factor(Ab: np.ndarray):
+    """Square-root-free Cholesky of a band matrix: ``(Lb, D)`` in band storage."""
+    m, w1 = Ab.shape
+    w = w1 - 1
+    Lb = np.zeros((m, w))
     D = np.zeros(m)
-    s = lib().orc_ldlt_factor(m, _p(_c(A)), _p(L), _p(D))
+    s = lib().orc_band_ldlt_factor(m, w, _p(_c(Ab)), _p(Lb), _p(D))
     if s:
-        raise OracleError(s, "ldlt_factor")
-    return L, D
+        raise OracleError(s, "band_ldlt_factor")
+    return Lb, D
+
+
+def band_ldlt_solve(Lb, D, b):
+    m, w = Lb.shape
+    x = np.zeros(m)
+    lib().orc_band_ldlt_solve(m, w, _p(_c(Lb)), _p(_c(D)), _p(_c(b)), _p(x))
+    return x
+
+
+def ldlt_factor(A: np.ndarray):
+    """Factor of a dense SPD matrix (the band routine with w = m - 1):
+    ``(L, D)`` with L unit lower triangular."""
+    m = A.shape[0]
+    Lb, D = band_ldlt_factor(band_of(A, max(m - 1, 1)))
+    return band_to_dense(Lb), D
 
 
 def ldlt_solve(L, D, b):
     m = L.shape[0]
-    x = np.zeros(m)
-    lib().orc_ldlt_solve(m, _p(_c(L)), _p(_c(D)), _p(_c(b)), _p(x))
-    return x
+    w = max(m - 1, 1)
+    Lb = np.zeros((m, w))
+    for i in range(m):
+        for k in range(max(0, i - w), i):
+            Lb[i, k - i + w] = L[i, k]
+    return band_ldlt_solve(Lb, D, b)
 
 
 def line_factor(O, W, S):
@@ -246,11 +287,12 @@ def interp_add(Ci, ec, u, dtype=np.float64):
 class Hierarchy:
     """FP64 BoxMG hierarchy built from a ``[n][n][K]`` stencil."""
 
-    def __init__(self, stencil: np.ndarray, nu1: int = 2, nu2: int = 1, smoother: str = "point"):
+    def __init__(self, stencil: np.ndarray, nu1: int = 2, nu2: int = 1, smoother: str = "point",
+                 coarsest: int = 3):
         st = _c(stencil)
         n, _, K = st.shape
         status = C.c_int(0)
-        h = lib().orc_setup(n, K, _p(st), nu1, nu2, C.byref(status))
+        h = lib().orc_setup(n, K, _p(st), nu1, nu2, coarsest, C.byref(status))
         if not h:
             raise OracleError(status.value, "setup")
         self._h = h
@@ -304,10 +346,14 @@ class Hierarchy:
         return tuple(self.field(l, nm) for nm in ("O", "W", "S", "SW", "NW"))
 
     def coarse_factor(self):
-        L = np.zeros(81)
-        D = np.zeros(9)
-        lib().orc_coarse_factor(self._h, _p(L), _p(D))
-        return L.reshape(9, 9), D
+        """Band factor of the coarsest level: ``(Lb, D)`` with ``Lb`` of shape
+        ``(m, w)``, ``Lb[i, k - i + w] = L[i, k]`` (m = n_L^2, w = n_L + 1)."""
+        m, w = C.c_int(0), C.c_int(0)
+        lib().orc_coarse_factor(self._h, None, None, C.byref(m), C.byref(w))
+        Lb = np.zeros((m.value, w.value))
+        D = np.zeros(m.value)
+        lib().orc_coarse_factor(self._h, _p(Lb), _p(D), None, None)
+        return Lb, D
 
     def step(self, l: int, op: str, arg: int = 1) -> None:
         code = {"smooth": 0, "residual": 1, "restrict": 2, "interp": 3, "coarse": 4}[op]

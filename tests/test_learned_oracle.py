@@ -303,3 +303,28 @@ def test_adam_first_step_closed_form():
     # a zero gradient leaves everything unchanged
     t2, m2, v2 = learned.adam(theta, z, z, z, 1, lr=1e-3)
     assert np.array_equal(t2, theta) and not m2.any() and not v2.any()
+
+
+def test_adam_several_steps_follow_the_real_arithmetic_update():
+    """Five Adam steps (Kingma and Ba, Algorithm 1) in the oracle's FP32 against
+    the same recurrence in FP64 on the FP32 values of the constants: equal to
+    the accumulated FP32 rounding (a few ulps of each quantity)."""
+    rng = np.random.default_rng(4)
+    theta = rng.standard_normal(2000).astype(np.float32)
+    m = np.zeros_like(theta)
+    v = np.zeros_like(theta)
+    b1, b2 = float(np.float32(0.9)), float(np.float32(0.999))
+    lr, eps = float(np.float32(1e-3)), float(np.float32(1e-8))
+    th64, m64, v64 = theta.astype(np.float64), np.zeros(2000), np.zeros(2000)
+    for t in range(1, 6):
+        g = rng.standard_normal(2000).astype(np.float32)
+        theta, m, v = learned.adam(theta, m, v, g, t, lr=1e-3)
+        g64 = g.astype(np.float64)
+        m64 = b1 * m64 + (1 - b1) * g64
+        v64 = b2 * v64 + (1 - b2) * g64 * g64
+        mh, vh = m64 / (1 - b1 ** t), v64 / (1 - b2 ** t)
+        th64 = th64 - lr * mh / (np.sqrt(vh) + eps)
+        assert np.allclose(m, m64, rtol=1e-5, atol=1e-7)
+        assert np.allclose(v, v64, rtol=1e-5, atol=1e-9)
+        assert np.abs(theta - th64).max() <= 1e-6
+

@@ -219,21 +219,64 @@ def test_p5_rap_restriction_interpolation_against_matrices(n, gen):
 
 
 # --------------------------------------------------------- a3 coarse solve
-def test_coarse_ldlt_matches_library_solve():
-    """The square-root-free Cholesky of the coarsest 9x9 operator reproduces the
-    matrix (L D L^T) and solves like numpy.linalg.solve."""
+@pytest.mark.parametrize("nc", [3, 7, 15, 31])
+def test_coarse_ldlt_matches_library_solve(nc):
+    """The square-root-free Cholesky of the coarsest operator (band storage,
+    half-bandwidth nc + 1) reproduces the matrix (L D L^T), has no entry outside
+    the band, and solves like numpy.linalg.solve."""
     n = 31
     p = inputs.jumping(n, 8, -3, 3, 9, 10)
     st, _ = ref.discretize(p.k, p.f)
-    H = ref.Hierarchy(st)
-    L3 = H.nlev - 1
-    A = dense.matrix_from_compact(*H.op(L3)).toarray()
-    Lf, D = H.coarse_factor()
-    assert np.allclose(np.tril(Lf), Lf) and np.all(np.diag(Lf) == 1.0) and np.all(D > 0)
+    H = ref.Hierarchy(st, coarsest=nc)
+    assert H.level_n(H.nlev - 1) == nc
+    A = dense.matrix_from_compact(*H.op(H.nlev - 1)).toarray()
+    Lb, D = H.coarse_factor()
+    assert Lb.shape == (nc * nc, nc + 1) and np.all(D > 0)
+    Lf = ref.band_to_dense(Lb)
     assert np.abs(Lf @ np.diag(D) @ Lf.T - A).max() <= 1e-14 * np.abs(A).max()
-    b = np.random.default_rng(1).standard_normal(9)
-    x = ref.ldlt_solve(Lf, D, b)
-    assert np.allclose(x, np.linalg.solve(A, b), rtol=1e-12, atol=0)
+    # the dense factor of numpy's Cholesky has the same band: L = C diag(C)^-1
+    C = np.linalg.cholesky(A)
+    Lc = C / np.diag(C)
+    assert np.abs(Lf - Lc).max() <= 1e-12 * np.abs(Lc).max()
+    b = np.random.default_rng(1).standard_normal(nc * nc)
+    x = ref.band_ldlt_solve(Lb, D, b)
+    xs = np.linalg.solve(A, b)
+    eps = np.finfo(float).eps
+    # forward error within the condition number's bound, backward error at
+    # rounding level (Cholesky is backward stable)
+    assert np.linalg.norm(x - xs) <= 10 * np.linalg.cond(A) * eps * np.linalg.norm(xs)
+    assert np.abs(A @ x - b).max() <= 100 * eps * np.abs(A).sum(axis=1).max() * np.abs(x).max()
+
+
+def test_band_ldlt_brute_force_small():
+    """On a random SPD band matrix the factor equals the textbook LDL^T (the
+    same recurrences written over the dense matrix in exact rational
+    arithmetic, then rounded) to a few ulps, and the solve's residual is at
+    rounding level."""
+    from fractions import Fraction
+    rng = np.random.default_rng(7)
+    m, w = 12, 3
+    B = np.zeros((m, m))
+    for i in range(m):
+        for k in range(max(0, i - w), i):
+            B[i, k] = B[k, i] = -rng.uniform(0.1, 1.0)
+    A = B + np.diag(np.abs(B).sum(axis=1) + rng.uniform(0.5, 1.5, m))
+    Lb, D = ref.band_ldlt_factor(ref.band_of(A, w))
+    Af = [[Fraction(float(v)) for v in row] for row in A]
+    L = [[Fraction(0)] * m for _ in range(m)]
+    Dx = [Fraction(0)] * m
+    for j in range(m):
+        Dx[j] = Af[j][j] - sum(L[j][k] * L[j][k] * Dx[k] for k in range(j))
+        for i in range(j + 1, m):
+            L[i][j] = (Af[i][j] - sum(L[i][k] * L[j][k] * Dx[k] for k in range(j))) / Dx[j]
+    Lx = np.array([[float(v) for v in row] for row in L]) + np.eye(m)
+    assert np.abs(ref.band_to_dense(Lb) - Lx).max() <= 1e-14
+    assert np.abs(D - np.array([float(v) for v in Dx])).max() <= 1e-14 * np.abs(D).max()
+    for i in range(m):                         # nothing outside the band
+        assert all(L[i][k] == 0 for k in range(0, max(0, i - w)))
+    b = rng.standard_normal(m)
+    x = ref.band_ldlt_solve(Lb, D, b)
+    assert np.abs(A @ x - b).max() <= 1e-14 * np.abs(b).max() * np.linalg.cond(A)
 
 
 # ------------------------------------------------------------ a4 smoother
@@ -287,6 +330,60 @@ def test_p8_one_vcycle_is_the_dense_two_grid_map():
     P = dense.prolongation(H.field(0, "Ci"), n)
     want = dense.two_grid(A, P, dense.interior(b), dense.interior(u), n, 2, 1)
     assert np.abs(dense.interior(got) - want).max() <= 1e-14 * np.abs(want).max()
+
+
+@pytest.mark.parametrize("n,nc", [(15, 7), (31, 15), (63, 31)])
+def test_p8_two_grid_map_with_a_larger_direct_coarse_level(n, nc):
+    """With the coarsest level one below the fine one (solved by the band
+    factor), one V(2,1)-cycle is exactly the two-grid map
+    S^1 (I - P Ac^-1 P^T A) S^2 with dense matrices."""
+    p = inputs.jumping(n, 4, -3, 3, 23, 24)
+    st, rhs = ref.discretize(p.k, p.f)
+    H = ref.Hierarchy(st, 2, 1, coarsest=nc)
+    assert H.nlev == 2
+    rng = np.random.default_rng(n)
+    u = ref.pad(rng.standard_normal((n, n)))
+    b = ref.pad(rhs)
+    got = H.vcycle(b, u)
+    A = dense.matrix_from_compact(*H.op(0))
+    P = dense.prolongation(H.field(0, "Ci"), n)
+    want = dense.two_grid(A, P, dense.interior(b), dense.interior(u), n, 2, 1)
+    assert np.abs(dense.interior(got) - want).max() <= 1e-12 * np.abs(want).max()
+
+
+def test_single_level_hierarchy_is_the_direct_solve():
+    """coarsest = n: the cycle is the direct solve itself."""
+    n = 15
+    p = inputs.jumping(n, 4, -2, 2, 25, 26)
+    st, rhs = ref.discretize(p.k, p.f)
+    H = ref.Hierarchy(st, coarsest=n)
+    assert H.nlev == 1
+    A = dense.matrix_from_compact(*H.op(0)).toarray()
+    b = ref.pad(rhs)
+    u = H.vcycle(b, np.zeros_like(b))
+    xs = np.linalg.solve(A, dense.interior(b))
+    assert np.abs(dense.interior(u) - xs).max() <= 1e-12 * np.abs(xs).max()
+
+
+@pytest.mark.parametrize("nc", [7, 15])
+def test_p7_larger_coarsest_converges_to_the_dense_solution(nc):
+    """n = 31: cycling with a 7^2 or 15^2 direct coarsest level reaches the dense
+    solution, and converges faster per cycle than with 3^2 on a field whose
+    coefficient blocks are wider than the 3^2 level's cells resolve."""
+    n = 31
+    p = inputs.jumping(n, 4, -4, 4, 33, 34)
+    st, rhs = ref.discretize(p.k, p.f)
+    b = ref.pad(rhs)
+    A = dense.matrix_from_compact(*ref.compact_from_stencil(st)).toarray()
+    xs = np.linalg.solve(A, dense.interior(b))
+    Hn = ref.Hierarchy(st, coarsest=nc)
+    u, hist = Hn.solve(b, tol=1e-14, max_cycles=200)
+    assert hist[-1] <= 1e-14
+    kappa = np.linalg.cond(A)
+    assert np.abs(dense.interior(u) - xs).max() <= 10 * kappa * 2.2e-16 * np.abs(xs).max()
+    H3 = ref.Hierarchy(st)
+    _, h3 = H3.solve(b, tol=1e-14, max_cycles=200)
+    assert len(hist) <= len(h3)
 
 
 @pytest.mark.parametrize("gen,tol", [("one", 1e-12), ("mild", 1e-12), ("hard", None)])
@@ -380,6 +477,108 @@ def test_lumping_only_changes_non_m_matrix_rows():
     for l in range(H.nlev - 1):
         Ci = H.field(l, "Ci")
         assert np.all(Ci >= 0) and np.all(Ci <= 1.0 + 1e-15)
+
+
+def _worked_example_stencil(case):
+    """The 7 x 7 nine-point operator of tests/golden/lump9_worked_example.txt."""
+    n = 7
+    st = np.zeros((n, n, 9))          # SW, S, SE, W, O, E, NW, N, NE
+    offs = [(-1, -1), (0, -1), (1, -1), (-1, 0), (0, 0), (1, 0), (-1, 1), (0, 1), (1, 1)]
+    for j in range(1, n + 1):
+        for i in range(1, n + 1):
+            for e, (di, dj) in enumerate(offs):
+                qi, qj = i + di, j + dj
+                if (di, dj) == (0, 0):
+                    st[j - 1, i - 1, e] = 8.0
+                elif 1 <= qi <= n and 1 <= qj <= n:
+                    st[j - 1, i - 1, e] = -1.0
+    # one symmetric pair of couplings set to +1: (p, entry at p, q, entry at q)
+    if case == "centre":
+        pairs = [((3, 3), 8, (4, 4), 0)]      # NE of (3,3) = SW of (4,4)
+    else:
+        pairs = [((3, 4), 6, (2, 5), 2)]      # NW of (3,4) = SE of (2,5)
+    for (pi, pj), ep, (qi, qj), eq in pairs:
+        st[pj - 1, pi - 1, ep] = 1.0
+        st[qj - 1, qi - 1, eq] = 1.0
+    return st
+
+
+def test_lumping_worked_example():
+    """Weights of rows with a positive coupling, computed by hand in
+    tests/golden/lump9_worked_example.txt, reproduced exactly (all values are
+    small rationals; the FP64 results must be their correctly rounded values)."""
+    from fractions import Fraction
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "lump9_worked_example.txt")
+    rows = [ln.split() for ln in open(path) if ln.strip() and not ln.startswith("#")]
+    assert len(rows) == 8
+    got = {}
+    for case in ("centre", "edges"):
+        O, W, S, SW, NW = ref.compact_from_stencil(_worked_example_stencil(case))
+        got[case] = ref.interp_weights(O, W, S, SW, NW)
+    for case, plane, I, J, num, den in rows:
+        w = got[case][PLANES[plane], int(J), int(I)]
+        assert w == float(Fraction(int(num), int(den))), (case, plane, I, J, w)
+
+
+def test_sumsq_is_the_correctly_rounded_exact_sum():
+    """The compensated sum of squares equals the exact rational sum rounded
+    once (to within one unit in the last place), on data where a plain running
+    sum loses every small term."""
+    from fractions import Fraction
+    rng = np.random.default_rng(12)
+    n = 31
+    r = np.zeros((n + 2, n + 2))
+    vals = rng.uniform(0.5, 1.0, (n, n)) * rng.choice([-1.0, 1.0], (n, n))
+    vals *= np.exp2(rng.integers(-3, 1, (n, n)))
+    vals[0, 0] = 2.0 ** 27 + 1.0          # first: its square absorbs every later one
+    r[1:-1, 1:-1] = vals
+    exact = sum(Fraction(float(v)) ** 2 for v in vals.reshape(-1))
+    got = ref.sumsq(r)
+    want = float(exact)
+    assert abs(Fraction(got) - exact) <= Fraction(np.spacing(want))
+    plain = 0.0
+    for v in vals.reshape(-1):
+        plain += v * v
+    assert abs(Fraction(plain) - exact) > 10 * Fraction(np.spacing(want))
+
+
+def test_accurate_residual_against_exact_rationals():
+    """r = b - A (x_hi + x_lo) from the error-free transformations equals the
+    exact rational residual up to one rounding of the result plus a term of
+    order eps^2 times the sum of |terms| (Ogita, Rump and Oishi 2005), on an
+    iterate so close to the solution that the plain residual has lost most of
+    its digits."""
+    from fractions import Fraction
+    n = 15
+    p = inputs.jumping(n, 4, -3, 3, 41, 42)
+    st, rhs = ref.discretize(p.k, p.f)
+    H = ref.Hierarchy(st)
+    op = H.op(0)
+    A = dense.matrix_from_compact(*op).tocsr()
+    b = ref.pad(rhs)
+    xs = np.linalg.solve(A.toarray(), dense.interior(b))
+    xh = ref.pad(xs.reshape(n, n))
+    rng = np.random.default_rng(3)
+    xl = ref.pad(xs.reshape(n, n) * rng.uniform(-1, 1, (n, n)) * 2.0 ** -60)
+    H.rel_residual(b, xh, xl)
+    got = dense.interior(H.field(0, "r"))
+    plain = dense.interior(ref.residual(*op, b, xh))
+    bi, xhi, xli = dense.interior(b), dense.interior(xh), dense.interior(xl)
+    eps = 2.0 ** -53
+    worst_plain = 0.0
+    for row in range(n * n):
+        lo, hi = A.indptr[row], A.indptr[row + 1]
+        r_ex = Fraction(float(bi[row]))
+        mag = Fraction(abs(float(bi[row])))
+        for c, a in zip(A.indices[lo:hi], A.data[lo:hi]):
+            xv = Fraction(float(xhi[c])) + Fraction(float(xli[c]))
+            r_ex -= Fraction(float(a)) * xv
+            mag += abs(Fraction(float(a)) * xv)
+        bound = eps * abs(r_ex) + Fraction(1e-28) * mag
+        assert abs(Fraction(float(got[row])) - r_ex) <= bound, row
+        worst_plain = max(worst_plain, float(abs(Fraction(float(plain[row])) - r_ex) / max(abs(r_ex), 1e-300)))
+    assert worst_plain > 1e-6           # the plain residual is far less accurate here
 
 
 # ------------------------------------------------------------ a12 refinement
