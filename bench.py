@@ -80,6 +80,17 @@ def workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
+def default_coarsest(name: str, n: int) -> int:
+    """Points per side of the directly solved coarsest level.  The 127^2
+    Poisson workload fixes 3x3.  On the block-wise jumping fields the coarsest
+    level is the last one whose grid lines still carry every coefficient jump
+    (64-cell blocks at 4095^2, 128-cell blocks at 8191^2: the 63^2 level), the
+    largest the one-wave band solve takes."""
+    if name.startswith("jumping_") or name.startswith("learned"):
+        return min(63, n)
+    return 3
+
+
 def omp_threads() -> int:
     try:
         import ctypes
@@ -88,27 +99,62 @@ def omp_threads() -> int:
         return os.cpu_count() or 1
 
 
-def cpu_baseline(p, gpu_cycles: int, sample_cycles: int):
-    """The oracle on this host: set-up plus `sample_cycles` V-cycles, scaled to
-    the GPU's cycle count for the whole solve."""
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_solve_times(p, coarsest: int, tol: float, threads: int | None = None):
+    """The oracle's whole solve on this host: (set-up s, solve s, cycles).
+    threads: OpenMP threads (None = all), with the process pinned to that many
+    cores while it runs."""
+    import ctypes
     from oracle import ref
+    gomp = ctypes.CDLL("libgomp.so.1")
     st, rhs = ref.discretize(p.k, p.f)
     b = ref.pad(rhs)
-    t0 = time.perf_counter()
-    H = ref.Hierarchy(st)
-    t_setup = time.perf_counter() - t0
-    u = np.zeros_like(b)
-    t0 = time.perf_counter()
-    for _ in range(sample_cycles):
-        u = H.vcycle(b, u)
-        H.rel_residual(b, u)
-    t_cyc = (time.perf_counter() - t0) / sample_cycles
-    t_total = t_setup + gpu_cycles * t_cyc
-    return {"value": p.n * p.n / t_total, "unit": "DOF/s", "cores": omp_threads(),
-            "kind": "oracle",
-            "sample": f"set-up + {sample_cycles} V(2,1)-cycles (with residual norm) on the "
-                      f"same {p.n}^2 problem, scaled to the {gpu_cycles} cycles the GPU "
-                      f"solve took; set-up {t_setup:.2f} s, {t_cyc * 1e3:.1f} ms per cycle"}
+    old_aff = os.sched_getaffinity(0)
+    old_thr = gomp.omp_get_max_threads()
+    try:
+        if threads:
+            os.sched_setaffinity(0, set(sorted(old_aff)[:threads]))
+            gomp.omp_set_num_threads(threads)
+        t0 = time.perf_counter()
+        H = ref.Hierarchy(st, coarsest=coarsest)
+        t1 = time.perf_counter()
+        u, hist = H.solve(b, tol=tol, max_cycles=2000)
+        t2 = time.perf_counter()
+        H.close()
+    finally:
+        gomp.omp_set_num_threads(old_thr)
+        os.sched_setaffinity(0, old_aff)
+    return t1 - t0, t2 - t1, len(hist)
+
+
+def cpu_baseline(p, coarsest: int, tol: float, full: bool):
+    """The oracle solving the same problem on this host's cores: set-up and the
+    solve to the tolerance timed separately, no extrapolation.  Default: one
+    solve on all cores.  full: the median of 3 on all cores and of 3 on one
+    core."""
+    runs = 3 if full else 1
+    allc = [oracle_solve_times(p, coarsest, tol) for _ in range(runs)]
+    med = sorted(allc, key=lambda r: r[0] + r[1])[len(allc) // 2]
+    out = {"value": p.n * p.n / (med[0] + med[1]), "unit": "DOF/s", "cores": omp_threads(),
+           "kind": "oracle", "cpu": cpu_model(),
+           "setup_s": med[0], "solve_s": med[1], "cycles": med[2],
+           "sample": f"the whole {p.n}^2 solve to {tol:g} (set-up + {med[2]} cycles, coarsest "
+                     f"{coarsest}^2), {'median of 3' if full else 'one run'} on all host cores"}
+    if full:
+        one = [oracle_solve_times(p, coarsest, tol, threads=1) for _ in range(runs)]
+        m1 = sorted(one, key=lambda r: r[0] + r[1])[len(one) // 2]
+        out["one_core"] = {"value": p.n * p.n / (m1[0] + m1[1]), "setup_s": m1[0], "solve_s": m1[1],
+                           "cycles": m1[2], "runs": runs}
+    return out
 
 
 def bench_batch(args):
@@ -143,18 +189,25 @@ def bench_batch(args):
             boxmg.tile_rows_set(n, r)
     else:
         # untimed: one batched solve per candidate tile height
-        tuned = autotune.tune_batch(lambda: step()[-1], sizes)
+        def tune_once():
+            out = step()
+            out[0].close()
+            return out[-1]
+        tuned = autotune.tune_batch(tune_once, sizes)
     for _ in range(args.warmup):
-        step()
+        step()[0].close()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     solve_s = 0.0
-    for _ in range(args.steps):
+    for k in range(args.steps):
         B, x, steps, rel, status, ts = step()
         solve_s += ts
+        if k + 1 < args.steps:
+            B.close()
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
     info = B.info()
+    B.close()
     sizes = sorted({q.n for q in probs})
     out = {
         "metric": f"fine DOF/s solved to {args.tol:g} rel. residual (512 problems, FP32 V-cycle in FP64 refinement)",
@@ -190,7 +243,8 @@ def bench_learned(args):
     n = p.n
     st, rhs = boxmg.discretize(torch.from_numpy(p.k).to(dev), torch.from_numpy(p.f).to(dev))
     net = boxmg.Net(params, max_n=n, train=False)
-    opts = dict(max_cycles=args.max_cycles, check_every=16)
+    opts = dict(max_cycles=args.max_cycles, check_every=16,
+                coarsest_n=args.coarsest or default_coarsest("learned", n))
 
     def timed(fn):
         torch.cuda.synchronize()
@@ -200,17 +254,17 @@ def bench_learned(args):
         return out, time.perf_counter() - t0
 
     def run_boxmg():
-        B = boxmg.Solver(st, **opts)
-        return B.solve(rhs, tol=args.tol, raise_on_noconv=False)
+        with boxmg.Solver(st, **opts) as B:
+            return B.solve(rhs, tol=args.tol, raise_on_noconv=False)
 
     def run_learned():
-        L = boxmg.Solver(st, interp=boxmg.BMG_INTERP_LEARNED, net=net, **opts)
-        return L.solve(rhs, tol=args.tol, raise_on_noconv=False)
+        with boxmg.Solver(st, interp=boxmg.BMG_INTERP_LEARNED, net=net, **opts) as L:
+            return L.solve(rhs, tol=args.tol, raise_on_noconv=False)
 
     def run_select():
-        L = boxmg.Solver(st, interp=boxmg.BMG_INTERP_LEARNED, net=net, **opts)
-        B = boxmg.Solver(st, **opts)
-        return boxmg.solve_select(L, B, rhs, tol=args.tol, raise_on_noconv=False)
+        with boxmg.Solver(st, interp=boxmg.BMG_INTERP_LEARNED, net=net, **opts) as L, \
+                boxmg.Solver(st, **opts) as B:
+            return boxmg.solve_select(L, B, rhs, tol=args.tol, raise_on_noconv=False)
 
     for _ in range(args.warmup):
         run_select()
@@ -254,6 +308,8 @@ def bench_learned(args):
     fwd_ms = e0.elapsed_time(e1) / reps
     flop = 2.0 * (9 * 9 * 32) * n * n + 2.0 * (32 * 9 * 32 + 32 * 9 * 8) * (nc + 1) ** 2
     tflops = flop / (fwd_ms * 1e-3) / 1e12
+    S0.close()
+    net.close()
     out["roofline"] = {"bound": "mfma", "kernel": "network forward (k_net_features, k_conv x 3)",
                        "achieved": tflops, "peak": 2500.0, "unit": "TFLOP/s", "frac": tflops / 2500.0,
                        "traffic": None, "flop_per_launch": flop, "avg_launch_ms": fwd_ms,
@@ -277,7 +333,8 @@ def bench_block(args):
     stencil, _ = boxmg.discretize(kk, torch.from_numpy(p.f).to(dev))
     rhs = torch.stack([boxmg.discretize(kk, torch.from_numpy(f).to(dev))[1]
                        for f in inputs.extra_sources(n, K)])
-    opts = dict(max_cycles=args.max_cycles, check_every=16)
+    opts = dict(max_cycles=args.max_cycles, check_every=16,
+                coarsest_n=args.coarsest or default_coarsest(args.workload, n))
     ws = {}
 
     def step(trace: bool):
@@ -291,13 +348,16 @@ def bench_block(args):
         return S, B, x, infos
 
     for _ in range(args.warmup):
-        step(False)
+        S, B, _, _ = step(False)
+        B.close()
+        S.close()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     launches, kms, kbytes, cyc, working = 0, 0.0, 0.0, 0, 0
     for _ in range(args.steps):
         S, B, x, infos = step(True)
         nl, ms, nb = B.trace_read()
+        B.close()
         launches += nl
         kms += ms
         kbytes += nb
@@ -306,6 +366,7 @@ def bench_block(args):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     n1 = S.level_n(1)
+    S.close()
     # the library counts every launch with all k right-hand sides; launches
     # where some have stopped move less: count the operator and weights once per
     # working launch and the per-right-hand-side arrays once per cycle of each
@@ -349,8 +410,13 @@ def main():
     ap.add_argument("--compare-fp64", action="store_true",
                     help="with --precision fp32ir: also time the FP64 solve of the same "
                          "problem and report the difference of the two solutions")
-    ap.add_argument("--cpu-sample-cycles", type=int, default=8)
+    ap.add_argument("--cpu-baseline", choices=("solve", "full", "none"), default="solve",
+                    help="solve: the oracle's whole solve once on all host cores; full: the "
+                         "median of 3 on all cores and of 3 on one core; none: skip")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--coarsest", type=int, default=0,
+                    help="points per side of the directly solved coarsest level (0 = the "
+                         "workload's default: 63 on the jumping fields, 3 otherwise)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device (a kernel of known traffic, to "
                          "calibrate hardware byte counters) and print the achieved GB/s")
@@ -404,8 +470,10 @@ def main():
     kern = boxmg.BMG_KERNELS_FUSED if args.kernels == "fused" else boxmg.BMG_KERNELS_BASIC
     prec = boxmg.BMG_FP32_IR if args.precision == "fp32ir" else boxmg.BMG_FP64
     line = args.smoother == "line"
+    coarsest = args.coarsest or default_coarsest(args.workload, n)
     opts = dict(max_cycles=args.max_cycles, kernels=kern, check_every=16, precision=prec,
-                smoother=boxmg.BMG_SMOOTH_LINE if line else boxmg.BMG_SMOOTH_POINT)
+                smoother=boxmg.BMG_SMOOTH_LINE if line else boxmg.BMG_SMOOTH_POINT,
+                coarsest_n=coarsest)
     tclass = "pre" if args.kernels == "fused" and not line else "smooth"
     if prec == boxmg.BMG_FP32_IR:
         tclass = "resnorm"     # the FP64 outer residual (accurate, 64 B per point)
@@ -422,7 +490,7 @@ def main():
         return S, x, info
 
     for _ in range(args.warmup):
-        step(False)
+        step(False)[0].close()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     infos = []
@@ -430,6 +498,7 @@ def main():
     for _ in range(args.steps):
         S, x, info = step(True)
         nl, ms, nb = S.trace_read()
+        S.close()
         launches += nl
         kms += ms
         kbytes += nb
@@ -455,6 +524,17 @@ def main():
         working = min(launches, sum(plain(i) for i in infos))
     avg_ms = kms / max(working, 1)
     achieved = bpl / (avg_ms * 1e-3) / 1e9 if working else None
+    # the survey's counting rule for a fused pass: the smoother's stream (stencil,
+    # b, u read, u written: 48 B per fine point) once, plus the interpolation
+    # weights (16), e_c and b_c (2 each) it reads or writes: 68 B per fine point
+    # for k_postpre; the library's count (bpl) adds the second iterate written
+    # (u_k, 8) and the zeroed coarse iterate (2): 78
+    survey_bpl = None
+    if tclass == "postpre":
+        survey_bpl = 68.0 * n * n
+    if survey_bpl is not None and working:
+        achieved_lib = achieved
+        achieved = survey_bpl / (avg_ms * 1e-3) / 1e9
     traffic = None
     if tclass == "pre" and args.kernels == "fused":
         traffic = measured_traffic(f"{args.workload} {args.precision} pre", boxmg.tile_rows_get(n))
@@ -474,6 +554,7 @@ def main():
             x64, info64 = S64.solve(rhs, tol=args.tol, raise_on_noconv=False)
             torch.cuda.synchronize()
             t64 = time.perf_counter() - t1
+            S64.close()
             d = (x - x64)
             extra = {"fp64_ms_per_solve": t64 * 1e3, "fp64_cycles": info64["cycles"],
                      "fp64_final_rel_res": info64["rel_res"],
@@ -495,6 +576,9 @@ def main():
         "config": {"workload": args.workload, "n": n, "dof": n * n, "tol": args.tol,
                    "cycles": info["cycles"], "final_rel_res": info["rel_res"],
                    "converged": info["status"] == 0, "rho": info["rho"],
+                   "coarsest": coarsest, "floor_est": info["floor_est"],
+                   "setup_ms": float(np.mean([i["t_setup_ms"] for i in infos])),
+                   "solve_ms": float(np.mean([i["t_solve_ms"] for i in infos])),
                    "kernels": "basic" if line else args.kernels, "smoother": args.smoother,
                    "nu1": 2, "nu2": 1, "precision": args.precision,
                    **extra},
@@ -503,10 +587,17 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS if achieved else None,
                      "traffic": traffic, "traffic_unit": "B/launch",
                      "launches": launches, "working_launches": working, "avg_launch_ms": avg_ms,
-                     "bytes_per_launch": bpl, "bytes_per_point": bpl / (n * n)},
+                     "bytes_per_launch": survey_bpl or bpl, "bytes_per_point": (survey_bpl or bpl) / (n * n)},
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(p, info["cycles"], args.cpu_sample_cycles)
+    if survey_bpl is not None and working:
+        out["roofline"]["counting"] = ("achieved/frac: 68 B per fine point (smoother stream 48 once, weights 16, "
+                                       "e_c 2, b_c 2); achieved_all_arrays/frac_all_arrays: 78 B per fine "
+                                       "point, every array the pass touches once (adds u_k written 8, u_c "
+                                       "zeroed 2)")
+        out["roofline"]["achieved_all_arrays"] = achieved_lib
+        out["roofline"]["frac_all_arrays"] = achieved_lib / HBM_PEAK_GBS
+    if not args.no_cpu_baseline and args.cpu_baseline != "none":
+        out["cpu_baseline"] = cpu_baseline(p, coarsest, args.tol, args.cpu_baseline == "full")
     print(json.dumps(out))
 
 

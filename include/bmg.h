@@ -13,7 +13,8 @@
  *
  * Conventions for every entry point:
  *  - Grids: interior n x n with n = 2^m - 1, m >= 2; the mesh width is
- *    h = 1/(n+1); level l has n_l = 2^(m-l) - 1 down to n_L = 3.
+ *    h = 1/(n+1); level l has n_l = 2^(m-l) - 1 down to the coarsest n_L
+ *    (bmg_options.coarsest_n, 3 by default).
  *  - Pointers are DEVICE pointers unless the comment says "host".
  *  - Work is enqueued on the stream given at set-up (NULL = the null stream);
  *    entry points that return a number to the host synchronise that stream.
@@ -86,7 +87,16 @@ typedef struct {
                         exactly with a factor formed at set-up.  FP64 only; the
                         cycle then runs one launch per step (kernels is
                         ignored) */
-    int reserved[3];
+    int coarsest_n;  /* points per side of the coarsest level, which is solved
+                        directly (Fig. vcycle_flowchart: Cholesky) with the
+                        square-root-free Cholesky factor of its band matrix
+                        (lexicographic unknowns, half-bandwidth coarsest_n + 1):
+                        2^k - 1 with 3 <= coarsest_n <= min(n, 63); 0 = 3 */
+    int persistent_below_n; /* coarse levels of at most this many points per
+                        side (below the fine level) run as one persistent
+                        one-workgroup launch per cycle: 2^k - 1 <= 63, or 1 for
+                        none; 0 = 63 */
+    int reserved[1];
 } bmg_options;
 
 typedef struct {
@@ -97,6 +107,13 @@ typedef struct {
                          FP64: history[k] = relative residual after cycle k+1;
                          FP32_IR: history[0] is the initial relative residual,
                          history[k] the one after correction k */
+    double floor_est; /* eps * || |A| |x| + |b| ||_2 / ||b||_2 for the returned
+                         x (eps = 2^-53): the scale of the relative residual
+                         that rounding x to FP64 alone can leave */
+    double t_setup_ms; /* host wall time of the handle's bmg_setup */
+    double t_solve_ms; /* host wall time of this call */
+    int interp_used;  /* BMG_INTERP_BOXMG or BMG_INTERP_LEARNED: the weights of
+                         the hierarchy that produced x */
 } bmg_info;
 
 /* Fills *o with the defaults above.  Host only. */
@@ -128,7 +145,9 @@ bmg_status bmg_discretize(const double *k, const double *f, int n, double *stenc
  *   stored as the eight planes LNE, LA, LNW, LR, LL, LSE, LB, LSW of
  *   Fig. restrict_kernel at the coarse point north-east of each F-point triple;
  *   the Galerkin coarse operator P^T A P as a nine-point stencil; and the
- *   square-root-free Cholesky (LDL^T) factor of the coarsest 9 x 9 matrix.
+ *   square-root-free Cholesky (LDL^T) factor of the coarsest level's matrix
+ *   (n_L^2 unknowns in lexicographic order, a band of half-bandwidth n_L + 1,
+ *   factored column by column with every sum over increasing index).
  *   stencil: n x n x kind, row-major; kind 5: S, W, O, E, N; kind 9: SW, S, SE,
  *            W, O, E, NW, N, NE (the rows of Fig. stencil_operator, south first).
  *            Signed matrix entries, entries toward boundary vertices zero, the
@@ -227,8 +246,10 @@ const char *bmg_last_error(void);
  *   level arrays: (n_l+2) x (n_l+2) row-major with the Dirichlet ring;
  *   BMG_F_CI: 8 x (n_{l+1}+2) x (n_{l+1}+2), planes LNE, LA, LNW, LR, LL, LSE,
  *   LB, LSW (the weights between level l and l+1);
- *   BMG_F_COARSE_LD: the coarsest factor, 81 entries of L (row-major, unit
- *   lower triangular) followed by the 9 entries of D (level argument ignored);
+ *   BMG_F_COARSE_LD: the coarsest factor, m = n_L^2 unknowns, w = n_L + 1:
+ *   m x w entries of L in band storage (row i holds L_ik for k = i-w .. i-1
+ *   at column k - i + w, zero for k < 0; the unit diagonal is implicit)
+ *   followed by the m entries of D (level argument ignored);
  *   BMG_F_XLO: the low part of the last solve's double-FP64 iterate, level-0
  *   layout (zero if the solve never switched to refinement);
  *   BMG_F_STENCIL (export only): the level's operator as bmg_setup reads it,
@@ -420,8 +441,10 @@ bmg_status bmg_net_twogrid(bmg_net *net, bmg_solver *h, const double *r0, double
  * BMG_INTERP_LEARNED or BMG_INTERP_BOXMG; rho (host, 2 entries) the probe
  * factors of the learned and the BoxMG hierarchy; info->cycles counts every
  * cycle after the probes plus the finishing hierarchy's probe, the other
- * fields describe the last bmg_solve call (info->history, if given, holds
- * that call's history).  FP64 handles only. */
+ * fields describe the last bmg_solve call, except info->history (if given,
+ * max_cycles + 1 entries), which receives the relative residual after each
+ * cycle that followed the probes, in order, and info->interp_used, the
+ * hierarchy that finished.  FP64 handles only. */
 bmg_status bmg_solve_select(bmg_solver *learned, bmg_solver *boxmg, const double *rhs, double *x, double tol,
                             int probe_cycles, bmg_info *info, int *used, double *rho);
 

@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import sys
 
 import torch
 
@@ -41,12 +42,47 @@ class Options(C.Structure):
                 ("precision", C.c_int), ("kernels", C.c_int), ("check_every", C.c_int),
                 ("refine_factor", C.c_int), ("tile_rows", C.c_int), ("interp", C.c_int),
                 ("learned_levels", C.c_int), ("net", C.c_void_p), ("smoother", C.c_int),
-                ("reserved", C.c_int * 3)]
+                ("coarsest_n", C.c_int), ("persistent_below_n", C.c_int), ("reserved", C.c_int * 1)]
 
 
 class Info(C.Structure):
     _fields_ = [("cycles", C.c_int), ("rel_res", C.c_double), ("rho", C.c_double),
-                ("history", C.POINTER(C.c_double))]
+                ("history", C.POINTER(C.c_double)), ("floor_est", C.c_double),
+                ("t_setup_ms", C.c_double), ("t_solve_ms", C.c_double), ("interp_used", C.c_int)]
+
+
+def _new_info(hist) -> Info:
+    info = Info()
+    info.history = C.cast(hist, C.POINTER(C.c_double))
+    return info
+
+
+def _info_dict(info: Info, hist, nh: int, status: int) -> dict:
+    return {"cycles": info.cycles, "rel_res": info.rel_res, "rho": info.rho,
+            "history": [hist[t] for t in range(nh)], "status": status, "floor_est": info.floor_est,
+            "t_setup_ms": info.t_setup_ms, "t_solve_ms": info.t_solve_ms, "interp_used": info.interp_used}
+
+
+class _Handle:
+    """Explicit release (``close()`` or a ``with`` block).  During interpreter
+    shutdown ``__del__`` does nothing: the HIP runtime (and a profiler's hooks
+    around it) may already be torn down, and a late release call into it can
+    crash the process after its work is done."""
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
+
+    def __del__(self):
+        if sys.is_finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class BoxMGError(RuntimeError):
@@ -172,7 +208,7 @@ def discretize(k: torch.Tensor, f: torch.Tensor):
     return st, rhs
 
 
-class Solver:
+class Solver(_Handle):
     """BoxMG hierarchy of a ``[n][n][K]`` stencil (K = 5 or 9) on the GPU."""
 
     def __init__(self, stencil: torch.Tensor, workspace: torch.Tensor | None = None, **options):
@@ -202,11 +238,6 @@ class Solver:
             lib().bmg_destroy(self._h)
             self._h = None
 
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
 
     # -------------------------------------------------------------- solves
     def vcycle(self, rhs: torch.Tensor, x: torch.Tensor, want_residual: bool = True):
@@ -221,14 +252,12 @@ class Solver:
         if x is None:
             x = torch.zeros_like(rhs)
         hist = (C.c_double * (self.options.max_cycles + 2))()
-        info = Info(0, 0.0, 0.0, C.cast(hist, C.POINTER(C.c_double)))
+        info = _new_info(hist)
         st = lib().bmg_solve(self._h, _ptr(rhs), _ptr(x), float(tol), C.byref(info))
         if st not in (BMG_OK, BMG_ENOCONV) or (st == BMG_ENOCONV and raise_on_noconv):
             _check(st, "bmg_solve")
         nh = info.cycles + (1 if self.options.precision == BMG_FP32_IR else 0)
-        out = {"cycles": info.cycles, "rel_res": info.rel_res, "rho": info.rho,
-               "history": [hist[t] for t in range(nh)], "status": st}
-        return x, out
+        return x, _info_dict(info, hist, nh, st)
 
     # ------------------------------------------------------- level access
     def level_n(self, level: int) -> int:
@@ -240,7 +269,8 @@ class Solver:
         base = field[:-2] if field.endswith("32") else field
         dtype = torch.float32 if field.endswith("32") else torch.float64
         if base == "LD":
-            return (90,), torch.float64
+            nl = self.level_n(self.nlev - 1)
+            return (nl * nl * (nl + 2),), torch.float64
         if base == "xlo":
             return (self.n + 2, self.n + 2), torch.float64
         if base == "stencil":
@@ -278,7 +308,7 @@ class Solver:
         return n.value, ms.value, nb.value
 
 
-class Block:
+class Block(_Handle):
     """k right-hand sides solved together on the hierarchy of ``solver`` (which
     must stay open while the block is used)."""
 
@@ -300,11 +330,6 @@ class Block:
             lib().bmg_block_destroy(self._b)
             self._b = None
 
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
 
     def solve(self, rhs: torch.Tensor, x: torch.Tensor | None = None, tol: float = 1e-10,
               raise_on_noconv: bool = True):
@@ -349,7 +374,7 @@ def tile_rows_get(n: int) -> int:
     return r.value
 
 
-class Batch:
+class Batch(_Handle):
     """Independent problems of uneven sizes solved together (FP32 V-cycles in
     double-FP64 refinement, one persistent launch per group of steps)."""
 
@@ -376,11 +401,6 @@ class Batch:
             lib().bmg_batch_destroy(self._h)
             self._h = None
 
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
 
     def solve(self, rhs: list, x: list | None = None, tol: float = 1e-10,
               raise_on_noconv: bool = True):
@@ -409,7 +429,7 @@ class Batch:
         return {"workgroups": nb.value, "graph": {0: "not built", 1: "replayed", 2: "refused"}[g.value]}
 
 
-class Net:
+class Net(_Handle):
     """Learned-interpolation network on the GPU (parameters, Adam state and
     activation buffers in one workspace)."""
 
@@ -437,11 +457,6 @@ class Net:
             lib().bmg_net_destroy(self._h)
             self._h = None
 
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
 
     def set_params(self, params) -> None:
         import numpy as np
@@ -515,12 +530,13 @@ def solve_select(learned: Solver, boxmg: Solver, rhs: torch.Tensor, x: torch.Ten
         x = torch.zeros_like(rhs)
     cap = max(learned.options.max_cycles, boxmg.options.max_cycles) + 2
     hist = (C.c_double * cap)()
-    info = Info(0, 0.0, 0.0, C.cast(hist, C.POINTER(C.c_double)))
+    info = _new_info(hist)
     used = C.c_int(0)
     rho = (C.c_double * 2)()
     st = lib().bmg_solve_select(learned._h, boxmg._h, _ptr(rhs), _ptr(x), float(tol), int(probe_cycles),
                                 C.byref(info), C.byref(used), rho)
     if st not in (BMG_OK, BMG_ENOCONV) or (st == BMG_ENOCONV and raise_on_noconv):
         _check(st, "bmg_solve_select")
-    out = {"cycles": info.cycles, "rel_res": info.rel_res, "rho": info.rho, "status": st}
+    nh = max(0, info.cycles - int(probe_cycles))
+    out = _info_dict(info, hist, min(nh, cap), st)
     return x, out, used.value, (rho[0], rho[1])

@@ -426,6 +426,8 @@ bmg_status bmg_batch_workspace_bytes(int nprob, const int *n, const bmg_options 
         if (!valid_n(n[p]) || n[p] < 7) return fail(BMG_EINVAL, "problem %d: n=%d is not 2^m-1 >= 7", p, n[p]);
     const bmg_options op = batch_options(o);
     if (op.nu1 != 2 || op.nu2 != 1) return fail(BMG_EINVAL, "the batched path runs V(2,1) cycles");
+    if (op.coarsest_n != 0 && op.coarsest_n != 3)
+        return fail(BMG_EINVAL, "the batched path solves a 3 x 3 coarsest level (coarsest_n = %d)", op.coarsest_n);
     *bytes = batch_layout(nprob, n, op, nullptr, nullptr);
     return *bytes ? BMG_OK : fail(BMG_EINVAL, "bad batch options");
 }
@@ -516,7 +518,7 @@ bmg_status bmg_batch_setup(bmg_batch **out, int nprob, const int *n, const doubl
         }
         const int lds_small = small_layout(S) * (int)sizeof(float);
         B->lds = std::max(B->lds, (size_t)lds_small);
-        S.LD = h->LD;
+        S.band = h->band;
         S.nu1 = 2;
         S.nu2 = 1;
         q.L0 = h->L[0];
@@ -666,9 +668,11 @@ bmg_status bmg_batch_solve(bmg_batch *B, const double *const *rhs, double *const
         if (active < 0) {
             if (!via_graph || !B->graph_ok) return fail(BMG_EDEVICE, "the persistent launch was not cooperative");
             // the graph node ran without a grid barrier and did nothing: use
-            // direct launches from here on
+            // direct launches from here on, and release the graph now
             B->graph_ok = false;
             B->graph_refused = true;
+            if (B->exec) { (void)hipGraphExecDestroy(B->exec); B->exec = nullptr; }
+            if (B->graph) { (void)hipGraphDestroy(B->graph); B->graph = nullptr; }
             TRY(batch_launch(B, MODE_STEPS, per_launch, tol));
             HIPCHK(hipMemcpyAsync(&active, B->dactive, sizeof(int), hipMemcpyDeviceToHost, B->st));
             HIPCHK(hipStreamSynchronize(B->st));

@@ -1544,8 +1544,8 @@ struct SmallH {
     int nl;                    // levels in the kernel: first .. coarsest
     Lev<T> L[SMALL_MAXL];
     Wts<T> C[SMALL_MAXL];      // C[l]: weights between L[l] and L[l+1]
-    int off_u[SMALL_MAXL], off_b[SMALL_MAXL], off_r;
-    const double *LD;          // coarsest LDL^T factor
+    int off_u[SMALL_MAXL], off_b[SMALL_MAXL], off_r, off_z;
+    BandSolve band;            // coarsest factor (one-wave band solve)
     int nu1, nu2;
     // workgroup k runs right-hand side k: the first level's u and b start
     // k*ks0 elements after the first's, its stop flag k*kstop ints after
@@ -1649,6 +1649,12 @@ __host__ __device__ inline int small_layout(SmallH<T> &H)
     }
     H.off_r = off;
     off += (H.L[0].n + 2) * (H.L[0].n + 2);
+    // FP64 scratch of the coarsest solve, 8-byte aligned
+    constexpr int per = (int)(sizeof(double) / sizeof(T));
+    off = (off + per - 1) / per * per;
+    H.off_z = off;
+    const int nL = H.L[H.nl - 1].n;
+    off += band_padded(nL * nL) * per;
     return off;
 }
 
@@ -1706,24 +1712,15 @@ __device__ void small_vcycle_body(const SmallH<T> &H, T *sm, size_t rhs_off)
         }
         __syncthreads();
     }
-    // coarsest 3x3: y = L^-1 b, z = y / D, x = L^-T z in FP64
-    if (threadIdx.x == 0) {
-        const double *LD = H.LD;
+    // coarsest level: the band LDL^T solve in FP64 by the first wave
+    if (threadIdx.x < 64) {
+        const int nc = H.L[last].n, pc = nc + 2;
         const T *b = sm + H.off_b[last];
         T *u = sm + H.off_u[last];
-        double y[9], x[9];
-        for (int i = 0; i < 9; ++i) {
-            double s = (double)b[(1 + i / 3) * 5 + 1 + i % 3];
-            for (int k = 0; k < i; ++k) s = s - LD[i * 9 + k] * y[k];
-            y[i] = s;
-        }
-        for (int i = 0; i < 9; ++i) y[i] = y[i] / LD[81 + i];
-        for (int i = 8; i >= 0; --i) {
-            double s = y[i];
-            for (int k = i + 1; k < 9; ++k) s = s - LD[k * 9 + i] * x[k];
-            x[i] = s;
-        }
-        for (int i = 0; i < 9; ++i) u[(1 + i / 3) * 5 + 1 + i % 3] = (T)x[i];
+        band_solve_direct(
+            H.band, [&](int k) -> double { return (double)b[(k / nc + 1) * pc + k % nc + 1]; },
+            [&](int k, double x) { u[(k / nc + 1) * pc + k % nc + 1] = (T)x; },
+            reinterpret_cast<double *>(sm + H.off_z));
     }
     __syncthreads();
     // up: interpolate and correct, relax

@@ -84,7 +84,10 @@ struct bmg_solver {
     double *B0 = nullptr;       // fine right-hand side during refinement
     double *XH = nullptr;       // double-FP64 iterate, high part
     double *XL = nullptr;       // double-FP64 iterate, low part
-    double *LD = nullptr;       // coarsest factor: 81 L + 9 D
+    double *Lb = nullptr;       // coarsest factor in band storage (m x w), D (m) right after
+    double *Dd = nullptr;
+    BandSolve band{};           // the factor rearranged for the one-wave solve
+    double t_setup_ms = 0.0;    // host wall time of bmg_setup
     int *flags = nullptr;       // validation / breakdown bits
     double *part = nullptr;     // NPART partial sums
     double *scal = nullptr;     // scalars (see enum below)

@@ -289,70 +289,267 @@ static __global__ void k_rap(Lev<double> F, Wts<double> C, Lev<double> Cl)
     Cl.NW[c] = acc[4];
 }
 
-// ------------------------------------------- coarsest LDL^T (3x3 interior)
-// Dense matrix in the unknown order k = (i-1) + 3(j-1), then the
-// square-root-free Cholesky: w_k = L_jk D_k, D_j = A_jj - sum L_jk w_k,
-// L_ij = (A_ij - sum L_ik w_k) / D_j (sums over increasing k).
-static __global__ void k_coarse_factor(Lev<double> Cl, double *__restrict__ LD, int *__restrict__ flags)
+// ------------------------------------------------ coarsest level: band LDL^T
+// The coarsest level (nc points per side, 3 <= nc <= 63) is solved directly.
+// Its unknowns in lexicographic order k = (i-1) + nc (j-1) give a band matrix
+// of half-bandwidth w = nc + 1 <= 64, whose square-root-free Cholesky factor
+// L D L^T stays inside the band.  Set-up keeps
+//   Lb[i w + (k - i + w)] = L_ik  (k = i-w .. i-1, zero for k < 0), D[i];
+// and, for the solve, the same entries rearranged by the lane that uses them
+// (BandSolve below).
+constexpr int BAND_MAX_NC = 63;
+constexpr int BAND_FACTOR_THREADS = 128;
+
+// A(i, i - d) of the coarsest level's matrix, d = 0 .. w, from its compact
+// stencil: d = 1 W, nc - 1 SE (the NW entry of the point below-right), nc S,
+// nc + 1 SW; couplings to points outside the grid are zero.
+__device__ inline double band_entry(const Lev<double> &L, int i, int d)
 {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    double A[81], Lm[81], D[9], w[9];
-    for (int t = 0; t < 81; ++t) { A[t] = 0.0; Lm[t] = 0.0; }
-    for (int j = 1; j <= 3; ++j) {
-        for (int i = 1; i <= 3; ++i) {
-            double a[9];
-            row_of(Cl, (size_t)j * Cl.ld + i, a);
-            const int k = (i - 1) + 3 * (j - 1);
-            for (int e = 0; e < 9; ++e) {
-                const int qi = i + (e % 3) - 1, qj = j + (e / 3) - 1;
-                if (qi < 1 || qi > 3 || qj < 1 || qj > 3) continue;
-                A[k * 9 + (qi - 1) + 3 * (qj - 1)] = a[e];
-            }
-        }
-    }
-    int bad = 0;
-    for (int j = 0; j < 9; ++j) {
-        for (int k = 0; k < j; ++k) w[k] = Lm[j * 9 + k] * D[k];
-        double s = A[j * 9 + j];
-        for (int k = 0; k < j; ++k) s = s - Lm[j * 9 + k] * w[k];
-        if (!(s > 0.0)) bad = F_BREAK_COARSE;
-        D[j] = s;
-        Lm[j * 9 + j] = 1.0;
-        for (int i = j + 1; i < 9; ++i) {
-            double t = A[i * 9 + j];
-            for (int k = 0; k < j; ++k) t = t - Lm[i * 9 + k] * w[k];
-            Lm[i * 9 + j] = t / s;
-        }
-    }
-    for (int t = 0; t < 81; ++t) LD[t] = Lm[t];
-    for (int t = 0; t < 9; ++t) LD[81 + t] = D[t];
-    if (bad) atomicOr(flags, bad);
+    const int nc = L.n;
+    const int ii = i % nc + 1, jj = i / nc + 1;
+    const size_t p = (size_t)jj * L.ld + ii;
+    if (d == 0) return L.O[p];
+    if (d == 1) return ii > 1 ? L.W[p] : 0.0;
+    if (d == nc - 1) return (ii < nc && jj > 1 && L.NW) ? L.NW[p + 1 - L.ld] : 0.0;
+    if (d == nc) return jj > 1 ? L.S[p] : 0.0;
+    if (d == nc + 1) return (ii > 1 && jj > 1 && L.SW) ? L.SW[p] : 0.0;
+    return 0.0;
 }
 
-// Solve with the factor: y = L^-1 b, z = y / D, x = L^-T z.  The right-hand side
-// and solution are level arrays of precision T (FP32 hierarchy: widened to
-// FP64 for the solve and rounded back).
-template <typename T>
-static __global__ void k_coarse_solve(Lev<T> Cl, const double *__restrict__ LD, const int *stop)
+// Column by column (one workgroup; thread t works on row j + t of column j):
+//   v_k = L_jk D_k (k = j-w .. j-1);  D_j = A_jj - sum_k L_jk v_k;
+//   L_ij = (A_ij - sum_{k = i-w .. j-1} L_ik v_k) / D_j  (i = j+1 .. j+w),
+// every sum over increasing k.  The rows j .. j+w of L live in an LDS ring of
+// w + 1 rows (a row's slot is reused by row j + w + 1, which starts at column
+// j + 1), D_k in a ring of the same length.
+static __global__ __launch_bounds__(BAND_FACTOR_THREADS) void k_band_factor(Lev<double> L, double *__restrict__ Lb,
+                                                                             double *__restrict__ D,
+                                                                             int *__restrict__ flags)
 {
-    if (stopped(stop)) return;
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    double y[9], x[9];
-    for (int i = 0; i < 9; ++i) {
-        const int ci = 1 + i % 3, cj = 1 + i / 3;
-        double s = (double)Cl.b[(size_t)cj * Cl.ld + ci];
-        for (int k = 0; k < i; ++k) s = s - LD[i * 9 + k] * y[k];
-        y[i] = s;
+    __shared__ double ring[(BAND_MAX_NC + 2) * (BAND_MAX_NC + 1)];
+    __shared__ double dring[BAND_MAX_NC + 2];
+    __shared__ double v[BAND_MAX_NC + 1];
+    __shared__ double col[BAND_MAX_NC + 2];
+    const int nc = L.n, m = nc * nc, w = nc + 1, R = w + 1, t = threadIdx.x;
+    int bad = 0;
+    for (int j = 0; j < m; ++j) {
+        if (t < w) {
+            const int k = j - w + t;
+            v[t] = k >= 0 ? ring[(j % R) * w + t] * dring[k % R] : 0.0;
+        }
+        __syncthreads();
+        const int i = j + t;
+        if (t <= w && i < m) {
+            double s = band_entry(L, i, t);
+            const double *Li = ring + (i % R) * w;
+            for (int k = max(0, i - w); k < j; ++k) s = s - Li[k - i + w] * v[k - j + w];
+            col[t] = s;
+        }
+        __syncthreads();
+        const double d = col[0];
+        if (t == 0) {
+            dring[j % R] = d;
+            D[j] = d;
+            if (!(d > 0.0)) bad = 1;
+        } else if (t <= w && i < m) {
+            const double l = col[t] / d;
+            ring[(i % R) * w + (w - t)] = l;
+            Lb[(size_t)i * w + (w - t)] = l;
+        }
+        __syncthreads();
     }
-    for (int i = 0; i < 9; ++i) y[i] = y[i] / LD[81 + i];
-    for (int i = 8; i >= 0; --i) {
-        double s = y[i];
-        for (int k = i + 1; k < 9; ++k) s = s - LD[k * 9 + i] * x[k];
-        x[i] = s;
+    if (t == 0 && bad) atomicOr(flags, F_BREAK_COARSE);
+}
+
+// The factor as the one-wave solve reads it.  Unknowns are padded to M, a
+// multiple of 64; lane l keeps the pending values of unknowns 64q + l (block
+// q, "current") and 64(q+1) + l (block q+1, "next"), since w <= 64 means an
+// unknown only couples to its own block and the neighbouring one.  Every step
+// reads one row of 2 x 64 doubles (FF for the forward substitution, GG for the
+// backward one):
+//   forward step j = 64q + r:  FF[j][l] = L(64q + l, j) for l > r,
+//                              FF[j][64 + l] = L(64q + 64 + l, j);
+//   backward step k = 64q + r: GG[k][l] = L(k, 64q + l) for l < r,
+//                              GG[k][64 + l] = L(k, 64q - 64 + l);
+// zero wherever the entry lies outside the band or the matrix; Dp = D padded
+// with ones.
+struct BandSolve {
+    const double *FF, *GG, *Dp;
+    int m, M, nc;
+};
+
+__host__ __device__ inline int band_padded(int m) { return (m + 63) & ~63; }
+
+static __global__ void k_band_expand(int nc, const double *__restrict__ Lb, const double *__restrict__ D,
+                                     double *__restrict__ FF, double *__restrict__ GG, double *__restrict__ Dp)
+{
+    const int m = nc * nc, w = nc + 1, M = band_padded(m);
+    const int l = threadIdx.x & 63;
+    const int s = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);   // step
+    if (s >= M) return;
+    const int q = s >> 6, r = s & 63;
+    // L(i, k) for i - w <= k < i < m, else 0
+    auto Lik = [&](int i, int k) -> double {
+        return (i < m && k >= 0 && k < i && i - k <= w) ? Lb[(size_t)i * w + (k - i + w)] : 0.0;
+    };
+    const size_t o = (size_t)s * 128 + l;
+    FF[o] = l > r ? Lik(64 * q + l, s) : 0.0;
+    FF[o + 64] = Lik(64 * q + 64 + l, s);
+    GG[o] = l < r ? Lik(s, 64 * q + l) : 0.0;
+    GG[o + 64] = q >= 1 ? Lik(s, 64 * q - 64 + l) : 0.0;
+    if (l == 0) Dp[s] = s < m ? D[s] : 1.0;
+}
+
+__device__ __forceinline__ double readlane_d(double v, int lane)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// One step: the final value held by lane LANE of a0 is broadcast and its
+// multiples (row `f`: current block, then next block) are subtracted.  Lanes
+// whose entry is zero keep their value (up to the sign of a zero).
+template <int LANE>
+__device__ __forceinline__ void band_step(double &a0, double &a1, const double *f, int l)
+{
+    const double y = readlane_d(a0, LANE);
+    a0 = a0 - f[l] * y;
+    a1 = a1 - f[64 + l] * y;
+}
+
+// NSTEP consecutive steps whose broadcasting lanes are LANE0, LANE0 + LDIR,
+// ..., reading the rows at `rows`, rows + RDIR * 128, ...
+template <int LANE0, int LDIR, int RDIR, int NSTEP>
+__device__ __forceinline__ void band_steps(double &a0, double &a1, const double *rows, int l)
+{
+    if constexpr (NSTEP > 0) {
+        band_step<LANE0>(a0, a1, rows, l);
+        band_steps<LANE0 + LDIR, LDIR, RDIR, NSTEP - 1>(a0, a1, rows + RDIR * 128, l);
     }
-    for (int i = 0; i < 9; ++i) {
-        const int ci = 1 + i % 3, cj = 1 + i / 3;
-        Cl.u[(size_t)cj * Cl.ld + ci] = (T)x[i];
+}
+
+// The coarsest solve x = L^-T D^-1 L^-1 b, in the order of the oracle's
+// column form: y_i takes its terms over increasing j, z_i = y_i / D_i, x_i
+// takes its terms over decreasing k.  Run by one wave (lanes l = 0..63),
+// reading the step rows from global memory (the persistent small-level
+// kernel).  get(k): right-hand side of unknown k < m as FP64; put(k, x): the
+// result; z: M doubles of scratch.
+template <typename Get, typename Put>
+__device__ void band_solve_direct(const BandSolve &B, Get get, Put put, double *z)
+{
+    const int l = threadIdx.x & 63, m = B.m, nb = B.M >> 6;
+    double a0 = l < m ? get(l) : 0.0;
+    double a1 = 64 + l < m ? get(64 + l) : 0.0;
+    for (int q = 0; q < nb; ++q) {
+        const double *rows = B.FF + (size_t)q * 64 * 128;
+#pragma unroll 4
+        for (int r = 0; r < 64; ++r) {
+            const double y = readlane_d(a0, r);
+            a0 = a0 - rows[r * 128 + l] * y;
+            a1 = a1 - rows[r * 128 + 64 + l] * y;
+        }
+        z[64 * q + l] = a0 / B.Dp[64 * q + l];
+        a0 = a1;
+        a1 = 64 * (q + 2) + l < m ? get(64 * (q + 2) + l) : 0.0;
+    }
+    a0 = z[64 * (nb - 1) + l];
+    a1 = nb >= 2 ? z[64 * (nb - 2) + l] : 0.0;
+    for (int q = nb - 1; q >= 0; --q) {
+        const double *rows = B.GG + (size_t)q * 64 * 128;
+#pragma unroll 4
+        for (int r = 63; r >= 0; --r) {   // steps k = 64q + 63 down to 64q
+            const double x = readlane_d(a0, r);
+            a0 = a0 - rows[r * 128 + l] * x;
+            a1 = a1 - rows[r * 128 + 64 + l] * x;
+        }
+        if (64 * q + l < m) put(64 * q + l, a0);
+        a0 = a1;
+        a1 = q >= 2 ? z[64 * q - 128 + l] : 0.0;
+    }
+}
+
+// The coarsest solve as a kernel of its own (the coarsest level is larger
+// than the persistent small-level kernel handles, or the basic path runs):
+// wave 0 solves as band_solve_direct does, waves 1..3 stage the step rows of
+// the next chunk of 32 steps into LDS while wave 0 works through the current
+// one (two slots of 32 KB), with one workgroup barrier per chunk.  The chunks
+// run through the forward rows 0 .. M-1, then the backward rows M-1 .. 0, so
+// both sides pass 1 + 4 M / 64 barriers.  Workgroup k solves right-hand side
+// k (its arrays ks elements, its stop flag kstop ints after the first's).
+constexpr int BAND_SOLVE_THREADS = 256;
+constexpr int BAND_CHUNK = 32;
+
+__host__ __device__ inline size_t band_solve_lds(int M) { return ((size_t)M + 2 * BAND_CHUNK * 128) * sizeof(double); }
+
+template <typename T>
+static __global__ __launch_bounds__(BAND_SOLVE_THREADS) void k_coarse_solve(Lev<T> Cl, BandSolve B, size_t ks,
+                                                                               const int *stop, int kstop)
+{
+    const int rk = blockIdx.x;
+    if (stopped(stop ? stop + rk * kstop : stop)) return;
+    extern __shared__ double band_sm[];
+    double *z = band_sm, *slot = band_sm + B.M;
+    const int nb = B.M >> 6, nch = 4 * nb;   // chunks of 32 steps: 2 per block, forward then backward
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+    auto stage = [&](int c) {   // rows of chunk c into slot c & 1 (waves 1..3)
+        double *dst = slot + (size_t)(c & 1) * BAND_CHUNK * 128;
+        const int fwd = c < 2 * nb;
+        const int c2 = fwd ? c : c - 2 * nb;
+        for (int e = threadIdx.x - 64; e < BAND_CHUNK * 64; e += BAND_SOLVE_THREADS - 64) {
+            const int t = e >> 6, h = e & 63;   // row t of the chunk, double2 h of the row
+            const size_t row = fwd ? (size_t)(BAND_CHUNK * c2 + t) : (size_t)(B.M - 1 - BAND_CHUNK * c2 - t);
+            const double2 v = reinterpret_cast<const double2 *>((fwd ? B.FF : B.GG) + row * 128)[h];
+            reinterpret_cast<double2 *>(dst + (size_t)t * 128)[h] = v;
+        }
+    };
+    if (wave != 0) {
+        stage(0);
+        __syncthreads();
+        for (int c = 0; c < nch; ++c) {
+            if (c + 1 < nch) stage(c + 1);
+            __syncthreads();
+        }
+        return;
+    }
+    const T *bv = Cl.b + (size_t)rk * ks;
+    T *uv = Cl.u + (size_t)rk * ks;
+    const int nc = B.nc, m = B.m;
+    auto pos = [&](int k) { return (size_t)(k / nc + 1) * Cl.ld + (k % nc + 1); };
+    auto get = [&](int k) -> double { return k < m ? (double)bv[pos(k)] : 0.0; };
+    double a0 = get(l), a1 = get(64 + l), bn = get(128 + l), dp = B.Dp[l];
+    __syncthreads();
+    for (int c = 0; c < nch; ++c) {
+        const double *rows = slot + (size_t)(c & 1) * BAND_CHUNK * 128;
+        if (c < 2 * nb) {                      // forward, block q = c / 2
+            const int q = c >> 1;
+            if (!(c & 1)) {
+                band_steps<0, 1, 1, 32>(a0, a1, rows, l);
+            } else {
+                band_steps<32, 1, 1, 32>(a0, a1, rows, l);
+                z[64 * q + l] = a0 / dp;
+                a0 = a1;
+                a1 = bn;
+                bn = get(64 * (q + 3) + l);
+                dp = q + 1 < nb ? B.Dp[64 * (q + 1) + l] : 1.0;
+                if (q + 1 == nb) {             // backward starts from the top block
+                    a0 = z[64 * (nb - 1) + l];
+                    a1 = nb >= 2 ? z[64 * (nb - 2) + l] : 0.0;
+                }
+            }
+        } else {                               // backward, block q = nb - 1 - (c - 2 nb) / 2
+            const int c2 = c - 2 * nb, q = nb - 1 - (c2 >> 1);
+            if (!(c2 & 1)) {
+                band_steps<63, -1, 1, 32>(a0, a1, rows, l);   // k = 64q + 63 .. 64q + 32
+            } else {
+                band_steps<31, -1, 1, 32>(a0, a1, rows, l);   // k = 64q + 31 .. 64q
+                if (64 * q + l < m) uv[pos(64 * q + l)] = (T)a0;
+                a0 = a1;
+                a1 = q >= 2 ? z[64 * q - 128 + l] : 0.0;
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -511,6 +708,36 @@ static __global__ void k_sumsq_partial(Lev<T> L, const T *__restrict__ x, double
             const size_t p = (size_t)j * L.ld + i;
             const double v = RES ? (double)residual_point<T, NINE>(L, L.u, p) : (double)x[p];
             acc += v * v;
+        }
+    }
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+// Partial sums of s_p^2 with s_p = |b_p| + sum_d |A_d(p)| |x_(p+d)| (the
+// nine entries of the row, centre included): eps * sqrt(sum) / ||b|| bounds
+// the relative residual that rounding the exact solution to FP64 can leave,
+// the floor below which no FP64 vector's residual reliably goes.  An estimate
+// only, summed in plain FP64.
+template <bool NINE>
+static __global__ void k_floor_partial(Lev<double> L, const double *__restrict__ B, const double *__restrict__ X,
+                                       double *__restrict__ part)
+{
+    double acc = 0.0;
+    const int n = L.n;
+    const size_t ld = L.ld;
+    for (int j = 1 + blockIdx.x; j <= n; j += gridDim.x) {
+        for (int i = 1 + threadIdx.x; i <= n; i += blockDim.x) {
+            const size_t p = (size_t)j * ld + i;
+            double s = fabs(B[p]);
+            s += fabs(L.S[p]) * fabs(X[p - ld]) + fabs(L.W[p]) * fabs(X[p - 1]);
+            s += fabs(L.O[p]) * fabs(X[p]);
+            s += fabs(L.W[p + 1]) * fabs(X[p + 1]) + fabs(L.S[p + ld]) * fabs(X[p + ld]);
+            if (NINE) {
+                s += fabs(L.SW[p]) * fabs(X[p - ld - 1]) + fabs(L.NW[p + 1 - ld]) * fabs(X[p - ld + 1]);
+                s += fabs(L.NW[p]) * fabs(X[p + ld - 1]) + fabs(L.SW[p + ld + 1]) * fabs(X[p + ld + 1]);
+            }
+            acc += s * s;
         }
     }
     acc = block_sum(acc);

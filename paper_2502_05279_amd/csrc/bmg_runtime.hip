@@ -12,6 +12,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <type_traits>
 #include <utility>
 #include <vector>
@@ -92,7 +93,15 @@ extern "C" bmg_status bmg_tile_rows_get(int n, int *rows)
 
 namespace {
 
-enum { S_SUMSQ = 0, S_BNORM = 1, S_REL0 = 2, S_TMP = 3, S_RMAX = 4, S_SCALE = 5, S_NSCAL = 8 };
+enum { S_SUMSQ = 0, S_BNORM = 1, S_REL0 = 2, S_TMP = 3, S_RMAX = 4, S_SCALE = 5, S_FLOOR = 6, S_NSCAL = 8 };
+
+int coarsest_of(const bmg_options &o) { return o.coarsest_n > 0 ? o.coarsest_n : 3; }
+
+double ms_since(std::chrono::steady_clock::time_point t0)
+{
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+int persistent_of(const bmg_options &o) { return o.persistent_below_n > 0 ? o.persistent_below_n : SMALL_MAX_N; }
 
 // Walks the workspace layout; with base == nullptr it only measures.
 size_t plan(bmg_solver *h, int n, int kind, const bmg_options &o, char *base)
@@ -105,7 +114,8 @@ size_t plan(bmg_solver *h, int n, int kind, const bmg_options &o, char *base)
         return p;
     };
     int nl = 0, ns[MAXL];
-    for (int m = n; m >= 3 && nl < MAXL; m = (m - 1) / 2) ns[nl++] = m;
+    const int ncoarse = coarsest_of(o);
+    for (int m = n; m >= ncoarse && nl < MAXL; m = (m - 1) / 2) ns[nl++] = m;
     const bool f32 = o.precision == BMG_FP32_IR;
     for (int l = 0; l < nl; ++l) {
         const int ld = pitch_of(ns[l]);
@@ -174,7 +184,13 @@ size_t plan(bmg_solver *h, int n, int kind, const bmg_options &o, char *base)
     double *B0 = (double *)take(pl0 * 8);
     double *XH = (double *)take(pl0 * 8);
     double *XL = (double *)take(pl0 * 8);
-    double *LD = (double *)take(90 * 8);
+    // coarsest factor: band storage of L and D (one block, for export), and
+    // the rows of the one-wave solve
+    const int cm = ns[nl - 1] * ns[nl - 1], cw = ns[nl - 1] + 1, cM = band_padded(cm);
+    double *Lb = (double *)take(((size_t)cm * cw + cm) * 8);
+    double *FF = (double *)take((size_t)cM * 128 * 8);
+    double *GG = (double *)take((size_t)cM * 128 * 8);
+    double *Dp = (double *)take((size_t)cM * 8);
     int *flags = (int *)take(64);
     double *part = (double *)take(NPART * 8);
     double *scal = (double *)take(S_NSCAL * 8);
@@ -187,7 +203,14 @@ size_t plan(bmg_solver *h, int n, int kind, const bmg_options &o, char *base)
         h->B0 = B0;
         h->XH = XH;
         h->XL = XL;
-        h->LD = LD;
+        h->Lb = Lb;
+        h->Dd = Lb + (size_t)cm * cw;
+        h->band.FF = FF;
+        h->band.GG = GG;
+        h->band.Dp = Dp;
+        h->band.m = cm;
+        h->band.M = cM;
+        h->band.nc = ns[nl - 1];
         h->flags = flags;
         h->part = part;
         h->scal = scal;
@@ -224,6 +247,12 @@ bmg_status check_options(const bmg_options &o)
         return fail(BMG_EINVAL, "unknown smoother %d", o.smoother);
     if (o.smoother == BMG_SMOOTH_LINE && o.precision != BMG_FP64)
         return fail(BMG_EINVAL, "line relaxation runs FP64 hierarchies");
+    if (o.coarsest_n != 0 && (!valid_n(o.coarsest_n) || o.coarsest_n > BAND_MAX_NC))
+        return fail(BMG_EINVAL, "coarsest_n=%d must be 2^k-1 in [3, %d] (0 = 3)", o.coarsest_n, BAND_MAX_NC);
+    if (o.persistent_below_n != 0 && o.persistent_below_n != 1 &&
+        (!valid_n(o.persistent_below_n) || o.persistent_below_n > SMALL_MAX_N))
+        return fail(BMG_EINVAL, "persistent_below_n=%d must be 2^k-1 <= %d, 1 (none) or 0 (= %d)",
+                    o.persistent_below_n, SMALL_MAX_N, SMALL_MAX_N);
     return BMG_OK;
 }
 
@@ -347,14 +376,15 @@ bmg_status interp(bmg_solver *h, const Lev<T> &F, const Wts<T> &C, const Lev<T> 
 template <typename T>
 bmg_status coarse(bmg_solver *h, const Lev<T> &Cl, const int *stop)
 {
-    const size_t ks = h->ks[h->nlev - 1];
-    for (int k = 0; k < h->nrhs; ++k) {
-        Lev<T> Ck = Cl;
-        Ck.u += k * ks;
-        Ck.b += k * ks;
-        hipLaunchKernelGGL((k_coarse_solve<T>), dim3(1), dim3(64), 0, h->st, Ck, (const double *)h->LD,
-                           stop ? stop + k * h->kstop : stop);
+    static bool attr_set[2] = {false, false};
+    const int which = sizeof(T) == 8 ? 0 : 1;
+    if (!attr_set[which]) {
+        HIPCHK(hipFuncSetAttribute((const void *)k_coarse_solve<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)band_solve_lds(band_padded(BAND_MAX_NC * BAND_MAX_NC))));
+        attr_set[which] = true;
     }
+    hipLaunchKernelGGL((k_coarse_solve<T>), dim3(h->nrhs), dim3(BAND_SOLVE_THREADS), band_solve_lds(h->band.M), h->st,
+                       Cl, h->band, h->ks[h->nlev - 1], stop, h->kstop);
     LAUNCHCHK();
     return BMG_OK;
 }
@@ -546,9 +576,9 @@ bmg_status fused_post(bmg_solver *h, int l, int nu, const int *stop, bool norm =
     return BMG_OK;
 }
 
-// Coarse levels of at most SMALL_N points per side: their whole sub-cycle in
-// one workgroup (k_small_vcycle), iterates and right-hand sides in LDS.
-constexpr int SMALL_N = SMALL_MAX_N;
+// Coarse levels of at most persistent_below_n points per side: their whole
+// sub-cycle in one workgroup (k_small_vcycle), iterates and right-hand sides in
+// LDS.
 
 template <typename T>
 bmg_status small_cycle(bmg_solver *h, int l, const int *stop)
@@ -562,7 +592,7 @@ bmg_status small_cycle(bmg_solver *h, int l, const int *stop)
         if (k + 1 < S.nl) S.C[k] = wts<T>(h, l + k);
     }
     const int off = small_layout(S);
-    S.LD = h->LD;
+    S.band = h->band;
     S.nu1 = h->opt.nu1;
     S.nu2 = h->opt.nu2;
     S.ks0 = h->ks[l];
@@ -584,7 +614,7 @@ template <typename T>
 bmg_status fused_cycle_from(bmg_solver *h, int l, const int *stop, bool norm)
 {
     if (l == h->nlev - 1) return coarse<T>(h, lev<T>(h, l), stop);
-    if (l >= 1 && lev<T>(h, l).n <= SMALL_N) return small_cycle<T>(h, l, stop);
+    if (l >= 1 && lev<T>(h, l).n <= persistent_of(h->opt)) return small_cycle<T>(h, l, stop);
     TRY(fused_pre<T>(h, l, h->opt.nu1, stop));
     TRY(fused_cycle_from<T>(h, l + 1, stop, false));
     return fused_post<T>(h, l, h->opt.nu2, stop, norm && l == 0);
@@ -734,6 +764,19 @@ bmg_status pack_out(bmg_solver *h, const double *src, double *dst)
     return BMG_OK;
 }
 
+// eps * || |A| |XH| + |B| || into scal[S_FLOOR] (unnormalised).
+bmg_status floor_sum(bmg_solver *h, const double *B, const double *XH)
+{
+    const Lev<double> &L = h->L[0];
+    const int nb = std::min(NPART_ROWS, L.n);
+    if (h->nine[0]) hipLaunchKernelGGL((k_floor_partial<true>), dim3(nb), dim3(256), 0, h->st, L, B, XH, h->part);
+    else hipLaunchKernelGGL((k_floor_partial<false>), dim3(nb), dim3(256), 0, h->st, L, B, XH, h->part);
+    hipLaunchKernelGGL(k_sumsq_final, dim3(1), dim3(1024), 0, h->st, (const double *)h->part, nb, h->scal + S_FLOOR,
+                       nullptr, h->count, h->stop, (const double *)(h->scal + S_BNORM), 0.0, 0, 0.0);
+    LAUNCHCHK();
+    return BMG_OK;
+}
+
 }  // namespace
 
 namespace bmgi {
@@ -812,6 +855,7 @@ bmg_status bmg_workspace_bytes(int n, int kind, const bmg_options *o, size_t *by
     bmg_default_options(&d);
     const bmg_options &op = o ? *o : d;
     TRY(check_options(op));
+    if (coarsest_of(op) > n) return fail(BMG_EINVAL, "coarsest_n=%d exceeds n=%d", op.coarsest_n, n);
     *bytes = plan(nullptr, n, kind, op, nullptr);
     return BMG_OK;
 }
@@ -829,23 +873,13 @@ bmg_status bmg_discretize(const double *k, const double *f, int n, double *stenc
     return BMG_OK;
 }
 
-bmg_status bmg_setup(bmg_solver **out, const double *stencil, int n, int kind, const bmg_options *o,
-                     void *workspace, size_t ws_bytes, bmg_stream stream)
+}  // extern "C"
+
+// The set-up of bmg_setup into the handle h (fresh), after the arguments have
+// been checked; on failure the caller releases h.
+static bmg_status setup_into(bmg_solver *h, const double *stencil, int n, int kind, const bmg_options &op,
+                             void *workspace, size_t ws_bytes, size_t need, bmg_stream stream)
 {
-    if (!out) return fail(BMG_EINVAL, "out pointer is NULL");
-    *out = nullptr;
-    if (!valid_n(n)) return fail(BMG_EINVAL, "n=%d is not 2^m-1 with 2 <= m <= 15", n);
-    if (kind != 5 && kind != 9) return fail(BMG_EINVAL, "stencil kind %d is not 5 or 9", kind);
-    if (!stencil) return fail(BMG_EINVAL, "stencil is NULL");
-    bmg_options op;
-    bmg_default_options(&op);
-    if (o) op = *o;
-    TRY(check_options(op));
-    const size_t need = plan(nullptr, n, kind, op, nullptr);
-    if (!workspace || ws_bytes < need || ((uintptr_t)workspace & (ALIGN - 1)))
-        return fail(BMG_EWORKSPACE, "workspace %p of %zu bytes; need %zu bytes, 256-byte aligned",
-                    workspace, ws_bytes, need);
-    bmg_solver *h = new bmg_solver();
     h->n = n;
     h->kind = kind;
     h->opt = op;
@@ -853,7 +887,7 @@ bmg_status bmg_setup(bmg_solver **out, const double *stencil, int n, int kind, c
     h->ws = (char *)workspace;
     h->ws_bytes = ws_bytes;
     plan(h, n, kind, op, h->ws);
-    auto bail = [&](bmg_status s) { delete h; return s; };
+    auto bail = [&](bmg_status s) { return s; };
 #define SCHK(x)                                  \
     do {                                         \
         bmg_status s_ = (x);                     \
@@ -874,7 +908,10 @@ bmg_status bmg_setup(bmg_solver **out, const double *stencil, int n, int kind, c
         }
         hipLaunchKernelGGL(k_rap, grid2(nc, nc, dim3(32, 4)), dim3(32, 4), 0, h->st, h->L[l], h->C[l], h->L[l + 1]);
     }
-    hipLaunchKernelGGL(k_coarse_factor, dim3(1), dim3(64), 0, h->st, h->L[h->nlev - 1], h->LD, h->flags);
+    hipLaunchKernelGGL(k_band_factor, dim3(1), dim3(BAND_FACTOR_THREADS), 0, h->st, h->L[h->nlev - 1], h->Lb, h->Dd,
+                       h->flags);
+    hipLaunchKernelGGL(k_band_expand, dim3(h->band.M / 4), dim3(256), 0, h->st, h->band.nc, (const double *)h->Lb,
+                       (const double *)h->Dd, (double *)h->band.FF, (double *)h->band.GG, (double *)h->band.Dp);
     if (op.smoother == BMG_SMOOTH_LINE) {
         // y-lines in the grid's frame; x-lines on the transposed O (in the
         // scratch plane) and W
@@ -937,6 +974,45 @@ bmg_status bmg_setup(bmg_solver **out, const double *stencil, int n, int kind, c
                                                : (flags & F_BREAK_COARSE) ? "coarsest pivot <= 0"
                                                                           : "line factor pivot <= 0"));
 #undef SCHK
+    return BMG_OK;
+}
+
+// Arguments of bmg_setup, checked; *need receives the workspace bytes.
+static bmg_status check_setup(const double *stencil, int n, int kind, const bmg_options *o, bmg_options *op,
+                              size_t *need)
+{
+    if (!valid_n(n)) return fail(BMG_EINVAL, "n=%d is not 2^m-1 with 2 <= m <= 15", n);
+    if (kind != 5 && kind != 9) return fail(BMG_EINVAL, "stencil kind %d is not 5 or 9", kind);
+    if (!stencil) return fail(BMG_EINVAL, "stencil is NULL");
+    bmg_default_options(op);
+    if (o) *op = *o;
+    TRY(check_options(*op));
+    if (coarsest_of(*op) > n) return fail(BMG_EINVAL, "coarsest_n=%d exceeds n=%d", op->coarsest_n, n);
+    *need = plan(nullptr, n, kind, *op, nullptr);
+    return BMG_OK;
+}
+
+extern "C" {
+
+bmg_status bmg_setup(bmg_solver **out, const double *stencil, int n, int kind, const bmg_options *o,
+                     void *workspace, size_t ws_bytes, bmg_stream stream)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!out) return fail(BMG_EINVAL, "out pointer is NULL");
+    *out = nullptr;
+    bmg_options op;
+    size_t need = 0;
+    TRY(check_setup(stencil, n, kind, o, &op, &need));
+    if (!workspace || ws_bytes < need || ((uintptr_t)workspace & (ALIGN - 1)))
+        return fail(BMG_EWORKSPACE, "workspace %p of %zu bytes; need %zu bytes, 256-byte aligned",
+                    workspace, ws_bytes, need);
+    bmg_solver *h = new bmg_solver();
+    const bmg_status s = setup_into(h, stencil, n, kind, op, workspace, ws_bytes, need, stream);
+    if (s != BMG_OK) {
+        delete h;
+        return s;
+    }
+    h->t_setup_ms = ms_since(t0);
     *out = h;
     return BMG_OK;
 }
@@ -1155,6 +1231,7 @@ static bmg_status poll(bmg_solver *h, int cs[2])
 
 bmg_status bmg_solve(bmg_solver *h, const double *rhs, double *x, double tol, bmg_info *info)
 {
+    const auto t0 = std::chrono::steady_clock::now();
     if (!h || !rhs || !x) return fail(BMG_EINVAL, "NULL argument");
     if (!(tol >= 0.0)) return fail(BMG_EINVAL, "tol must be >= 0");
     const Lev<double> &L = h->L[0];
@@ -1174,7 +1251,10 @@ bmg_status bmg_solve(bmg_solver *h, const double *rhs, double *x, double tol, bm
         HIPCHK(hipMemsetAsync(h->XH, 0, pl0, h->st));
         TRY(pack_out(h, h->XH, x));
         HIPCHK(hipStreamSynchronize(h->st));
-        if (info) { info->cycles = 0; info->rel_res = 0.0; info->rho = 0.0; }
+        if (info) {
+            info->cycles = 0; info->rel_res = 0.0; info->rho = 0.0; info->floor_est = 0.0;
+            info->t_setup_ms = h->t_setup_ms; info->t_solve_ms = ms_since(t0); info->interp_used = h->opt.interp;
+        }
         return BMG_OK;
     }
     double init[2] = {sqrt(v[S_TMP]), sqrt(v[S_SUMSQ]) / sqrt(v[S_TMP])};
@@ -1233,6 +1313,11 @@ bmg_status bmg_solve(bmg_solver *h, const double *rhs, double *x, double tol, bm
         HIPCHK(hipMemsetAsync(h->XL, 0, pl0, h->st));
     }
     TRY(pack_out(h, h->XH, x));
+    double fl = 0.0;
+    if (info) {
+        TRY(floor_sum(h, h->B0, h->XH));
+        HIPCHK(hipMemcpyAsync(&fl, h->scal + S_FLOOR, sizeof fl, hipMemcpyDeviceToHost, h->st));
+    }
     std::vector<double> hist(std::max(cs[0], 1));
     HIPCHK(hipMemcpyAsync(hist.data(), h->hist, cs[0] * sizeof(double), hipMemcpyDeviceToHost, h->st));
     HIPCHK(hipStreamSynchronize(h->st));
@@ -1243,6 +1328,10 @@ bmg_status bmg_solve(bmg_solver *h, const double *rhs, double *x, double tol, bm
         const double r0 = h->f32 ? hist[0] : init[1];
         info->rho = steps > 0 ? pow(info->rel_res / r0, 1.0 / steps) : 0.0;
         if (info->history) memcpy(info->history, hist.data(), cs[0] * sizeof(double));
+        info->floor_est = ldexp(sqrt(fl), -53) / init[0];
+        info->t_setup_ms = h->t_setup_ms;
+        info->t_solve_ms = ms_since(t0);
+        info->interp_used = h->opt.interp;
     }
     if (cs[1] == 2) return fail(BMG_EDIVERGED, "residual %.3e after %d cycles", hist[cs[0] - 1], steps);
     if (cs[1] == 3) return fail(BMG_ENOCONV, "relative residual %.3e > tol %.3e after %d cycles",
@@ -1293,13 +1382,18 @@ bmg_status bmg_solve_select(bmg_solver *learned, bmg_solver *boxmg, const double
     TRY(probe(boxmg, rhs, x, scratch, probe_cycles, &rho[1]));
     HIPCHK(hipStreamSynchronize(boxmg->st));
     TRY(probe(learned, rhs, x, x, probe_cycles, &rho[0]));
+    // the learned probe's write of x completes before any other stream uses x
+    HIPCHK(hipStreamSynchronize(learned->st));
     if (rho[0] > rho[1]) {
         *used = BMG_INTERP_BOXMG;
         HIPCHK(hipMemcpyAsync(x, scratch, (size_t)boxmg->n * boxmg->n * sizeof(double), hipMemcpyDeviceToDevice,
                               boxmg->st));
         HIPCHK(hipStreamSynchronize(boxmg->st));
         const bmg_status s = bmg_solve(boxmg, rhs, x, tol, info);
-        if (info) info->cycles += probe_cycles;
+        if (info) {
+            info->cycles += probe_cycles;
+            info->interp_used = BMG_INTERP_BOXMG;
+        }
         return s;
     }
     // the learned hierarchy continues in chunks of WATCH cycles; a chunk whose
@@ -1311,26 +1405,36 @@ bmg_status bmg_solve_select(bmg_solver *learned, bmg_solver *boxmg, const double
     bmg_status s = BMG_ENOCONV;
     double *hist = info ? info->history : nullptr;
     bmg_info ci{};
+    // each chunk's history goes after the previous chunks' (the caller's
+    // array holds max_cycles + 1 entries, the cycles after the probes)
     while (done < maxc + probe_cycles) {
         learned->opt.max_cycles = std::min(WATCH, maxc + probe_cycles - done);
         ci = bmg_info{};
-        ci.history = hist;
+        ci.history = hist ? hist + (done - probe_cycles) : nullptr;
         s = bmg_solve(learned, rhs, x, tol, &ci);
         learned->opt.max_cycles = maxc;
         done += ci.cycles;
         if (s != BMG_ENOCONV) break;
         if (ci.rho > rho[1]) {
             *used = BMG_INTERP_BOXMG;
+            const int left = maxc + probe_cycles - done;
+            if (left <= 0) break;
+            const int keep = boxmg->opt.max_cycles;
+            boxmg->opt.max_cycles = std::min(keep, left);
             ci = bmg_info{};
-            ci.history = hist;
+            ci.history = hist ? hist + (done - probe_cycles) : nullptr;
             s = bmg_solve(boxmg, rhs, x, tol, &ci);
+            boxmg->opt.max_cycles = keep;
             done += ci.cycles;
             break;
         }
     }
     if (info) {
+        double *h0 = info->history;
         *info = ci;
+        info->history = h0;
         info->cycles = done;
+        info->interp_used = *used;
     }
     return s;
 }
@@ -1357,7 +1461,8 @@ static bmg_status locate(bmg_solver *h, int level, int field, char **ptr, size_t
 {
     if (!h) return fail(BMG_EINVAL, "NULL handle");
     if (field == BMG_F_COARSE_LD) {
-        *ptr = (char *)h->LD; *es = 8; *pitch = 90 * 8; *rows = 1; *width = 90;
+        const size_t cnt = (size_t)h->band.m * (h->band.nc + 1) + h->band.m;
+        *ptr = (char *)h->Lb; *es = 8; *pitch = cnt * 8; *rows = 1; *width = cnt;
         return BMG_OK;
     }
     if (field == BMG_F_XLO) {

@@ -1,0 +1,175 @@
+"""Coarsest levels larger than 3x3 on the GPU against the CPU oracle.
+
+The coarsest level is solved directly with the square-root-free Cholesky
+factor of its band matrix (Fig. vcycle_flowchart: a Cholesky factorisation on
+the coarsest grid).  The factor is formed on the GPU column by column and the
+solve runs in one wave; both take every sum in the oracle's order, so the
+factor, every iterate and the cycle counts are compared for exact equality.
+The cases cover each place the direct solve runs: inside the persistent
+small-level kernel (the coarsest level below a small level), in its own
+staged kernel (the coarsest level is the largest small level, or the basic
+path, or no persistent kernel), FP64 and the FP32 cycle inside refinement."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import ref
+from paper_2502_05279_amd import boxmg, inputs
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def same(a, b, what=""):
+    a, b = np.asarray(a), np.asarray(b)
+    assert a.shape == b.shape, (what, a.shape, b.shape)
+    bad = ~(a == b)
+    assert not bad.any(), f"{what}: {bad.sum()} of {a.size} differ; first at " \
+                          f"{np.argwhere(bad)[0]}: {a[bad][0]!r} vs {b[bad][0]!r}"
+
+
+def problem(n, block=64, lo=-4, hi=4, seed=0):
+    return inputs.jumping(n, min(block, (n + 1) // 4), lo, hi, 700 + seed, 800 + seed)
+
+
+def gpu_problem(p):
+    return boxmg.discretize(dev(p.k), dev(p.f))
+
+
+@pytest.mark.parametrize("n,nc", [(31, 7), (63, 15), (127, 31), (127, 63), (255, 63), (63, 63)])
+def test_band_factor_bitwise(gpu, n, nc):
+    """The coarsest band factor (L in band storage, then D) equals the
+    oracle's bit for bit."""
+    p = problem(n, seed=1)
+    st, _ = gpu_problem(p)
+    with boxmg.Solver(st, coarsest_n=nc) as S:
+        H = ref.Hierarchy(host(st), coarsest=nc)
+        assert S.nlev == H.nlev and S.level_n(S.nlev - 1) == nc
+        Lb, D = H.coarse_factor()
+        m, w = Lb.shape
+        LD = host(S.export(0, "LD"))
+        same(LD[:m * w].reshape(m, w), Lb, "coarsest L")
+        same(LD[m * w:], D, "coarsest D")
+
+
+@pytest.mark.parametrize("n,nc", [(31, 7), (127, 31), (127, 63)])
+def test_coarse_step_bitwise(gpu, n, nc):
+    """One direct solve of the coarsest level on a random right-hand side, in
+    FP64 and (widened, solved, rounded) on the FP32 hierarchy."""
+    p = problem(n, seed=2)
+    st, _ = gpu_problem(p)
+    with boxmg.Solver(st, coarsest_n=nc, precision=boxmg.BMG_FP32_IR) as S:
+        H = ref.Hierarchy(host(st), coarsest=nc)
+        L = H.nlev - 1
+        Lb, D = H.coarse_factor()
+        rng = np.random.default_rng(nc)
+        b = np.zeros((nc + 2, nc + 2))
+        b[1:-1, 1:-1] = rng.standard_normal((nc, nc))
+        S.import_(L, "b", dev(b))
+        S.step(L, "coarse")
+        x = ref.band_ldlt_solve(Lb, D, b[1:-1, 1:-1].reshape(-1))
+        same(host(S.export(L, "u"))[1:-1, 1:-1].reshape(-1), x, "coarse solve FP64")
+        b32 = b.astype(np.float32)
+        S.import_(L, "b32", dev(b32))
+        S.step(L, "coarse", fp32=True)
+        x32 = ref.band_ldlt_solve(Lb, D, b32[1:-1, 1:-1].reshape(-1).astype(np.float64)).astype(np.float32)
+        same(host(S.export(L, "u32"))[1:-1, 1:-1].reshape(-1), x32, "coarse solve FP32")
+
+
+# (n, coarsest, persistent_below_n, kernels): the direct solve inside the
+# persistent kernel (511/31, 255/7), as its own kernel after the fused passes
+# (511/63, 1023/63), on the basic path (255/15) and with no persistent kernel
+# at all (127/3 and 255/15 with persistent_below_n = 1)
+SOLVES = [(255, 7, 0, "fused"), (511, 31, 0, "fused"), (511, 63, 0, "fused"), (1023, 63, 0, "fused"),
+          (255, 15, 0, "basic"), (127, 3, 1, "fused"), (255, 15, 1, "fused")]
+
+
+@pytest.mark.parametrize("n,nc,pb,kernels", SOLVES)
+def test_solve_with_larger_coarsest_matches_oracle(gpu, n, nc, pb, kernels):
+    """Whole FP64 solves to 1e-10 (plain cycles, then double-FP64 refinement):
+    cycle count, both parts of the iterate bitwise, history to 1e-12."""
+    p = problem(n, seed=3)
+    st, rhs = gpu_problem(p)
+    kern = boxmg.BMG_KERNELS_FUSED if kernels == "fused" else boxmg.BMG_KERNELS_BASIC
+    with boxmg.Solver(st, max_cycles=400, coarsest_n=nc, persistent_below_n=pb, kernels=kern) as S:
+        x, info = S.solve(rhs, tol=1e-10, raise_on_noconv=False)
+        H = ref.Hierarchy(host(st), coarsest=nc)
+        u, hist = H.solve(ref.pad(host(rhs)), tol=1e-10, max_cycles=400, refine_factor=16)
+        assert info["cycles"] == len(hist)
+        same(host(x), u[1:-1, 1:-1], "solution (high part)")
+        same(host(S.export(0, "xlo")), H.xl, "solution (low part)")
+        h = np.array(info["history"])
+        assert np.all(np.abs(h - hist) <= 1e-12 * hist), np.abs(h / hist - 1).max()
+        assert info["status"] == 0 and info["rel_res"] <= 1e-10
+
+
+@pytest.mark.parametrize("n,nc", [(255, 31), (511, 63)])
+def test_fp32_refinement_with_larger_coarsest_matches_oracle(gpu, n, nc):
+    """FP32 V-cycles (FP64 direct coarsest solve) inside double-FP64
+    refinement, every step bitwise."""
+    p = problem(n, 128, -3, 3, seed=4)
+    st, rhs = gpu_problem(p)
+    with boxmg.Solver(st, max_cycles=300, coarsest_n=nc, precision=boxmg.BMG_FP32_IR) as S:
+        x, info = S.solve(rhs, tol=1e-11)
+        H = ref.Hierarchy(host(st), coarsest=nc)
+        u, hist = H.solve_ir(ref.pad(host(rhs)), tol=1e-11, max_iter=300)
+        assert info["cycles"] == len(hist) - 1
+        same(host(x), u[1:-1, 1:-1], "refined solution (high part)")
+        same(host(S.export(0, "xlo")), H.xl, "refined solution (low part)")
+
+
+def test_larger_coarsest_cuts_cycles_on_blocky_field(gpu):
+    """The headline generator (64-cell blocks, log10 k in [-4, 4], seeds 201 and
+    202) at 1023^2: a 63^2 direct coarsest level takes 35 cycles where 3^2 takes
+    872 (the oracle's counts; the GPU's equal the oracle's in the tests
+    above)."""
+    p = inputs.jumping_4095(n=1023)
+    st, rhs = gpu_problem(p)
+    counts = {}
+    for nc in (3, 63):
+        with boxmg.Solver(st, max_cycles=2000, coarsest_n=nc) as S:
+            _, info = S.solve(rhs, tol=1e-10, raise_on_noconv=False)
+            counts[nc] = info["cycles"]
+    assert counts == {3: 872, 63: 35}, counts
+
+
+def test_coarsest_option_errors(gpu):
+    p = problem(63, seed=6)
+    st, _ = gpu_problem(p)
+    for bad in (5, 127, 2):
+        with pytest.raises(boxmg.BoxMGError):
+            boxmg.Solver(st, coarsest_n=bad)
+    with pytest.raises(boxmg.BoxMGError):
+        boxmg.Solver(st[:31, :31].contiguous(), coarsest_n=63)
+    with pytest.raises(boxmg.BoxMGError):
+        boxmg.Solver(st, persistent_below_n=127)
+
+
+def test_info_fields(gpu):
+    """bmg_info: set-up and solve times, the interpolation used, and the FP64
+    floor estimate eps || |A| |x| + |b| || / ||b|| (recomputed here on the host
+    from the returned x)."""
+    p = problem(255, seed=7)
+    st, rhs = gpu_problem(p)
+    with boxmg.Solver(st, coarsest_n=15) as S:
+        x, info = S.solve(rhs, tol=1e-10)
+        assert info["t_setup_ms"] > 0 and info["t_solve_ms"] > 0
+        assert info["interp_used"] == boxmg.BMG_INTERP_BOXMG
+        H = ref.Hierarchy(host(st))
+        O, W, S_, _, _ = H.op(0)
+        X = np.abs(ref.pad(host(x)))
+        b = np.abs(host(rhs))
+        s = b + np.abs(O[1:-1, 1:-1]) * X[1:-1, 1:-1]
+        s = s + np.abs(W[1:-1, 1:-1]) * X[1:-1, :-2] + np.abs(W[1:-1, 2:]) * X[1:-1, 2:]
+        s = s + np.abs(S_[1:-1, 1:-1]) * X[:-2, 1:-1] + np.abs(S_[2:, 1:-1]) * X[2:, 1:-1]
+        want = 2.0 ** -53 * np.linalg.norm(s) / np.linalg.norm(b)
+        assert info["floor_est"] == pytest.approx(want, rel=1e-10)
