@@ -1554,6 +1554,7 @@ struct SmallH {
 };
 
 constexpr int SMALL_MAX_N = 63;
+constexpr int SMALL_LDS_MAX = 160 * 1024;   // LDS of one workgroup on gfx950
 
 // The stencil rows of this thread's points, one per colour c (colour c: i odd
 // if c & 1, j odd if c & 2): a[c] holds SW, S, SE (the NW entry of the point

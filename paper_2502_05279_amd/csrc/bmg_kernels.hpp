@@ -298,7 +298,6 @@ static __global__ void k_rap(Lev<double> F, Wts<double> C, Lev<double> Cl)
 // and, for the solve, the same entries rearranged by the lane that uses them
 // (BandSolve below).
 constexpr int BAND_MAX_NC = 63;
-constexpr int BAND_FACTOR_THREADS = 128;
 
 // A(i, i - d) of the coarsest level's matrix, d = 0 .. w, from its compact
 // stencil: d = 1 W, nc - 1 SE (the NW entry of the point below-right), nc S,
@@ -316,72 +315,127 @@ __device__ inline double band_entry(const Lev<double> &L, int i, int d)
     return 0.0;
 }
 
-// Column by column (one workgroup; thread t works on row j + t of column j):
-//   v_k = L_jk D_k (k = j-w .. j-1);  D_j = A_jj - sum_k L_jk v_k;
-//   L_ij = (A_ij - sum_{k = i-w .. j-1} L_ik v_k) / D_j  (i = j+1 .. j+w),
-// every sum over increasing k.  The rows j .. j+w of L live in an LDS ring of
-// w + 1 rows (a row's slot is reused by row j + w + 1, which starts at column
-// j + 1), D_k in a ring of the same length.
+// A workgroup barrier that orders LDS only: loads from global memory stay in
+// flight across it.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// The factor, column by column in one workgroup, in right-looking form: once
+// column k is final (D_k = a_kk, L_ik = a_ik / D_k, v_j = L_jk D_k), every
+// entry of the trailing window takes its term, a_ij <- a_ij - L_ik v_j
+// (k < j <= i <= k + w).  An entry thus receives its terms in order of
+// increasing k, each the same product of the same operands as in the
+// column-by-column sums of the definition
+//   D_j = A_jj - sum_k L_jk v_k,  L_ij = (A_ij - sum_k L_ik v_k) / D_j,
+// so the factor is the same to the bit, while the w (w + 1) / 2 updates of a
+// column run in parallel: two barriers per column.  The window's rows live in
+// an LDS ring (row i, column j at slot i mod RR, offset j - i + w); row
+// k + w + 1 enters at column k with its entries of A, which are requested a
+// chunk of 64 columns ahead (registers, then a staging buffer), so no column
+// waits on memory.
+constexpr int BAND_FACTOR_THREADS = 1024;
+constexpr int BAND_NNZ = 5;   // lower-band entries of a row of A: distances 0, 1, nc - 1, nc, nc + 1
+
+__device__ inline int band_nz_dist(int e, int nc) { return e == 0 ? 0 : e == 1 ? 1 : e == 2 ? nc - 1 : e == 3 ? nc : nc + 1; }
+
 static __global__ __launch_bounds__(BAND_FACTOR_THREADS) void k_band_factor(Lev<double> L, double *__restrict__ Lb,
                                                                              double *__restrict__ D,
                                                                              int *__restrict__ flags)
 {
-    __shared__ double ring[(BAND_MAX_NC + 2) * (BAND_MAX_NC + 1)];
-    __shared__ double dring[BAND_MAX_NC + 2];
-    __shared__ double v[BAND_MAX_NC + 1];
-    __shared__ double col[BAND_MAX_NC + 2];
-    const int nc = L.n, m = nc * nc, w = nc + 1, R = w + 1, t = threadIdx.x;
-    int bad = 0;
-    for (int j = 0; j < m; ++j) {
-        if (t < w) {
-            const int k = j - w + t;
-            v[t] = k >= 0 ? ring[(j % R) * w + t] * dring[k % R] : 0.0;
-        }
-        __syncthreads();
-        const int i = j + t;
-        if (t <= w && i < m) {
-            double s = band_entry(L, i, t);
-            const double *Li = ring + (i % R) * w;
-            for (int k = max(0, i - w); k < j; ++k) s = s - Li[k - i + w] * v[k - j + w];
-            col[t] = s;
-        }
-        __syncthreads();
-        const double d = col[0];
-        if (t == 0) {
-            dring[j % R] = d;
-            D[j] = d;
-            if (!(d > 0.0)) bad = 1;
-        } else if (t <= w && i < m) {
-            const double l = col[t] / d;
-            ring[(i % R) * w + (w - t)] = l;
-            Lb[(size_t)i * w + (w - t)] = l;
-        }
-        __syncthreads();
+    constexpr int RW = BAND_MAX_NC + 2, RR = BAND_MAX_NC + 3;
+    __shared__ double ring[RR * RW];
+    __shared__ double Lcol[BAND_MAX_NC + 2], vcol[BAND_MAX_NC + 2];
+    __shared__ double stage[2][64 * BAND_NNZ];
+    const int nc = L.n, m = nc * nc, w = nc + 1, t = threadIdx.x;
+    auto at = [&](int i, int j) -> double & { return ring[(i % RR) * RW + (j - i + w)]; };
+    // rows 0 .. w of A, and the entries of the rows entering during the first chunk
+    for (int e = t; e < (w + 1) * (w + 1); e += blockDim.x) {
+        const int i = e / (w + 1), off = e % (w + 1), j = i - w + off;
+        if (i < m) at(i, j) = j >= 0 ? band_entry(L, i, i - j) : 0.0;
     }
-    if (t == 0 && bad) atomicOr(flags, F_BREAK_COARSE);
+    auto entering = [&](int c, int u) -> double {   // entry u of the staging buffer of chunk c
+        const int i = 64 * c + u / BAND_NNZ + w + 1;
+        return i < m ? band_entry(L, i, band_nz_dist(u % BAND_NNZ, nc)) : 0.0;
+    };
+    if (t < 64 * BAND_NNZ) stage[0][t] = entering(0, t);
+    // this thread's entries of the trailing triangle, e = t + s * blockDim.x
+    const int ntri = w * (w + 1) / 2;
+    int di[3], dj[3];
+#pragma unroll
+    for (int s2 = 0; s2 < 3; ++s2) {
+        const int e = t + s2 * BAND_FACTOR_THREADS;
+        int d = (int)((1.0f + sqrtf(8.0f * (float)e + 1.0f)) * 0.5f);
+        while (d > 1 && d * (d - 1) / 2 > e) --d;
+        while ((d + 1) * d / 2 <= e) ++d;
+        di[s2] = e < ntri ? d : 0;
+        dj[s2] = e - d * (d - 1) / 2 + 1;
+    }
+    const int tnew = t - (BAND_FACTOR_THREADS - (w + 1));   // offset in the entering row, if >= 0
+    double pf = 0.0;
+    int bad = 0;
+    lds_barrier();
+    for (int k = 0; k < m; ++k) {
+        const int kc = k & 63, c = k >> 6;
+        if (kc == 0 && t < 64 * BAND_NNZ) pf = entering(c + 1, t);   // in flight for the whole chunk
+        if (t <= w) {
+            const double Dk = at(k, k);
+            if (t == 0) {
+                D[k] = Dk;
+                if (!(Dk > 0.0)) bad = 1;
+            } else if (k + t < m) {
+                const int i = k + t;
+                const double l = at(i, k) / Dk;
+                Lcol[t] = l;
+                vcol[t] = l * Dk;
+                Lb[(size_t)i * w + (k - i + w)] = l;
+            }
+        }
+        lds_barrier();
+#pragma unroll
+        for (int s2 = 0; s2 < 3; ++s2) {
+            const int i = k + di[s2], j = k + dj[s2];
+            if (di[s2] > 0 && i < m) at(i, j) = at(i, j) - Lcol[di[s2]] * vcol[dj[s2]];
+        }
+        if (tnew >= 0 && k + w + 1 < m) {
+            const int i = k + w + 1, d = w - tnew;
+            int u = -1;
+#pragma unroll
+            for (int e = 0; e < BAND_NNZ; ++e)
+                if (d == band_nz_dist(e, nc)) u = e;
+            at(i, i - d) = u >= 0 ? stage[c & 1][kc * BAND_NNZ + u] : 0.0;
+        }
+        if (kc == 63 && t < 64 * BAND_NNZ) stage[(c + 1) & 1][t] = pf;
+        lds_barrier();
+    }
+    if (bad) atomicOr(flags, F_BREAK_COARSE);
 }
 
 // The factor as the one-wave solve reads it.  Unknowns are padded to M, a
 // multiple of 64; lane l keeps the pending values of unknowns 64q + l (block
 // q, "current") and 64(q+1) + l (block q+1, "next"), since w <= 64 means an
-// unknown only couples to its own block and the neighbouring one.  Every step
-// reads one row of 2 x 64 doubles (FF for the forward substitution, GG for the
-// backward one):
-//   forward step j = 64q + r:  FF[j][l] = L(64q + l, j) for l > r,
-//                              FF[j][64 + l] = L(64q + 64 + l, j);
-//   backward step k = 64q + r: GG[k][l] = L(k, 64q + l) for l < r,
-//                              GG[k][64 + l] = L(k, 64q - 64 + l);
+// unknown only couples to its own block and the neighbouring one.  A step
+// subtracts multiples of one final unknown from at most w <= 64 pending ones,
+// one per lane, so every step reads one row of 64 doubles (CF for the forward
+// substitution, CG for the backward one):
+//   forward step j = 64q + r:  CF[j][l] = L(64q + l, j)       for l > r (current block),
+//                                         L(64q + 64 + l, j)  for l <= r (next block);
+//   backward step k = 64q + r: CG[k][l] = L(k, 64q + l)       for l < r (current block),
+//                                         L(k, 64q - 64 + l)  for l >= r (previous block);
 // zero wherever the entry lies outside the band or the matrix; Dp = D padded
-// with ones.
+// with ones.  The 64 rows of a block are contiguous (32 KB).
 struct BandSolve {
-    const double *FF, *GG, *Dp;
+    const double *CF, *CG, *Dp;
     int m, M, nc;
 };
 
 __host__ __device__ inline int band_padded(int m) { return (m + 63) & ~63; }
 
 static __global__ void k_band_expand(int nc, const double *__restrict__ Lb, const double *__restrict__ D,
-                                     double *__restrict__ FF, double *__restrict__ GG, double *__restrict__ Dp)
+                                     double *__restrict__ CF, double *__restrict__ CG, double *__restrict__ Dp)
 {
     const int m = nc * nc, w = nc + 1, M = band_padded(m);
     const int l = threadIdx.x & 63;
@@ -392,11 +446,9 @@ static __global__ void k_band_expand(int nc, const double *__restrict__ Lb, cons
     auto Lik = [&](int i, int k) -> double {
         return (i < m && k >= 0 && k < i && i - k <= w) ? Lb[(size_t)i * w + (k - i + w)] : 0.0;
     };
-    const size_t o = (size_t)s * 128 + l;
-    FF[o] = l > r ? Lik(64 * q + l, s) : 0.0;
-    FF[o + 64] = Lik(64 * q + 64 + l, s);
-    GG[o] = l < r ? Lik(s, 64 * q + l) : 0.0;
-    GG[o + 64] = q >= 1 ? Lik(s, 64 * q - 64 + l) : 0.0;
+    const size_t o = (size_t)s * 64 + l;
+    CF[o] = l > r ? Lik(64 * q + l, s) : Lik(64 * q + 64 + l, s);
+    CG[o] = l < r ? Lik(s, 64 * q + l) : (q >= 1 ? Lik(s, 64 * q - 64 + l) : 0.0);
     if (l == 0) Dp[s] = s < m ? D[s] : 1.0;
 }
 
@@ -408,47 +460,52 @@ __device__ __forceinline__ double readlane_d(double v, int lane)
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-// One step: the final value held by lane LANE of a0 is broadcast and its
-// multiples (row `f`: current block, then next block) are subtracted.  Lanes
-// whose entry is zero keep their value (up to the sign of a zero).
-template <int LANE>
-__device__ __forceinline__ void band_step(double &a0, double &a1, const double *f, int l)
+// Forward step r of a block: the final value of lane r is broadcast and its
+// multiples are subtracted from the pending values, lane l > r in the
+// current block (a0), lane l <= r in the next one (a1).  A lane whose entry
+// is zero keeps its value (up to the sign of a zero).
+__device__ __forceinline__ void band_fwd_step(double &a0, double &a1, double f, int r, int l)
 {
-    const double y = readlane_d(a0, LANE);
-    a0 = a0 - f[l] * y;
-    a1 = a1 - f[64 + l] * y;
+    const double y = readlane_d(a0, r);
+    const double f0 = l > r ? f : 0.0, f1 = l > r ? 0.0 : f;
+    a0 = a0 - f0 * y;
+    a1 = a1 - f1 * y;
 }
 
-// NSTEP consecutive steps whose broadcasting lanes are LANE0, LANE0 + LDIR,
-// ..., reading the rows at `rows`, rows + RDIR * 128, ...
-template <int LANE0, int LDIR, int RDIR, int NSTEP>
-__device__ __forceinline__ void band_steps(double &a0, double &a1, const double *rows, int l)
+// Backward step r of a block: lane l < r in the current block (a0), lane
+// l >= r in the previous one (a1).
+__device__ __forceinline__ void band_bwd_step(double &a0, double &a1, double g, int r, int l)
 {
-    if constexpr (NSTEP > 0) {
-        band_step<LANE0>(a0, a1, rows, l);
-        band_steps<LANE0 + LDIR, LDIR, RDIR, NSTEP - 1>(a0, a1, rows + RDIR * 128, l);
-    }
+    const double x = readlane_d(a0, r);
+    const double g0 = l < r ? g : 0.0, g1 = l < r ? 0.0 : g;
+    a0 = a0 - g0 * x;
+    a1 = a1 - g1 * x;
 }
 
 // The coarsest solve x = L^-T D^-1 L^-1 b, in the order of the oracle's
 // column form: y_i takes its terms over increasing j, z_i = y_i / D_i, x_i
 // takes its terms over decreasing k.  Run by one wave (lanes l = 0..63),
 // reading the step rows from global memory (the persistent small-level
-// kernel).  get(k): right-hand side of unknown k < m as FP64; put(k, x): the
-// result; z: M doubles of scratch.
+// kernel, whose coarsest level is small).  Steps of padding unknowns (index
+// >= m) change nothing and are skipped.  get(k): right-hand side of unknown
+// k < m as FP64; put(k, x): the result; z: M doubles of scratch.
 template <typename Get, typename Put>
 __device__ void band_solve_direct(const BandSolve &B, Get get, Put put, double *z)
 {
     const int l = threadIdx.x & 63, m = B.m, nb = B.M >> 6;
     double a0 = l < m ? get(l) : 0.0;
     double a1 = 64 + l < m ? get(64 + l) : 0.0;
+    constexpr int G = 16;   // steps whose rows are requested together
     for (int q = 0; q < nb; ++q) {
-        const double *rows = B.FF + (size_t)q * 64 * 128;
-#pragma unroll 4
-        for (int r = 0; r < 64; ++r) {
-            const double y = readlane_d(a0, r);
-            a0 = a0 - rows[r * 128 + l] * y;
-            a1 = a1 - rows[r * 128 + 64 + l] * y;
+        const double *rows = B.CF + (size_t)q * 4096;
+        const int nr = min(64, m - 64 * q);
+        for (int r0 = 0; r0 < nr; r0 += G) {
+            double f[G];
+#pragma unroll
+            for (int i = 0; i < G; ++i) f[i] = r0 + i < nr ? rows[(r0 + i) * 64 + l] : 0.0;
+#pragma unroll
+            for (int i = 0; i < G; ++i)
+                if (r0 + i < nr) band_fwd_step(a0, a1, f[i], r0 + i, l);
         }
         z[64 * q + l] = a0 / B.Dp[64 * q + l];
         a0 = a1;
@@ -457,12 +514,14 @@ __device__ void band_solve_direct(const BandSolve &B, Get get, Put put, double *
     a0 = z[64 * (nb - 1) + l];
     a1 = nb >= 2 ? z[64 * (nb - 2) + l] : 0.0;
     for (int q = nb - 1; q >= 0; --q) {
-        const double *rows = B.GG + (size_t)q * 64 * 128;
-#pragma unroll 4
-        for (int r = 63; r >= 0; --r) {   // steps k = 64q + 63 down to 64q
-            const double x = readlane_d(a0, r);
-            a0 = a0 - rows[r * 128 + l] * x;
-            a1 = a1 - rows[r * 128 + 64 + l] * x;
+        const double *rows = B.CG + (size_t)q * 4096;
+        for (int r0 = min(63, m - 1 - 64 * q); r0 >= 0; r0 -= G) {
+            double g[G];
+#pragma unroll
+            for (int i = 0; i < G; ++i) g[i] = r0 - i >= 0 ? rows[(r0 - i) * 64 + l] : 0.0;
+#pragma unroll
+            for (int i = 0; i < G; ++i)
+                if (r0 - i >= 0) band_bwd_step(a0, a1, g[i], r0 - i, l);
         }
         if (64 * q + l < m) put(64 * q + l, a0);
         a0 = a1;
@@ -471,17 +530,37 @@ __device__ void band_solve_direct(const BandSolve &B, Get get, Put put, double *
 }
 
 // The coarsest solve as a kernel of its own (the coarsest level is larger
-// than the persistent small-level kernel handles, or the basic path runs):
-// wave 0 solves as band_solve_direct does, waves 1..3 stage the step rows of
-// the next chunk of 32 steps into LDS while wave 0 works through the current
-// one (two slots of 32 KB), with one workgroup barrier per chunk.  The chunks
-// run through the forward rows 0 .. M-1, then the backward rows M-1 .. 0, so
-// both sides pass 1 + 4 M / 64 barriers.  Workgroup k solves right-hand side
-// k (its arrays ks elements, its stop flag kstop ints after the first's).
-constexpr int BAND_SOLVE_THREADS = 256;
-constexpr int BAND_CHUNK = 32;
+// than the persistent small-level kernel handles, or the basic path runs).
+// Wave 0 solves as band_solve_direct does, one 64-step block per phase,
+// reading the block's rows from LDS; the loader waves copy block c + 1 into
+// the other of two LDS slots meanwhile, with the global loads of blocks
+// c + 2 .. c + 1 + BAND_INFLIGHT already in flight in their registers, so the
+// latency of memory is hidden behind several blocks of the chain.  The blocks
+// run forward 0 .. nb-1, then backward nb-1 .. 0: 2 nb phases and 2 nb + 1
+// barriers on every wave.  Workgroup k solves right-hand side k (its arrays
+// ks elements, its stop flag kstop ints after the first's).
+constexpr int BAND_LOADERS = 8;
+constexpr int BAND_SOLVE_THREADS = 64 * (1 + BAND_LOADERS);
+constexpr int BAND_INFLIGHT = 3;
+constexpr int BAND_PER_LANE = 4096 / 2 / (64 * BAND_LOADERS);   // double2 per loader lane per block
 
-__host__ __device__ inline size_t band_solve_lds(int M) { return ((size_t)M + 2 * BAND_CHUNK * 128) * sizeof(double); }
+// Barriers of k_coarse_solve on every wave: one before the first block and
+// one after each, rounded up to whole rounds of the loaders' register sets.
+__host__ __device__ inline int band_phases(int nch) { return (nch + BAND_INFLIGHT) / BAND_INFLIGHT * BAND_INFLIGHT; }
+
+__host__ __device__ inline size_t band_solve_lds(int M) { return ((size_t)M + 2 * 4096) * sizeof(double); }
+
+__device__ __forceinline__ void band_fwd_block(double &a0, double &a1, const double *rows, int l)
+{
+#pragma unroll
+    for (int r = 0; r < 64; ++r) band_fwd_step(a0, a1, rows[r * 64 + l], r, l);
+}
+
+__device__ __forceinline__ void band_bwd_block(double &a0, double &a1, const double *rows, int l)
+{
+#pragma unroll
+    for (int r = 63; r >= 0; --r) band_bwd_step(a0, a1, rows[r * 64 + l], r, l);
+}
 
 template <typename T>
 static __global__ __launch_bounds__(BAND_SOLVE_THREADS) void k_coarse_solve(Lev<T> Cl, BandSolve B, size_t ks,
@@ -491,25 +570,47 @@ static __global__ __launch_bounds__(BAND_SOLVE_THREADS) void k_coarse_solve(Lev<
     if (stopped(stop ? stop + rk * kstop : stop)) return;
     extern __shared__ double band_sm[];
     double *z = band_sm, *slot = band_sm + B.M;
-    const int nb = B.M >> 6, nch = 4 * nb;   // chunks of 32 steps: 2 per block, forward then backward
-    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
-    auto stage = [&](int c) {   // rows of chunk c into slot c & 1 (waves 1..3)
-        double *dst = slot + (size_t)(c & 1) * BAND_CHUNK * 128;
-        const int fwd = c < 2 * nb;
-        const int c2 = fwd ? c : c - 2 * nb;
-        for (int e = threadIdx.x - 64; e < BAND_CHUNK * 64; e += BAND_SOLVE_THREADS - 64) {
-            const int t = e >> 6, h = e & 63;   // row t of the chunk, double2 h of the row
-            const size_t row = fwd ? (size_t)(BAND_CHUNK * c2 + t) : (size_t)(B.M - 1 - BAND_CHUNK * c2 - t);
-            const double2 v = reinterpret_cast<const double2 *>((fwd ? B.FF : B.GG) + row * 128)[h];
-            reinterpret_cast<double2 *>(dst + (size_t)t * 128)[h] = v;
-        }
-    };
-    if (wave != 0) {
-        stage(0);
-        __syncthreads();
-        for (int c = 0; c < nch; ++c) {
-            if (c + 1 < nch) stage(c + 1);
-            __syncthreads();
+    const int nb = B.M >> 6, nch = 2 * nb;
+    const int l = threadIdx.x & 63;
+    if (threadIdx.x >= 64) {
+        // loaders: block c of the sequence is forward block c (c < nb) or
+        // backward block 2 nb - 1 - c; register set u holds the blocks c with
+        // c mod BAND_INFLIGHT = u
+        const int t = threadIdx.x - 64;
+        typedef double v2d __attribute__((ext_vector_type(2)));
+        auto src = [&](int c) {
+            return reinterpret_cast<const v2d *>(c < nb ? B.CF + (size_t)c * 4096
+                                                         : B.CG + (size_t)(2 * nb - 1 - c) * 4096);
+        };
+        // one register set per block in flight (three named sets, so that
+        // every index is static)
+        static_assert(BAND_INFLIGHT == 3, "three register sets");
+        v2d b0[BAND_PER_LANE], b1[BAND_PER_LANE], b2[BAND_PER_LANE];
+        // the loads are unconditional (a block past the last is read as the
+        // last) and so are the phases, so that the compiler's wait for a set
+        // covers that set's loads only and the others stay in flight
+        auto request = [&](v2d(&r)[BAND_PER_LANE], int c) {
+            const v2d *g = src(min(c, nch - 1));
+#pragma unroll
+            for (int e = 0; e < BAND_PER_LANE; ++e) r[e] = g[t + e * 64 * BAND_LOADERS];
+        };
+        // phase c: block c goes from its register set into slot c & 1 (a
+        // slot no longer read once c >= nch), the set requests block
+        // c + BAND_INFLIGHT, then the barrier
+        auto phase = [&](v2d(&r)[BAND_PER_LANE], int c) {
+            v2d *dst = reinterpret_cast<v2d *>(slot + (size_t)(c & 1) * 4096);
+#pragma unroll
+            for (int e = 0; e < BAND_PER_LANE; ++e) dst[t + e * 64 * BAND_LOADERS] = r[e];
+            request(r, c + BAND_INFLIGHT);
+            lds_barrier();
+        };
+        request(b0, 0);
+        request(b1, 1);
+        request(b2, 2);
+        for (int c0 = 0; c0 < band_phases(nch); c0 += BAND_INFLIGHT) {
+            phase(b0, c0);
+            phase(b1, c0 + 1);
+            phase(b2, c0 + 2);
         }
         return;
     }
@@ -519,38 +620,31 @@ static __global__ __launch_bounds__(BAND_SOLVE_THREADS) void k_coarse_solve(Lev<
     auto pos = [&](int k) { return (size_t)(k / nc + 1) * Cl.ld + (k % nc + 1); };
     auto get = [&](int k) -> double { return k < m ? (double)bv[pos(k)] : 0.0; };
     double a0 = get(l), a1 = get(64 + l), bn = get(128 + l), dp = B.Dp[l];
-    __syncthreads();
+    lds_barrier();                                  // block 0 is in its slot
     for (int c = 0; c < nch; ++c) {
-        const double *rows = slot + (size_t)(c & 1) * BAND_CHUNK * 128;
-        if (c < 2 * nb) {                      // forward, block q = c / 2
-            const int q = c >> 1;
-            if (!(c & 1)) {
-                band_steps<0, 1, 1, 32>(a0, a1, rows, l);
-            } else {
-                band_steps<32, 1, 1, 32>(a0, a1, rows, l);
-                z[64 * q + l] = a0 / dp;
-                a0 = a1;
-                a1 = bn;
-                bn = get(64 * (q + 3) + l);
-                dp = q + 1 < nb ? B.Dp[64 * (q + 1) + l] : 1.0;
-                if (q + 1 == nb) {             // backward starts from the top block
-                    a0 = z[64 * (nb - 1) + l];
-                    a1 = nb >= 2 ? z[64 * (nb - 2) + l] : 0.0;
-                }
+        const double *rows = slot + (size_t)(c & 1) * 4096;
+        if (c < nb) {                               // forward block q = c
+            const int q = c;
+            band_fwd_block(a0, a1, rows, l);
+            z[64 * q + l] = a0 / dp;
+            a0 = a1;
+            a1 = bn;
+            bn = get(64 * (q + 3) + l);
+            dp = q + 1 < nb ? B.Dp[64 * (q + 1) + l] : 1.0;
+            if (q + 1 == nb) {                      // the backward pass starts from the top block
+                a0 = z[64 * (nb - 1) + l];
+                a1 = nb >= 2 ? z[64 * (nb - 2) + l] : 0.0;
             }
-        } else {                               // backward, block q = nb - 1 - (c - 2 nb) / 2
-            const int c2 = c - 2 * nb, q = nb - 1 - (c2 >> 1);
-            if (!(c2 & 1)) {
-                band_steps<63, -1, 1, 32>(a0, a1, rows, l);   // k = 64q + 63 .. 64q + 32
-            } else {
-                band_steps<31, -1, 1, 32>(a0, a1, rows, l);   // k = 64q + 31 .. 64q
-                if (64 * q + l < m) uv[pos(64 * q + l)] = (T)a0;
-                a0 = a1;
-                a1 = q >= 2 ? z[64 * q - 128 + l] : 0.0;
-            }
+        } else {                                    // backward block q = 2 nb - 1 - c
+            const int q = 2 * nb - 1 - c;
+            band_bwd_block(a0, a1, rows, l);
+            if (64 * q + l < m) uv[pos(64 * q + l)] = (T)a0;
+            a0 = a1;
+            a1 = q >= 2 ? z[64 * q - 128 + l] : 0.0;
         }
-        __syncthreads();
+        lds_barrier();
     }
+    for (int c = nch + 1; c < band_phases(nch); ++c) lds_barrier();   // the loaders' last phases
 }
 
 // ------------------------------------------------------ basic cycle steps

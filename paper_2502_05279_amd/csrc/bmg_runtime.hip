@@ -188,8 +188,8 @@ size_t plan(bmg_solver *h, int n, int kind, const bmg_options &o, char *base)
     // the rows of the one-wave solve
     const int cm = ns[nl - 1] * ns[nl - 1], cw = ns[nl - 1] + 1, cM = band_padded(cm);
     double *Lb = (double *)take(((size_t)cm * cw + cm) * 8);
-    double *FF = (double *)take((size_t)cM * 128 * 8);
-    double *GG = (double *)take((size_t)cM * 128 * 8);
+    double *CF = (double *)take((size_t)cM * 64 * 8);
+    double *CG = (double *)take((size_t)cM * 64 * 8);
     double *Dp = (double *)take((size_t)cM * 8);
     int *flags = (int *)take(64);
     double *part = (double *)take(NPART * 8);
@@ -205,8 +205,8 @@ size_t plan(bmg_solver *h, int n, int kind, const bmg_options &o, char *base)
         h->XL = XL;
         h->Lb = Lb;
         h->Dd = Lb + (size_t)cm * cw;
-        h->band.FF = FF;
-        h->band.GG = GG;
+        h->band.CF = CF;
+        h->band.CG = CG;
         h->band.Dp = Dp;
         h->band.m = cm;
         h->band.M = cM;
@@ -598,11 +598,14 @@ bmg_status small_cycle(bmg_solver *h, int l, const int *stop)
     S.ks0 = h->ks[l];
     S.kstop = h->kstop;
     const size_t shmem = (size_t)off * sizeof(T);
+    if (shmem > SMALL_LDS_MAX)
+        return fail(BMG_EINVAL, "levels %d..%d need %zu bytes of LDS in one workgroup (at most %d)", l,
+                    h->nlev - 1, shmem, SMALL_LDS_MAX);
     static bool attr_set[2] = {false, false};
     const int which = sizeof(T) == 8 ? 0 : 1;
     if (!attr_set[which]) {
         HIPCHK(hipFuncSetAttribute((const void *)k_small_vcycle<T, true>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, SMALL_LDS_MAX));
         attr_set[which] = true;
     }
     hipLaunchKernelGGL((k_small_vcycle<T, true>), dim3(h->nrhs), dim3(SMALL_THREADS), shmem, h->st, S, stop);
@@ -911,7 +914,7 @@ static bmg_status setup_into(bmg_solver *h, const double *stencil, int n, int ki
     hipLaunchKernelGGL(k_band_factor, dim3(1), dim3(BAND_FACTOR_THREADS), 0, h->st, h->L[h->nlev - 1], h->Lb, h->Dd,
                        h->flags);
     hipLaunchKernelGGL(k_band_expand, dim3(h->band.M / 4), dim3(256), 0, h->st, h->band.nc, (const double *)h->Lb,
-                       (const double *)h->Dd, (double *)h->band.FF, (double *)h->band.GG, (double *)h->band.Dp);
+                       (const double *)h->Dd, (double *)h->band.CF, (double *)h->band.CG, (double *)h->band.Dp);
     if (op.smoother == BMG_SMOOTH_LINE) {
         // y-lines in the grid's frame; x-lines on the transposed O (in the
         // scratch plane) and W
