@@ -549,17 +549,19 @@ int orc_band_ldlt_factor(int m, int w, const double *Ab, double *Lb, double *D)
  *   forward:  y = b; for j = 0 .. m-1: y_i -= L_ij y_j   (i = j+1 .. j+w)
  *   scaling:  z_i = y_i / D_i
  *   backward: x = z; for k = m-1 .. 0: x_i -= L_ki x_k   (i = k-w .. k-1)
- * so y_i sums its terms with j increasing and x_i with k decreasing. */
+ * so y_i sums its terms with j increasing and x_i with k decreasing.  Each
+ * update is one fused multiply-add, y_i - L_ij y_j rounded once (C99 fma, the
+ * correctly rounded operation of IEEE 754-2008). */
 void orc_band_ldlt_solve(int m, int w, const double *Lb, const double *D, const double *b, double *x)
 {
     for (int i = 0; i < m; ++i) x[i] = b[i];
     for (int j = 0; j < m; ++j) {
         const int i1 = j + w < m - 1 ? j + w : m - 1;
-        for (int i = j + 1; i <= i1; ++i) x[i] = x[i] - LB(i, j) * x[j];
+        for (int i = j + 1; i <= i1; ++i) x[i] = fma(-LB(i, j), x[j], x[i]);
     }
     for (int i = 0; i < m; ++i) x[i] = x[i] / D[i];
     for (int k = m - 1; k >= 0; --k) {
-        for (int i = k - w > 0 ? k - w : 0; i < k; ++i) x[i] = x[i] - LB(k, i) * x[k];
+        for (int i = k - w > 0 ? k - w : 0; i < k; ++i) x[i] = fma(-LB(k, i), x[k], x[i]);
     }
 #undef AB
 #undef LB

@@ -279,6 +279,43 @@ def test_band_ldlt_brute_force_small():
     assert np.abs(A @ x - b).max() <= 1e-14 * np.abs(b).max() * np.linalg.cond(A)
 
 
+def test_band_solve_updates_are_fused_and_in_column_order():
+    """The band solve's recurrence, written out in exact rational arithmetic
+    with one rounding to the nearest double per update (y_i - L_ij y_j as one
+    fused multiply-add), then y_i / D_i, then the backward updates with k
+    decreasing: equal to the oracle's solve bit for bit.  The same recurrence
+    with the product rounded separately differs from it in some entry, so the
+    pin tells the two roundings apart."""
+    from fractions import Fraction
+    rng = np.random.default_rng(11)
+    m, w = 40, 7
+    Lb = np.zeros((m, w))
+    for i in range(m):
+        for k in range(max(0, i - w), i):
+            Lb[i, k - i + w] = rng.uniform(-0.9, 0.9)
+    D = rng.uniform(0.5, 2.0, m)
+    b = rng.standard_normal(m)
+
+    def recurrence(fused):
+        def upd(a, l, y):
+            if fused:
+                return float(Fraction(a) - Fraction(l) * Fraction(y))
+            return float(Fraction(a) - Fraction(float(Fraction(l) * Fraction(y))))
+        x = [float(v) for v in b]
+        for j in range(m):
+            for i in range(j + 1, min(j + w, m - 1) + 1):
+                x[i] = upd(x[i], Lb[i, j - i + w], x[j])
+        x = [x[i] / float(D[i]) for i in range(m)]
+        for k in range(m - 1, -1, -1):
+            for i in range(max(0, k - w), k):
+                x[i] = upd(x[i], Lb[k, i - k + w], x[k])
+        return np.array(x)
+
+    got = ref.band_ldlt_solve(Lb, D, b)
+    assert np.array_equal(got, recurrence(True))
+    assert not np.array_equal(got, recurrence(False))
+
+
 # ------------------------------------------------------------ a4 smoother
 @pytest.mark.parametrize("level", [0, 1])
 def test_p9_colour_gs_is_the_triangular_solve(level):
