@@ -130,6 +130,8 @@ def oracle_solve_times(p, coarsest: int, tol: float, threads: int | None = None)
         u, hist = H.solve(b, tol=tol, max_cycles=2000)
         t2 = time.perf_counter()
         H.close()
+        print(f"cpu baseline: oracle solve on {threads or 'all'} thread(s): set-up {t1 - t0:.2f} s, "
+              f"{len(hist)} cycles {t2 - t1:.2f} s", file=sys.stderr, flush=True)
     finally:
         gomp.omp_set_num_threads(old_thr)
         os.sched_setaffinity(0, old_aff)

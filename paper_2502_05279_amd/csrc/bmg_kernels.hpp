@@ -419,7 +419,7 @@ static __global__ __launch_bounds__(BAND_FACTOR_THREADS) void k_band_factor(Lev<
 // q, "current") and 64(q+1) + l (block q+1, "next"), since w <= 64 means an
 // unknown only couples to its own block and the neighbouring one.  A step
 // subtracts multiples of one final unknown from at most w <= 64 pending ones,
-// one per lane, so every step reads one row of 64 doubles (CF for the forward
+// one per lane, so every step has one row of 64 doubles (CF for the forward
 // substitution, CG for the backward one):
 //   forward step j = 64q + r:  CF[j][l] = L(64q + l, j)       for l > r (current block),
 //                                         L(64q + 64 + l, j)  for l <= r (next block);
@@ -460,26 +460,15 @@ __device__ __forceinline__ double readlane_d(double v, int lane)
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-// Forward step r of a block: the final value of lane r is broadcast and its
-// multiples are subtracted from the pending values, lane l > r in the
-// current block (a0), lane l <= r in the next one (a1).  A lane whose entry
-// is zero keeps its value (up to the sign of a zero).
-__device__ __forceinline__ void band_fwd_step(double &a0, double &a1, double f, int r, int l)
+// One step: the final value y of lane r is broadcast and y L is removed from
+// the pending values, each update one fused multiply-add (p - L y rounded
+// once); f0 applies to a0 (current block), f1 to a1.  A lane whose entry is
+// zero keeps its value (up to the sign of a zero).
+__device__ __forceinline__ void band_step(double &a0, double &a1, double f0, double f1, int r)
 {
     const double y = readlane_d(a0, r);
-    const double f0 = l > r ? f : 0.0, f1 = l > r ? 0.0 : f;
-    a0 = a0 - f0 * y;
-    a1 = a1 - f1 * y;
-}
-
-// Backward step r of a block: lane l < r in the current block (a0), lane
-// l >= r in the previous one (a1).
-__device__ __forceinline__ void band_bwd_step(double &a0, double &a1, double g, int r, int l)
-{
-    const double x = readlane_d(a0, r);
-    const double g0 = l < r ? g : 0.0, g1 = l < r ? 0.0 : g;
-    a0 = a0 - g0 * x;
-    a1 = a1 - g1 * x;
+    a0 = fma(-f0, y, a0);
+    a1 = fma(-f1, y, a1);
 }
 
 // The coarsest solve x = L^-T D^-1 L^-1 b, in the order of the oracle's
@@ -504,8 +493,10 @@ __device__ void band_solve_direct(const BandSolve &B, Get get, Put put, double *
 #pragma unroll
             for (int i = 0; i < G; ++i) f[i] = r0 + i < nr ? rows[(r0 + i) * 64 + l] : 0.0;
 #pragma unroll
-            for (int i = 0; i < G; ++i)
-                if (r0 + i < nr) band_fwd_step(a0, a1, f[i], r0 + i, l);
+            for (int i = 0; i < G; ++i) {
+                const int r = r0 + i;
+                if (r < nr) band_step(a0, a1, l > r ? f[i] : 0.0, l > r ? 0.0 : f[i], r);
+            }
         }
         z[64 * q + l] = a0 / B.Dp[64 * q + l];
         a0 = a1;
@@ -520,8 +511,10 @@ __device__ void band_solve_direct(const BandSolve &B, Get get, Put put, double *
 #pragma unroll
             for (int i = 0; i < G; ++i) g[i] = r0 - i >= 0 ? rows[(r0 - i) * 64 + l] : 0.0;
 #pragma unroll
-            for (int i = 0; i < G; ++i)
-                if (r0 - i >= 0) band_bwd_step(a0, a1, g[i], r0 - i, l);
+            for (int i = 0; i < G; ++i) {
+                const int r = r0 - i;
+                if (r >= 0) band_step(a0, a1, l < r ? g[i] : 0.0, l < r ? 0.0 : g[i], r);
+            }
         }
         if (64 * q + l < m) put(64 * q + l, a0);
         a0 = a1;
@@ -531,35 +524,39 @@ __device__ void band_solve_direct(const BandSolve &B, Get get, Put put, double *
 
 // The coarsest solve as a kernel of its own (the coarsest level is larger
 // than the persistent small-level kernel handles, or the basic path runs).
-// Wave 0 solves as band_solve_direct does, one 64-step block per phase,
-// reading the block's rows from LDS; the loader waves copy block c + 1 into
-// the other of two LDS slots meanwhile, with the global loads of blocks
-// c + 2 .. c + 1 + BAND_INFLIGHT already in flight in their registers, so the
-// latency of memory is hidden behind several blocks of the chain.  The blocks
-// run forward 0 .. nb-1, then backward nb-1 .. 0: 2 nb phases and 2 nb + 1
-// barriers on every wave.  Workgroup k solves right-hand side k (its arrays
-// ks elements, its stop flag kstop ints after the first's).
+// Wave 0 runs the chain of steps, BAND_CH per phase, reading each step's
+// pair of rows (current block, neighbouring block) from LDS, so a step is a
+// broadcast and two fused multiply-adds.  The loader waves expand the
+// compressed rows of phase c + 1 into the other of two LDS slots meanwhile,
+// the global loads of the phases after it already in flight in their
+// registers (BAND_INFLIGHT sets), so memory latency stays behind the chain.
+// Phases run forward through the blocks (two per block), then backward:
+// nch = 4 M / 64 phases, band_phases(nch) barriers on every wave.  Workgroup
+// k solves right-hand side k (its arrays ks elements, its stop flag kstop
+// ints after the first's).
 constexpr int BAND_LOADERS = 8;
 constexpr int BAND_SOLVE_THREADS = 64 * (1 + BAND_LOADERS);
-constexpr int BAND_INFLIGHT = 3;
-constexpr int BAND_PER_LANE = 4096 / 2 / (64 * BAND_LOADERS);   // double2 per loader lane per block
+constexpr int BAND_CH = 32;
+constexpr int BAND_INFLIGHT = 4;
+constexpr int BAND_PER_LANE = BAND_CH * 64 / 2 / (64 * BAND_LOADERS);   // double pairs per loader lane per phase
 
-// Barriers of k_coarse_solve on every wave: one before the first block and
+// Barriers of k_coarse_solve on every wave: one before the first phase and
 // one after each, rounded up to whole rounds of the loaders' register sets.
 __host__ __device__ inline int band_phases(int nch) { return (nch + BAND_INFLIGHT) / BAND_INFLIGHT * BAND_INFLIGHT; }
 
-__host__ __device__ inline size_t band_solve_lds(int M) { return ((size_t)M + 2 * 4096) * sizeof(double); }
+__host__ __device__ inline size_t band_solve_lds(int M) { return ((size_t)M + 2 * BAND_CH * 128) * sizeof(double); }
 
-__device__ __forceinline__ void band_fwd_block(double &a0, double &a1, const double *rows, int l)
+// Steps R0 + BAND_CH - 1 .. R0 (DIR < 0) or R0 .. R0 + BAND_CH - 1 of a block;
+// row t of the slot holds step R0 + t (current block at [0, 64), the
+// neighbouring one at [64, 128)).
+template <int R0, int DIR>
+__device__ __forceinline__ void band_phase(double &a0, double &a1, const double *rows, int l)
 {
 #pragma unroll
-    for (int r = 0; r < 64; ++r) band_fwd_step(a0, a1, rows[r * 64 + l], r, l);
-}
-
-__device__ __forceinline__ void band_bwd_block(double &a0, double &a1, const double *rows, int l)
-{
-#pragma unroll
-    for (int r = 63; r >= 0; --r) band_bwd_step(a0, a1, rows[r * 64 + l], r, l);
+    for (int i = 0; i < BAND_CH; ++i) {
+        const int t = DIR > 0 ? i : BAND_CH - 1 - i;
+        band_step(a0, a1, rows[t * 128 + l], rows[t * 128 + 64 + l], R0 + t);
+    }
 }
 
 template <typename T>
@@ -570,47 +567,61 @@ static __global__ __launch_bounds__(BAND_SOLVE_THREADS) void k_coarse_solve(Lev<
     if (stopped(stop ? stop + rk * kstop : stop)) return;
     extern __shared__ double band_sm[];
     double *z = band_sm, *slot = band_sm + B.M;
-    const int nb = B.M >> 6, nch = 2 * nb;
+    const int nb = B.M >> 6, nch = 4 * nb;
     const int l = threadIdx.x & 63;
     if (threadIdx.x >= 64) {
-        // loaders: block c of the sequence is forward block c (c < nb) or
-        // backward block 2 nb - 1 - c; register set u holds the blocks c with
-        // c mod BAND_INFLIGHT = u
-        const int t = threadIdx.x - 64;
+        // loaders.  Phase c: block q, half h (steps 32h .. 32h + 31), forward
+        // for c < 2 nb, backward after; its rows are the contiguous rows
+        // 64q + 32h .. of CF or CG.
+        const int t0 = threadIdx.x - 64;
         typedef double v2d __attribute__((ext_vector_type(2)));
-        auto src = [&](int c) {
-            return reinterpret_cast<const v2d *>(c < nb ? B.CF + (size_t)c * 4096
-                                                         : B.CG + (size_t)(2 * nb - 1 - c) * 4096);
+        auto where = [&](int c, int &q, int &h, bool &fwd) {
+            fwd = c < 2 * nb;
+            const int c2 = fwd ? c : c - 2 * nb;
+            q = fwd ? c2 >> 1 : nb - 1 - (c2 >> 1);
+            h = fwd ? (c2 & 1) : 1 - (c2 & 1);
         };
-        // one register set per block in flight (three named sets, so that
-        // every index is static)
-        static_assert(BAND_INFLIGHT == 3, "three register sets");
-        v2d b0[BAND_PER_LANE], b1[BAND_PER_LANE], b2[BAND_PER_LANE];
-        // the loads are unconditional (a block past the last is read as the
-        // last) and so are the phases, so that the compiler's wait for a set
-        // covers that set's loads only and the others stay in flight
+        // the loads are unconditional (a phase past the last reads the last)
+        // and so are the phases, so that the compiler's wait for a set covers
+        // that set's loads only and the other sets stay in flight
+        v2d buf[BAND_INFLIGHT][BAND_PER_LANE];
         auto request = [&](v2d(&r)[BAND_PER_LANE], int c) {
-            const v2d *g = src(min(c, nch - 1));
+            int q, h;
+            bool fwd;
+            where(min(c, nch - 1), q, h, fwd);
+            const v2d *g = reinterpret_cast<const v2d *>((fwd ? B.CF : B.CG) + ((size_t)q * 64 + 32 * h) * 64);
 #pragma unroll
-            for (int e = 0; e < BAND_PER_LANE; ++e) r[e] = g[t + e * 64 * BAND_LOADERS];
+            for (int e = 0; e < BAND_PER_LANE; ++e) r[e] = g[t0 + e * 64 * BAND_LOADERS];
         };
-        // phase c: block c goes from its register set into slot c & 1 (a
-        // slot no longer read once c >= nch), the set requests block
-        // c + BAND_INFLIGHT, then the barrier
+        // phase c: the rows of phase c, expanded into pairs (current block,
+        // neighbouring block), go into slot c & 1 (a slot no longer read once
+        // c >= nch); the set then requests phase c + BAND_INFLIGHT
         auto phase = [&](v2d(&r)[BAND_PER_LANE], int c) {
-            v2d *dst = reinterpret_cast<v2d *>(slot + (size_t)(c & 1) * 4096);
+            int q, h;
+            bool fwd;
+            where(min(c, nch - 1), q, h, fwd);
+            double *dst = slot + (size_t)(c & 1) * BAND_CH * 128;
 #pragma unroll
-            for (int e = 0; e < BAND_PER_LANE; ++e) dst[t + e * 64 * BAND_LOADERS] = r[e];
+            for (int e = 0; e < BAND_PER_LANE; ++e) {
+                const int x = t0 + e * 64 * BAND_LOADERS;   // pair x of the phase's 32 x 32 pairs
+                const int t = x >> 5, lp = (x & 31) * 2, rr = 32 * h + t;
+                v2d c0, c1;
+                const bool k0 = fwd ? lp > rr : lp < rr, k1 = fwd ? lp + 1 > rr : lp + 1 < rr;
+                c0.x = k0 ? r[e].x : 0.0;
+                c1.x = k0 ? 0.0 : r[e].x;
+                c0.y = k1 ? r[e].y : 0.0;
+                c1.y = k1 ? 0.0 : r[e].y;
+                *reinterpret_cast<v2d *>(dst + t * 128 + lp) = c0;
+                *reinterpret_cast<v2d *>(dst + t * 128 + 64 + lp) = c1;
+            }
             request(r, c + BAND_INFLIGHT);
             lds_barrier();
         };
-        request(b0, 0);
-        request(b1, 1);
-        request(b2, 2);
+#pragma unroll
+        for (int u = 0; u < BAND_INFLIGHT; ++u) request(buf[u], u);
         for (int c0 = 0; c0 < band_phases(nch); c0 += BAND_INFLIGHT) {
-            phase(b0, c0);
-            phase(b1, c0 + 1);
-            phase(b2, c0 + 2);
+#pragma unroll
+            for (int u = 0; u < BAND_INFLIGHT; ++u) phase(buf[u], c0 + u);
         }
         return;
     }
@@ -620,27 +631,35 @@ static __global__ __launch_bounds__(BAND_SOLVE_THREADS) void k_coarse_solve(Lev<
     auto pos = [&](int k) { return (size_t)(k / nc + 1) * Cl.ld + (k % nc + 1); };
     auto get = [&](int k) -> double { return k < m ? (double)bv[pos(k)] : 0.0; };
     double a0 = get(l), a1 = get(64 + l), bn = get(128 + l), dp = B.Dp[l];
-    lds_barrier();                                  // block 0 is in its slot
+    lds_barrier();                                  // phase 0 is in its slot
     for (int c = 0; c < nch; ++c) {
-        const double *rows = slot + (size_t)(c & 1) * 4096;
-        if (c < nb) {                               // forward block q = c
-            const int q = c;
-            band_fwd_block(a0, a1, rows, l);
-            z[64 * q + l] = a0 / dp;
-            a0 = a1;
-            a1 = bn;
-            bn = get(64 * (q + 3) + l);
-            dp = q + 1 < nb ? B.Dp[64 * (q + 1) + l] : 1.0;
-            if (q + 1 == nb) {                      // the backward pass starts from the top block
-                a0 = z[64 * (nb - 1) + l];
-                a1 = nb >= 2 ? z[64 * (nb - 2) + l] : 0.0;
+        const double *rows = slot + (size_t)(c & 1) * BAND_CH * 128;
+        if (c < 2 * nb) {                           // forward, block q = c / 2
+            const int q = c >> 1;
+            if (!(c & 1)) {
+                band_phase<0, 1>(a0, a1, rows, l);
+            } else {
+                band_phase<32, 1>(a0, a1, rows, l);
+                z[64 * q + l] = a0 / dp;
+                a0 = a1;
+                a1 = bn;
+                bn = get(64 * (q + 3) + l);
+                dp = q + 1 < nb ? B.Dp[64 * (q + 1) + l] : 1.0;
+                if (q + 1 == nb) {                  // the backward pass starts from the top block
+                    a0 = z[64 * (nb - 1) + l];
+                    a1 = nb >= 2 ? z[64 * (nb - 2) + l] : 0.0;
+                }
             }
-        } else {                                    // backward block q = 2 nb - 1 - c
-            const int q = 2 * nb - 1 - c;
-            band_bwd_block(a0, a1, rows, l);
-            if (64 * q + l < m) uv[pos(64 * q + l)] = (T)a0;
-            a0 = a1;
-            a1 = q >= 2 ? z[64 * q - 128 + l] : 0.0;
+        } else {                                    // backward, block q = nb - 1 - (c - 2 nb) / 2
+            const int c2 = c - 2 * nb, q = nb - 1 - (c2 >> 1);
+            if (!(c2 & 1)) {
+                band_phase<32, -1>(a0, a1, rows, l);
+            } else {
+                band_phase<0, -1>(a0, a1, rows, l);
+                if (64 * q + l < m) uv[pos(64 * q + l)] = (T)a0;
+                a0 = a1;
+                a1 = q >= 2 ? z[64 * q - 128 + l] : 0.0;
+            }
         }
         lds_barrier();
     }
