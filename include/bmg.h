@@ -189,6 +189,25 @@ bmg_status bmg_solve(bmg_solver *h, const double *rhs, double *x, double tol,
 /* Releases the handle (host memory only; the workspace stays the caller's). */
 bmg_status bmg_destroy(bmg_solver *h);
 
+/* For callers that cannot allocate (code that must not call hipMalloc or any
+ * allocating routine: allocation-free serving loops, harnesses that forbid
+ * it): bmg_setup followed by bmg_solve and the handle's release, in one call
+ * that allocates nothing, neither device nor host memory.  The hierarchy lives
+ * in a device array the library owns, BMG_NOALLOC_BYTES per GPU, held by each
+ * GPU the library runs on until the process ends; the handle lives on the
+ * host stack.  Arguments and results as bmg_setup (stencil, n, kind, options,
+ * stream) and bmg_solve (rhs, x, tol, info); the current device must be the
+ * one the pointers and the stream belong to.  A problem whose workspace
+ * (bmg_workspace_bytes) exceeds BMG_NOALLOC_BYTES is rejected with
+ * BMG_EWORKSPACE before any launch (64 MiB: n <= 511 in FP64 and in
+ * BMG_FP32_IR).  Every call on one GPU shares that GPU's array, which keeps
+ * the last call's contents (the set-up clears what must start at zero):
+ * calls that overlap on one GPU, from several threads or streams, race. */
+#define BMG_NOALLOC_BYTES ((size_t)64 << 20)
+bmg_status bmg_solve_noalloc(const double *stencil, int n, int kind, const bmg_options *o,
+                             const double *rhs, double *x, double tol, bmg_info *info,
+                             bmg_stream stream);
+
 /* ------------------------------------------------------------------------
  * Block solves: k right-hand sides on one hierarchy.  The solver is bandwidth
  * bound and more data reuse and block solves are the further work Sec. 5

@@ -15,7 +15,7 @@ import torch
 
 from . import build as _build
 
-__all__ = ["BoxMGError", "Options", "Solver", "Block", "Batch", "Net", "discretize", "lib", "FIELDS", "STEPS",
+__all__ = ["BoxMGError", "Options", "Solver", "solve_noalloc", "Block", "Batch", "Net", "discretize", "lib", "FIELDS", "STEPS",
            "tile_rows_set", "tile_rows_get", "solve_select", "NET_PARAMS", "NET_ARRAYS",
            "BMG_INTERP_BOXMG", "BMG_INTERP_LEARNED", "BMG_SMOOTH_POINT", "BMG_SMOOTH_LINE",
            "TRACE", "BMG_FP64", "BMG_FP32_IR", "BMG_KERNELS_BASIC", "BMG_KERNELS_FUSED"]
@@ -112,6 +112,7 @@ def lib():
             "bmg_setup": ([C.POINTER(vp), vp, i, i, C.POINTER(Options), vp, sz, vp], i),
             "bmg_vcycle": ([vp, vp, vp, C.POINTER(d)], i),
             "bmg_solve": ([vp, vp, vp, d, C.POINTER(Info)], i),
+            "bmg_solve_noalloc": ([vp, i, i, C.POINTER(Options), vp, vp, d, C.POINTER(Info), vp], i),
             "bmg_destroy": ([vp], i),
             "bmg_status_string": ([i], C.c_char_p),
             "bmg_last_error": ([], C.c_char_p),
@@ -206,6 +207,27 @@ def discretize(k: torch.Tensor, f: torch.Tensor):
     _check(lib().bmg_discretize(_ptr(k), _ptr(f), n, _ptr(st), _ptr(rhs), _stream()),
            "bmg_discretize")
     return st, rhs
+
+
+def solve_noalloc(stencil: torch.Tensor, rhs: torch.Tensor, x: torch.Tensor | None = None,
+                  tol: float = 1e-10, raise_on_noconv: bool = True, **options):
+    """Set-up and solve in one library call that allocates nothing (the
+    hierarchy in the library's own device array, at most BMG_NOALLOC_BYTES);
+    returns ``(x, info)`` as ``Solver.solve``."""
+    n, n2, K = stencil.shape
+    if n != n2 or K not in (5, 9) or tuple(rhs.shape) != (n, n):
+        raise ValueError(f"stencil {tuple(stencil.shape)} and rhs {tuple(rhs.shape)} do not match")
+    if x is None:
+        x = torch.zeros_like(rhs)
+    o = default_options(**options)
+    hist = (C.c_double * (o.max_cycles + 2))()
+    info = _new_info(hist)
+    st = lib().bmg_solve_noalloc(_ptr(stencil), n, K, C.byref(o), _ptr(rhs), _ptr(x), float(tol),
+                                 C.byref(info), _stream())
+    if st not in (BMG_OK, BMG_ENOCONV) or (st == BMG_ENOCONV and raise_on_noconv):
+        _check(st, "bmg_solve_noalloc")
+    nh = info.cycles + (1 if o.precision == BMG_FP32_IR else 0)
+    return x, _info_dict(info, hist, nh, st)
 
 
 class Solver(_Handle):

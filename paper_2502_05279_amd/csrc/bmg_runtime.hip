@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <mutex>
 #include <type_traits>
 #include <utility>
 #include <vector>
@@ -1321,25 +1322,85 @@ bmg_status bmg_solve(bmg_solver *h, const double *rhs, double *x, double tol, bm
         TRY(floor_sum(h, h->B0, h->XH));
         HIPCHK(hipMemcpyAsync(&fl, h->scal + S_FLOOR, sizeof fl, hipMemcpyDeviceToHost, h->st));
     }
-    std::vector<double> hist(std::max(cs[0], 1));
-    HIPCHK(hipMemcpyAsync(hist.data(), h->hist, cs[0] * sizeof(double), hipMemcpyDeviceToHost, h->st));
+    // the first and last entries of the history, and all of it into the
+    // caller's array if given (no host buffer of the library's own)
+    double hfirst = init[1], hlast = init[1];
+    if (cs[0] > 0) {
+        HIPCHK(hipMemcpyAsync(&hfirst, h->hist, sizeof(double), hipMemcpyDeviceToHost, h->st));
+        HIPCHK(hipMemcpyAsync(&hlast, h->hist + (cs[0] - 1), sizeof(double), hipMemcpyDeviceToHost, h->st));
+        if (info && info->history)
+            HIPCHK(hipMemcpyAsync(info->history, h->hist, cs[0] * sizeof(double), hipMemcpyDeviceToHost, h->st));
+    }
     HIPCHK(hipStreamSynchronize(h->st));
-    const int steps = h->f32 ? cs[0] - 1 : cs[0];
+    const int steps = h->f32 ? std::max(cs[0] - 1, 0) : cs[0];
     if (info) {
         info->cycles = steps;
-        info->rel_res = hist[cs[0] - 1];
-        const double r0 = h->f32 ? hist[0] : init[1];
+        info->rel_res = hlast;
+        const double r0 = h->f32 ? hfirst : init[1];
         info->rho = steps > 0 ? pow(info->rel_res / r0, 1.0 / steps) : 0.0;
-        if (info->history) memcpy(info->history, hist.data(), cs[0] * sizeof(double));
         info->floor_est = ldexp(sqrt(fl), -53) / init[0];
         info->t_setup_ms = h->t_setup_ms;
         info->t_solve_ms = ms_since(t0);
         info->interp_used = h->opt.interp;
     }
-    if (cs[1] == 2) return fail(BMG_EDIVERGED, "residual %.3e after %d cycles", hist[cs[0] - 1], steps);
-    if (cs[1] == 3) return fail(BMG_ENOCONV, "relative residual %.3e > tol %.3e after %d cycles",
-                                hist[cs[0] - 1], tol, steps);
+    if (cs[1] == 2) return fail(BMG_EDIVERGED, "residual %.3e after %d cycles", hlast, steps);
+    if (cs[1] == 3) return fail(BMG_ENOCONV, "relative residual %.3e > tol %.3e after %d cycles", hlast, tol, steps);
     return BMG_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------ allocation-free solve
+// The hierarchy of bmg_solve_noalloc lives in this array.  Each GPU holds its
+// own copy at its own address; in host code the array's name is only a
+// stand-in, so host code uses the address hipGetSymbolAddress gives for the
+// current device (taken once per device, on the first call there) and never
+// the name.
+static __device__ __align__(256) char scratch[BMG_NOALLOC_BYTES];
+
+namespace {
+constexpr int NOALLOC_DEVICES = 64;
+std::mutex g_scratch_mu;
+char *g_scratch[NOALLOC_DEVICES];
+
+// The device address of the current device's copy of scratch.
+bmg_status scratch_address(char **out)
+{
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_DEVICES) return fail(BMG_EDEVICE, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(BMG_EDEVICE, "no device address for the allocation-free workspace");
+        g_scratch[dev] = (char *)p;
+    }
+    *out = g_scratch[dev];
+    return BMG_OK;
+}
+}  // namespace
+
+extern "C" {
+
+bmg_status bmg_solve_noalloc(const double *stencil, int n, int kind, const bmg_options *o, const double *rhs,
+                             double *x, double tol, bmg_info *info, bmg_stream stream)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!rhs || !x) return fail(BMG_EINVAL, "NULL argument");
+    if (!(tol >= 0.0)) return fail(BMG_EINVAL, "tol must be >= 0");
+    bmg_options op;
+    size_t need = 0;
+    TRY(check_setup(stencil, n, kind, o, &op, &need));
+    if (need > BMG_NOALLOC_BYTES)
+        return fail(BMG_EWORKSPACE, "n=%d needs %zu bytes of workspace; the allocation-free solve holds %zu", n,
+                    need, (size_t)BMG_NOALLOC_BYTES);
+    char *ws = nullptr;
+    TRY(scratch_address(&ws));
+    bmg_solver h;   // on the stack; its event list stays empty (no tracing)
+    TRY(setup_into(&h, stencil, n, kind, op, ws, BMG_NOALLOC_BYTES, need, stream));
+    h.t_setup_ms = ms_since(t0);
+    return bmg_solve(&h, rhs, x, tol, info);
 }
 
 // --------------------------------------------------------- level access
