@@ -411,8 +411,14 @@ bmg_status bmg_net_destroy(bmg_net *net);
 
 /* Forward pass on one level given by its padded compact planes ((n+2) rows of
  * pitch ld; SW and NW NULL for a five-point level) into the weight planes
- * Ci (8 planes of (nc+2) rows of pitch ldc, plane stride ps).  The
- * activations stay in the workspace for bmg_net_backward. */
+ * Ci (8 planes of (nc+2) rows of pitch ldc, plane stride ps, every entry
+ * written).  The weights are BoxMG's operator-induced ones plus the network's
+ * eight outputs at each coarse point as corrections that keep each F-point's
+ * weight sum: x-edge e = (y_LR - y_LL) / 2 added to LR and taken from LL,
+ * y-edge likewise with LA, LB, and the corner weights each y_w minus the
+ * mean of the four; F-points that do not exist keep zero weights.  A zero
+ * network therefore gives BoxMG's weights.  The activations stay in the
+ * workspace for bmg_net_backward. */
 bmg_status bmg_net_forward(bmg_net *net, int n, int ld, const double *O, const double *W, const double *S,
                            const double *SW, const double *NW, double *Ci, int ldc, size_t ps);
 
@@ -432,8 +438,10 @@ bmg_status bmg_net_adam(bmg_net *net, float lr, float beta1, float beta2, float 
  * point-major layout (channels innermost):
  *   X  (n+2)^2 x 16 (9 used),  H1 (n+3)^2 x 32,  H2 (nc+3)^2 x 32,
  *   D3 (nc+3)^2 x 16 (8 used), D2 (nc+3)^2 x 32, D1 (n+2)^2 x 32,
+ * and the output layer's values Y, (nc+2)^2 x 8 FP32,
  * with point (i, j) at j * (side) + i.  *bytes receives the size. */
-enum { BMG_NET_X = 0, BMG_NET_H1 = 1, BMG_NET_H2 = 2, BMG_NET_D3 = 3, BMG_NET_D2 = 4, BMG_NET_D1 = 5 };
+enum { BMG_NET_X = 0, BMG_NET_H1 = 1, BMG_NET_H2 = 2, BMG_NET_D3 = 3, BMG_NET_D2 = 4, BMG_NET_D1 = 5,
+       BMG_NET_Y = 6 };
 bmg_status bmg_net_export(bmg_net *net, int what, void *dst, size_t *bytes);
 
 /* One training sample: h must have been set up with BMG_INTERP_LEARNED,

@@ -17,10 +17,19 @@ bfloat16.  Three 3x3 convolutions follow:
 * conv3, stride 1, 32 -> 8 channels, no activation, at the same coarse points.
 
 Each layer reads zeros outside the points the previous layer is defined on.
-The eight outputs at (I, J) are the interpolation weights stored there, in the
-plane order LNE, LA, LNW, LR, LL, LSE, LB, LSW.  The weights of F-points that
-do not exist are set to zero: LR and LL in the top row J = nc+1, LA and LB in
-the right column I = nc+1.
+The eight outputs y at (I, J) are corrections to BoxMG's operator-induced
+weights stored there (plane order LNE, LA, LNW, LR, LL, LSE, LB, LSW), made to
+keep each F-point's weight sum, so that constants stay interpolated wherever
+BoxMG interpolates them and a zero network is BoxMG itself.  In FP64, from the
+FP32 outputs:
+
+* x-edge point (LL, LR): e = 0.5 (y_LR - y_LL), LR = LR_b + e, LL = LL_b - e;
+* y-edge point (LB, LA): e = 0.5 (y_LA - y_LB), LA = LA_b + e, LB = LB_b - e;
+* cell centre: m = 0.25 (((y_LNE + y_LNW) + y_LSE) + y_LSW), and each of the
+  four corner weights w = w_b + (y_w - m).
+
+F-points that do not exist (the x-edge in the top row J = nc+1, the y-edge in
+the right column I = nc+1) take no correction: BoxMG's zero weights stay.
 
 Precision.  Weights and activations are bfloat16 (round to nearest, ties to
 even), biases FP32.  A product of two bfloat16 numbers is exact in FP32; the
@@ -161,20 +170,58 @@ def forward(theta: np.ndarray, O, W, S, SW=None, NW=None, rounding: bool = True)
     y = conv(H2, p["W3"], p["b3"], crs, crs)                      # (nc+1, nc+1, 8)
     if rounding:
         y = y.astype(np.float32).astype(np.float64)
-    Ci = np.zeros((8, nc + 2, nc + 2))
-    Ci[:, 1:, 1:] = np.moveaxis(y, -1, 0)
-    Ci[[PLANE["LR"], PLANE["LL"]], nc + 1, :] = 0.0
-    Ci[[PLANE["LA"], PLANE["LB"]], :, nc + 1] = 0.0
-    return {"X": X, "z1": z1, "H1": H1, "z2": z2, "H2": H2, "y": y, "Ci": Ci,
+    Cb = ref.interp_weights(O, W, S, SW, NW)
+    Ci = corrected(Cb, y, nc)
+    return {"X": X, "z1": z1, "H1": H1, "z2": z2, "H2": H2, "y": y, "Cb": Cb, "Ci": Ci,
             "n": n, "nc": nc, "params": p, "rounding": rounding}
 
 
 def output_mask(nc: int) -> np.ndarray:
-    """(nc+1, nc+1, 8) mask of the output weights that exist."""
+    """(nc+1, nc+1, 8) mask of the weights whose F-point exists."""
     m = np.ones((nc + 1, nc + 1, 8))
     m[nc, :, [PLANE["LR"], PLANE["LL"]]] = 0.0
     m[:, nc, [PLANE["LA"], PLANE["LB"]]] = 0.0
     return m
+
+
+CORNERS = ("LNE", "LNW", "LSE", "LSW")
+
+
+def corrected(Cb: np.ndarray, y: np.ndarray, nc: int) -> np.ndarray:
+    """BoxMG's weight planes Cb plus the network's outputs y (nc+1, nc+1, 8) as
+    weight-sum-preserving corrections (module docstring)."""
+    Ci = Cb.copy()
+    k = PLANE
+    e = 0.5 * (y[..., k["LR"]] - y[..., k["LL"]])
+    e[nc, :] = 0.0                                                # no x-edge point in row nc+1
+    Ci[k["LR"], 1:, 1:] = Cb[k["LR"], 1:, 1:] + e
+    Ci[k["LL"], 1:, 1:] = Cb[k["LL"], 1:, 1:] - e
+    e = 0.5 * (y[..., k["LA"]] - y[..., k["LB"]])
+    e[:, nc] = 0.0                                                # no y-edge point in column nc+1
+    Ci[k["LA"], 1:, 1:] = Cb[k["LA"], 1:, 1:] + e
+    Ci[k["LB"], 1:, 1:] = Cb[k["LB"], 1:, 1:] - e
+    m = 0.25 * (((y[..., k["LNE"]] + y[..., k["LNW"]]) + y[..., k["LSE"]]) + y[..., k["LSW"]])
+    for name in CORNERS:
+        Ci[k[name], 1:, 1:] = Cb[k[name], 1:, 1:] + (y[..., k[name]] - m)
+    return Ci
+
+
+def correction_grad(dCi: np.ndarray, nc: int) -> np.ndarray:
+    """dL/dy (nc+1, nc+1, 8) from dL/dCi: the transpose of the linear map
+    y -> Ci of ``corrected`` (it is symmetric), in the same FP64 order."""
+    g = np.moveaxis(dCi[:, 1:, 1:], 0, -1)
+    k = PLANE
+    dY = np.zeros_like(g)
+    d = 0.5 * (g[..., k["LR"]] - g[..., k["LL"]])
+    d[nc, :] = 0.0
+    dY[..., k["LR"]], dY[..., k["LL"]] = d, -d
+    d = 0.5 * (g[..., k["LA"]] - g[..., k["LB"]])
+    d[:, nc] = 0.0
+    dY[..., k["LA"]], dY[..., k["LB"]] = d, -d
+    m = 0.25 * (((g[..., k["LNE"]] + g[..., k["LNW"]]) + g[..., k["LSE"]]) + g[..., k["LSW"]])
+    for name in CORNERS:
+        dY[..., k[name]] = g[..., k[name]] - m
+    return dY
 
 
 def bwd_conv3(fw: dict, dY: np.ndarray):
@@ -220,7 +267,7 @@ def backward(fw: dict, dCi: np.ndarray) -> dict:
     by the ReLU (where the stored activation is non-zero)."""
     rounding, n, nc = fw["rounding"], fw["n"], fw["nc"]
     g = {}
-    dY = grad_in(np.moveaxis(dCi[:, 1:, 1:], 0, -1) * output_mask(nc), rounding)
+    dY = grad_in(correction_grad(dCi, nc), rounding)
     g["W3"], g["b3"], dh2 = bwd_conv3(fw, dY)
     live2 = (fw["H2"][1:nc + 2, 1:nc + 2] > 0) if rounding else (fw["z2"] > 0)
     d2 = grad_in(dh2 * live2, rounding)

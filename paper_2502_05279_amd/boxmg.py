@@ -27,7 +27,7 @@ BMG_KERNELS_BASIC, BMG_KERNELS_FUSED = 0, 1
 BMG_SMOOTH_POINT, BMG_SMOOTH_LINE = 0, 1
 BMG_INTERP_BOXMG, BMG_INTERP_LEARNED = 0, 1
 NET_PARAMS = 14184
-NET_ARRAYS = {"X": 0, "H1": 1, "H2": 2, "D3": 3, "D2": 4, "D1": 5}
+NET_ARRAYS = {"X": 0, "H1": 1, "H2": 2, "D3": 3, "D2": 4, "D1": 5, "Y": 6}
 
 FIELDS = {"u": 0, "b": 1, "r": 2, "O": 3, "W": 4, "S": 5, "SW": 6, "NW": 7, "Ci": 8, "LD": 9,
           "xlo": 10, "stencil": 11,

@@ -21,8 +21,10 @@ constexpr int MAX_TRACE = 65536;
 // Records a one-line description for bmg_last_error() and returns s.
 bmg_status fail(bmg_status s, const char *fmt, ...);
 
-// Interpolation weights of level L from the network (learned interpolation).
-bmg_status net_level_weights(bmg_net *net, const Lev<double> &L, bool nine, const Wts<double> &C, void *stream);
+// Interpolation weights of level L from the network (learned interpolation):
+// BoxMG's weights (breakdown bits into flags) with the network's corrections.
+bmg_status net_level_weights(bmg_net *net, const Lev<double> &L, bool nine, const Wts<double> &C, int *flags,
+                             void *stream);
 
 // FP64 V-cycles of the handle from level l (right-hand side L[l].b, iterate
 // L[l].u from zero) until ||b - A u|| / ||b|| <= tol (accurate residual) or

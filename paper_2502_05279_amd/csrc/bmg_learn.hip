@@ -124,10 +124,10 @@ static __global__ void k_net_features(Lev<double> L, bool nine, bf16_t *__restri
 // stride-1 layer); 3: transposed stride 2 (input at (point - tap) / 2 where
 // both coordinates are even).  Epilogues: EP_RELU stores bf16(max(z, 0));
 // EP_MASK stores bf16(z) where the mask activation is non-zero, else 0;
-// EP_PLANES writes the eight weight planes (FP64) with the rows and columns
-// of missing F-points zeroed.  Points of the output domain outside the valid
-// region are written as zeros.
-enum { EP_RELU = 0, EP_MASK = 1, EP_PLANES = 2 };
+// EP_OUT stores the eight FP32 outputs per point (the corrections that
+// k_net_apply turns into weight planes).  Points of the output domain outside
+// the valid region are written as zeros.
+enum { EP_RELU = 0, EP_MASK = 1, EP_OUT = 2 };
 
 struct ConvArgs {
     const bf16_t *in;
@@ -141,10 +141,7 @@ struct ConvArgs {
     int out_side;
     const bf16_t *mask;          // EP_MASK: activation (COUTP channels per point)
     int mask_side;
-    double *planes;              // EP_PLANES
-    int pld;
-    size_t pps;
-    int nc;
+    float *yout;                 // EP_OUT: 8 values per point, out_side points per row
 };
 
 template <int CINP, int COUTP, int MODE, int EP>
@@ -202,16 +199,14 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a)
         }
     }
     if (!in_dom) return;
-    if (EP == EP_PLANES) {
+    if (EP == EP_OUT) {
         if (kq < 8) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int k = kq + e;
-                float v = valid ? acc[0][e] : 0.0f;
-                if ((k == LR || k == LL) && j == a.nc + 1) v = 0.0f;
-                if ((k == LA || k == LB) && pi == a.nc + 1) v = 0.0f;
-                a.planes[(size_t)k * a.pps + (size_t)j * a.pld + pi] = (double)v;
-            }
+            float4 v;
+            v.x = valid ? acc[0][0] : 0.0f;
+            v.y = valid ? acc[0][1] : 0.0f;
+            v.z = valid ? acc[0][2] : 0.0f;
+            v.w = valid ? acc[0][3] : 0.0f;
+            *reinterpret_cast<float4 *>(a.yout + ((size_t)j * a.out_side + pi) * 8 + kq) = v;
         }
         return;
     }
@@ -235,9 +230,56 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a)
     }
 }
 
-// dL/dy of the output layer as the layer's bfloat16 input gradient: the eight
-// planes at the valid coarse points (weights of missing F-points masked),
-// zeros on the ring and in channels 8..15.
+// The weight planes of a level from BoxMG's (already in C) and the network's
+// outputs y (8 FP32 values per coarse point, side nc + 2): corrections that
+// keep each F-point's weight sum, in FP64,
+//   x-edge: e = 0.5 (y_LR - y_LL), LR += e, LL -= e;
+//   y-edge: e = 0.5 (y_LA - y_LB), LA += e, LB -= e;
+//   cell centre: m = 0.25 (((y_LNE + y_LNW) + y_LSE) + y_LSW), w += y_w - m;
+// the weights of F-points that do not exist (x-edges in row nc + 1, y-edges in
+// column nc + 1) and the row and column 0 are zero.
+static __global__ void k_net_apply(Wts<double> C, int nc, const float *__restrict__ Y)
+{
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    const int J = blockIdx.y * blockDim.y + threadIdx.y;
+    if (I > nc + 1 || J > nc + 1) return;
+    const size_t c = (size_t)J * C.ld + I;
+    double *w = C.p;
+    if (I == 0 || J == 0) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) w[k * C.ps + c] = 0.0;
+        return;
+    }
+    double y[8];
+    const float *yp = Y + ((size_t)J * (nc + 2) + I) * 8;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) y[k] = (double)yp[k];
+    if (J <= nc) {
+        const double e = 0.5 * (y[LR] - y[LL]);
+        w[LR * C.ps + c] = w[LR * C.ps + c] + e;
+        w[LL * C.ps + c] = w[LL * C.ps + c] - e;
+    } else {
+        w[LR * C.ps + c] = 0.0;
+        w[LL * C.ps + c] = 0.0;
+    }
+    if (I <= nc) {
+        const double e = 0.5 * (y[LA] - y[LB]);
+        w[LA * C.ps + c] = w[LA * C.ps + c] + e;
+        w[LB * C.ps + c] = w[LB * C.ps + c] - e;
+    } else {
+        w[LA * C.ps + c] = 0.0;
+        w[LB * C.ps + c] = 0.0;
+    }
+    const double m = 0.25 * (((y[LNE] + y[LNW]) + y[LSE]) + y[LSW]);
+    w[LNE * C.ps + c] = w[LNE * C.ps + c] + (y[LNE] - m);
+    w[LNW * C.ps + c] = w[LNW * C.ps + c] + (y[LNW] - m);
+    w[LSE * C.ps + c] = w[LSE * C.ps + c] + (y[LSE] - m);
+    w[LSW * C.ps + c] = w[LSW * C.ps + c] + (y[LSW] - m);
+}
+
+// dL/dy of the output layer as the layer's bfloat16 input gradient: the
+// transpose of k_net_apply's map from y to the planes (the same FP64 order)
+// at the valid coarse points, zeros on the ring and in channels 8..15.
 static __global__ void k_net_dy(const double *__restrict__ dCi, int ldc, size_t ps, int nc, bf16_t *__restrict__ D3)
 {
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
@@ -246,13 +288,22 @@ static __global__ void k_net_dy(const double *__restrict__ dCi, int ldc, size_t 
     if (I >= side || J >= side) return;
     bf16_t v[16] = {};
     if (I >= 1 && I <= nc + 1 && J >= 1 && J <= nc + 1) {
+        double g[8], dy[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            double g = dCi[(size_t)k * ps + (size_t)J * ldc + I];
-            if ((k == LR || k == LL) && J == nc + 1) g = 0.0;
-            if ((k == LA || k == LB) && I == nc + 1) g = 0.0;
-            v[k] = bf16_rne((float)g);
-        }
+        for (int k = 0; k < 8; ++k) g[k] = dCi[(size_t)k * ps + (size_t)J * ldc + I];
+        const double d1 = J <= nc ? 0.5 * (g[LR] - g[LL]) : 0.0;
+        dy[LR] = d1;
+        dy[LL] = -d1;
+        const double d2 = I <= nc ? 0.5 * (g[LA] - g[LB]) : 0.0;
+        dy[LA] = d2;
+        dy[LB] = -d2;
+        const double m = 0.25 * (((g[LNE] + g[LNW]) + g[LSE]) + g[LSW]);
+        dy[LNE] = g[LNE] - m;
+        dy[LNW] = g[LNW] - m;
+        dy[LSE] = g[LSE] - m;
+        dy[LSW] = g[LSW] - m;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = bf16_rne((float)dy[k]);
     }
     uint2 *dst = reinterpret_cast<uint2 *>(D3 + ((size_t)J * side + I) * 16);
 #pragma unroll
@@ -452,6 +503,8 @@ struct bmg_net {
     double *G = nullptr;                              // gradient sum
     uint2 *PK = nullptr;                              // packed bfloat16 operands
     bf16_t *X = nullptr, *H1 = nullptr, *H2 = nullptr, *D3 = nullptr, *D2 = nullptr, *D1 = nullptr;
+    float *Y = nullptr;                               // the output layer's FP32 values
+    int *flags = nullptr;                             // breakdown bits of BoxMG's weights
     float *part = nullptr;
     double *vec = nullptr;                            // two-grid vectors
     size_t vec_cap = 0;                               // doubles in vec
@@ -481,6 +534,8 @@ size_t net_plan(bmg_net *h, int max_n, int train, char *base)
     bf16_t *X = (bf16_t *)take((n + 2) * (n + 2) * 16 * 2);
     bf16_t *H1 = (bf16_t *)take((n + 3) * (n + 3) * 32 * 2);
     bf16_t *H2 = (bf16_t *)take((nc + 3) * (nc + 3) * 32 * 2);
+    float *Y = (float *)take((nc + 2) * (nc + 2) * 8 * 4);
+    int *flags = (int *)take(64);
     bf16_t *D3 = nullptr, *D2 = nullptr, *D1 = nullptr;
     float *part = nullptr;
     double *vec = nullptr;
@@ -493,7 +548,7 @@ size_t net_plan(bmg_net *h, int max_n, int train, char *base)
     }
     if (h) {
         h->P = P; h->M = M; h->V = V; h->G = G; h->PK = PK;
-        h->X = X; h->H1 = H1; h->H2 = H2; h->D3 = D3; h->D2 = D2; h->D1 = D1;
+        h->X = X; h->H1 = H1; h->H2 = H2; h->D3 = D3; h->D2 = D2; h->D1 = D1; h->Y = Y; h->flags = flags;
         h->part = part; h->vec = vec; h->vec_cap = train ? vec_cap : 0;
     }
     return (off + ALIGN - 1) & ~(ALIGN - 1);
@@ -531,10 +586,15 @@ bmg_status wgrad(bmg_net *h, const bf16_t *in, int in_side, const bf16_t *d, int
     return BMG_OK;
 }
 
-bmg_status forward(bmg_net *h, const Lev<double> &L, bool nine, double *Ci, int ldc, size_t ps)
+// The weight planes of level L: BoxMG's operator-induced weights (breakdown
+// bits into flags), the network, then its corrections applied.
+bmg_status forward(bmg_net *h, const Lev<double> &L, bool nine, double *Ci, int ldc, size_t ps, int *flags)
 {
     const int n = L.n, nc = (n - 1) / 2;
     if (n > h->max_n) return fail(BMG_EINVAL, "level of %d points exceeds the network's max_n=%d", n, h->max_n);
+    const Wts<double> C{Ci, ldc, ps};
+    hipLaunchKernelGGL(k_weights_edges, tiles(nc + 1, nc + 1), dim3(32, 8), 0, h->st, L, C, nc, flags);
+    hipLaunchKernelGGL(k_weights_corners, tiles(nc + 1, nc + 1), dim3(32, 8), 0, h->st, L, C, nc, flags);
     hipLaunchKernelGGL(k_net_features, tiles(n + 2, n + 2), dim3(32, 8), 0, h->st, L, nine, h->X);
     LAUNCHCHK();
     const float *P = h->P;
@@ -548,11 +608,13 @@ bmg_status forward(bmg_net *h, const Lev<double> &L, bool nine, double *Ci, int 
     a.in = h->H1; a.in_side = n + 3; a.w = h->PK + PKO2; a.bias = P + OB2; a.cout = 32;
     a.lo = 0; a.hi = nc + 2; a.vlo = 1; a.vhi = nc + 1; a.out = h->H2; a.out_side = nc + 3;
     TRY((conv<32, 32, 1, EP_RELU>(h, a)));
-    // conv3: the weight planes at [1, nc+1], zeros at index 0
+    // conv3: the eight outputs at [1, nc+1], zeros at index 0
     a = ConvArgs{};
     a.in = h->H2; a.in_side = nc + 3; a.w = h->PK + PKO3; a.bias = P + OB3; a.cout = 8;
-    a.lo = 0; a.hi = nc + 1; a.vlo = 1; a.vhi = nc + 1; a.planes = Ci; a.pld = ldc; a.pps = ps; a.nc = nc;
-    TRY((conv<32, 16, 0, EP_PLANES>(h, a)));
+    a.lo = 0; a.hi = nc + 1; a.vlo = 1; a.vhi = nc + 1; a.yout = h->Y; a.out_side = nc + 2;
+    TRY((conv<32, 16, 0, EP_OUT>(h, a)));
+    hipLaunchKernelGGL(k_net_apply, tiles(nc + 2, nc + 2), dim3(32, 8), 0, h->st, C, nc, (const float *)h->Y);
+    LAUNCHCHK();
     h->last_n = n;
     h->last_nine = nine;
     return BMG_OK;
@@ -589,12 +651,13 @@ bmg_status backward(bmg_net *h, const double *dCi, int ldc, size_t ps)
 // ================================================================== internal
 namespace bmgi {
 
-bmg_status net_level_weights(bmg_net *net, const Lev<double> &L, bool nine, const Wts<double> &C, void *stream)
+bmg_status net_level_weights(bmg_net *net, const Lev<double> &L, bool nine, const Wts<double> &C, int *flags,
+                             void *stream)
 {
     // run on the solver's stream, in order with the rest of its set-up
     const hipStream_t saved = net->st;
     net->st = (hipStream_t)stream;
-    const bmg_status s = forward(net, L, nine, C.p, C.ld, C.ps);
+    const bmg_status s = forward(net, L, nine, C.p, C.ld, C.ps, flags);
     net->st = saved;
     return s;
 }
@@ -735,7 +798,7 @@ bmg_status bmg_net_forward(bmg_net *net, int n, int ld, const double *O, const d
     L.S = const_cast<double *>(S);
     L.SW = const_cast<double *>(SW);
     L.NW = const_cast<double *>(NW);
-    return forward(net, L, SW != nullptr, Ci, ldc, ps);
+    return forward(net, L, SW != nullptr, Ci, ldc, ps, net->flags);
 }
 
 bmg_status bmg_net_backward(bmg_net *net, const double *dCi, int ldc, size_t ps)
@@ -789,6 +852,7 @@ bmg_status bmg_net_export(bmg_net *net, int what, void *dst, size_t *bytes)
     case BMG_NET_D3: src = net->D3; sz = (nc + 3) * (nc + 3) * 16; break;
     case BMG_NET_D2: src = net->D2; sz = (nc + 3) * (nc + 3) * 32; break;
     case BMG_NET_D1: src = net->D1; sz = (n + 2) * (n + 2) * 32; break;
+    case BMG_NET_Y: src = reinterpret_cast<const bf16_t *>(net->Y); sz = (nc + 2) * (nc + 2) * 8 * 2; break;
     default: return fail(BMG_EINVAL, "unknown array %d", what);
     }
     if (!src) return fail(BMG_EINVAL, "array %d exists only in a training network", what);

@@ -903,7 +903,7 @@ static bmg_status setup_into(bmg_solver *h, const double *stencil, int n, int ki
     for (int l = 0; l + 1 < h->nlev; ++l) {
         const int nc = h->L[l + 1].n;
         if (op.interp == BMG_INTERP_LEARNED && (op.learned_levels == 0 || l < op.learned_levels)) {
-            SCHK(net_level_weights(op.net, h->L[l], h->nine[l], h->C[l], h->st));
+            SCHK(net_level_weights(op.net, h->L[l], h->nine[l], h->C[l], h->flags, h->st));
         } else {
             hipLaunchKernelGGL(k_weights_edges, grid2(nc + 1, nc + 1, B2), B2, 0, h->st, h->L[l], h->C[l], nc,
                                h->flags);

@@ -166,12 +166,16 @@ NET_SIZE = sum(int(np.prod(s)) for _, s in NET_SHAPES)
 
 
 def net_init(seed: int = 501) -> np.ndarray:
-    """Initial flat parameter vector (float32): weights uniform in
-    +-sqrt(6 / fan_in) (fan_in = 9 taps x input channels), biases zero."""
+    """Initial flat parameter vector (float32): weights of the first two layers
+    uniform in +-sqrt(6 / fan_in) (fan_in = 9 taps x input channels), the
+    output layer's weights and every bias zero, so that training starts from
+    corrections of zero."""
     rng = np.random.default_rng(seed)
     out = []
     for name, shape in NET_SHAPES:
-        if name.startswith("W"):
+        if name == "W3":
+            out.append(np.zeros(shape).ravel())
+        elif name.startswith("W"):
             bound = np.sqrt(6.0 / (shape[0] * shape[1]))
             out.append(rng.uniform(-bound, bound, size=shape).ravel())
         else:

@@ -50,10 +50,11 @@ def training_set(nfields: int, n: int = 255, seed0: int = 10_000, block: int = 1
 class Trainer:
     """Adam on the two-grid loss over a list of level operators."""
 
-    def __init__(self, net: boxmg.Net, inner_tol: float = 1e-8, inner_max: int = 30):
+    def __init__(self, net: boxmg.Net, inner_tol: float = 1e-8, inner_max: int = 30, coarsest: int = 15):
         self.net = net
         self.inner_tol = inner_tol
         self.inner_max = inner_max
+        self.coarsest = coarsest    # the inner coarse solves' direct level (at most the sample's coarse level)
         self._ws = None
 
         self.skipped = 0
@@ -63,12 +64,12 @@ class Trainer:
         None when the operator-induced weights of the levels below the learned
         one break down on the coarse operator (the sample is skipped)."""
         n = st.shape[0]
-        need = boxmg.workspace_bytes(n, st.shape[2])   # the layout does not depend on the weights
+        need = boxmg.workspace_bytes(n, st.shape[2], coarsest_n=min(self.coarsest, (n - 1) // 2))
         if self._ws is None or self._ws.numel() < need:
             self._ws = torch.empty(max(need, 1 << 20), dtype=torch.uint8, device=st.device)
         try:
             S = boxmg.Solver(st, workspace=self._ws, interp=boxmg.BMG_INTERP_LEARNED, learned_levels=1,
-                             net=self.net)
+                             net=self.net, coarsest_n=min(self.coarsest, (n - 1) // 2))
         except boxmg.BoxMGError as e:
             if e.status != boxmg.BMG_EBREAKDOWN:
                 raise
@@ -94,9 +95,9 @@ class Trainer:
 
 
 def train(fields: int = 2000, epochs: int = 1, batch: int = 16, lr: float = 1e-3, n: int = 255,
-          seed: int = 501, max_minutes: float | None = None, log=print):
+          seed: int = 501, max_minutes: float | None = None, coarsest: int = 15, log=print):
     net = boxmg.Net(inputs.net_init(seed), max_n=n, train=True)
-    tr = Trainer(net)
+    tr = Trainer(net, coarsest=coarsest)
     samples = training_set(fields, n)
     held = training_set(4, n, seed0=90_000)
     rng = np.random.default_rng(seed)
@@ -141,11 +142,12 @@ def main():
     t.add_argument("--lr", type=float, default=1e-3)
     t.add_argument("--seed", type=int, default=501)
     t.add_argument("--max-minutes", type=float, default=None)
+    t.add_argument("--coarsest", type=int, default=15)
     t.add_argument("--out", default=DEFAULT_PARAMS)
     a = ap.parse_args()
     if a.cmd == "train":
         net, hist = train(a.fields, a.epochs, a.batch, a.lr, seed=a.seed, max_minutes=a.max_minutes,
-                          log=lambda s: print(s, flush=True))
+                          coarsest=a.coarsest, log=lambda s: print(s, flush=True))
         os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
         np.save(a.out, net.params())
         print(json.dumps({"saved": a.out, "held_out": hist["held_out"]}), flush=True)

@@ -98,7 +98,10 @@ def _brute_forward(theta, O, W, S, SW, NW):
                         for c in range(32):
                             out = out + v[c] * p["W2"][t, c]
             H2[J, I] = learned.act(out, True)
-    Ci = np.zeros((8, nc + 2, nc + 2))
+    # BoxMG's weights, then each F-point's corrections written out: the x-edge
+    # pair (LL 4, LR 3), the y-edge pair (LB 6, LA 1), the corners (0, 2, 5, 7)
+    Cb = ref.interp_weights(O, W, S, SW, NW)
+    Ci = Cb.copy()
     for J in range(1, nc + 2):
         for I in range(1, nc + 2):
             out = np.array(p["b3"], dtype=float)
@@ -109,9 +112,18 @@ def _brute_forward(theta, O, W, S, SW, NW):
                     if v is not None:
                         for c in range(32):
                             out = out + v[c] * p["W3"][t, c]
-            Ci[:, J, I] = out.astype(np.float32)
-    Ci[[3, 4], nc + 1, :] = 0.0
-    Ci[[1, 6], :, nc + 1] = 0.0
+            y = [float(np.float32(v)) for v in out]
+            if J <= nc:                            # the x-edge point (2I-1, 2J) exists
+                e = 0.5 * (y[3] - y[4])
+                Ci[3, J, I] = Cb[3, J, I] + e
+                Ci[4, J, I] = Cb[4, J, I] - e
+            if I <= nc:                            # the y-edge point (2I, 2J-1) exists
+                e = 0.5 * (y[1] - y[6])
+                Ci[1, J, I] = Cb[1, J, I] + e
+                Ci[6, J, I] = Cb[6, J, I] - e
+            m = 0.25 * (((y[0] + y[2]) + y[5]) + y[7])
+            for k in (0, 2, 5, 7):
+                Ci[k, J, I] = Cb[k, J, I] + (y[k] - m)
     return Ci
 
 
@@ -140,10 +152,34 @@ def test_forward_translation_equivariance():
     assert np.array_equal(B[:, 3:12, 3:12], A[:, 4:13, 4:13])
 
 
-def test_zero_network_gives_zero_weights():
-    planes = _level(15, 2, False)
+@pytest.mark.parametrize("nine", [False, True])
+def test_zero_network_gives_boxmg_weights(nine):
+    """The outputs are corrections: a zero network leaves BoxMG's
+    operator-induced weights exactly (the start of training)."""
+    planes = _level(15, 2, nine)
     Ci = learned.forward(np.zeros(learned.NPARAM, np.float32), *planes)["Ci"]
-    assert not Ci.any()
+    assert np.array_equal(Ci, ref.interp_weights(*planes))
+    Ci = learned.forward(inputs.net_init(5), *planes)["Ci"]
+    assert np.array_equal(Ci, ref.interp_weights(*planes))
+
+
+@pytest.mark.parametrize("nine", [False, True])
+def test_corrections_keep_each_points_weight_sum(nine):
+    """Whatever the network outputs, each F-point's weights sum to BoxMG's sum
+    (up to the rounding of the additions), so a constant is interpolated
+    wherever BoxMG interpolates it; the weights of missing F-points and of
+    the ring stay zero."""
+    planes = _level(31, 7, nine)
+    fw = learned.forward(inputs.net_random(8), *planes)
+    Ci, Cb, nc = fw["Ci"], fw["Cb"], fw["nc"]
+    assert np.abs(Ci - Cb).max() > 1e-3                   # the network does change them
+    k = learned.PLANE
+    for pair in (("LR", "LL"), ("LA", "LB"), ("LNE", "LNW", "LSE", "LSW")):
+        got = sum(Ci[k[q]] for q in pair)
+        want = sum(Cb[k[q]] for q in pair)
+        assert np.abs(got - want).max() <= 4e-16 * (1 + np.abs(Ci[[k[q] for q in pair]]).sum(axis=0)).max()
+    assert not Ci[[k["LR"], k["LL"]], nc + 1, :].any() and not Ci[[k["LA"], k["LB"]], :, nc + 1].any()
+    assert not Ci[:, 0, :].any() and not Ci[:, :, 0].any()
 
 
 # ----------------------------------------------------------- backward
