@@ -21,6 +21,7 @@
  * Every sum is evaluated left to right as written; division is IEEE division.
  */
 #include <math.h>
+#include <stddef.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -1022,3 +1023,6 @@ int orc_solve_ir(orc_hier *H, const double *b, double *x, double *xl_out, double
     free(xl);
     return it;
 }
+
+/* -------------------------------------------------- nonsymmetric BoxMG */
+#include "bmg_oracle_ns.c"

@@ -2,7 +2,8 @@
 
     python oracle/build.py
 
-compiles ``bmg_oracle.c`` with gcc, FP contraction off (so that every product
+compiles ``bmg_oracle.c`` (which includes the precision-generic core and the
+nonsymmetric part) with gcc, FP contraction off (so that every product
 and sum is rounded exactly as written), OpenMP inside each colour / loop.
 """
 from __future__ import annotations
@@ -14,7 +15,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "liboracle.so")
-SOURCES = ["bmg_oracle.c", "bmg_oracle_core.inc"]
+SOURCES = ["bmg_oracle.c", "bmg_oracle_core.inc", "bmg_oracle_ns.c"]
 
 
 def build(verbose: bool = False) -> str:

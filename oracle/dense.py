@@ -230,3 +230,49 @@ def zebra_line_gs(A: sp.spmatrix, b: np.ndarray, u: np.ndarray, n: int) -> np.nd
         rhs = b[S] - A[S][:, rest] @ u[rest]
         u[S] = spla.spsolve(sp.csc_matrix(A[S][:, S]), rhs)
     return u
+
+
+# ------------------------------------------------- nonsymmetric operators
+def matrix_from_planes(planes) -> sp.csr_matrix:
+    """Matrix of nine padded planes (SW..NE): row (i,j) couples to (i+di, j+dj)
+    with planes[3 (dj+1) + (di+1)][j, i]; couplings to the ring are dropped."""
+    n = planes[0].shape[0] - 2
+    rows, cols, vals = [], [], []
+    for j in range(1, n + 1):
+        for i in range(1, n + 1):
+            for e, (di, dj) in enumerate(_DIRS):
+                qi, qj = i + di, j + dj
+                v = planes[e][j, i]
+                if 1 <= qi <= n and 1 <= qj <= n and v != 0.0:
+                    rows.append(_idx(n, i, j))
+                    cols.append(_idx(n, qi, qj))
+                    vals.append(v)
+    return sp.coo_matrix((vals, (rows, cols)), shape=(n * n, n * n)).tocsr()
+
+
+def planes_from_matrix(A: sp.spmatrix, n: int):
+    """Inverse of ``matrix_from_planes`` for a nine-point matrix."""
+    A = A.tocsr()
+    out = [np.zeros((n + 2, n + 2)) for _ in range(9)]
+    for j in range(1, n + 1):
+        for i in range(1, n + 1):
+            for e, (di, dj) in enumerate(_DIRS):
+                qi, qj = i + di, j + dj
+                if 1 <= qi <= n and 1 <= qj <= n:
+                    out[e][j, i] = A[_idx(n, i, j), _idx(n, qi, qj)]
+    return out
+
+
+def two_grid_pg(A, P, R, b, u, n, nu1, nu2):
+    """Explicit two-grid cycle with the Petrov-Galerkin coarse operator R A P,
+    solved exactly."""
+    Ad, Pd, Rd = A.toarray(), P.toarray(), R.toarray()
+    Ac = Rd @ Ad @ Pd
+    M, N = gs_matrix(A, n)
+    for _ in range(nu1):
+        u = M @ u + N @ b
+    r = b - Ad @ u
+    u = u + Pd @ np.linalg.solve(Ac, Rd @ r)
+    for _ in range(nu2):
+        u = M @ u + N @ b
+    return u

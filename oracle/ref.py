@@ -95,6 +95,36 @@ def lib():
         L.orc_line_relax.restype = None
         L.orc_set_line_relax.argtypes = [C.c_void_p]
         L.orc_set_line_relax.restype = C.c_int
+        # nonsymmetric BoxMG
+        P9 = _dp * 9
+        L.orc_ns_weights.argtypes = [C.c_int, P9, C.c_int, _dp]
+        L.orc_ns_weights.restype = C.c_int
+        L.orc_ns_rap.argtypes = [C.c_int, P9, _dp, _dp, P9]
+        L.orc_ns_rap.restype = C.c_int
+        L.orc_ns_gs.argtypes = [C.c_int, P9, _dp, _dp, C.c_int]
+        L.orc_ns_gs.restype = None
+        L.orc_ns_residual.argtypes = [C.c_int, P9, _dp, _dp, _dp]
+        L.orc_ns_residual.restype = None
+        L.orc_band_ldu_factor.argtypes = [C.c_int, C.c_int, _dp, _dp, _dp, _dp]
+        L.orc_band_ldu_factor.restype = C.c_int
+        L.orc_band_ldu_solve.argtypes = [C.c_int, C.c_int, _dp, _dp, _dp, _dp, _dp]
+        L.orc_band_ldu_solve.restype = None
+        L.orc_ns_setup.argtypes = [C.c_int, C.c_int, _dp, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int)]
+        L.orc_ns_setup.restype = C.c_void_p
+        L.orc_ns_destroy.argtypes = [C.c_void_p]
+        L.orc_ns_destroy.restype = None
+        L.orc_ns_num_levels.argtypes = [C.c_void_p]
+        L.orc_ns_num_levels.restype = C.c_int
+        L.orc_ns_level_n.argtypes = [C.c_void_p, C.c_int]
+        L.orc_ns_level_n.restype = C.c_int
+        L.orc_ns_field.argtypes = [C.c_void_p, C.c_int, C.c_int]
+        L.orc_ns_field.restype = _dp
+        L.orc_ns_coarse_factor.argtypes = [C.c_void_p, _dp, _dp, _dp, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.orc_ns_coarse_factor.restype = None
+        L.orc_ns_step.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int]
+        L.orc_ns_step.restype = None
+        L.orc_ns_solve.argtypes = [C.c_void_p, _dp, _dp, C.c_double, C.c_int, _dp]
+        L.orc_ns_solve.restype = C.c_int
         _lib = L
     return _lib
 
@@ -394,3 +424,148 @@ class Hierarchy:
         if k < 0:
             raise OracleError(k, "solve_ir")
         return x, hist[:k + 1].copy()
+
+
+# ------------------------------------------------- nonsymmetric BoxMG
+def _planes9(planes):
+    """Nine padded planes (SW..NE) as the C array of pointers the library takes."""
+    arr = [_c(a) for a in planes]
+    return arr, (_dp * 9)(*[_p(a) for a in arr])
+
+
+def ns_weights(planes, transpose: bool = False) -> np.ndarray:
+    """Operator-induced weights of the full nine-plane operator (P), or of its
+    transpose (the weights whose transpose is the restriction R)."""
+    keep, A = _planes9(planes)
+    nf = keep[0].shape[0] - 2
+    nc = (nf - 1) // 2
+    Ci = np.zeros((8, nc + 2, nc + 2))
+    s = lib().orc_ns_weights(nf, A, int(transpose), _p(Ci))
+    if s:
+        raise OracleError(s, "ns_weights")
+    return Ci
+
+
+def ns_rap(planes, Pi, Ri):
+    """Petrov-Galerkin coarse operator R A P as nine padded planes."""
+    keep, A = _planes9(planes)
+    nf = keep[0].shape[0] - 2
+    nc = (nf - 1) // 2
+    out = [np.zeros((nc + 2, nc + 2)) for _ in range(9)]
+    _, Ac = _planes9(out)
+    lib().orc_ns_rap(nf, A, _p(_c(Pi)), _p(_c(Ri)), Ac)
+    return out
+
+
+def ns_gs(planes, b, u, sweeps=1):
+    keep, A = _planes9(planes)
+    u = np.array(u, dtype=np.float64, copy=True)
+    lib().orc_ns_gs(keep[0].shape[0] - 2, A, _p(_c(b)), _p(u), sweeps)
+    return u
+
+
+def ns_residual(planes, b, u):
+    keep, A = _planes9(planes)
+    r = np.zeros_like(u, dtype=np.float64)
+    lib().orc_ns_residual(keep[0].shape[0] - 2, A, _p(_c(b)), _p(_c(u)), _p(r))
+    return r
+
+
+def band_ldu_factor(Ab: np.ndarray):
+    """L D U of a band matrix in storage (m, 2w+1): returns (Lb, Ub, D)."""
+    m, rw = Ab.shape
+    w = (rw - 1) // 2
+    Lb, Ub, D = np.zeros((m, w)), np.zeros((m, w)), np.zeros(m)
+    s = lib().orc_band_ldu_factor(m, w, _p(_c(Ab)), _p(Lb), _p(Ub), _p(D))
+    if s:
+        raise OracleError(s, "band_ldu_factor")
+    return Lb, Ub, D
+
+
+def band_ldu_solve(Lb, Ub, D, b):
+    m, w = Lb.shape
+    x = np.zeros(m)
+    lib().orc_band_ldu_solve(m, w, _p(_c(Lb)), _p(_c(Ub)), _p(_c(D)), _p(_c(b)), _p(x))
+    return x
+
+
+def full_planes(stencil: np.ndarray):
+    """Nine padded planes (SW..NE) from a [n][n][K] stencil (K = 5: S, W, O, E,
+    N; K = 9: SW..NE), zero on the ring."""
+    n, _, K = stencil.shape
+    out = [np.zeros((n + 2, n + 2)) for _ in range(9)]
+    idx = (1, 3, 4, 5, 7) if K == 5 else tuple(range(9))
+    for t, e in enumerate(idx):
+        out[e][1:-1, 1:-1] = stencil[:, :, t]
+    return out
+
+
+NS_FIELDS = {**{f"A{e}": e for e in range(9)}, "Pi": 9, "Ri": 10, "u": 11, "b": 12, "r": 13}
+
+
+class NSHierarchy:
+    """Nonsymmetric BoxMG hierarchy (R = P~^T from the transposed operator,
+    coarse operators R A P) of a ``[n][n][K]`` stencil."""
+
+    def __init__(self, stencil: np.ndarray, nu1: int = 2, nu2: int = 1, coarsest: int = 3):
+        st = _c(stencil)
+        n, _, K = st.shape
+        status = C.c_int(0)
+        h = lib().orc_ns_setup(n, K, _p(st), nu1, nu2, coarsest, C.byref(status))
+        if not h:
+            raise OracleError(status.value, "ns_setup")
+        self._h = h
+        self.n = n
+        self.nlev = lib().orc_ns_num_levels(h)
+
+    def close(self):
+        if self._h:
+            lib().orc_ns_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def level_n(self, l: int) -> int:
+        return lib().orc_ns_level_n(self._h, l)
+
+    def field(self, l: int, name: str) -> np.ndarray:
+        ptr = lib().orc_ns_field(self._h, l, NS_FIELDS[name])
+        if not ptr:
+            raise KeyError(name)
+        n = self.level_n(l)
+        if name in ("Pi", "Ri"):
+            nc = self.level_n(l + 1)
+            shape = (8, nc + 2, nc + 2)
+        else:
+            shape = (n + 2, n + 2)
+        return np.ctypeslib.as_array(ptr, shape=shape).copy()
+
+    def set_field(self, l: int, name: str, value: np.ndarray) -> None:
+        ptr = lib().orc_ns_field(self._h, l, NS_FIELDS[name])
+        n = self.level_n(l)
+        np.ctypeslib.as_array(ptr, shape=(n + 2, n + 2))[...] = value
+
+    def planes(self, l: int):
+        return [self.field(l, f"A{e}") for e in range(9)]
+
+    def coarse_factor(self):
+        m, w = C.c_int(0), C.c_int(0)
+        lib().orc_ns_coarse_factor(self._h, None, None, None, C.byref(m), C.byref(w))
+        Lb, Ub, D = np.zeros((m.value, w.value)), np.zeros((m.value, w.value)), np.zeros(m.value)
+        lib().orc_ns_coarse_factor(self._h, _p(Lb), _p(Ub), _p(D), None, None)
+        return Lb, Ub, D
+
+    def step(self, l: int, op: str, arg: int = 1) -> None:
+        code = {"smooth": 0, "residual": 1, "restrict": 2, "interp": 3, "coarse": 4}[op]
+        lib().orc_ns_step(self._h, l, code, arg)
+
+    def solve(self, b: np.ndarray, u: np.ndarray | None = None, tol: float = 1e-10, max_cycles: int = 100):
+        """Returns ``(u, history)``; history[k] = ||b - A u^{k+1}|| / ||b||."""
+        u = np.zeros_like(b) if u is None else np.array(u, dtype=np.float64, copy=True)
+        hist = np.zeros(max_cycles)
+        k = lib().orc_ns_solve(self._h, _p(_c(b)), _p(u), tol, max_cycles, _p(hist))
+        return u, hist[:k].copy()

@@ -206,3 +206,36 @@ def learned_eval_4095(seed_k: int = 601, seed_f: int = 602, n: int = 4095, block
     """Evaluation field of the learned interpolation: contrast 1e6 (log10 k
     uniform in [-3, 3]) on blocks of the training fields' size."""
     return jumping(n, block, -3.0, 3.0, seed_k, seed_f, f"learned_eval_{n}")
+
+
+# ----------------------------------------------------- nonsymmetric operators
+def upwind_convection(n: int, beta: float, flow: str = "rotating") -> np.ndarray:
+    """The convection part of a convection-diffusion test operator, as a
+    [n][n][5] stencil (S, W, O, E, N) to add to the diffusion stencil: the
+    first-order upwind difference of b . grad u on the vertex grid, scaled
+    like the diffusion operator (times h^2, so h |b| per direction), which
+    keeps the sum an M-matrix.  Velocity at vertex (x, y) = (i h, j h):
+    "rotating": b = beta (-sin(pi x) cos(pi y), cos(pi x) sin(pi y)) (a
+    recirculating cell); "constant": b = beta (cos 0.4, sin 0.4).  Couplings
+    to the Dirichlet boundary are dropped from the off-diagonal entries and
+    kept in the centre, as in the diffusion stencil."""
+    _check_n(n)
+    h = 1.0 / (n + 1)
+    x = np.arange(1, n + 1) * h
+    X, Y = np.meshgrid(x, x)                           # [j][i]
+    if flow == "rotating":
+        bx = -beta * np.sin(np.pi * X) * np.cos(np.pi * Y)
+        by = beta * np.cos(np.pi * X) * np.sin(np.pi * Y)
+    elif flow == "constant":
+        bx = np.full((n, n), beta * np.cos(0.4))
+        by = np.full((n, n), beta * np.sin(0.4))
+    else:
+        raise ValueError(flow)
+    st = np.zeros((n, n, 5))
+    st[:, :, 1] = -h * np.maximum(bx, 0.0)            # W: upwind side for bx > 0
+    st[:, :, 3] = -h * np.maximum(-bx, 0.0)           # E
+    st[:, :, 0] = -h * np.maximum(by, 0.0)            # S
+    st[:, :, 4] = -h * np.maximum(-by, 0.0)           # N
+    st[:, :, 2] = h * (np.abs(bx) + np.abs(by))       # O
+    st[:, 0, 1] = st[0, :, 0] = st[:, -1, 3] = st[-1, :, 4] = 0.0
+    return st
