@@ -319,6 +319,71 @@ def bench_learned(args):
     print(json.dumps(out))
 
 
+def bench_nonsym(args):
+    """Nonsymmetric BoxMG (restriction from the transposed operator, coarse
+    operators R A P) on a convection-diffusion operator: unit diffusion plus
+    the upwind part of a recirculating flow of speed 300 on the 4095^2 grid,
+    coarsest level 63^2.  One step = set-up + solve to the tolerance.  The
+    roofline is that of the fine level's Gauss-Seidel sweep (four colour
+    launches), timed with HIP events on the library's stream after the timed
+    steps: per launch the stencil rows, right-hand side and new values of its
+    quarter of the points (88 B each) and the iterate read once (8 B per
+    point), 30 B per grid point."""
+    import torch
+    from paper_2502_05279_amd import boxmg, inputs
+
+    dev = torch.device("cuda:0")
+    n = int(args.workload.split("_")[1]) if args.workload != "cd_4095" else 4095
+    beta = 300.0
+    k = torch.from_numpy(inputs.constant_k(n)).to(dev)
+    f = torch.from_numpy(inputs.uniform_source(n, 702)).to(dev)
+    diff, rhs = boxmg.discretize(k, f)
+    st = (diff + torch.from_numpy(inputs.upwind_convection(n, beta, "rotating")).to(dev)).contiguous()
+    coarsest = args.coarsest or min(63, n)
+    opts = dict(max_cycles=args.max_cycles, coarsest_n=coarsest)
+
+    def step():
+        S = boxmg.NSSolver(st, **opts)
+        x, info = S.solve(rhs, tol=args.tol, raise_on_noconv=False)
+        return S, x, info
+
+    for _ in range(args.warmup):
+        step()[0].close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k_ in range(args.steps):
+        S, x, info = step()
+        if k_ + 1 < args.steps:
+            S.close()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    # the fine level's sweep, timed on the library's stream
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 20
+    ev0.record()
+    for _ in range(reps):
+        S.step(0, "smooth", 1)
+    ev1.record()
+    torch.cuda.synchronize()
+    launch_ms = ev0.elapsed_time(ev1) / (4 * reps)
+    S.close()
+    bytes_per_launch = 30.0 * n * n
+    achieved = bytes_per_launch / (launch_ms * 1e-3) / 1e9
+    out = {
+        "metric": f"fine DOF/s solved to {args.tol:g} rel. residual ({n}^2 convection-diffusion, nonsymmetric BoxMG)",
+        "value": n * n / dt, "unit": "DOF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"cd_{n}", "n": n, "beta": beta, "flow": "rotating", "coarsest": coarsest,
+                   "cycles": info["cycles"], "rho": info["rho"], "final_rel_res": info["rel_res"],
+                   "converged": info["status"] == 0},
+        "roofline": {"bound": "hbm", "kernel": "k_ns_gs_colour (fine level, one colour)", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "avg_launch_ms": launch_ms, "bytes_per_launch": bytes_per_launch},
+    }
+    print(json.dumps(out))
+
+
 def bench_block(args):
     """k right-hand sides on the jumping_4095 operator solved as one block: the
     fused passes run the tiles of all of them per launch and read the operator
@@ -446,6 +511,8 @@ def main():
     dev = torch.device("cuda:0")
     if args.workload == "batch_512":
         return bench_batch(args)
+    if args.workload.startswith("cd_"):
+        return bench_nonsym(args)
     if args.workload == "learned_4095":
         return bench_learned(args)
     if args.rhs > 1:

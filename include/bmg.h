@@ -475,6 +475,56 @@ bmg_status bmg_net_twogrid(bmg_net *net, bmg_solver *h, const double *r0, double
 bmg_status bmg_solve_select(bmg_solver *learned, bmg_solver *boxmg, const double *rhs, double *x, double tol,
                             int probe_cycles, bmg_info *info, int *used, double *rho);
 
+/* ------------------------------------------------------------------------
+ * Nonsymmetric black-box multigrid (operators with A != A^T, e.g.
+ * convection-diffusion): the member of the BoxMG family the paper's
+ * references (Section 1) describe for nonsymmetric problems, with the V-cycle
+ * of Fig. vcycle_flowchart.  Interpolation P is induced by A with the
+ * symmetric solver's collapse formulas; the restriction is R = P~^T, P~ the
+ * interpolation the same formulas induce from A^T, applied with the term
+ * order of Fig. restrict_kernel; the coarse operators are R A P in all nine
+ * directions; every level stores all nine entries of each row; relaxation is
+ * four-colour Gauss-Seidel (one launch per colour); the coarsest level (size
+ * coarsest_n, 3 by default, at most 63) is factored as a band L D U (unit
+ * triangular L and U) and solved by the one-wave band substitutions, each
+ * update one fused multiply-add.  Options used: nu1, nu2, max_cycles,
+ * coarsest_n; precision, smoother and interpolation must be the defaults.
+ * ---------------------------------------------------------------------- */
+typedef struct bmg_ns bmg_ns;
+
+/* Device workspace of a nonsymmetric hierarchy (host only). */
+bmg_status bmg_ns_workspace_bytes(int n, int kind, const bmg_options *o, size_t *bytes);
+
+/* Set-up from the stencil (device, [n][n][K], K = 5: S, W, O, E, N; K = 9: SW,
+ * S, SE, W, O, E, NW, N, NE; signed matrix entries, entries toward boundary
+ * vertices zero, no symmetry required).  Ownership, alignment and errors as
+ * bmg_setup; BMG_EBREAKDOWN if an interpolation denominator or a pivot of the
+ * coarsest factor is not positive. */
+bmg_status bmg_ns_setup(bmg_ns **out, const double *stencil, int n, int kind, const bmg_options *o,
+                        void *workspace, size_t ws_bytes, bmg_stream stream);
+
+/* V(nu1,nu2)-cycles from the initial guess x (device, n x n, in/out) until
+ * ||rhs - A x||_2 / ||rhs||_2 <= tol (plain FP64 residual, checked after every
+ * cycle) or max_cycles.  info (host, nullable): cycles, final residual, mean
+ * factor and, if info->history is given (max_cycles entries), the residual
+ * after each cycle.  BMG_ENOCONV / BMG_EDIVERGED as bmg_solve; ||rhs|| = 0
+ * gives x = 0 after 0 cycles. */
+bmg_status bmg_ns_solve(bmg_ns *h, const double *rhs, double *x, double tol, bmg_info *info);
+bmg_status bmg_ns_destroy(bmg_ns *h);
+
+/* Level access for tests: fields 0..8 the stencil planes (SW..NE), 9 P's and
+ * 10 R's weights (8 planes of the coarse level's (nc+2)^2 shape), 11 u, 12 b,
+ * 13 r (padded (n+2)^2, tight on output), 14 the coarsest factor (L band
+ * m x w, U band m x w with U_ik at i w + (k - i - 1), D m).  Import takes u, b,
+ * r.  Steps: 0 = arg sweeps, 1 = residual, 2 = restriction of r into the next
+ * level's b (its u zeroed), 3 = u += P u_next, 4 = the coarsest solve.  All
+ * synchronous on the handle's stream. */
+bmg_status bmg_ns_num_levels(const bmg_ns *h, int *nlev);
+bmg_status bmg_ns_level_n(const bmg_ns *h, int level, int *n);
+bmg_status bmg_ns_export(bmg_ns *h, int level, int field, double *dst);
+bmg_status bmg_ns_import(bmg_ns *h, int level, int field, const double *src);
+bmg_status bmg_ns_step(bmg_ns *h, int level, int step, int arg);
+
 #ifdef __cplusplus
 }
 #endif

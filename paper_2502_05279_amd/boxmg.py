@@ -15,7 +15,7 @@ import torch
 
 from . import build as _build
 
-__all__ = ["BoxMGError", "Options", "Solver", "solve_noalloc", "Block", "Batch", "Net", "discretize", "lib", "FIELDS", "STEPS",
+__all__ = ["BoxMGError", "Options", "Solver", "NSSolver", "solve_noalloc", "Block", "Batch", "Net", "discretize", "lib", "FIELDS", "STEPS",
            "tile_rows_set", "tile_rows_get", "solve_select", "NET_PARAMS", "NET_ARRAYS",
            "BMG_INTERP_BOXMG", "BMG_INTERP_LEARNED", "BMG_SMOOTH_POINT", "BMG_SMOOTH_LINE",
            "TRACE", "BMG_FP64", "BMG_FP32_IR", "BMG_KERNELS_BASIC", "BMG_KERNELS_FUSED"]
@@ -151,6 +151,15 @@ def lib():
             "bmg_block_trace_enable": ([vp, i, i, i], i),
             "bmg_block_trace_read": ([vp, C.POINTER(i), C.POINTER(d), C.POINTER(d)], i),
             "bmg_block_destroy": ([vp], i),
+            "bmg_ns_workspace_bytes": ([i, i, C.POINTER(Options), C.POINTER(sz)], i),
+            "bmg_ns_setup": ([C.POINTER(vp), vp, i, i, C.POINTER(Options), vp, sz, vp], i),
+            "bmg_ns_solve": ([vp, vp, vp, d, C.POINTER(Info)], i),
+            "bmg_ns_destroy": ([vp], i),
+            "bmg_ns_num_levels": ([vp, C.POINTER(i)], i),
+            "bmg_ns_level_n": ([vp, i, C.POINTER(i)], i),
+            "bmg_ns_export": ([vp, i, i, vp], i),
+            "bmg_ns_import": ([vp, i, i, vp], i),
+            "bmg_ns_step": ([vp, i, i, i], i),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -207,6 +216,74 @@ def discretize(k: torch.Tensor, f: torch.Tensor):
     _check(lib().bmg_discretize(_ptr(k), _ptr(f), n, _ptr(st), _ptr(rhs), _stream()),
            "bmg_discretize")
     return st, rhs
+
+
+NS_FIELDS = {**{f"A{e}": e for e in range(9)}, "Pi": 9, "Ri": 10, "u": 11, "b": 12, "r": 13, "LDU": 14}
+
+
+class NSSolver(_Handle):
+    """Nonsymmetric BoxMG hierarchy (restriction from the transposed operator,
+    Petrov-Galerkin coarse operators) of a ``[n][n][K]`` stencil on the GPU."""
+
+    def __init__(self, stencil: torch.Tensor, **options):
+        n, n2, K = stencil.shape
+        if n != n2 or K not in (5, 9):
+            raise ValueError(f"stencil shape {tuple(stencil.shape)}")
+        self.n = n
+        self.options = default_options(**options)
+        need = C.c_size_t(0)
+        _check(lib().bmg_ns_workspace_bytes(n, K, C.byref(self.options), C.byref(need)), "bmg_ns_workspace_bytes")
+        self.device = stencil.device
+        self.workspace = torch.empty(need.value, dtype=torch.uint8, device=self.device)
+        h = C.c_void_p(None)
+        _check(lib().bmg_ns_setup(C.byref(h), _ptr(stencil), n, K, C.byref(self.options),
+                                  self.workspace.data_ptr(), need.value, _stream()), "bmg_ns_setup")
+        self._h = h
+        nl = C.c_int(0)
+        _check(lib().bmg_ns_num_levels(self._h, C.byref(nl)), "bmg_ns_num_levels")
+        self.nlev = nl.value
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().bmg_ns_destroy(self._h)
+            self._h = None
+
+    def level_n(self, level: int) -> int:
+        out = C.c_int(0)
+        _check(lib().bmg_ns_level_n(self._h, level, C.byref(out)), "bmg_ns_level_n")
+        return out.value
+
+    def solve(self, rhs: torch.Tensor, x: torch.Tensor | None = None, tol: float = 1e-10,
+              raise_on_noconv: bool = True):
+        if x is None:
+            x = torch.zeros_like(rhs)
+        hist = (C.c_double * (self.options.max_cycles + 2))()
+        info = _new_info(hist)
+        st = lib().bmg_ns_solve(self._h, _ptr(rhs), _ptr(x), float(tol), C.byref(info))
+        if st not in (BMG_OK, BMG_ENOCONV) or (st == BMG_ENOCONV and raise_on_noconv):
+            _check(st, "bmg_ns_solve")
+        return x, _info_dict(info, hist, info.cycles, st)
+
+    def export(self, level: int, field: str) -> torch.Tensor:
+        f = NS_FIELDS[field]
+        if f == 14:
+            m = self.level_n(self.nlev - 1) ** 2
+            w = self.level_n(self.nlev - 1) + 1
+            out = torch.empty(2 * m * w + m, dtype=torch.float64, device=self.device)
+        elif f in (9, 10):
+            nc = self.level_n(level + 1)
+            out = torch.empty((8, nc + 2, nc + 2), dtype=torch.float64, device=self.device)
+        else:
+            nl = self.level_n(level)
+            out = torch.empty((nl + 2, nl + 2), dtype=torch.float64, device=self.device)
+        _check(lib().bmg_ns_export(self._h, level, f, _ptr(out)), "bmg_ns_export")
+        return out
+
+    def import_(self, level: int, field: str, value: torch.Tensor) -> None:
+        _check(lib().bmg_ns_import(self._h, level, NS_FIELDS[field], _ptr(value.contiguous())), "bmg_ns_import")
+
+    def step(self, level: int, step: str, arg: int = 1) -> None:
+        _check(lib().bmg_ns_step(self._h, level, STEPS[step], arg), "bmg_ns_step")
 
 
 def solve_noalloc(stencil: torch.Tensor, rhs: torch.Tensor, x: torch.Tensor | None = None,

@@ -18,7 +18,7 @@ OUT_DIR = os.path.join(HERE, "lib")
 LIB = os.path.join(OUT_DIR, "libbmg.so")
 ARCH = os.environ.get("BMG_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["bmg_runtime.hip", "bmg_batch.hip", "bmg_learn.hip"]
+SOURCES = ["bmg_runtime.hip", "bmg_batch.hip", "bmg_learn.hip", "bmg_nonsym.hip"]
 HEADERS = [os.path.join(ROOT, "include", "bmg.h")]
 
 

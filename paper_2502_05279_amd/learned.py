@@ -25,25 +25,25 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_PARAMS = os.path.join(HERE, "data", "learned_p.npy")
 
 
-def level_stencils(k: np.ndarray, f: np.ndarray, device="cuda:0", min_n: int = 7):
-    """The operators of a BoxMG hierarchy's levels (n >= min_n) as [n][n][K]
-    device tensors, finest first."""
+def level_stencils(k: np.ndarray, f: np.ndarray, device="cuda:0", min_n: int = 7, max_n: int = 1 << 15):
+    """The operators of a BoxMG hierarchy's levels (min_n <= n <= max_n) as
+    [n][n][K] device tensors, finest first."""
     st, _ = boxmg.discretize(torch.from_numpy(k).to(device), torch.from_numpy(f).to(device))
     S = boxmg.Solver(st)
     out = []
     for lvl in range(S.nlev):
-        if S.level_n(lvl) >= min_n:
+        if min_n <= S.level_n(lvl) <= max_n:
             out.append(S.export(lvl, "stencil"))
     S.close()
     return out
 
 
 def training_set(nfields: int, n: int = 255, seed0: int = 10_000, block: int = 16,
-                 lo: float = -4.0, hi: float = 4.0, device="cuda:0"):
+                 lo: float = -4.0, hi: float = 4.0, device="cuda:0", min_n: int = 7, max_n: int = 1 << 15):
     samples = []
     for s in range(nfields):
         p = inputs.learned_train_field(seed0 + s, n, block, lo, hi)
-        samples.extend(level_stencils(p.k, p.f, device))
+        samples.extend(level_stencils(p.k, p.f, device, min_n, max_n))
     return samples
 
 
@@ -95,11 +95,12 @@ class Trainer:
 
 
 def train(fields: int = 2000, epochs: int = 1, batch: int = 16, lr: float = 1e-3, n: int = 255,
-          seed: int = 501, max_minutes: float | None = None, coarsest: int = 15, log=print):
+          seed: int = 501, max_minutes: float | None = None, coarsest: int = 15, min_n: int = 7,
+          max_n: int = 1 << 15, log=print):
     net = boxmg.Net(inputs.net_init(seed), max_n=n, train=True)
     tr = Trainer(net, coarsest=coarsest)
-    samples = training_set(fields, n)
-    held = training_set(4, n, seed0=90_000)
+    samples = training_set(fields, n, min_n=min_n, max_n=max_n)
+    held = training_set(8, n, seed0=90_000, min_n=min_n, max_n=max_n)
     rng = np.random.default_rng(seed)
     t0 = time.perf_counter()
     hist = {"held_out": [tr.mean_loss(held, 123_000)], "train": []}
@@ -143,11 +144,13 @@ def main():
     t.add_argument("--seed", type=int, default=501)
     t.add_argument("--max-minutes", type=float, default=None)
     t.add_argument("--coarsest", type=int, default=15)
+    t.add_argument("--min-n", type=int, default=7)
+    t.add_argument("--max-n", type=int, default=1 << 15)
     t.add_argument("--out", default=DEFAULT_PARAMS)
     a = ap.parse_args()
     if a.cmd == "train":
         net, hist = train(a.fields, a.epochs, a.batch, a.lr, seed=a.seed, max_minutes=a.max_minutes,
-                          coarsest=a.coarsest, log=lambda s: print(s, flush=True))
+                          coarsest=a.coarsest, min_n=a.min_n, max_n=a.max_n, log=lambda s: print(s, flush=True))
         os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
         np.save(a.out, net.params())
         print(json.dumps({"saved": a.out, "held_out": hist["held_out"]}), flush=True)
