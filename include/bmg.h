@@ -96,7 +96,11 @@ typedef struct {
                         side (below the fine level) run as one persistent
                         one-workgroup launch per cycle: 2^k - 1 <= 63, or 1 for
                         none; 0 = 63 */
-    int reserved[1];
+    int square_tiles_below_n; /* nine-point levels of at most this many points
+                        per side run their fused pre and post passes with one
+                        workgroup per 32 x 32 square tile, every sweep of the
+                        pass inside the tile's LDS copy (one right-hand side):
+                        2^k - 1, or 1 for none; 0 = 511 */
 } bmg_options;
 
 typedef struct {
@@ -336,9 +340,11 @@ bmg_status bmg_tile_rows_get(int n, int *rows);
  * Batched solves: nprob independent problems of uneven sizes (n[p] = 2^m - 1,
  * n[p] >= 7, five-point operators as for bmg_setup), FP32 V(2,1)-cycles
  * inside double-FP64 iterative refinement (the precision option is ignored),
- * advanced together by one persistent cooperative launch (replayed from a HIP
- * graph) that runs every problem's refinement steps phase by phase with a
- * device-side stop flag per problem.  Each problem's iterates equal those of
+ * advanced together by one persistent cooperative launch per group of steps
+ * that runs every problem's refinement steps phase by phase with a
+ * device-side stop flag per problem (a replay from a HIP graph is tried first;
+ * where the runtime replays the cooperative node without its grid barrier,
+ * direct cooperative launches run it, see bmg_batch_info).  Each problem's iterates equal those of
  * bmg_solve with precision BMG_FP32_IR.
  * ---------------------------------------------------------------------- */
 typedef struct bmg_batch bmg_batch;

@@ -42,7 +42,8 @@ class Options(C.Structure):
                 ("precision", C.c_int), ("kernels", C.c_int), ("check_every", C.c_int),
                 ("refine_factor", C.c_int), ("tile_rows", C.c_int), ("interp", C.c_int),
                 ("learned_levels", C.c_int), ("net", C.c_void_p), ("smoother", C.c_int),
-                ("coarsest_n", C.c_int), ("persistent_below_n", C.c_int), ("reserved", C.c_int * 1)]
+                ("coarsest_n", C.c_int), ("persistent_below_n", C.c_int),
+                ("square_tiles_below_n", C.c_int)]
 
 
 class Info(C.Structure):

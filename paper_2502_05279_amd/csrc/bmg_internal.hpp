@@ -4,6 +4,7 @@
 
 #include "bmg.h"
 #include "bmg_fused.hpp"
+#include "bmg_tile2d.hpp"
 #include "bmg_line.hpp"
 
 #include <vector>

@@ -103,6 +103,12 @@ double ms_since(std::chrono::steady_clock::time_point t0)
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 int persistent_of(const bmg_options &o) { return o.persistent_below_n > 0 ? o.persistent_below_n : SMALL_MAX_N; }
+// Fused passes of level l in square tiles (k_pre2d, k_post2d)?
+static bool square_tiles(const bmg_solver *h, int l)
+{
+    const int lim = h->opt.square_tiles_below_n > 0 ? h->opt.square_tiles_below_n : T2D_MAX_N;
+    return h->nine[l] && h->nrhs == 1 && h->L[l].n <= lim;
+}
 
 // Walks the workspace layout; with base == nullptr it only measures.
 size_t plan(bmg_solver *h, int n, int kind, const bmg_options &o, char *base)
@@ -254,6 +260,9 @@ bmg_status check_options(const bmg_options &o)
         (!valid_n(o.persistent_below_n) || o.persistent_below_n > SMALL_MAX_N))
         return fail(BMG_EINVAL, "persistent_below_n=%d must be 2^k-1 <= %d, 1 (none) or 0 (= %d)",
                     o.persistent_below_n, SMALL_MAX_N, SMALL_MAX_N);
+    if (o.square_tiles_below_n != 0 && o.square_tiles_below_n != 1 && !valid_n(o.square_tiles_below_n))
+        return fail(BMG_EINVAL, "square_tiles_below_n=%d must be 2^k-1, 1 (none) or 0 (= %d)",
+                    o.square_tiles_below_n, T2D_MAX_N);
     return BMG_OK;
 }
 
@@ -500,6 +509,8 @@ bmg_status fused_pre(bmg_solver *h, int l, int nu, const int *stop)
     // weights (no formula), and not nine-point levels, whose divisions cost
     // more time than the loads they replace.
     const bool wrec = pre_weights_in_pass<T>(h, l, nine);
+    // small nine-point levels: every sweep inside one square tile's LDS copy
+    const bool sq = square_tiles(h, l) && nu <= 2;
     // stencil once and b, u read, u written for each right-hand side on the
     // fine level; b and u (zero) written for each on the coarse level, and the
     // 8 weight planes read once unless computed
@@ -507,7 +518,13 @@ bmg_status fused_pre(bmg_solver *h, int l, int nu, const int *stop)
     trace_begin(h, BMG_TRACE_PRE, l,
                 sizeof(T) * ((stencil_planes(nine) + 3.0 * K) * (double)F.n * F.n +
                              (2.0 * K + (wrec ? 0.0 : 8.0)) * (double)Cl.n * Cl.n));
-    if (wrec) {
+    if (sq) {
+        const dim3 g2((F.n + T2D - 1) / T2D, (F.n + T2D - 1) / T2D);
+        if (nu == 1)
+            hipLaunchKernelGGL((k_pre2d<T, 1>), g2, dim3(T2D_THREADS), 0, h->st, F, out, C, Cl, stop);
+        else
+            hipLaunchKernelGGL((k_pre2d<T, 2>), g2, dim3(T2D_THREADS), 0, h->st, F, out, C, Cl, stop);
+    } else if (wrec) {
         if constexpr (std::is_same<T, double>::value) {
             if (nu == 1) PREW(false, 1); else if (nu == 2) PREW(false, 2); else PREW(false, 3);
         }
@@ -546,6 +563,9 @@ bmg_status fused_post(bmg_solver *h, int l, int nu, const int *stop, bool norm =
     // each sweep invalidates 2 (five-point) or 4 (nine-point) more columns and
     // the fused residual one more
     const TileGeo g = level_tiles(h, l, nine ? 4 * nu + 2 : 2 * nu + 2);
+    // small nine-point levels without the norm: every sweep inside one square
+    // tile's LDS copy
+    const bool sq = !norm && square_tiles(h, l);
     norm = norm && std::is_same<T, double>::value && g.ntiles <= NPART;
     T *out = ualt<T>(h, l);
     const dim3 grid = tile_grid(g), blk(FW);
@@ -558,7 +578,13 @@ bmg_status fused_post(bmg_solver *h, int l, int nu, const int *stop, bool norm =
     const double K = h->nrhs;
     trace_begin(h, BMG_TRACE_POST, l,
                 sizeof(T) * ((stencil_planes(nine) + 3.0 * K) * (double)F.n * F.n + (K + 8.0) * (double)Cl.n * Cl.n));
-    if (!nine && BMG_FIVE_POINT_STEP_ROWS == 4) {
+    if (sq) {
+        const dim3 g2((F.n + T2D - 1) / T2D, (F.n + T2D - 1) / T2D);
+        if (nu == 1)
+            hipLaunchKernelGGL((k_post2d<T, 1>), g2, dim3(T2D_THREADS), 0, h->st, F, out, C, (const T *)Cl.u, stop);
+        else
+            hipLaunchKernelGGL((k_post2d<T, 2>), g2, dim3(T2D_THREADS), 0, h->st, F, out, C, (const T *)Cl.u, stop);
+    } else if (!nine && BMG_FIVE_POINT_STEP_ROWS == 4) {
         if (norm) { if (nu == 1) POST4(1, true); else POST4(2, true); }
         else { if (nu == 1) POST4(1, false); else POST4(2, false); }
     } else if (norm) {

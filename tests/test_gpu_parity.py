@@ -316,18 +316,21 @@ def test_breakdown_is_reported(gpu):
 
 
 # ------------------------------------------------------------ fused passes
-@pytest.mark.parametrize("kind,n,tile_rows", [("jump16", 15, 0), ("lognormal", 127, 6),
-                                              ("jump16", 255, 2), ("jump64", 511, 32),
-                                              ("lognormal", 1023, 64)])
+@pytest.mark.parametrize("kind,n,tile_rows,square", [("jump16", 15, 0, 0), ("lognormal", 127, 6, 0),
+                                                     ("jump16", 255, 2, 0), ("jump64", 511, 32, 0),
+                                                     ("lognormal", 1023, 64, 0), ("jump64", 511, 14, 1),
+                                                     ("lognormal", 1023, 0, 1023)])
 @pytest.mark.parametrize("fp32", [False, True])
-def test_fused_passes_bitwise(gpu, kind, n, tile_rows, fp32):
+def test_fused_passes_bitwise(gpu, kind, n, tile_rows, square, fp32):
     """The fused pre pass (nu sweeps + residual + restriction) and post pass
     (interpolation + nu sweeps) equal the single steps of the oracle bit for bit,
     on five- and nine-point levels, across several strips and row tiles (small
-    tile_rows), in FP64 and in the FP32 hierarchy."""
+    tile_rows), in FP64 and in the FP32 hierarchy; nine-point levels up to 511
+    (square = 0), none (1) or up to 1023 run in square tiles (each ragged at
+    its last tile row and column)."""
     p = problem(kind, n, 9)
     st, _ = gpu_problem(p)
-    opts = dict(tile_rows=tile_rows)
+    opts = dict(tile_rows=tile_rows, square_tiles_below_n=square)
     if fp32:
         opts["precision"] = boxmg.BMG_FP32_IR
     S = boxmg.Solver(st, **opts)
