@@ -530,7 +530,8 @@ __device__ void band_solve_direct(const BandSolve &B, Get get, Put put, double *
 // compressed rows of phase c + 1 into the other of two LDS slots meanwhile,
 // the global loads of the phases after it already in flight in their
 // registers (BAND_INFLIGHT sets), so memory latency stays behind the chain.
-// Phases run forward through the blocks (two per block), then backward:
+// The right-hand side and the pivots are staged in LDS first (z, dpl), so
+// the chain itself waits on no global load.  Phases run forward through the blocks (two per block), then backward:
 // nch = 4 M / 64 phases, band_phases(nch) barriers on every wave.  Workgroup
 // k solves right-hand side k (its arrays ks elements, its stop flag kstop
 // ints after the first's).
@@ -544,19 +545,40 @@ constexpr int BAND_PER_LANE = BAND_CH * 64 / 2 / (64 * BAND_LOADERS);   // doubl
 // one after each, rounded up to whole rounds of the loaders' register sets.
 __host__ __device__ inline int band_phases(int nch) { return (nch + BAND_INFLIGHT) / BAND_INFLIGHT * BAND_INFLIGHT; }
 
-__host__ __device__ inline size_t band_solve_lds(int M) { return ((size_t)M + 2 * BAND_CH * 128) * sizeof(double); }
+__host__ __device__ inline size_t band_solve_lds(int M) { return (2 * (size_t)M + 2 * BAND_CH * 128) * sizeof(double); }
 
 // Steps R0 + BAND_CH - 1 .. R0 (DIR < 0) or R0 .. R0 + BAND_CH - 1 of a block;
 // row t of the slot holds step R0 + t (current block at [0, 64), the
-// neighbouring one at [64, 128)).
+// neighbouring one at [64, 128)).  Each step's pair of rows is read
+// BAND_AHEAD steps before it runs, and the steps keep their order (a
+// scheduling barrier after each), so the chain waits on no LDS read: left
+// to itself the scheduler reads a row just before its step to save
+// registers, and the read's latency joins the chain.  (Forming two steps'
+// broadcasts at once, the second from the first by one fused multiply-add
+// on the broadcast values, was measured slower: 21 ns per step against 19.6,
+// the extra operations costing more issue time than the broadcast saved.)
+constexpr int BAND_AHEAD = 8;
 template <int R0, int DIR>
 __device__ __forceinline__ void band_phase(double &a0, double &a1, const double *rows, int l)
 {
+    double f0[BAND_CH], f1[BAND_CH];
+    auto row = [&](int i) {
+        const int t = DIR > 0 ? i : BAND_CH - 1 - i;
+        f0[i] = rows[t * 128 + l];
+        f1[i] = rows[t * 128 + 64 + l];
+    };
+#pragma unroll
+    for (int i = 0; i < BAND_AHEAD; ++i) row(i);
 #pragma unroll
     for (int i = 0; i < BAND_CH; ++i) {
-        const int t = DIR > 0 ? i : BAND_CH - 1 - i;
-        band_step(a0, a1, rows[t * 128 + l], rows[t * 128 + 64 + l], R0 + t);
+        if (i + BAND_AHEAD < BAND_CH) row(i + BAND_AHEAD);
+        band_step(a0, a1, f0[i], f1[i], R0 + (DIR > 0 ? i : BAND_CH - 1 - i));
+        __builtin_amdgcn_sched_barrier(0);
     }
+    // both values complete here: the updates of a1 (off the chain) are not
+    // deferred past the barrier that follows, which would keep the phase's
+    // rows and broadcasts live across it
+    asm volatile("" : "+v"(a0), "+v"(a1));
 }
 
 template <typename T>
@@ -566,9 +588,20 @@ static __global__ __launch_bounds__(BAND_SOLVE_THREADS) void k_coarse_solve(Lev<
     const int rk = blockIdx.x;
     if (stopped(stop ? stop + rk * kstop : stop)) return;
     extern __shared__ double band_sm[];
-    double *z = band_sm, *slot = band_sm + B.M;
+    double *z = band_sm, *dpl = band_sm + B.M, *slot = band_sm + 2 * B.M;
     const int nb = B.M >> 6, nch = 4 * nb;
     const int l = threadIdx.x & 63;
+    const int nc = B.nc, m = B.m;
+    auto pos = [&](int k) { return (size_t)(k / nc + 1) * Cl.ld + (k % nc + 1); };
+    // every wave: the right-hand side as FP64 (zero past m) into z, the padded
+    // pivots into dpl, so that the chain reads no global memory
+    {
+        const T *bv = Cl.b + (size_t)rk * ks;
+        for (int k = threadIdx.x; k < B.M; k += BAND_SOLVE_THREADS) {
+            z[k] = k < m ? (double)bv[pos(k)] : 0.0;
+            dpl[k] = B.Dp[k];
+        }
+    }
     if (threadIdx.x >= 64) {
         // loaders.  Phase c: block q, half h (steps 32h .. 32h + 31), forward
         // for c < 2 nb, backward after; its rows are the contiguous rows
@@ -625,42 +658,31 @@ static __global__ __launch_bounds__(BAND_SOLVE_THREADS) void k_coarse_solve(Lev<
         }
         return;
     }
-    const T *bv = Cl.b + (size_t)rk * ks;
+    // wave 0: forward through the blocks, two phases each, then backward
     T *uv = Cl.u + (size_t)rk * ks;
-    const int nc = B.nc, m = B.m;
-    auto pos = [&](int k) { return (size_t)(k / nc + 1) * Cl.ld + (k % nc + 1); };
-    auto get = [&](int k) -> double { return k < m ? (double)bv[pos(k)] : 0.0; };
-    double a0 = get(l), a1 = get(64 + l), bn = get(128 + l), dp = B.Dp[l];
-    lds_barrier();                                  // phase 0 is in its slot
-    for (int c = 0; c < nch; ++c) {
-        const double *rows = slot + (size_t)(c & 1) * BAND_CH * 128;
-        if (c < 2 * nb) {                           // forward, block q = c / 2
-            const int q = c >> 1;
-            if (!(c & 1)) {
-                band_phase<0, 1>(a0, a1, rows, l);
-            } else {
-                band_phase<32, 1>(a0, a1, rows, l);
-                z[64 * q + l] = a0 / dp;
-                a0 = a1;
-                a1 = bn;
-                bn = get(64 * (q + 3) + l);
-                dp = q + 1 < nb ? B.Dp[64 * (q + 1) + l] : 1.0;
-                if (q + 1 == nb) {                  // the backward pass starts from the top block
-                    a0 = z[64 * (nb - 1) + l];
-                    a1 = nb >= 2 ? z[64 * (nb - 2) + l] : 0.0;
-                }
-            }
-        } else {                                    // backward, block q = nb - 1 - (c - 2 nb) / 2
-            const int c2 = c - 2 * nb, q = nb - 1 - (c2 >> 1);
-            if (!(c2 & 1)) {
-                band_phase<32, -1>(a0, a1, rows, l);
-            } else {
-                band_phase<0, -1>(a0, a1, rows, l);
-                if (64 * q + l < m) uv[pos(64 * q + l)] = (T)a0;
-                a0 = a1;
-                a1 = q >= 2 ? z[64 * q - 128 + l] : 0.0;
-            }
-        }
+    lds_barrier();                                  // phase 0, b and the pivots are in LDS
+    double a0 = z[l], a1 = nb >= 2 ? z[64 + l] : 0.0, bn = nb >= 3 ? z[128 + l] : 0.0;
+    for (int q = 0; q < nb; ++q) {
+        band_phase<0, 1>(a0, a1, slot, l);
+        lds_barrier();
+        band_phase<32, 1>(a0, a1, slot + BAND_CH * 128, l);
+        z[64 * q + l] = a0 / dpl[64 * q + l];       // b of block q is no longer needed
+        a0 = a1;
+        a1 = bn;
+        bn = q + 3 < nb ? z[64 * (q + 3) + l] : 0.0;
+        lds_barrier();
+    }
+    a0 = z[64 * (nb - 1) + l];
+    a1 = nb >= 2 ? z[64 * (nb - 2) + l] : 0.0;
+    bn = nb >= 3 ? z[64 * (nb - 3) + l] : 0.0;
+    for (int q = nb - 1; q >= 0; --q) {
+        band_phase<32, -1>(a0, a1, slot, l);
+        lds_barrier();
+        band_phase<0, -1>(a0, a1, slot + BAND_CH * 128, l);
+        if (64 * q + l < m) uv[pos(64 * q + l)] = (T)a0;
+        a0 = a1;
+        a1 = bn;
+        bn = q >= 3 ? z[64 * (q - 3) + l] : 0.0;
         lds_barrier();
     }
     for (int c = nch + 1; c < band_phases(nch); ++c) lds_barrier();   // the loaders' last phases
