@@ -259,19 +259,38 @@ def bench_learned(args):
         with boxmg.Solver(st, **opts) as B:
             return B.solve(rhs, tol=args.tol, raise_on_noconv=False)
 
+    # a learned set-up can break down (a coarse operator built with learned
+    # weights on which BoxMG's formula has a denominator <= 0): the step then
+    # solves with BoxMG alone, the fallback, and the line says so
+    broke = []
+
     def run_learned():
-        with boxmg.Solver(st, interp=boxmg.BMG_INTERP_LEARNED, net=net, **opts) as L:
-            return L.solve(rhs, tol=args.tol, raise_on_noconv=False)
+        try:
+            with boxmg.Solver(st, interp=boxmg.BMG_INTERP_LEARNED, net=net, **opts) as L:
+                return L.solve(rhs, tol=args.tol, raise_on_noconv=False)
+        except boxmg.BoxMGError as e:
+            if e.status != boxmg.BMG_EBREAKDOWN:
+                raise
+            broke.append(str(e))
+            return None, None
 
     def run_select():
-        with boxmg.Solver(st, interp=boxmg.BMG_INTERP_LEARNED, net=net, **opts) as L, \
-                boxmg.Solver(st, **opts) as B:
+        try:
+            L = boxmg.Solver(st, interp=boxmg.BMG_INTERP_LEARNED, net=net, **opts)
+        except boxmg.BoxMGError as e:
+            if e.status != boxmg.BMG_EBREAKDOWN:
+                raise
+            broke.append(str(e))
+            x, info = run_boxmg()
+            return x, info, boxmg.BMG_INTERP_BOXMG, (None, None)
+        with L, boxmg.Solver(st, **opts) as B:
             return boxmg.solve_select(L, B, rhs, tol=args.tol, raise_on_noconv=False)
 
     for _ in range(args.warmup):
         run_select()
     (_, ib), tb = timed(run_boxmg)
     (_, il), tl = timed(run_learned)
+    il = il or {"cycles": None, "rho": None, "rel_res": None}
     times = []
     for _ in range(args.steps):
         (x, info, used, rho), ts = timed(run_select)
@@ -289,7 +308,8 @@ def bench_learned(args):
                    "cycles": info["cycles"], "final_rel_res": info["rel_res"],
                    "boxmg_ms": tb * 1e3, "boxmg_cycles": ib["cycles"], "boxmg_rho": ib["rho"],
                    "learned_ms": tl * 1e3, "learned_cycles": il["cycles"], "learned_rho": il["rho"],
-                   "learned_final_rel_res": il["rel_res"]},
+                   "learned_final_rel_res": il["rel_res"],
+                   "learned_setup": broke[0] if broke else "ok"},
     }
     # the network's forward pass on the fine operator, the learned set-up's
     # dominant work: conv1 (9 -> 32 channels, 3x3) at every fine point, conv2
@@ -484,6 +504,9 @@ def main():
     ap.add_argument("--coarsest", type=int, default=0,
                     help="points per side of the directly solved coarsest level (0 = the "
                          "workload's default: 63 on the jumping fields, 3 otherwise)")
+    ap.add_argument("--square-tiles", type=int, default=0, metavar="N",
+                    help="nine-point levels of at most N points per side run their fused "
+                         "passes in square tiles (2^k - 1; 1 = none; 0 = the library's 511)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device (a kernel of known traffic, to "
                          "calibrate hardware byte counters) and print the achieved GB/s")
@@ -542,7 +565,7 @@ def main():
     coarsest = args.coarsest or default_coarsest(args.workload, n)
     opts = dict(max_cycles=args.max_cycles, kernels=kern, check_every=16, precision=prec,
                 smoother=boxmg.BMG_SMOOTH_LINE if line else boxmg.BMG_SMOOTH_POINT,
-                coarsest_n=coarsest)
+                coarsest_n=coarsest, square_tiles_below_n=args.square_tiles)
     tclass = "pre" if args.kernels == "fused" and not line else "smooth"
     if prec == boxmg.BMG_FP32_IR:
         tclass = "resnorm"     # the FP64 outer residual (accurate, 64 B per point)

@@ -77,8 +77,9 @@ class _Handle:
         self.close()
         return False
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # (bound at definition: the module's globals may be gone by then)
+        if _finalizing():
             return
         try:
             self.close()

@@ -1,12 +1,15 @@
 """Training and use of the learned interpolation (all arithmetic in the HIP
 library; this module only schedules samples and moves arrays).
 
-Training data are the operators of every level (with at least 7 points per
-side) of BoxMG hierarchies built on seeded coefficient fields; each sample is
-one two-grid cycle on a level operator from a random residual, and the network
-minimises the mean residual reduction ||r3||^2 / ||r0||^2 with Adam.
+Training data are the operators of the levels with 31 to 255 points per side
+of BoxMG hierarchies built on seeded coefficient fields; each sample is one
+two-grid cycle on a level operator from a random residual, and the network
+minimises the mean residual reduction ||r3||^2 / ||r0||^2 with Adam.  (Levels
+of 7 and 15 points, where a coarse grid point stands for a quarter of the
+domain, made the training diverge; the network corrects the weights of levels
+of 31 points and more.)
 
-    python -m paper_2502_05279_amd.learned train --fields 2000 --epochs 1 \
+    python -m paper_2502_05279_amd.learned train --fields 1000 --epochs 6 --lr 1e-4 \
         --out paper_2502_05279_amd/data/learned_p.npy
 """
 from __future__ import annotations
@@ -95,7 +98,7 @@ class Trainer:
 
 
 def train(fields: int = 2000, epochs: int = 1, batch: int = 16, lr: float = 1e-3, n: int = 255,
-          seed: int = 501, max_minutes: float | None = None, coarsest: int = 15, min_n: int = 7,
+          seed: int = 501, max_minutes: float | None = None, coarsest: int = 15, min_n: int = 31,
           max_n: int = 1 << 15, log=print):
     net = boxmg.Net(inputs.net_init(seed), max_n=n, train=True)
     tr = Trainer(net, coarsest=coarsest)
@@ -144,7 +147,7 @@ def main():
     t.add_argument("--seed", type=int, default=501)
     t.add_argument("--max-minutes", type=float, default=None)
     t.add_argument("--coarsest", type=int, default=15)
-    t.add_argument("--min-n", type=int, default=7)
+    t.add_argument("--min-n", type=int, default=31)
     t.add_argument("--max-n", type=int, default=1 << 15)
     t.add_argument("--out", default=DEFAULT_PARAMS)
     a = ap.parse_args()
