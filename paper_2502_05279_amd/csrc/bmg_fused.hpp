@@ -175,15 +175,24 @@ __device__ __forceinline__ void five_point_sweeps(T *su, const T *sW, int lane, 
             su[slot<RU>(row) * FW + lane] = v;
         }
     };
-    // a phase where odd columns update window row ko and even columns row ke
+    // a phase where odd columns update window row ko and even columns row ke.
+    // The entries of both rows are taken as values first (the empty asm keeps
+    // them values): a select between two elements of a register array is
+    // otherwise turned into one element at a per-lane index, a chain of a
+    // select per array element for each half of each value, which was a fifth
+    // of the fine pass's vector instructions.
+    auto pick = [](T vo, T ve, bool odd_lane) {
+        asm volatile("" : "+v"(vo), "+v"(ve));
+        return odd_lane ? vo : ve;
+    };
     auto pair = [&](bool on_odd, int ko, bool on_even, int ke) {
         const bool on = odd ? on_odd : on_even;
         const int row = base + (odd ? ko : ke);
         if (on && col_upd && row >= 1 && row <= n) {
-            const T b = odd ? rB[ko] : rB[ke];
-            const T o = odd ? rO[ko] : rO[ke];
-            const T s0 = odd ? rS[ko] : rS[ke];
-            const T s1 = odd ? rS[ko + 1] : rS[ke + 1];
+            const T b = pick(rB[ko], rB[ke], odd);
+            const T o = pick(rO[ko], rO[ke], odd);
+            const T s0 = pick(rS[ko], rS[ke], odd);
+            const T s1 = pick(rS[ko + 1], rS[ke + 1], odd);
             const T v = gs_lds<T, false, RU>(su, sW, nullptr, nullptr, lane, row, b, o, s0, s1);
             su[slot<RU>(row) * FW + lane] = v;
         }
@@ -759,7 +768,7 @@ __global__ __launch_bounds__(FW) void k_post(Lev<T> L, T *__restrict__ uout, Wts
 // four-row LDS ring, from which the per-tile sum of squares of its accurate
 // residual goes to part[tile]; sweeps 1..NB give the next cycle's
 // pre-smoothed iterate u'' (written), whose residual is restricted with the
-// operator-induced weights computed in the pass, as in pre_tile.  Every array
+// stored weights (the rows the interpolation read, requested again).  Every array
 // value is the one the two separate passes give (the norm's partial sums follow
 // this pass's tiles).  u_c = 0 goes to a separate coarse buffer (ucz), since the
 // coarse correction e_c is still read by other tiles.
@@ -767,9 +776,9 @@ template <int NB>
 struct PostPreLds {
     static constexpr int NS = NB + 1;
     static constexpr int RW = 2 * NS + 4;
+    static constexpr int RU = RW + 2;      // ring rows (see postpre_tile)
     static constexpr int CW = FW / 2 + 2;  // coarse columns of a strip
-    double su[RW * FW], sW[RW * FW], sx[4 * FW];
-    double wy[FW], wx[3 * FW];
+    double su[RU * FW], sW[RU * FW], sx[4 * FW];
     double sec[8 * CW];                    // e_c rows, ring of 8
     double uk[4 * FW];                     // u_k rows, ring of 4
 };
@@ -784,7 +793,11 @@ __device__ __forceinline__ void postpre_tile(const Lev<double> &L, double *__res
     using T = double;
     constexpr int NS = NB + 1;                     // sweeps: one post, NB pre
     constexpr int RW = 2 * NS + 4;                 // window rows e-2NS-2 .. e+1
-    constexpr int RU = RW;                         // LDS ring rows
+    // LDS ring rows: two more than the window, so that the rows a step
+    // brings in take the slots of rows no step still reads, and a step needs
+    // no barrier before writing them (the previous step's residuals read its
+    // whole window)
+    constexpr int RU = PostPreLds<NB>::RU;
     constexpr int CW = PostPreLds<NB>::CW;
     T *su = S.su, *sW = S.sW, *sr = S.sx, *sec = S.sec, *suk = S.uk;
 
@@ -883,31 +896,27 @@ __device__ __forceinline__ void postpre_tile(const Lev<double> &L, double *__res
             rB[k + t] = ld_row(L.b, row + t);
         }
     }
-    // the lumped row of this column at window row k (in-pass weights)
-    auto row9 = [&](int k, int row, T a[9]) {
-        const int r0 = slot<RU>(row) * FW + lane;
-        a[0] = (T)0;
-        a[1] = rS[k];
-        a[2] = (T)0;
-        a[3] = sW[r0];
-        a[4] = rO[k];
-        a[5] = sW[r0 + 1];
-        a[6] = (T)0;
-        a[7] = rS[k + 1];
-        a[8] = (T)0;
-#pragma unroll
-        for (int q = 0; q < 9; ++q) {
-            if (q == 4) continue;
-            if (a[q] > (T)0) {
-                a[4] = a[4] + a[q];
-                a[q] = (T)0;
-            }
-        }
+    // the stored weights of the coarse point a restriction step takes, as
+    // k_restrict reads them (even columns that own a coarse point): requested
+    // during step e, used when the restriction of step e runs after the first
+    // barrier of step e + 2.  The post pass read the same rows four steps before, so
+    // they come from the caches; computing them here instead (two lumped
+    // rows and eight divisions per coarse point, in branches the odd and the
+    // even columns each take) cost more time than the loads.
+    T rw[8];
+    auto fetch_rw = [&](int e) {
+        const int J = (e - 2 * NS - 2) >> 1;
+        const bool ok = restrictor && J >= 1 && J <= nc;
+        const size_t c = ok ? (size_t)J * ldc + I : 0, cn = c + ldc;
+        rw[0] = ok ? C.at(LNE, c) : (T)0;
+        rw[1] = ok ? C.at(LA, c) : (T)0;
+        rw[2] = ok ? C.at(LNW, c + 1) : (T)0;
+        rw[3] = ok ? C.at(LR, c) : (T)0;
+        rw[4] = ok ? C.at(LL, c + 1) : (T)0;
+        rw[5] = ok ? C.at(LSE, cn) : (T)0;
+        rw[6] = ok ? C.at(LB, cn) : (T)0;
+        rw[7] = ok ? C.at(LSW, cn + 1) : (T)0;
     };
-    const int wl = lane >> 1;
-    const bool odd_col = i & 1;
-    T pLNE = 0, pLNW = 0, pLR = 0, pLL = 0, pLA = 0, yLB = 0, yLA = 0;
-    T w[8];
 
     T pu0, pu1, pW0, pW1, pO0, pO1, pS0, pS1, pB0, pB1, pec;
     IW pw;
@@ -924,21 +933,11 @@ __device__ __forceinline__ void postpre_tile(const Lev<double> &L, double *__res
     fetch(es);
     double acc = 0.0;
     // restriction of the coarse row of step e (J = (e - 2NS - 2) / 2) by the
-    // even columns, from the residual ring and the weights step e left in LDS;
+    // even columns, from the residual ring and the weights step e requested;
     // it runs after the next step's first barrier (or after the last step),
-    // before anything overwrites them
+    // before that step's residuals overwrite the ring
     auto restrict_step = [&](int e) {
-        if (restrictor) {
-            w[0] = S.wx[wl];
-            w[1] = pLA;
-            w[2] = S.wx[FW / 2 + wl + 1];
-            w[3] = S.wx[FW + wl];
-            w[4] = S.wx[3 * FW / 2 + wl + 1];
-            w[5] = S.wx[2 * FW + wl];
-            w[6] = yLB;
-            w[7] = S.wx[5 * FW / 2 + wl + 1];
-        }
-        if (!odd_col) pLA = yLA;
+        const T *w = rw;
         const int f = e - 2 * NS - 2, J = f >> 1;
         if (restrictor && J >= 1 && J <= nc && f >= y0 && f < y1) {
             const size_t c = (size_t)J * Cl.ld + I;
@@ -959,8 +958,6 @@ __device__ __forceinline__ void postpre_tile(const Lev<double> &L, double *__res
     };
 
     for (int e = es; e <= elast; e += 2) {
-        __syncthreads();  // the previous step is done with the slots reused below
-        if (e > es) restrict_step(e - 2);
         if (lane < CW) sec[(((e >> 1) + 2) & 7) * CW + lane] = pec;
 #pragma unroll
         for (int k = 0; k < RW - 2; ++k) { rO[k] = rO[k + 2]; rS[k] = rS[k + 2]; rB[k] = rB[k + 2]; }
@@ -975,20 +972,8 @@ __device__ __forceinline__ void postpre_tile(const Lev<double> &L, double *__res
         }
         if (e + 2 <= elast) fetch(e + 2);
         __syncthreads();
-        if (!odd_col) {
-            // y-edge of row e-2NS-1 (window row 1), as in pre_tile
-            const int row = e - 2 * NS - 1;
-            yLB = yLA = (T)0;
-            if (col_upd && row >= 1 && row <= n) {
-                T a[9];
-                row9(1, row, a);
-                const T D = (a[4] + a[3]) + a[5];
-                yLB = -((a[1] + a[0]) + a[2]) / D;
-                yLA = -((a[7] + a[6]) + a[8]) / D;
-            }
-            S.wy[wl] = yLB;
-            S.wy[FW / 2 + wl] = yLA;
-        }
+        if (e > es) restrict_step(e - 2);
+        fetch_rw(e);
         // sweep 0 completes rows e and e-1 of u_k: written, and kept for the norm
         five_point_sweeps<T, NS, RU>(su, sW, lane, i, col_upd, n, e, rB, rO, rS, [&](int s) {
             if (s == 0) {
@@ -1007,31 +992,6 @@ __device__ __forceinline__ void postpre_tile(const Lev<double> &L, double *__res
             const int row = e - 2 * NS + 2 - t;
             if (col_own && row >= y0 && row < y1)
                 uout[(size_t)row * ld + i] = su[slot<RU>(row) * FW + lane];
-        }
-        if (col_upd && odd_col) {
-            // x-edge of window row 2 and cell centre of window row 1
-            T a[9];
-            T xLL = (T)0, xLR = (T)0;
-            if (e - 2 * NS >= 1 && e - 2 * NS <= n) {
-                row9(2, e - 2 * NS, a);
-                const T D = (a[4] + a[7]) + a[1];
-                xLL = -((a[3] + a[6]) + a[0]) / D;
-                xLR = -((a[5] + a[8]) + a[2]) / D;
-            }
-            row9(1, e - 2 * NS - 1, a);
-            const T lbw = S.wy[wl - 1], law = S.wy[FW / 2 + wl - 1];
-            const T lbe = S.wy[wl], lae = S.wy[FW / 2 + wl];
-            const T cLNE = -((a[8] + a[7] * xLR) + a[5] * lae) / a[4];
-            const T cLNW = -((a[6] + a[7] * xLL) + a[3] * law) / a[4];
-            const T cLSE = -((a[2] + a[1] * pLR) + a[5] * lbe) / a[4];
-            const T cLSW = -((a[0] + a[1] * pLL) + a[3] * lbw) / a[4];
-            S.wx[wl] = pLNE;
-            S.wx[FW / 2 + wl] = pLNW;
-            S.wx[FW + wl] = pLR;
-            S.wx[3 * FW / 2 + wl] = pLL;
-            S.wx[2 * FW + wl] = cLSE;
-            S.wx[5 * FW / 2 + wl] = cLSW;
-            pLNE = cLNE; pLNW = cLNW; pLR = xLR; pLL = xLL;
         }
         // residual of rows e-2NS and e-2NS-1
 #pragma unroll

@@ -1140,14 +1140,15 @@ static TileGeo postpre_geo(const bmg_solver *h)
 }
 
 // Plain FP64 cycles where the fine post pass of each cycle runs together with
-// the fine pre pass of the next (k_postpre): a five-point fine level with the
-// in-pass restriction weights, one post sweep and one or two pre sweeps, and
-// at most NPART tiles (their norm partials).
+// the fine pre pass of the next (k_postpre): an FP64 five-point fine level
+// with one right-hand side (operator-induced or learned weights: the pass
+// reads the stored ones), one post sweep and one or two pre sweeps, and at
+// most NPART tiles (their norm partials).
 static bool postpre_ok(const bmg_solver *h)
 {
     return !h->f32 && h->opt.kernels == BMG_KERNELS_FUSED && h->opt.smoother == BMG_SMOOTH_POINT && !h->nine[0] &&
            BMG_FIVE_POINT_STEP_ROWS == 2 && h->nlev >= 2 && h->opt.nu2 == 1 && (h->opt.nu1 == 1 || h->opt.nu1 == 2) &&
-           pre_weights_in_pass<double>(h, 0, false) && postpre_geo(h).ntiles <= NPART;
+           h->nrhs == 1 && postpre_geo(h).ntiles <= NPART;
 }
 
 // One plain FP64 cycle and its recorded norm on the k_postpre schedule.
