@@ -613,6 +613,15 @@ __device__ __forceinline__ void post_tile(const Lev<T> &L, T *__restrict__ uout,
             rB[k + t] = ld_row(L.b, row + t);
         }
     }
+    // coarse row es/2 + 1, which the first step reads with es/2; from then on
+    // each step writes the row two steps ahead of its own, so that no step
+    // reads a row written in it
+    {
+        const T v = ld_crow((es >> 1) + 1);
+        __syncthreads();
+        sec[(((es >> 1) + 1) & 3) * FW + lane] = v;
+        __syncthreads();
+    }
     T pu0, pu1, pW0, pW1, pO0, pO1, pS0, pS1, pB0, pB1, pSW0 = 0, pSW1 = 0, pNW0 = 0, pNW1 = 0, pec;
     IW pw;
     // IRUP: the double-FP64 iterate at the two rows a step finalises (rows
@@ -639,15 +648,18 @@ __device__ __forceinline__ void post_tile(const Lev<T> &L, T *__restrict__ uout,
             pSW0 = ld_row(L.SW, e); pSW1 = ld_row(L.SW, e + 1);
             pNW0 = ld_row(L.NW, e); pNW1 = ld_row(L.NW, e + 1);
         }
-        pec = ld_crow((e >> 1) + 1);
+        pec = ld_crow((e >> 1) + 2);
         pw = ld_iw(e);
     };
     fetch(es);
     double acc = 0.0;
     for (int e = es; e <= elast; e += 2) {
-        __syncthreads();
-        // coarse row e/2 + 1 joins the e_c ring (rows e/2 and e/2 + 1 are used)
-        sec[(((e >> 1) + 1) & 3) * FW + lane] = pec;
+        // with two ring rows beyond the window the rows this step brings in
+        // take slots no lane still reads, and no barrier is needed before them
+        if constexpr (RU - RW < 2) __syncthreads();
+        // coarse row e/2 + 2 joins the e_c ring for the next step (this step
+        // reads rows e/2 and e/2 + 1; the slot is that of e/2 - 2)
+        sec[(((e >> 1) + 2) & 3) * FW + lane] = pec;
 #pragma unroll
         for (int k = 0; k < RW - 2; ++k) { rO[k] = rO[k + 2]; rS[k] = rS[k + 2]; rB[k] = rB[k + 2]; }
         rO[RW - 2] = pO0; rO[RW - 1] = pO1;
@@ -657,7 +669,6 @@ __device__ __forceinline__ void post_tile(const Lev<T> &L, T *__restrict__ uout,
 #pragma unroll
             for (int t = 0; t < 2; ++t) { xh[t] = pxh[t]; xl[t] = pxl[t]; }
         }
-        __syncthreads();
         {
             const int s0 = slot<RU>(e) * FW + lane, s1 = slot<RU>(e + 1) * FW + lane;
             su[s0] = interp(e, pu0, pw);
