@@ -504,6 +504,9 @@ def main():
     ap.add_argument("--coarsest", type=int, default=0,
                     help="points per side of the directly solved coarsest level (0 = the "
                          "workload's default: 63 on the jumping fields, 3 otherwise)")
+    ap.add_argument("--refine-factor", type=int, default=None, metavar="F",
+                    help="FP64: turn to double-FP64 refinement steps at F * tol (default: "
+                         "the library's 16; 0 = never)")
     ap.add_argument("--square-tiles", type=int, default=0, metavar="N",
                     help="nine-point levels of at most N points per side run their fused "
                          "passes in square tiles (2^k - 1; 1 = none; 0 = the library's 511)")
@@ -566,6 +569,8 @@ def main():
     opts = dict(max_cycles=args.max_cycles, kernels=kern, check_every=16, precision=prec,
                 smoother=boxmg.BMG_SMOOTH_LINE if line else boxmg.BMG_SMOOTH_POINT,
                 coarsest_n=coarsest, square_tiles_below_n=args.square_tiles)
+    if args.refine_factor is not None:
+        opts["refine_factor"] = args.refine_factor
     tclass = "pre" if args.kernels == "fused" and not line else "smooth"
     if prec == boxmg.BMG_FP32_IR:
         tclass = "resnorm"     # the FP64 outer residual (accurate, 64 B per point)

@@ -557,7 +557,10 @@ __host__ __device__ inline size_t band_solve_lds(int M) { return (2 * (size_t)M 
 // broadcasts at once, the second from the first by one fused multiply-add
 // on the broadcast values, was measured slower: 21 ns per step against 19.6,
 // the extra operations costing more issue time than the broadcast saved.)
-constexpr int BAND_AHEAD = 8;
+#ifndef BMG_BAND_AHEAD
+#define BMG_BAND_AHEAD 8
+#endif
+constexpr int BAND_AHEAD = BMG_BAND_AHEAD;
 template <int R0, int DIR>
 __device__ __forceinline__ void band_phase(double &a0, double &a1, const double *rows, int l)
 {

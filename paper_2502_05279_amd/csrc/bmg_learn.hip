@@ -118,7 +118,7 @@ static __global__ void k_net_features(Lev<double> L, bool nine, bf16_t *__restri
 
 // ------------------------------------------------------------- convolutions
 // Implicit-GEMM 3x3 convolution, D[out channel][point] = sum over taps and
-// input channels of W * input, 16 output points of one grid row per wave.
+// input channels of W * input, groups of 16 output points of one grid row per wave.
 // MODE 0: input centre = output point (stride 1); 1: centre = 2 x output point
 // (stride 2); 2: transposed stride 1 (input at point - tap, backward of a
 // stride-1 layer); 3: transposed stride 2 (input at (point - tap) / 2 where
@@ -144,29 +144,47 @@ struct ConvArgs {
     float *yout;                 // EP_OUT: 8 values per point, out_side points per row
 };
 
+// Each wave keeps the layer's A operands (all taps and channel blocks) in
+// registers and computes CONV_GROUPS groups of 16 consecutive output points
+// of its row with them, so the weights are read once per wave instead of once
+// per group; every group's products are accumulated in the same order as
+// before (taps, input blocks, output blocks).
+constexpr int CONV_GROUPS = 4;
 template <int CINP, int COUTP, int MODE, int EP>
 __global__ __launch_bounds__(256) void k_conv(ConvArgs a)
 {
-    constexpr int KB = CINP / 16, MB = COUTP / 16;
+    constexpr int KB = CINP / 16, MB = COUTP / 16, NA = 9 * KB * MB;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int j = a.lo + blockIdx.y;
-    const int i0 = a.lo + (blockIdx.x * 4 + wave) * 16;
-    if (i0 > a.hi) return;   // whole wave past the row end; no barriers below
-    const int pi = i0 + (lane & 15);
+    const int ibase = a.lo + (blockIdx.x * 4 + wave) * 16 * CONV_GROUPS;
+    if (ibase > a.hi) return;   // whole wave past the row end; no barriers below
     const int kq = 4 * (lane >> 4);
-    const bool in_dom = pi <= a.hi;
-    const bool valid = in_dom && j >= a.vlo && j <= a.vhi && pi >= a.vlo && pi <= a.vhi;
     const bool row_valid = j >= a.vlo && j <= a.vhi;
 
-    f32x4 acc[MB];
+    bf16x4 wr[NA];
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+        const uint2 wv = a.w[q * 64 + lane];
+        wr[q][0] = (short)(wv.x & 0xffff);
+        wr[q][1] = (short)(wv.x >> 16);
+        wr[q][2] = (short)(wv.y & 0xffff);
+        wr[q][3] = (short)(wv.y >> 16);
+    }
+    float bias[MB][4];
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int co = mb * 16 + kq + e;
-            acc[mb][e] = (a.bias && co < a.cout) ? a.bias[co] : 0.0f;
+            bias[mb][e] = (a.bias && co < a.cout) ? a.bias[co] : 0.0f;
         }
-    if (row_valid) {
+
+    // the input fragments of a group (tap t, channel block kb); those of the
+    // next group are requested before this group's products, so a wave waits
+    // for its inputs once rather than once per group
+    auto load_group = [&](int g, bf16x4 (&in)[9][KB]) {
+        const int pi = ibase + 16 * g + (lane & 15);
+        const bool valid = row_valid && pi <= a.hi && pi >= a.vlo && pi <= a.vhi;
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
             const int dx = t % 3 - 1, dy = t / 3 - 1;
@@ -182,51 +200,69 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a)
             }
 #pragma unroll
             for (int kb = 0; kb < KB; ++kb) {
-                bf16x4 b = {0, 0, 0, 0};
-                if (ok)
-                    b = *reinterpret_cast<const bf16x4 *>(a.in + ((size_t)sy * a.in_side + sx) * CINP + kb * 16 + kq);
-#pragma unroll
-                for (int mb = 0; mb < MB; ++mb) {
-                    const uint2 wv = a.w[((t * KB + kb) * MB + mb) * 64 + lane];
-                    bf16x4 wa;
-                    wa[0] = (short)(wv.x & 0xffff);
-                    wa[1] = (short)(wv.x >> 16);
-                    wa[2] = (short)(wv.y & 0xffff);
-                    wa[3] = (short)(wv.y >> 16);
-                    acc[mb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa, b, acc[mb], 0, 0, 0);
-                }
+                bf16x4 v = {0, 0, 0, 0};
+                if (ok) v = *reinterpret_cast<const bf16x4 *>(a.in + ((size_t)sy * a.in_side + sx) * CINP + kb * 16 + kq);
+                in[t][kb] = v;
             }
         }
-    }
-    if (!in_dom) return;
-    if (EP == EP_OUT) {
-        if (kq < 8) {
-            float4 v;
-            v.x = valid ? acc[0][0] : 0.0f;
-            v.y = valid ? acc[0][1] : 0.0f;
-            v.z = valid ? acc[0][2] : 0.0f;
-            v.w = valid ? acc[0][3] : 0.0f;
-            *reinterpret_cast<float4 *>(a.yout + ((size_t)j * a.out_side + pi) * 8 + kq) = v;
+    };
+    bf16x4 cur[9][KB], nxt[9][KB];
+    load_group(0, cur);
+#pragma unroll
+    for (int g = 0; g < CONV_GROUPS; ++g) {
+        const int i0 = ibase + 16 * g;
+        if (i0 > a.hi) break;
+        if (g + 1 < CONV_GROUPS && i0 + 16 <= a.hi) load_group(g + 1, nxt);
+        const int pi = i0 + (lane & 15);
+        const bool in_dom = pi <= a.hi;
+        const bool valid = in_dom && row_valid && pi >= a.vlo && pi <= a.vhi;
+        f32x4 acc[MB];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[mb][e] = bias[mb][e];
+#pragma unroll
+        for (int t = 0; t < 9; ++t)
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb)
+                    acc[mb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wr[(t * KB + kb) * MB + mb], cur[t][kb],
+                                                                       acc[mb], 0, 0, 0);
+#pragma unroll
+        for (int t = 0; t < 9; ++t)
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb) cur[t][kb] = nxt[t][kb];
+        if (!in_dom) continue;
+        if (EP == EP_OUT) {
+            if (kq < 8) {
+                float4 v;
+                v.x = valid ? acc[0][0] : 0.0f;
+                v.y = valid ? acc[0][1] : 0.0f;
+                v.z = valid ? acc[0][2] : 0.0f;
+                v.w = valid ? acc[0][3] : 0.0f;
+                *reinterpret_cast<float4 *>(a.yout + ((size_t)j * a.out_side + pi) * 8 + kq) = v;
+            }
+            continue;
         }
-        return;
-    }
-    const size_t base = ((size_t)j * a.out_side + pi) * COUTP;
+        const size_t base = ((size_t)j * a.out_side + pi) * COUTP;
 #pragma unroll
-    for (int mb = 0; mb < MB; ++mb) {
-        const int c0 = mb * 16 + kq;
-        bf16_t h[4];
-        if (EP == EP_MASK) {
-            uint2 mv = make_uint2(0, 0);
-            if (valid) mv = *reinterpret_cast<const uint2 *>(a.mask + ((size_t)j * a.mask_side + pi) * COUTP + c0);
-            const bf16_t m[4] = {(bf16_t)(mv.x & 0xffff), (bf16_t)(mv.x >> 16), (bf16_t)(mv.y & 0xffff),
-                                 (bf16_t)(mv.y >> 16)};
+        for (int mb = 0; mb < MB; ++mb) {
+            const int c0 = mb * 16 + kq;
+            bf16_t h[4];
+            if (EP == EP_MASK) {
+                uint2 mv = make_uint2(0, 0);
+                if (valid) mv = *reinterpret_cast<const uint2 *>(a.mask + ((size_t)j * a.mask_side + pi) * COUTP + c0);
+                const bf16_t m[4] = {(bf16_t)(mv.x & 0xffff), (bf16_t)(mv.x >> 16), (bf16_t)(mv.y & 0xffff),
+                                     (bf16_t)(mv.y >> 16)};
 #pragma unroll
-            for (int e = 0; e < 4; ++e) h[e] = (valid && m[e] != 0) ? bf16_rne(acc[mb][e]) : (bf16_t)0;
-        } else {
+                for (int e = 0; e < 4; ++e) h[e] = (valid && m[e] != 0) ? bf16_rne(acc[mb][e]) : (bf16_t)0;
+            } else {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) h[e] = valid ? bf16_rne(fmaxf(acc[mb][e], 0.0f)) : (bf16_t)0;
+                for (int e = 0; e < 4; ++e) h[e] = valid ? bf16_rne(fmaxf(acc[mb][e], 0.0f)) : (bf16_t)0;
+            }
+            *reinterpret_cast<uint2 *>(a.out + base + c0) = pack4(h[0], h[1], h[2], h[3]);
         }
-        *reinterpret_cast<uint2 *>(a.out + base + c0) = pack4(h[0], h[1], h[2], h[3]);
     }
 }
 
@@ -566,7 +602,9 @@ template <int CINP, int COUTP, int MODE, int EP>
 bmg_status conv(bmg_net *h, ConvArgs a)
 {
     const int w = a.hi - a.lo + 1;
-    hipLaunchKernelGGL((k_conv<CINP, COUTP, MODE, EP>), dim3((w + 63) / 64, w), dim3(256), 0, h->st, a);
+    const int per_block = 4 * 16 * CONV_GROUPS;
+    hipLaunchKernelGGL((k_conv<CINP, COUTP, MODE, EP>), dim3((w + per_block - 1) / per_block, w), dim3(256), 0, h->st,
+                       a);
     LAUNCHCHK();
     return BMG_OK;
 }
