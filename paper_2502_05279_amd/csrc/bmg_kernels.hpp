@@ -324,21 +324,43 @@ __device__ __forceinline__ void lds_barrier()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// The factor, column by column in one workgroup, in right-looking form: once
-// column k is final (D_k = a_kk, L_ik = a_ik / D_k, v_j = L_jk D_k), every
-// entry of the trailing window takes its term, a_ij <- a_ij - L_ik v_j
-// (k < j <= i <= k + w).  An entry thus receives its terms in order of
-// increasing k, each the same product of the same operands as in the
-// column-by-column sums of the definition
+// v of lane `lane`, on every lane.
+__device__ __forceinline__ double readlane_d(double v, int lane)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// The factor in one workgroup, in right-looking form by panels of
+// BAND_PANEL columns.  Once column k is final (D_k = a_kk, L_ik = a_ik / D_k,
+// v_j = L_jk D_k), every entry of the trailing window takes its term,
+// a_ij <- a_ij - L_ik v_j (k < j <= i <= k + w).  An entry thus receives its
+// terms in order of increasing k, each the same product of the same operands
+// as in the column-by-column sums of the definition
 //   D_j = A_jj - sum_k L_jk v_k,  L_ij = (A_ij - sum_k L_ik v_k) / D_j,
-// so the factor is the same to the bit, while the w (w + 1) / 2 updates of a
-// column run in parallel: two barriers per column.  The window's rows live in
-// an LDS ring (row i, column j at slot i mod RR, offset j - i + w); row
-// k + w + 1 enters at column k with its entries of A, which are requested a
-// chunk of 64 columns ahead (registers, then a staging buffer), so no column
-// waits on memory.
+// so the factor is the same to the bit.  A panel's columns are finished by
+// wave 0 alone in registers, one after the other, together with the terms
+// they give to the panel's own later columns (each lane holds two rows of
+// the panel; the diagonal and the v values come from their rows' lanes by
+// readlane); then every thread applies the panel's terms, in column order,
+// to its entries of the trailing triangle: two barriers per panel instead of
+// two per column (at 63^2: 2.81 ms against 2.92 by columns, and 2.87 ms with
+// panels of 4, so the factor's time is the work of its columns rather than
+// its barriers).  The window's rows live in an LDS ring (row i,
+// column j at slot i mod RR, offset j - i + w); the B rows a panel adds to the
+// window enter during the previous panel's trailing update, their entries of
+// A requested from memory two panels ahead (registers, then a staging
+// buffer), so no panel waits on memory.
 constexpr int BAND_FACTOR_THREADS = 1024;
 constexpr int BAND_NNZ = 5;   // lower-band entries of a row of A: distances 0, 1, nc - 1, nc, nc + 1
+#ifndef BMG_BAND_PANEL
+#define BMG_BAND_PANEL 8
+#endif
+constexpr int BAND_PANEL = BMG_BAND_PANEL;
+static_assert(BAND_PANEL * (BAND_MAX_NC + 2) <= BAND_FACTOR_THREADS && BAND_PANEL <= 64,
+              "the rows a panel adds take one thread per entry, and wave 0 holds the panel's rows");
 
 __device__ inline int band_nz_dist(int e, int nc) { return e == 0 ? 0 : e == 1 ? 1 : e == 2 ? nc - 1 : e == 3 ? nc : nc + 1; }
 
@@ -346,22 +368,27 @@ static __global__ __launch_bounds__(BAND_FACTOR_THREADS) void k_band_factor(Lev<
                                                                              double *__restrict__ D,
                                                                              int *__restrict__ flags)
 {
-    constexpr int RW = BAND_MAX_NC + 2, RR = BAND_MAX_NC + 3;
+    constexpr int B = BAND_PANEL, RW = BAND_MAX_NC + 2, RR = BAND_MAX_NC + 1 + B;
     __shared__ double ring[RR * RW];
-    __shared__ double Lcol[BAND_MAX_NC + 2], vcol[BAND_MAX_NC + 2];
-    __shared__ double stage[2][64 * BAND_NNZ];
+    __shared__ double Lp[B][RW], vp[B][RW];           // the panel's columns: L(k + d, k), v at offset d
+    __shared__ double stage[2][B * BAND_NNZ];
     const int nc = L.n, m = nc * nc, w = nc + 1, t = threadIdx.x;
+    const int npanel = (m + B - 1) / B;
     auto at = [&](int i, int j) -> double & { return ring[(i % RR) * RW + (j - i + w)]; };
-    // rows 0 .. w of A, and the entries of the rows entering during the first chunk
-    for (int e = t; e < (w + 1) * (w + 1); e += blockDim.x) {
+    // the rows panel q adds to the window: q B + w .. q B + w + B - 1; entry u
+    // of its staging buffer is row q B + w + u / NNZ at distance nz(u % NNZ)
+    auto entering = [&](int q, int u) -> double {
+        const int i = q * B + w + u / BAND_NNZ;
+        return i < m ? band_entry(L, i, band_nz_dist(u % BAND_NNZ, nc)) : 0.0;
+    };
+    // rows 0 .. w + B - 1 of A (the window of panel 0)
+    for (int e = t; e < (w + B) * (w + 1); e += blockDim.x) {
         const int i = e / (w + 1), off = e % (w + 1), j = i - w + off;
         if (i < m) at(i, j) = j >= 0 ? band_entry(L, i, i - j) : 0.0;
     }
-    auto entering = [&](int c, int u) -> double {   // entry u of the staging buffer of chunk c
-        const int i = 64 * c + u / BAND_NNZ + w + 1;
-        return i < m ? band_entry(L, i, band_nz_dist(u % BAND_NNZ, nc)) : 0.0;
-    };
-    if (t < 64 * BAND_NNZ) stage[0][t] = entering(0, t);
+    const bool loader = t < B * BAND_NNZ;
+    if (loader) stage[1] [t] = entering(1, t);
+    double pf = loader ? entering(2, t) : 0.0;        // panel 2's rows, in flight
     // this thread's entries of the trailing triangle, e = t + s * blockDim.x
     const int ntri = w * (w + 1) / 2;
     int di[3], dj[3];
@@ -374,41 +401,92 @@ static __global__ __launch_bounds__(BAND_FACTOR_THREADS) void k_band_factor(Lev<
         di[s2] = e < ntri ? d : 0;
         dj[s2] = e - d * (d - 1) / 2 + 1;
     }
-    const int tnew = t - (BAND_FACTOR_THREADS - (w + 1));   // offset in the entering row, if >= 0
-    double pf = 0.0;
+    // this thread's entry of the rows entering the window: row b, offset off
+    const int eb = t / (w + 1), eoff = t % (w + 1);
+    const bool enters = t < B * (w + 1);
+    int eu = -1;   // its index in the staging buffer (-1: a zero of the band)
+    if (enters) {
+#pragma unroll
+        for (int e = 0; e < BAND_NNZ; ++e)
+            if (w - eoff == band_nz_dist(e, nc)) eu = eb * BAND_NNZ + e;
+    }
     int bad = 0;
     lds_barrier();
-    for (int k = 0; k < m; ++k) {
-        const int kc = k & 63, c = k >> 6;
-        if (kc == 0 && t < 64 * BAND_NNZ) pf = entering(c + 1, t);   // in flight for the whole chunk
-        if (t <= w) {
-            const double Dk = at(k, k);
-            if (t == 0) {
-                D[k] = Dk;
-                if (!(Dk > 0.0)) bad = 1;
-            } else if (k + t < m) {
-                const int i = k + t;
-                const double l = at(i, k) / Dk;
-                Lcol[t] = l;
-                vcol[t] = l * Dk;
-                Lb[(size_t)i * w + (k - i + w)] = l;
+    for (int p = 0; p < npanel; ++p) {
+        const int k0 = p * B;
+        if (t < 64) {
+            // wave 0: the panel's columns, in registers.  Lane l holds the
+            // panel entries of rows k0 + l and k0 + 64 + l; the diagonal and
+            // the v of a later panel column come from the lane of its row
+            const int r0 = k0 + t, r1 = k0 + 64 + t;
+            double a0[B], a1[B];
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                const int k = k0 + b;
+                a0[b] = (r0 >= k && r0 < m && r0 - k <= w) ? at(r0, k) : 0.0;
+                a1[b] = (r1 < m && r1 - k <= w) ? at(r1, k) : 0.0;
+            }
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                const int k = k0 + b;
+                if (k >= m) break;
+                const double Dk = readlane_d(a0[b], b);
+                if (t == 0) {
+                    D[k] = Dk;
+                    if (!(Dk > 0.0)) bad = 1;
+                }
+                const bool in0 = r0 > k && r0 < m && r0 - k <= w, in1 = r1 < m && r1 - k <= w;
+                double l0 = 0.0, l1 = 0.0, v0 = 0.0, v1 = 0.0;
+                if (in0) {
+                    l0 = a0[b] / Dk;
+                    v0 = l0 * Dk;
+                    Lp[b][r0 - k] = l0;
+                    vp[b][r0 - k] = v0;
+                    Lb[(size_t)r0 * w + (k - r0 + w)] = l0;
+                }
+                if (in1) {
+                    l1 = a1[b] / Dk;
+                    v1 = l1 * Dk;
+                    Lp[b][r1 - k] = l1;
+                    vp[b][r1 - k] = v1;
+                    Lb[(size_t)r1 * w + (k - r1 + w)] = l1;
+                }
+                // the terms of column k in the panel's later columns j <= r
+#pragma unroll
+                for (int jb = b + 1; jb < B; ++jb) {
+                    const double vj = readlane_d(v0, jb);   // v(k0 + jb, k), the lane of row k0 + jb
+                    if (in0 && r0 >= k0 + jb) a0[jb] = a0[jb] - l0 * vj;
+                    if (in1) a1[jb] = a1[jb] - l1 * vj;
+                }
             }
         }
         lds_barrier();
+        // the panel's terms in the trailing triangle (rows and columns
+        // k0 + B .. k0 + B - 1 + w), in column order
 #pragma unroll
         for (int s2 = 0; s2 < 3; ++s2) {
-            const int i = k + di[s2], j = k + dj[s2];
-            if (di[s2] > 0 && i < m) at(i, j) = at(i, j) - Lcol[di[s2]] * vcol[dj[s2]];
-        }
-        if (tnew >= 0 && k + w + 1 < m) {
-            const int i = k + w + 1, d = w - tnew;
-            int u = -1;
+            const int i = k0 + B - 1 + di[s2], j = k0 + B - 1 + dj[s2];
+            if (di[s2] > 0 && i < m) {
+                double a = at(i, j);
 #pragma unroll
-            for (int e = 0; e < BAND_NNZ; ++e)
-                if (d == band_nz_dist(e, nc)) u = e;
-            at(i, i - d) = u >= 0 ? stage[c & 1][kc * BAND_NNZ + u] : 0.0;
+                for (int b = 0; b < B; ++b) {
+                    const int k = k0 + b;
+                    if (i - k <= w && k < m) a = a - Lp[b][i - k] * vp[b][j - k];
+                }
+                at(i, j) = a;
+            }
         }
-        if (kc == 63 && t < 64 * BAND_NNZ) stage[(c + 1) & 1][t] = pf;
+        // the rows of panel p + 1 enter (their slots are those of panel p's
+        // rows); the staging buffer of panel p + 2 is filled from the
+        // registers and panel p + 3's entries are requested
+        if (enters) {
+            const int i = (p + 1) * B + w + eb;
+            if (i < m) at(i, i - w + eoff) = eu >= 0 ? stage[(p + 1) & 1][eu] : 0.0;
+        }
+        if (loader) {
+            stage[p & 1][t] = pf;
+            pf = entering(p + 3, t);
+        }
         lds_barrier();
     }
     if (bad) atomicOr(flags, F_BREAK_COARSE);
@@ -450,14 +528,6 @@ static __global__ void k_band_expand(int nc, const double *__restrict__ Lb, cons
     CF[o] = l > r ? Lik(64 * q + l, s) : Lik(64 * q + 64 + l, s);
     CG[o] = l < r ? Lik(s, 64 * q + l) : (q >= 1 ? Lik(s, 64 * q - 64 + l) : 0.0);
     if (l == 0) Dp[s] = s < m ? D[s] : 1.0;
-}
-
-__device__ __forceinline__ double readlane_d(double v, int lane)
-{
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)b, lane);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
 // One step: the final value y of lane r is broadcast and y L is removed from
