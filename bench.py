@@ -507,6 +507,8 @@ def main():
     ap.add_argument("--refine-factor", type=int, default=None, metavar="F",
                     help="FP64: turn to double-FP64 refinement steps at F * tol (default: "
                          "the library's 16; 0 = never)")
+    ap.add_argument("--graph", action="store_true",
+                    help="plain FP64 cycles replayed from a captured HIP graph of two cycles")
     ap.add_argument("--square-tiles", type=int, default=0, metavar="N",
                     help="nine-point levels of at most N points per side run their fused "
                          "passes in square tiles (2^k - 1; 1 = none; 0 = the library's 511)")
@@ -571,6 +573,8 @@ def main():
                 coarsest_n=coarsest, square_tiles_below_n=args.square_tiles)
     if args.refine_factor is not None:
         opts["refine_factor"] = args.refine_factor
+    if args.graph:
+        opts["graph_mode"] = 1
     tclass = "pre" if args.kernels == "fused" and not line else "smooth"
     if prec == boxmg.BMG_FP32_IR:
         tclass = "resnorm"     # the FP64 outer residual (accurate, 64 B per point)
@@ -677,7 +681,7 @@ def main():
                    "setup_ms": float(np.mean([i["t_setup_ms"] for i in infos])),
                    "solve_ms": float(np.mean([i["t_solve_ms"] for i in infos])),
                    "kernels": "basic" if line else args.kernels, "smoother": args.smoother,
-                   "nu1": 2, "nu2": 1, "precision": args.precision,
+                   "nu1": 2, "nu2": 1, "precision": args.precision, "graph_mode": int(args.graph),
                    **extra},
         "roofline": {"bound": "hbm", "kernel": KERNEL_NAMES.get(tclass, tclass), "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",

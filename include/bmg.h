@@ -101,6 +101,13 @@ typedef struct {
                         workgroup per 32 x 32 square tile, every sweep of the
                         pass inside the tile's LDS copy (one right-hand side):
                         2^k - 1, or 1 for none; 0 = 511 */
+    int graph_mode;  /* 1: bmg_solve's plain FP64 cycles on the fused fine-level
+                        schedule run as replays of a HIP graph of two cycles,
+                        captured on the solve's stream at its first use (one
+                        graph launch in place of about 26 kernel launches); the
+                        results are those of the launches, bit for bit.  Not
+                        used while a trace is enabled.  0 (default): direct
+                        launches */
 } bmg_options;
 
 typedef struct {

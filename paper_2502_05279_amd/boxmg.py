@@ -43,7 +43,7 @@ class Options(C.Structure):
                 ("refine_factor", C.c_int), ("tile_rows", C.c_int), ("interp", C.c_int),
                 ("learned_levels", C.c_int), ("net", C.c_void_p), ("smoother", C.c_int),
                 ("coarsest_n", C.c_int), ("persistent_below_n", C.c_int),
-                ("square_tiles_below_n", C.c_int)]
+                ("square_tiles_below_n", C.c_int), ("graph_mode", C.c_int)]
 
 
 class Info(C.Structure):

@@ -98,6 +98,15 @@ struct bmg_solver {
     int *count = nullptr;       // entries in hist
     int *stop = nullptr;        // stop code of the running solve
     int hist_cap = 0;
+    // graph mode: two plain cycles on the k_postpre schedule, captured once
+    // and replayed while the host state (the level buffers) is the one the
+    // capture started from and ended in
+    hipGraphExec_t pair_exec = nullptr;
+    hipStream_t cap_st = nullptr;   // the stream the capture records on (the caller's may be the null stream)
+    std::vector<void *> pair_state;
+    double pair_tol = -1.0, pair_refine = -1.0;
+    int pair_maxc = -1;
+    bool pair_off = false;      // the schedule was not periodic over two cycles
     // kernel timing
     int tr_class = -1, tr_level = -1;
     std::vector<hipEvent_t> tr_ev;

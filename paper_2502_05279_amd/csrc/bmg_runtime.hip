@@ -260,6 +260,7 @@ bmg_status check_options(const bmg_options &o)
         (!valid_n(o.persistent_below_n) || o.persistent_below_n > SMALL_MAX_N))
         return fail(BMG_EINVAL, "persistent_below_n=%d must be 2^k-1 <= %d, 1 (none) or 0 (= %d)",
                     o.persistent_below_n, SMALL_MAX_N, SMALL_MAX_N);
+    if (o.graph_mode != 0 && o.graph_mode != 1) return fail(BMG_EINVAL, "graph_mode=%d must be 0 or 1", o.graph_mode);
     if (o.square_tiles_below_n != 0 && o.square_tiles_below_n != 1 && !valid_n(o.square_tiles_below_n))
         return fail(BMG_EINVAL, "square_tiles_below_n=%d must be 2^k-1, 1 (none) or 0 (= %d)",
                     o.square_tiles_below_n, T2D_MAX_N);
@@ -1051,6 +1052,8 @@ bmg_status bmg_destroy(bmg_solver *h)
 {
     if (!h) return BMG_OK;
     for (hipEvent_t e : h->tr_ev) (void)hipEventDestroy(e);
+    if (h->pair_exec) (void)hipGraphExecDestroy(h->pair_exec);
+    if (h->cap_st) (void)hipStreamDestroy(h->cap_st);
     delete h;
     return BMG_OK;
 }
@@ -1201,6 +1204,73 @@ static bmg_status cycle_and_norm_pp(bmg_solver *h, double tol, int maxc, double 
     return BMG_OK;
 }
 
+// The host state a cycle depends on: every level's buffer pointers.
+static std::vector<void *> cycle_state(const bmg_solver *h)
+{
+    std::vector<void *> v;
+    for (int l = 0; l < h->nlev; ++l) {
+        v.push_back(h->L[l].u);
+        v.push_back(h->L[l].r);
+        v.push_back(h->ualt[l]);
+    }
+    return v;
+}
+
+// Two plain cycles on the k_postpre schedule (a pre pass pending) as one
+// graph launch.  On the k_postpre schedule the level buffers rotate with
+// period two, so a graph captured from one state leaves the host state as it
+// found it and can be replayed for every later pair; the capture itself runs
+// the host code of the two cycles (their buffer swaps included), and the
+// captured graph is launched once to do their work.  The graph is rebuilt
+// when the state or the stop-test arguments differ from the capture's.  The
+// capture records on a stream of the handle's own (no work runs while it
+// records), and the graph is launched on the solve's stream, which may be
+// the null stream.
+static bmg_status cycle_pair_graph(bmg_solver *h, double tol, int maxc, double refine, bool *pending)
+{
+    const std::vector<void *> s0 = cycle_state(h);
+    if (h->pair_exec && (s0 != h->pair_state || tol != h->pair_tol || maxc != h->pair_maxc || refine != h->pair_refine)) {
+        HIPCHK(hipStreamSynchronize(h->st));
+        (void)hipGraphExecDestroy(h->pair_exec);
+        h->pair_exec = nullptr;
+    }
+    if (h->pair_exec) {
+        HIPCHK(hipGraphLaunch(h->pair_exec, h->st));
+        return BMG_OK;
+    }
+    if (!h->cap_st) HIPCHK(hipStreamCreateWithFlags(&h->cap_st, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(h->cap_st, hipStreamCaptureModeThreadLocal));
+    hipStream_t run = h->st;
+    h->st = h->cap_st;
+    bmg_status s = cycle_and_norm_pp(h, tol, maxc, refine, pending);
+    if (s == BMG_OK) s = cycle_and_norm_pp(h, tol, maxc, refine, pending);
+    h->st = run;
+    const hipError_t ce = hipStreamEndCapture(h->cap_st, &g);
+    if (s != BMG_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return s;
+    }
+    if (ce != hipSuccess || !g) return fail(BMG_EDEVICE, "capturing two cycles failed: %s", hipGetErrorString(ce));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) return fail(BMG_EDEVICE, "instantiating the cycle graph failed: %s", hipGetErrorString(ie));
+    HIPCHK(hipGraphLaunch(ex, h->st));
+    if (cycle_state(h) == s0) {
+        h->pair_exec = ex;
+        h->pair_state = s0;
+        h->pair_tol = tol;
+        h->pair_maxc = maxc;
+        h->pair_refine = refine;
+    } else {
+        HIPCHK(hipStreamSynchronize(h->st));
+        (void)hipGraphExecDestroy(ex);
+        h->pair_off = true;
+    }
+    return BMG_OK;
+}
+
 // One FP64 refinement step: L0.b holds r, L0.u = 0; V-cycle, (XH, XL) += u
 // (inside the fine post pass where the cycle allows).
 static bmg_status refine_step64(bmg_solver *h, const int *stop)
@@ -1305,8 +1375,14 @@ bmg_status bmg_solve(bmg_solver *h, const double *rhs, double *x, double tol, bm
         while (true) {
             for (int t = 0; t < every; ++t) {
                 if (!refining) {
-                    if (pp) TRY(cycle_and_norm_pp(h, tol, maxc, refine, &pending));
-                    else TRY(cycle_and_norm(h, tol, maxc, refine));
+                    if (pp && pending && h->opt.graph_mode && !h->pair_off && h->tr_class < 0 && t + 1 < every) {
+                        TRY(cycle_pair_graph(h, tol, maxc, refine, &pending));
+                        ++t;
+                    } else if (pp) {
+                        TRY(cycle_and_norm_pp(h, tol, maxc, refine, &pending));
+                    } else {
+                        TRY(cycle_and_norm(h, tol, maxc, refine));
+                    }
                 } else {
                     TRY(refine_step64(h, h->stop));
                     TRY(resnorm_dd(h, h->B0, h->XH, h->XL, 2, nullptr, S_SUMSQ, true, tol, maxc, 0.0));

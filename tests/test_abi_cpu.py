@@ -59,7 +59,7 @@ def test_workspace_rejects_bad_kind_and_options(L):
     for bad in ({"nu1": -1}, {"nu1": 0, "nu2": 0}, {"max_cycles": 0}, {"precision": 7},
                 {"kernels": 9}, {"check_every": 0}, {"smoother": 5},
                 {"smoother": boxmg.BMG_SMOOTH_LINE, "precision": boxmg.BMG_FP32_IR},
-                {"square_tiles_below_n": 100}, {"square_tiles_below_n": -1},
+                {"square_tiles_below_n": 100}, {"square_tiles_below_n": -1}, {"graph_mode": 2},
                 {"persistent_below_n": 127}):
         o = boxmg.default_options(**bad)
         assert L.bmg_workspace_bytes(127, 5, C.byref(o), C.byref(out)) == boxmg.BMG_EINVAL, bad

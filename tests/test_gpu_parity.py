@@ -485,3 +485,30 @@ def test_trace_counts_algorithmic_bytes(gpu):
                 S.trace_enable(cls, 0, on=False)
                 assert nl == 1 and nb == want, (cls, nb, want)
         S.close()
+
+
+# ----------------------------------------------------------------- graph mode
+@pytest.mark.parametrize("kind,n,every,own_stream", [("jump16", 255, 8, False), ("lognormal", 1023, 16, True),
+                                                     ("jump64", 511, 5, False)])
+def test_graph_mode_matches_launches(gpu, kind, n, every, own_stream):
+    """Plain cycles replayed from a captured graph of two cycles
+    (graph_mode = 1) give the iterate, its low part, the cycle count and every
+    history entry of direct launches bit for bit, on two solves on the same
+    handle (the graph is captured once and replayed between the host's polls
+    of the history), on the null stream and on a stream of the caller's."""
+    p = problem(kind, n, 23)
+    st, rhs = gpu_problem(p)
+    stream = torch.cuda.Stream() if own_stream else torch.cuda.current_stream()
+    with torch.cuda.stream(stream):
+        A = boxmg.Solver(st, check_every=every, max_cycles=300)
+        G = boxmg.Solver(st, check_every=every, max_cycles=300, graph_mode=1)
+        for rep in range(2):
+            xa, ia = A.solve(rhs, tol=1e-10, raise_on_noconv=False)
+            xg, ig = G.solve(rhs, tol=1e-10, raise_on_noconv=False)
+            stream.synchronize()
+            assert ig["cycles"] == ia["cycles"] > every, (ig["cycles"], ia["cycles"])
+            same(host(xg), host(xa), f"solution, solve {rep}")
+            same(host(G.export(0, "xlo")), host(A.export(0, "xlo")), f"low part, solve {rep}")
+            assert ig["history"] == ia["history"]
+        A.close()
+        G.close()
