@@ -125,6 +125,12 @@ typedef struct {
     double t_solve_ms; /* host wall time of this call */
     int interp_used;  /* BMG_INTERP_BOXMG or BMG_INTERP_LEARNED: the weights of
                          the hierarchy that produced x */
+    int learned_levels_used; /* levels of that hierarchy whose weights came from
+                         the network (0 for BoxMG's).  A learned set-up stops
+                         using the network above a level on whose coarse
+                         operator BoxMG's formula finds a denominator <= 0: that
+                         level takes BoxMG's weights and its coarse operator is
+                         formed again, and so are all levels below it */
 } bmg_info;
 
 /* Fills *o with the defaults above.  Host only. */

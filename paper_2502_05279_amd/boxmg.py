@@ -49,7 +49,8 @@ class Options(C.Structure):
 class Info(C.Structure):
     _fields_ = [("cycles", C.c_int), ("rel_res", C.c_double), ("rho", C.c_double),
                 ("history", C.POINTER(C.c_double)), ("floor_est", C.c_double),
-                ("t_setup_ms", C.c_double), ("t_solve_ms", C.c_double), ("interp_used", C.c_int)]
+                ("t_setup_ms", C.c_double), ("t_solve_ms", C.c_double), ("interp_used", C.c_int),
+                ("learned_levels_used", C.c_int)]
 
 
 def _new_info(hist) -> Info:
@@ -61,7 +62,8 @@ def _new_info(hist) -> Info:
 def _info_dict(info: Info, hist, nh: int, status: int) -> dict:
     return {"cycles": info.cycles, "rel_res": info.rel_res, "rho": info.rho,
             "history": [hist[t] for t in range(nh)], "status": status, "floor_est": info.floor_est,
-            "t_setup_ms": info.t_setup_ms, "t_solve_ms": info.t_solve_ms, "interp_used": info.interp_used}
+            "t_setup_ms": info.t_setup_ms, "t_solve_ms": info.t_solve_ms, "interp_used": info.interp_used,
+            "learned_levels_used": info.learned_levels_used}
 
 
 class _Handle:

@@ -91,6 +91,7 @@ struct bmg_solver {
     double *Dd = nullptr;
     BandSolve band{};           // the factor rearranged for the one-wave solve
     double t_setup_ms = 0.0;    // host wall time of bmg_setup
+    int learned_used = 0;       // levels with the network's weights (learned set-up)
     int *flags = nullptr;       // validation / breakdown bits
     double *part = nullptr;     // NPART partial sums
     double *scal = nullptr;     // scalars (see enum below)

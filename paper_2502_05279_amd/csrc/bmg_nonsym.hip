@@ -627,6 +627,7 @@ bmg_status bmg_ns_solve(bmg_ns *h, const double *rhs, double *x, double tol, bmg
         info->t_setup_ms = 0.0;
         info->t_solve_ms = 0.0;
         info->interp_used = BMG_INTERP_BOXMG;
+        info->learned_levels_used = 0;
     }
     if (!isfinite(rho)) return fail(BMG_EDIVERGED, "residual is not finite after %d cycles", k);
     if (rho > tol) return fail(BMG_ENOCONV, "relative residual %.3e > tol %.3e after %d cycles", rho, tol, k);

@@ -927,18 +927,49 @@ static bmg_status setup_into(bmg_solver *h, const double *stencil, int n, int ki
     if (hipMemsetAsync(h->ws, 0, need, h->st) != hipSuccess)
         return bail(fail(BMG_EDEVICE, "hipMemsetAsync of the workspace failed"));
     hipLaunchKernelGGL(k_import_stencil, grid2(n, n, B2), B2, 0, h->st, stencil, kind, h->L[0], h->flags);
-    for (int l = 0; l + 1 < h->nlev; ++l) {
+    auto boxmg_weights = [&](int l) {
         const int nc = h->L[l + 1].n;
-        if (op.interp == BMG_INTERP_LEARNED && (op.learned_levels == 0 || l < op.learned_levels)) {
-            SCHK(net_level_weights(op.net, h->L[l], h->nine[l], h->C[l], h->flags, h->st));
-        } else {
-            hipLaunchKernelGGL(k_weights_edges, grid2(nc + 1, nc + 1, B2), B2, 0, h->st, h->L[l], h->C[l], nc,
-                               h->flags);
-            hipLaunchKernelGGL(k_weights_corners, grid2(nc + 1, nc + 1, B2), B2, 0, h->st, h->L[l], h->C[l], nc,
-                               h->flags);
-        }
+        hipLaunchKernelGGL(k_weights_edges, grid2(nc + 1, nc + 1, B2), B2, 0, h->st, h->L[l], h->C[l], nc, h->flags);
+        hipLaunchKernelGGL(k_weights_corners, grid2(nc + 1, nc + 1, B2), B2, 0, h->st, h->L[l], h->C[l], nc,
+                           h->flags);
+    };
+    auto galerkin = [&](int l) {
+        const int nc = h->L[l + 1].n;
         hipLaunchKernelGGL(k_rap, grid2(nc, nc, dim3(32, 4)), dim3(32, 4), 0, h->st, h->L[l], h->C[l], h->L[l + 1]);
+    };
+    // levels whose weights come from the network: the first `cut`.  A coarse
+    // operator built with the network's weights can leave BoxMG's formula a
+    // denominator <= 0 on a level below (the network corrects weights, it
+    // does not keep the coarse operators M-matrices).  The last level above it
+    // that used the network then takes BoxMG's weights, and it and every level
+    // below are formed again; this repeats while learned levels are left.  A
+    // breakdown with no learned level above it (the fine level's own operator)
+    // stays an error.
+    int cut = 0;
+    if (op.interp == BMG_INTERP_LEARNED)
+        cut = op.learned_levels == 0 ? h->nlev - 1 : std::min(op.learned_levels, h->nlev - 1);
+    for (int l = 0; l + 1 < h->nlev;) {
+        if (l < cut) SCHK(net_level_weights(op.net, h->L[l], h->nine[l], h->C[l], h->flags, h->st));
+        else boxmg_weights(l);
+        if (l >= 1 && cut > 0) {
+            int fl = 0;
+            if (hipMemcpyAsync(&fl, h->flags, sizeof fl, hipMemcpyDeviceToHost, h->st) != hipSuccess ||
+                hipStreamSynchronize(h->st) != hipSuccess)
+                return bail(fail(BMG_EDEVICE, "reading the set-up flags failed"));
+            if (fl & F_BREAK_INTERP) {
+                const int cleared = fl & ~F_BREAK_INTERP;
+                if (hipMemcpyAsync(h->flags, &cleared, sizeof cleared, hipMemcpyHostToDevice, h->st) != hipSuccess ||
+                    hipStreamSynchronize(h->st) != hipSuccess)
+                    return bail(fail(BMG_EDEVICE, "writing the set-up flags failed"));
+                cut = std::min(cut, l) - 1;
+                l = cut;
+                continue;
+            }
+        }
+        galerkin(l);
+        ++l;
     }
+    h->learned_used = cut;
     hipLaunchKernelGGL(k_band_factor, dim3(1), dim3(BAND_FACTOR_THREADS), 0, h->st, h->L[h->nlev - 1], h->Lb, h->Dd,
                        h->flags);
     hipLaunchKernelGGL(k_band_expand, dim3(h->band.M / 4), dim3(256), 0, h->st, h->band.nc, (const double *)h->Lb,
@@ -1355,6 +1386,7 @@ bmg_status bmg_solve(bmg_solver *h, const double *rhs, double *x, double tol, bm
         if (info) {
             info->cycles = 0; info->rel_res = 0.0; info->rho = 0.0; info->floor_est = 0.0;
             info->t_setup_ms = h->t_setup_ms; info->t_solve_ms = ms_since(t0); info->interp_used = h->opt.interp;
+            info->learned_levels_used = h->learned_used;
         }
         return BMG_OK;
     }
@@ -1445,6 +1477,7 @@ bmg_status bmg_solve(bmg_solver *h, const double *rhs, double *x, double tol, bm
         info->t_setup_ms = h->t_setup_ms;
         info->t_solve_ms = ms_since(t0);
         info->interp_used = h->opt.interp;
+        info->learned_levels_used = h->learned_used;
     }
     if (cs[1] == 2) return fail(BMG_EDIVERGED, "residual %.3e after %d cycles", hlast, steps);
     if (cs[1] == 3) return fail(BMG_ENOCONV, "relative residual %.3e > tol %.3e after %d cycles", hlast, tol, steps);

@@ -375,3 +375,53 @@ def test_shipped_network_gains_over_boxmg(gpu):
         assert il["cycles"] <= 0.85 * ib["cycles"], (s, il["cycles"], ib["cycles"])
         assert il["rho"] < ib["rho"] - 0.05, (s, il["rho"], ib["rho"])
     net.close()
+
+
+def test_learned_setup_falls_back_per_level(gpu):
+    """Random network parameters at several times their scale on every level of
+    a 255^2 field: where a coarse operator built with the network's weights
+    leaves BoxMG's formula a denominator <= 0, the set-up keeps the network on
+    the levels above the last such fallback only (info reports how many) and
+    builds the rest with BoxMG's weights.  The result is the hierarchy an
+    explicit learned_levels of that count gives, bit for bit, every level's
+    coarse operator is R A P of its own weights, and the levels below the cut
+    have BoxMG's weights as the oracle forms them.  (Such a network still makes
+    a poor hierarchy; the fallback rule of solve_select then finishes with
+    BoxMG, converged.)"""
+    n = 255
+    p = inputs.jumping(n, 16, -3.0, 3.0, 61, 62)
+    st, rhs = boxmg.discretize(dev(p.k), dev(p.f))
+    found = None
+    for seed, scale in ((53, 2.0), (54, 3.0), (55, 4.0), (56, 6.0)):
+        net = boxmg.Net(inputs.net_random(seed) * np.float32(scale), max_n=n, train=False)
+        S = boxmg.Solver(st, interp=boxmg.BMG_INTERP_LEARNED, net=net, max_cycles=2)
+        _, info = S.solve(rhs, tol=1e-10, raise_on_noconv=False)
+        if info["learned_levels_used"] < S.nlev - 1:
+            found = (net, S, info)
+            break
+        S.close()
+        net.close()
+    assert found is not None, "no network of the list made a coarse operator break BoxMG's formula"
+    net, S, info = found
+    used = info["learned_levels_used"]
+    if used:
+        E = boxmg.Solver(st, interp=boxmg.BMG_INTERP_LEARNED, net=net, learned_levels=used, max_cycles=400)
+    else:
+        E = boxmg.Solver(st, max_cycles=400)
+    for lvl in range(S.nlev - 1):
+        planes = [S.export(lvl, nm) for nm in ("O", "W", "S")]
+        planes += [S.export(lvl, nm) for nm in ("SW", "NW")] if lvl > 0 else [None, None]
+        hp = [None if a is None else host(a) for a in planes]
+        Ci = host(S.export(lvl, "Ci"))
+        assert np.array_equal(Ci, host(E.export(lvl, "Ci"))), f"level {lvl}: automatic vs explicit cut"
+        if lvl >= used:
+            assert np.array_equal(Ci, ref.interp_weights(*hp)), f"level {lvl}: BoxMG weights"
+        for nm, want in zip(("O", "W", "S", "SW", "NW"), ref.rap(*hp, Ci)):
+            assert np.array_equal(host(S.export(lvl + 1, nm)), want), f"level {lvl + 1} {nm}"
+    with boxmg.Solver(st, interp=boxmg.BMG_INTERP_LEARNED, net=net, max_cycles=400) as L, \
+            boxmg.Solver(st, max_cycles=400) as B:
+        _, info, _, _ = boxmg.solve_select(L, B, rhs, tol=1e-10)
+    assert info["rel_res"] <= 1e-10 and info["status"] == 0
+    S.close()
+    E.close()
+    net.close()
