@@ -43,6 +43,11 @@ def test_binding_covers_every_entry_point(L):
 def test_default_options(L):
     o = boxmg.default_options()
     assert (o.nu1, o.nu2, o.max_cycles, o.precision, o.check_every) == (2, 1, 100, 0, 8)
+    # every field in the header's order (a field out of place in the binding
+    # would show here as a wrong default)
+    assert (o.kernels, o.refine_factor, o.tile_rows, o.interp, o.learned_levels, o.smoother, o.coarsest_n,
+            o.persistent_below_n, o.square_tiles_below_n, o.graph_mode) == (1, 16, 0, 0, 0, 0, 0, 0, 0, 0)
+    assert not o.net
 
 
 @pytest.mark.parametrize("n", [0, 1, 2, 4, 100, 4096, -1])
