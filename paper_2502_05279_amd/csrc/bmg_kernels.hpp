@@ -345,10 +345,12 @@ __device__ __forceinline__ double readlane_d(double v, int lane)
 // they give to the panel's own later columns (each lane holds two rows of
 // the panel; the diagonal and the v values come from their rows' lanes by
 // readlane); then every thread applies the panel's terms, in column order,
-// to its entries of the trailing triangle: two barriers per panel instead of
-// two per column (at 63^2: 2.81 ms against 2.92 by columns, and 2.87 ms with
-// panels of 4, so the factor's time is the work of its columns rather than
-// its barriers).  The window's rows live in an LDS ring (row i,
+// to its entries of the trailing triangle and writes the panel's L and D to
+// memory: two barriers per panel instead of two per column.  One wave's
+// column chain is what the factor waits on, so that part is straight-line
+// code with one division per lane and column and no stores to memory (at
+// 63^2: 2.04 ms; 2.81 ms with predicated updates and the stores in wave 0,
+// 2.92 ms by columns).  The window's rows live in an LDS ring (row i,
 // column j at slot i mod RR, offset j - i + w); the B rows a panel adds to the
 // window enter during the previous panel's trailing update, their entries of
 // A requested from memory two panels ahead (registers, then a staging
@@ -372,6 +374,7 @@ static __global__ __launch_bounds__(BAND_FACTOR_THREADS) void k_band_factor(Lev<
     __shared__ double ring[RR * RW];
     __shared__ double Lp[B][RW], vp[B][RW];           // the panel's columns: L(k + d, k), v at offset d
     __shared__ double stage[2][B * BAND_NNZ];
+    __shared__ double Dpan[B];
     const int nc = L.n, m = nc * nc, w = nc + 1, t = threadIdx.x;
     const int npanel = (m + B - 1) / B;
     auto at = [&](int i, int j) -> double & { return ring[(i % RR) * RW + (j - i + w)]; };
@@ -416,51 +419,63 @@ static __global__ __launch_bounds__(BAND_FACTOR_THREADS) void k_band_factor(Lev<
         const int k0 = p * B;
         if (t < 64) {
             // wave 0: the panel's columns, in registers.  Lane l holds the
-            // panel entries of rows k0 + l and k0 + 64 + l; the diagonal and
-            // the v of a later panel column come from the lane of its row
+            // panel entries of rows k0 + l and k0 + 64 + l.  The band rows
+            // below the diagonal of column k = k0 + b are k + 1 .. k + 64:
+            // the first row of lanes l > b and the second row of lanes
+            // l <= b, so every lane divides once per column.  The diagonal
+            // and the v of a later panel column come from the lane of its
+            // row.  A row outside a column's band holds zeros there, and
+            // rows past the matrix act as rows of the identity (D = 1, no
+            // terms), so the work is the same straight-line code for every
+            // panel; a lane's first row takes terms in every later panel
+            // column (those right of its diagonal are never read again),
+            // its second row only once it is the lane's row of the column
             const int r0 = k0 + t, r1 = k0 + 64 + t;
             double a0[B], a1[B];
 #pragma unroll
             for (int b = 0; b < B; ++b) {
                 const int k = k0 + b;
-                a0[b] = (r0 >= k && r0 < m && r0 - k <= w) ? at(r0, k) : 0.0;
+                a0[b] = r0 >= m ? (r0 == k ? 1.0 : 0.0) : (r0 >= k && r0 - k <= w) ? at(r0, k) : 0.0;
                 a1[b] = (r1 < m && r1 - k <= w) ? at(r1, k) : 0.0;
             }
+            double dg = 0.0;   // D of the lane's own panel column
 #pragma unroll
             for (int b = 0; b < B; ++b) {
-                const int k = k0 + b;
-                if (k >= m) break;
                 const double Dk = readlane_d(a0[b], b);
-                if (t == 0) {
-                    D[k] = Dk;
-                    if (!(Dk > 0.0)) bad = 1;
+                dg = t == b ? a0[b] : dg;
+                const bool first = t > b;
+                const double l = (first ? a0[b] : a1[b]) / Dk;
+                const double v = l * Dk;
+                const int d = first ? t - b : 64 + t - b;   // the lane's row of the column is k + d
+                if (d <= w) {
+                    Lp[b][d] = l;
+                    vp[b][d] = v;
                 }
-                const bool in0 = r0 > k && r0 < m && r0 - k <= w, in1 = r1 < m && r1 - k <= w;
-                double l0 = 0.0, l1 = 0.0, v0 = 0.0, v1 = 0.0;
-                if (in0) {
-                    l0 = a0[b] / Dk;
-                    v0 = l0 * Dk;
-                    Lp[b][r0 - k] = l0;
-                    vp[b][r0 - k] = v0;
-                    Lb[(size_t)r0 * w + (k - r0 + w)] = l0;
-                }
-                if (in1) {
-                    l1 = a1[b] / Dk;
-                    v1 = l1 * Dk;
-                    Lp[b][r1 - k] = l1;
-                    vp[b][r1 - k] = v1;
-                    Lb[(size_t)r1 * w + (k - r1 + w)] = l1;
-                }
-                // the terms of column k in the panel's later columns j <= r
+                const double l1 = first ? 0.0 : l;
+                // the terms of column k in the panel's later columns
 #pragma unroll
                 for (int jb = b + 1; jb < B; ++jb) {
-                    const double vj = readlane_d(v0, jb);   // v(k0 + jb, k), the lane of row k0 + jb
-                    if (in0 && r0 >= k0 + jb) a0[jb] = a0[jb] - l0 * vj;
-                    if (in1) a1[jb] = a1[jb] - l1 * vj;
+                    const double vj = readlane_d(v, jb);   // v(k0 + jb, k), the lane of row k0 + jb
+                    a0[jb] = a0[jb] - l * vj;
+                    a1[jb] = a1[jb] - l1 * vj;
                 }
             }
+            if (t < B) Dpan[t] = dg;
         }
         lds_barrier();
+        // the panel's columns go to memory, a row's B entries side by side
+        if (t < (w + B - 1) * B) {
+            const int r = k0 + 1 + t / B, b = t % B, d = r - k0 - b;
+            if (d >= 1 && d <= w && r < m) Lb[(size_t)r * w + (w - d)] = Lp[b][d];
+        }
+        if (t >= BAND_FACTOR_THREADS - B) {
+            const int b = t - (BAND_FACTOR_THREADS - B);
+            if (k0 + b < m) {
+                const double Dk = Dpan[b];
+                D[k0 + b] = Dk;
+                if (!(Dk > 0.0)) bad = 1;
+            }
+        }
         // the panel's terms in the trailing triangle (rows and columns
         // k0 + B .. k0 + B - 1 + w), in column order
 #pragma unroll
