@@ -140,19 +140,21 @@ static __global__ void k_import_stencil(const double *__restrict__ st, int K, Le
 }
 
 // ------------------------------------------------- interpolation weights
-// Row p of a compact stencil: SW, S, SE, W, O, E, NW, N, NE.
+// Row p of a compact stencil: SW, S, SE, W, O, E, NW, N, NE (a five-point
+// stencil has no SW and NW planes: its corners are zero).
+template <bool NINE>
 __device__ __forceinline__ void row_of(const Lev<double> &L, size_t p, double a[9])
 {
     const size_t ld = L.ld;
-    a[0] = L.SW ? L.SW[p] : 0.0;
+    a[0] = NINE ? L.SW[p] : 0.0;
     a[1] = L.S[p];
-    a[2] = L.NW ? L.NW[p + 1 - ld] : 0.0;
+    a[2] = NINE ? L.NW[p + 1 - ld] : 0.0;
     a[3] = L.W[p];
     a[4] = L.O[p];
     a[5] = L.W[p + 1];
-    a[6] = L.NW ? L.NW[p] : 0.0;
+    a[6] = NINE ? L.NW[p] : 0.0;
     a[7] = L.S[p + ld];
-    a[8] = L.SW ? L.SW[p + ld + 1] : 0.0;
+    a[8] = NINE ? L.SW[p + ld + 1] : 0.0;
 }
 
 // Positive off-diagonals moved onto the diagonal (SW,S,SE,W,E,NW,N,NE order).
@@ -171,6 +173,7 @@ __device__ __forceinline__ void lump_row(double a[9])
 // Edge weights: x-edge X(I,J) = (2I-1, 2J) for I <= nc+1, J <= nc collapses the
 // lumped stencil along y; y-edge Y(I,J) = (2I, 2J-1) for I <= nc, J <= nc+1
 // collapses along x.
+template <bool NINE>
 static __global__ void k_weights_edges(Lev<double> F, Wts<double> C, int nc, int *__restrict__ flags)
 {
     const int I = blockIdx.x * blockDim.x + threadIdx.x + 1;
@@ -181,7 +184,7 @@ static __global__ void k_weights_edges(Lev<double> F, Wts<double> C, int nc, int
     int bad = 0;
     double a[9];
     if (J <= nc) {
-        row_of(F, (size_t)(2 * J) * ld + (2 * I - 1), a);
+        row_of<NINE>(F, (size_t)(2 * J) * ld + (2 * I - 1), a);
         lump_row(a);
         const double D = (a[4] + a[7]) + a[1];
         if (!(D > 0.0)) bad = F_BREAK_INTERP;
@@ -189,7 +192,7 @@ static __global__ void k_weights_edges(Lev<double> F, Wts<double> C, int nc, int
         C.p[LR * C.ps + c] = -((a[5] + a[8]) + a[2]) / D;
     }
     if (I <= nc) {
-        row_of(F, (size_t)(2 * J - 1) * ld + (2 * I), a);
+        row_of<NINE>(F, (size_t)(2 * J - 1) * ld + (2 * I), a);
         lump_row(a);
         const double D = (a[4] + a[3]) + a[5];
         if (!(D > 0.0)) bad = F_BREAK_INTERP;
@@ -201,6 +204,7 @@ static __global__ void k_weights_edges(Lev<double> F, Wts<double> C, int nc, int
 
 // Cell-centre weights at Z(I,J) = (2I-1, 2J-1), I, J <= nc+1, from the lumped
 // stencil and the neighbouring edge weights.
+template <bool NINE>
 static __global__ void k_weights_corners(Lev<double> F, Wts<double> C, int nc, int *__restrict__ flags)
 {
     const int I = blockIdx.x * blockDim.x + threadIdx.x + 1;
@@ -209,7 +213,7 @@ static __global__ void k_weights_corners(Lev<double> F, Wts<double> C, int nc, i
     const size_t c = (size_t)J * C.ld + I;
     const size_t cs = c - C.ld, cw = c - 1;
     double a[9];
-    row_of(F, (size_t)(2 * J - 1) * F.ld + (2 * I - 1), a);
+    row_of<NINE>(F, (size_t)(2 * J - 1) * F.ld + (2 * I - 1), a);
     lump_row(a);
     if (!(a[4] > 0.0)) atomicOr(flags, F_BREAK_INTERP);
     const double lr = C.at(LR, c), ll = C.at(LL, c), la = C.at(LA, c), lb = C.at(LB, c);
@@ -241,21 +245,27 @@ __device__ __forceinline__ double basis_weight(const Wts<double> &C, int KI, int
 // A_c(I,J;d) = sum_p P(p;IJ) sum_q A(p,q) P(q;IJ+d), d = O, W, S, SW, NW, p over
 // the fine 3x3 patch of (2I,2J) (rows south to north, west to east inside a
 // row), q over p's neighbours SW..NE inside the support of basis IJ+d; both
-// sums start from zero.  Couplings to ring coarse points are zero.
-static __global__ void k_rap(Lev<double> F, Wts<double> C, Lev<double> Cl)
+// sums start from zero.  Couplings to ring coarse points are zero: their sums
+// are formed with the weights of the nearest interior point (so every load
+// is in range and none waits behind a branch) and then replaced by zero.
+template <bool NINE>
+static __global__ __launch_bounds__(128) void k_rap(Lev<double> F, Wts<double> C, Lev<double> Cl)
 {
     const int I = blockIdx.x * blockDim.x + threadIdx.x + 1;
     const int J = blockIdx.y * blockDim.y + threadIdx.y + 1;
     const int nc = Cl.n;
     if (I > nc || J > nc) return;
-    const int offI[5] = {0, -1, 0, -1, -1};
-    const int offJ[5] = {0, 0, -1, -1, 1};
+    constexpr int offI[5] = {0, -1, 0, -1, -1};
+    constexpr int offJ[5] = {0, 0, -1, -1, 1};
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     bool live[5];
+    int KI[5], KJ[5];
 #pragma unroll
     for (int d = 0; d < 5; ++d) {
-        const int KI = I + offI[d], KJ = J + offJ[d];
-        live[d] = KI >= 1 && KJ >= 1 && KJ <= nc;
+        const int ki = I + offI[d], kj = J + offJ[d];
+        live[d] = ki >= 1 && kj >= 1 && kj <= nc;
+        KI[d] = ki < 1 ? 1 : ki;
+        KJ[d] = kj < 1 ? 1 : kj > nc ? nc : kj;
     }
 #pragma unroll
     for (int jj = -1; jj <= 1; ++jj) {
@@ -263,19 +273,17 @@ static __global__ void k_rap(Lev<double> F, Wts<double> C, Lev<double> Cl)
         for (int ii = -1; ii <= 1; ++ii) {
             const int pi = 2 * I + ii, pj = 2 * J + jj;
             double a[9];
-            row_of(F, (size_t)pj * F.ld + pi, a);
+            row_of<NINE>(F, (size_t)pj * F.ld + pi, a);
             const double wp = basis_weight(C, I, J, ii, jj);
 #pragma unroll
             for (int d = 0; d < 5; ++d) {
-                if (!live[d]) continue;
-                const int KI = I + offI[d], KJ = J + offJ[d];
                 double t = 0.0;
 #pragma unroll
                 for (int e = 0; e < 9; ++e) {
-                    const int qi = pi + (e % 3) - 1, qj = pj + (e / 3) - 1;
-                    const int di = qi - 2 * KI, dj = qj - 2 * KJ;
+                    // q - 2(IJ+d), the same for the clamped point's support
+                    const int di = ii + (e % 3) - 1 - 2 * offI[d], dj = jj + (e / 3) - 1 - 2 * offJ[d];
                     if (di < -1 || di > 1 || dj < -1 || dj > 1) continue;
-                    t = t + a[e] * basis_weight(C, KI, KJ, di, dj);
+                    t = t + a[e] * basis_weight(C, KI[d], KJ[d], di, dj);
                 }
                 acc[d] = acc[d] + wp * t;
             }
@@ -283,10 +291,32 @@ static __global__ void k_rap(Lev<double> F, Wts<double> C, Lev<double> Cl)
     }
     const size_t c = (size_t)J * Cl.ld + I;
     Cl.O[c] = acc[0];
-    Cl.W[c] = acc[1];
-    Cl.S[c] = acc[2];
-    Cl.SW[c] = acc[3];
-    Cl.NW[c] = acc[4];
+    Cl.W[c] = live[1] ? acc[1] : 0.0;
+    Cl.S[c] = live[2] ? acc[2] : 0.0;
+    Cl.SW[c] = live[3] ? acc[3] : 0.0;
+    Cl.NW[c] = live[4] ? acc[4] : 0.0;
+}
+
+// The set-up kernels of one level pair, for a five- or nine-point fine stencil.
+static inline void launch_weights(const Lev<double> &F, const Wts<double> &C, int nc, int *flags, dim3 grid,
+                                  dim3 blk, hipStream_t st)
+{
+    if (F.SW) {
+        hipLaunchKernelGGL(k_weights_edges<true>, grid, blk, 0, st, F, C, nc, flags);
+        hipLaunchKernelGGL(k_weights_corners<true>, grid, blk, 0, st, F, C, nc, flags);
+    } else {
+        hipLaunchKernelGGL(k_weights_edges<false>, grid, blk, 0, st, F, C, nc, flags);
+        hipLaunchKernelGGL(k_weights_corners<false>, grid, blk, 0, st, F, C, nc, flags);
+    }
+}
+
+static inline void launch_rap(const Lev<double> &F, const Wts<double> &C, const Lev<double> &Cl, hipStream_t st)
+{
+    const dim3 blk(32, 4), grid((Cl.n + 31) / 32, (Cl.n + 3) / 4);
+    if (F.SW)
+        hipLaunchKernelGGL(k_rap<true>, grid, blk, 0, st, F, C, Cl);
+    else
+        hipLaunchKernelGGL(k_rap<false>, grid, blk, 0, st, F, C, Cl);
 }
 
 // ------------------------------------------------ coarsest level: band LDL^T

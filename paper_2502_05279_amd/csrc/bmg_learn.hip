@@ -631,8 +631,7 @@ bmg_status forward(bmg_net *h, const Lev<double> &L, bool nine, double *Ci, int 
     const int n = L.n, nc = (n - 1) / 2;
     if (n > h->max_n) return fail(BMG_EINVAL, "level of %d points exceeds the network's max_n=%d", n, h->max_n);
     const Wts<double> C{Ci, ldc, ps};
-    hipLaunchKernelGGL(k_weights_edges, tiles(nc + 1, nc + 1), dim3(32, 8), 0, h->st, L, C, nc, flags);
-    hipLaunchKernelGGL(k_weights_corners, tiles(nc + 1, nc + 1), dim3(32, 8), 0, h->st, L, C, nc, flags);
+    launch_weights(L, C, nc, flags, tiles(nc + 1, nc + 1), dim3(32, 8), h->st);
     hipLaunchKernelGGL(k_net_features, tiles(n + 2, n + 2), dim3(32, 8), 0, h->st, L, nine, h->X);
     LAUNCHCHK();
     const float *P = h->P;

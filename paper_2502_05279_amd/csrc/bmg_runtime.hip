@@ -929,13 +929,10 @@ static bmg_status setup_into(bmg_solver *h, const double *stencil, int n, int ki
     hipLaunchKernelGGL(k_import_stencil, grid2(n, n, B2), B2, 0, h->st, stencil, kind, h->L[0], h->flags);
     auto boxmg_weights = [&](int l) {
         const int nc = h->L[l + 1].n;
-        hipLaunchKernelGGL(k_weights_edges, grid2(nc + 1, nc + 1, B2), B2, 0, h->st, h->L[l], h->C[l], nc, h->flags);
-        hipLaunchKernelGGL(k_weights_corners, grid2(nc + 1, nc + 1, B2), B2, 0, h->st, h->L[l], h->C[l], nc,
-                           h->flags);
+        launch_weights(h->L[l], h->C[l], nc, h->flags, grid2(nc + 1, nc + 1, B2), B2, h->st);
     };
     auto galerkin = [&](int l) {
-        const int nc = h->L[l + 1].n;
-        hipLaunchKernelGGL(k_rap, grid2(nc, nc, dim3(32, 4)), dim3(32, 4), 0, h->st, h->L[l], h->C[l], h->L[l + 1]);
+        launch_rap(h->L[l], h->C[l], h->L[l + 1], h->st);
     };
     // levels whose weights come from the network: the first `cut`.  A coarse
     // operator built with the network's weights can leave BoxMG's formula a
