@@ -61,6 +61,42 @@ def test_band_factor_bitwise(gpu, n, nc):
         same(LD[m * w:], D, "coarsest D")
 
 
+@pytest.mark.parametrize("n,centre,nc", [(15, 3.9, 3), (63, 3.99, 15), (127, 3.995, 63)])
+def test_coarsest_pivot_breakdown_is_reported(gpu, n, centre, nc):
+    """A five-point stencil whose centre is a little below the sum of its
+    four couplings is indefinite: every interpolation denominator is still
+    positive, but the Galerkin coarsest operator has a negative eigenvalue, so
+    its L D L^T factor meets a pivot <= 0.  The oracle's band factor and the
+    GPU set-up both report the breakdown (the coarsest sizes give 2, 29 and
+    497 panels of eight columns to the GPU factor)."""
+    st = np.zeros((n, n, 5))
+    st[:, :, 2] = centre
+    st[:, 1:, 1] = -1.0; st[:, :-1, 3] = -1.0
+    st[1:, :, 0] = -1.0; st[:-1, :, 4] = -1.0
+    O, W, S, SW, NW = ref.compact_from_stencil(st)
+    while O.shape[0] - 2 > nc:           # the weights do not break down
+        O, W, S, SW, NW = ref.rap(O, W, S, SW, NW, ref.interp_weights(O, W, S, SW, NW))
+    m = nc * nc
+    A = np.zeros((m, m))
+    for j in range(1, nc + 1):
+        for i in range(1, nc + 1):
+            p = (j - 1) * nc + (i - 1)
+            A[p, p] = O[j, i]
+            for q, a in (((j - 1) * nc + i - 2, W[j, i] if i > 1 else 0.0),
+                         ((j - 2) * nc + i - 1, S[j, i] if j > 1 else 0.0),
+                         ((j - 2) * nc + i - 2, SW[j, i] if i > 1 and j > 1 else 0.0),
+                         (j * nc + i - 2, NW[j, i] if i > 1 and j < nc else 0.0)):
+                if a != 0.0:
+                    A[p, q] = A[q, p] = a
+    assert np.linalg.eigvalsh(A)[0] < 0.0
+    with pytest.raises(ref.OracleError):
+        ref.band_ldlt_factor(ref.band_of(A, nc + 1))
+    with pytest.raises(boxmg.BoxMGError) as e:
+        boxmg.Solver(dev(st), coarsest_n=nc)
+    assert e.value.status == boxmg.BMG_EBREAKDOWN
+    assert "coarsest pivot" in e.value.detail
+
+
 @pytest.mark.parametrize("n,nc", [(31, 7), (127, 31), (127, 63)])
 def test_coarse_step_bitwise(gpu, n, nc):
     """One direct solve of the coarsest level on a random right-hand side, in
