@@ -115,36 +115,42 @@ __global__ void k_ns_weights_corners(LevN F, Wts<double> C, int nc, bool transpo
 
 // A_c(I,J; d) = sum_p R(p; IJ) sum_q A(p, q) P(q; IJ + d) for the nine d, p over
 // the fine 3x3 patch (rows south to north), q over p's neighbours SW..NE in the
-// support of basis IJ + d; couplings to ring coarse points are zero.
-__global__ void k_ns_rap(LevN F, Wts<double> P, Wts<double> R, LevN Cl)
+// support of basis IJ + d; couplings to ring coarse points are zero: their
+// sums are formed with the weights of the nearest interior point (so every
+// load is in range and none waits behind a branch) and then replaced by zero.
+__global__ __launch_bounds__(256) void k_ns_rap(LevN F, Wts<double> P, Wts<double> R, LevN Cl)
 {
     const int I = 1 + blockIdx.x * blockDim.x + threadIdx.x;
     const int J = 1 + blockIdx.y * blockDim.y + threadIdx.y;
     const int nc = Cl.n;
     if (I > nc || J > nc) return;
     const size_t c = (size_t)J * Cl.ld + I;
-    for (int d = 0; d < NSD; ++d) {
-        const int KI = I + d % 3 - 1, KJ = J + d / 3 - 1;
-        double acc = 0.0;
-        if (KI >= 1 && KI <= nc && KJ >= 1 && KJ <= nc) {
-            for (int jj = -1; jj <= 1; ++jj) {
-                for (int ii = -1; ii <= 1; ++ii) {
-                    const int pi = 2 * I + ii, pj = 2 * J + jj;
-                    const double wp = basis_weight(R, I, J, ii, jj);
-                    double a[NSD];
-                    ns_row(F, (size_t)pj * F.ld + pi, false, a);
-                    double t = 0.0;
 #pragma unroll
-                    for (int e = 0; e < NSD; ++e) {
-                        const int dx = pi + e % 3 - 1 - 2 * KI, dy = pj + e / 3 - 1 - 2 * KJ;
-                        if (dx < -1 || dx > 1 || dy < -1 || dy > 1) continue;
-                        t = t + a[e] * basis_weight(P, KI, KJ, dx, dy);
-                    }
-                    acc = acc + wp * t;
+    for (int d = 0; d < NSD; ++d) {
+        const int ki = I + d % 3 - 1, kj = J + d / 3 - 1;
+        const bool live = ki >= 1 && ki <= nc && kj >= 1 && kj <= nc;
+        const int KI = ki < 1 ? 1 : ki > nc ? nc : ki, KJ = kj < 1 ? 1 : kj > nc ? nc : kj;
+        double acc = 0.0;
+#pragma unroll
+        for (int jj = -1; jj <= 1; ++jj) {
+#pragma unroll
+            for (int ii = -1; ii <= 1; ++ii) {
+                const int pi = 2 * I + ii, pj = 2 * J + jj;
+                const double wp = basis_weight(R, I, J, ii, jj);
+                double a[NSD];
+                ns_row(F, (size_t)pj * F.ld + pi, false, a);
+                double t = 0.0;
+#pragma unroll
+                for (int e = 0; e < NSD; ++e) {
+                    // q - 2(IJ + d), the same for the clamped point's support
+                    const int dx = ii + e % 3 - 1 - 2 * (d % 3 - 1), dy = jj + e / 3 - 1 - 2 * (d / 3 - 1);
+                    if (dx < -1 || dx > 1 || dy < -1 || dy > 1) continue;
+                    t = t + a[e] * basis_weight(P, KI, KJ, dx, dy);
                 }
+                acc = acc + wp * t;
             }
         }
-        Cl.A[d][c] = acc;
+        Cl.A[d][c] = live ? acc : 0.0;
     }
 }
 
