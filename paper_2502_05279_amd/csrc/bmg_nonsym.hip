@@ -190,29 +190,47 @@ __global__ void k_ns_residual(LevN L)
 
 // ------------------------------------------------ coarsest band L D U
 // A = L D U with unit triangular L, U (band of w = nc + 1 on each side of the
-// diagonal), column by column in right-looking form: once column k is final
-// (D_k = a_kk, L_ik = a_ik / D_k, U_kj = a_kj / D_k), every entry of the
-// trailing window takes its term, a_ij <- a_ij - L_ik a_kj (k < i, j <= k + w),
-// so each entry receives its terms in increasing k, the products of the
-// definition's column-by-column form.  Rows live in an LDS ring (row i,
-// column j at slot i mod NSB_RR, offset j - i + w); row k + w + 1 enters at
-// column k with its nine band entries of A, requested a chunk of 64 columns
-// ahead.  Lb[i w + (k - i + w)] = L_ik, Ub[i w + (k - i - 1)] = U_ik, D.
+// diagonal) in right-looking form: once column k is final (D_k = a_kk,
+// L_ik = a_ik / D_k, U_kj = a_kj / D_k), every entry of the trailing window
+// takes its term, a_ij <- a_ij - L_ik a_kj (k < i, j <= k + w), so each entry
+// receives its terms in increasing k, the products of the definition's
+// column-by-column form.  By panels of BAND_PANEL columns, as the symmetric
+// factor: wave 0 finishes a panel's columns and rows in registers (lane l
+// holds, for the panel, rows k0 + l and k0 + 64 + l of its columns and
+// columns k0 + l and k0 + 64 + l of its rows; the band below column k and the
+// band right of row k are one entry per lane), with the terms they give to
+// the panel's own later columns and rows; then every thread applies the
+// panel's terms, in column order, to its entries of the w x w trailing window,
+// writes the panel's L, U and D, and the rows the next panel adds enter the
+// window (their nine band entries of A requested two panels ahead).  Rows
+// live in an LDS ring (row i, column j at slot i mod NSB_RR, offset j - i + w).
+// Lb[i w + (k - i + w)] = L_ik, Ub[i w + (k - i - 1)] = U_ik, D.
 constexpr int NSB_THREADS = 1024;
-constexpr int NSB_RW = 2 * BAND_MAX_NC + 3;   // >= 2w + 1
-constexpr int NSB_RR = BAND_MAX_NC + 3;       // >= w + 2
+constexpr int NSB_RW = 2 * BAND_MAX_NC + 3;            // ring row: offsets 0 .. 2w
+constexpr int NSB_RR = BAND_MAX_NC + 1 + BAND_PANEL;   // ring rows: a panel's window
+constexpr int NSB_LW = BAND_MAX_NC + 2;                // a panel column's L (row's U) at offsets 1 .. w
+static_assert(BAND_PANEL * NSB_RW <= 2 * NSB_THREADS && (BAND_MAX_NC + 1) * (BAND_MAX_NC + 1) <= 4 * NSB_THREADS &&
+                  (BAND_MAX_NC + BAND_PANEL) * BAND_PANEL <= NSB_THREADS,
+              "entering rows in two passes, the trailing window in four, the panel's L in one");
 
-__host__ __device__ inline size_t ns_band_lds() { return ((size_t)NSB_RR * NSB_RW + 2 * 66 + 2 * 64 * NSD) * sizeof(double); }
+__host__ __device__ inline size_t ns_band_lds()
+{
+    return ((size_t)NSB_RR * NSB_RW + 2 * BAND_PANEL * NSB_LW + BAND_PANEL + 2 * BAND_PANEL * NSD) * sizeof(double);
+}
 
 __global__ __launch_bounds__(NSB_THREADS) void k_band_ldu_factor(LevN L, double *__restrict__ Lb,
                                                                   double *__restrict__ Ub, double *__restrict__ D,
                                                                   int *__restrict__ flags)
 {
+    constexpr int B = BAND_PANEL;
     extern __shared__ double nsb_sm[];
     double *ring = nsb_sm;
-    double *Lcol = ring + NSB_RR * NSB_RW, *Urow = Lcol + 66;
-    double *stage = Urow + 66;   // [2][64 * NSD]
+    double(*Lp)[NSB_LW] = reinterpret_cast<double(*)[NSB_LW]>(ring + NSB_RR * NSB_RW);   // L(k + d, k)
+    double(*Up)[NSB_LW] = Lp + B;                                                         // a(k, k + d)
+    double *Dpan = reinterpret_cast<double *>(Up + B);
+    double *stage = Dpan + B;   // [2][B * NSD]
     const int nc = L.n, m = nc * nc, w = nc + 1, t = threadIdx.x;
+    const int npanel = (m + B - 1) / B;
     auto at = [&](int i, int j) -> double & { return ring[(i % NSB_RR) * NSB_RW + (j - i + w)]; };
     // A(i, i + off(e)) for the nine entries of row i (zero outside the grid)
     auto entry = [&](int i, int e) -> double {
@@ -221,65 +239,140 @@ __global__ __launch_bounds__(NSB_THREADS) void k_band_ldu_factor(LevN L, double 
         return L.A[e][(size_t)jj * L.ld + ii];
     };
     auto col_of = [&](int i, int e) { return i + (e % 3 - 1) + (e / 3 - 1) * nc; };
-    for (int e2 = t; e2 < (w + 1) * (2 * w + 1); e2 += blockDim.x) {   // rows 0 .. w
+    // rows 0 .. w + B - 1 (the window of panel 0)
+    for (int e2 = t; e2 < (w + B) * (2 * w + 1); e2 += blockDim.x) {
         const int i = e2 / (2 * w + 1), off = e2 % (2 * w + 1);
         if (i < m) at(i, i - w + off) = 0.0;
     }
     lds_barrier();
-    for (int e2 = t; e2 < (w + 1) * NSD; e2 += blockDim.x) {
+    for (int e2 = t; e2 < (w + B) * NSD; e2 += blockDim.x) {
         const int i = e2 / NSD, e = e2 % NSD;
         if (i < m) at(i, col_of(i, e)) = entry(i, e);
     }
-    auto entering = [&](int c, int u) -> double {   // entry u of the staging buffer of chunk c
-        const int i = 64 * c + u / NSD + w + 1;
+    // the rows panel q adds to the window: q B + w .. q B + w + B - 1; entry u
+    // of its staging buffer is row q B + w + u / NSD, direction u % NSD
+    auto entering = [&](int q, int u) -> double {
+        const int i = q * B + w + u / NSD;
         return i < m ? entry(i, u % NSD) : 0.0;
     };
-    if (t < 64 * NSD) stage[t] = entering(0, t);
-    const int nsq = w * w;
-    int di[4], dj[4];
+    const bool loader = t < B * NSD;
+    if (loader) stage[B * NSD + t] = entering(1, t);
+    double pf = loader ? entering(2, t) : 0.0;        // panel 2's rows, in flight
+    // this thread's slots of the rows entering the window (row eb, offset
+    // eoff; eu: its staging entry, -1 for a zero of the band)
+    int eb[2], eoff[2], eu[2];
 #pragma unroll
-    for (int s2 = 0; s2 < 4; ++s2) {
+    for (int s2 = 0; s2 < 2; ++s2) {
         const int e = t + s2 * NSB_THREADS;
-        di[s2] = e < nsq ? 1 + e / w : 0;
-        dj[s2] = 1 + e % w;
+        eb[s2] = e < B * (2 * w + 1) ? e / (2 * w + 1) : -1;
+        eoff[s2] = e % (2 * w + 1);
+        eu[s2] = -1;
+#pragma unroll
+        for (int d = 0; d < NSD; ++d)
+            if (eoff[s2] - w == (d % 3 - 1) + (d / 3 - 1) * nc) eu[s2] = eb[s2] * NSD + d;
     }
-    const int tnew = t - (NSB_THREADS - (2 * w + 1));   // offset in the entering row, if >= 0
-    double pf = 0.0;
     int bad = 0;
     lds_barrier();
-    for (int k = 0; k < m; ++k) {
-        const int kc = k & 63, c = k >> 6;
-        if (kc == 0 && t < 64 * NSD) pf = entering(c + 1, t);
-        if (t <= w) {
-            const double Dk = at(k, k);
-            if (t == 0) {
-                D[k] = Dk;
-                if (!(Dk > 0.0)) bad = 1;
-            } else if (k + t < m) {
-                const int i = k + t;
-                const double l = at(i, k) / Dk;
-                const double akj = at(k, i);
-                Lcol[t] = l;
-                Urow[t] = akj;
-                Lb[(size_t)i * w + (k - i + w)] = l;
-                Ub[(size_t)k * w + (i - k - 1)] = akj / Dk;
+    for (int p = 0; p < npanel; ++p) {
+        const int k0 = p * B;
+        if (t < 64) {
+            // wave 0.  L view: rows r0 = k0 + l, r1 = k0 + 64 + l of the panel's
+            // columns; U view: columns r0, r1 of the panel's rows.  The rows
+            // below column k = k0 + b within the band are the first row of
+            // lanes l > b and the second row of lanes l <= b (and so for the
+            // columns right of row k); outside the band an entry holds zero
+            // and takes zero terms, rows and columns past the matrix act as
+            // those of the identity, and entries on the wrong side of the
+            // diagonal take terms that are never read
+            // the lane index, opaque to the compiler here, so that the
+            // per-column addresses and tests below are formed in each panel
+            // rather than kept (and spilled) across the loop
+            int ln = t;
+            asm volatile("" : "+v"(ln));
+            const int r0 = k0 + ln, r1 = k0 + 64 + ln;
+            double a0[B], a1[B], u0[B], u1[B];
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                const int k = k0 + b;
+                a0[b] = r0 >= m ? (r0 == k ? 1.0 : 0.0) : (r0 >= k && r0 - k <= w) ? at(r0, k) : 0.0;
+                a1[b] = (r1 < m && r1 - k <= w) ? at(r1, k) : 0.0;
+                u0[b] = (r0 < m && r0 > k && r0 - k <= w) ? at(k, r0) : 0.0;
+                u1[b] = (r1 < m && r1 - k <= w) ? at(k, r1) : 0.0;
             }
+            double dg = 0.0;   // D of the lane's own panel column
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                const double Dk = readlane_d(a0[b], b);
+                dg = ln == b ? a0[b] : dg;
+                const bool first = ln > b;
+                const double l = (first ? a0[b] : a1[b]) / Dk;
+                const double uv = first ? u0[b] : u1[b];
+                const int d = first ? ln - b : 64 + ln - b;   // the lane's row and column of k are k + d
+                if (d <= w) {
+                    Lp[b][d] = l;
+                    Up[b][d] = uv;
+                }
+                const double l1 = first ? 0.0 : l;
+                // the terms of column and row k in the panel's later columns and rows
+#pragma unroll
+                for (int jb = b + 1; jb < B; ++jb) {
+                    const double vj = readlane_d(u0[b], jb);   // a(k, k0 + jb)
+                    const double lj = readlane_d(l, jb);       // L(k0 + jb, k)
+                    a0[jb] = a0[jb] - l * vj;
+                    a1[jb] = a1[jb] - l1 * vj;
+                    u0[jb] = u0[jb] - lj * u0[b];
+                    u1[jb] = u1[jb] - lj * u1[b];
+                }
+            }
+            if (t < B) Dpan[t] = dg;
         }
         lds_barrier();
+        // the panel's L, U and D to memory
+        if (t < (w + B - 1) * B) {
+            const int r = k0 + 1 + t / B, b = t % B, d = r - k0 - b;
+            if (d >= 1 && d <= w && r < m) Lb[(size_t)r * w + (w - d)] = Lp[b][d];
+        }
+        if (t < B * w) {
+            const int b = t / w, d = 1 + t % w, k = k0 + b;
+            if (k + d < m) Ub[(size_t)k * w + (d - 1)] = Up[b][d] / Dpan[b];
+        }
+        if (t >= NSB_THREADS - B) {
+            const int b = t - (NSB_THREADS - B);
+            if (k0 + b < m) {
+                const double Dk = Dpan[b];
+                D[k0 + b] = Dk;
+                if (!(Dk > 0.0)) bad = 1;
+            }
+        }
+        // the panel's terms in the trailing window (rows and columns
+        // k0 + B .. k0 + B - 1 + w), in column order
 #pragma unroll
         for (int s2 = 0; s2 < 4; ++s2) {
-            const int i = k + di[s2], j = k + dj[s2];
-            if (di[s2] > 0 && i < m && j < m) at(i, j) = at(i, j) - Lcol[di[s2]] * Urow[dj[s2]];
-        }
-        if (tnew >= 0 && k + w + 1 < m) {
-            const int i = k + w + 1, j = i - w + tnew;
-            double v = 0.0;
+            const int e = t + s2 * NSB_THREADS;
+            const int i = k0 + B + e / w, j = k0 + B + e % w;
+            if (e < w * w && i < m && j < m) {
+                double a = at(i, j);
 #pragma unroll
-            for (int e = 0; e < NSD; ++e)
-                if (j == col_of(i, e)) v = stage[(c & 1) * 64 * NSD + kc * NSD + e];
-            at(i, j) = v;
+                for (int b = 0; b < B; ++b) {
+                    const int k = k0 + b;
+                    if (i - k <= w && j - k <= w && k < m) a = a - Lp[b][i - k] * Up[b][j - k];
+                }
+                at(i, j) = a;
+            }
         }
-        if (kc == 63 && t < 64 * NSD) stage[((c + 1) & 1) * 64 * NSD + t] = pf;
+        // the rows of panel p + 1 enter (their slots are those of panel p's
+        // rows); the staging buffer of panel p + 2 is filled from the
+        // registers and panel p + 3's entries are requested
+#pragma unroll
+        for (int s2 = 0; s2 < 2; ++s2) {
+            const int i = (p + 1) * B + w + eb[s2];
+            if (eb[s2] >= 0 && i < m)
+                at(i, i - w + eoff[s2]) = eu[s2] >= 0 ? stage[((p + 1) & 1) * B * NSD + eu[s2]] : 0.0;
+        }
+        if (loader) {
+            stage[(p & 1) * B * NSD + t] = pf;
+            pf = entering(p + 3, t);
+        }
         lds_barrier();
     }
     if (bad) atomicOr(flags, F_BREAK_COARSE);
