@@ -166,14 +166,86 @@ __device__ __forceinline__ double ns_offdiag(const LevN &L, const double *__rest
     return s;
 }
 
-// One colour of Gauss-Seidel, colour(i, j) = (i mod 2) + 2 (j mod 2).
-__global__ void k_ns_gs_colour(LevN L, int colour)
+// One sweep's two colours of the rows of one parity (rp = 0: the even rows,
+// colours 0 and 1; rp = 1: the odd rows, colours 2 and 3), one wave per row.
+// The wave walks its row from west to east in chunks of 64 column pairs:
+// first the chunk's even columns (the first colour), then its odd columns
+// (the second), whose west and east neighbours are the row's new even values
+// (the neighbouring lane's, or for lane 0 the last one of the previous
+// chunk).  An even point reads the odd values of its own and the next chunk,
+// which are not yet written; every other value a point reads lies in rows
+// j - 1 and j + 1, which this launch does not write.  So each point sees the
+// values, in the order, of one launch per colour, and the stencil rows are
+// read once for both colours.
+constexpr int NS_PAIR_WAVES = 4;
+
+// The operands of one chunk for one lane: the even point's nine stencil
+// entries, eight neighbours and right-hand side, the odd point's nine entries,
+// its six neighbours in rows j - 1 and j + 1, and right-hand side.  None of
+// them is written by an earlier chunk of the row, so the next chunk's are
+// requested before the current one computes.
+struct NsPair {
+    double ae[NSD], ue[NSD], be, ao[NSD], uo[NSD], bo;
+};
+
+__device__ __forceinline__ void ns_pair_load(const LevN &L, size_t row, int g, NsPair &c)
 {
-    const int i = ((colour & 1) ? 1 : 2) + 2 * (blockIdx.x * blockDim.x + threadIdx.x);
-    const int j = ((colour >> 1) ? 1 : 2) + 2 * (blockIdx.y * blockDim.y + threadIdx.y);
-    if (i > L.n || j > L.n) return;
-    const size_t p = (size_t)j * L.ld + i;
-    L.u[p] = ns_offdiag(L, L.u, p) / L.A[E_O][p];
+    const int n = L.n, ie = 2 + 2 * g, io = 1 + 2 * g;
+    const size_t pe = row + ie, po = row + io;
+    const bool ev = ie <= n, od = io <= n;
+#pragma unroll
+    for (int e = 0; e < NSD; ++e) {
+        const ptrdiff_t d = ns_off(e, L.ld);
+        c.ae[e] = ev ? L.A[e][pe] : 0.0;
+        c.ue[e] = ev && e != E_O ? L.u[(size_t)((ptrdiff_t)pe + d)] : 0.0;
+        c.ao[e] = od ? L.A[e][po] : 0.0;
+        c.uo[e] = od && e != E_O && e != E_W && e != E_E ? L.u[(size_t)((ptrdiff_t)po + d)] : 0.0;
+    }
+    c.be = ev ? L.b[pe] : 0.0;
+    c.bo = od ? L.b[po] : 0.0;
+}
+
+__global__ __launch_bounds__(64 * NS_PAIR_WAVES) void k_ns_gs_pair(LevN L, int rp)
+{
+    const int lane = threadIdx.x & 63, n = L.n;
+    const int j = (rp ? 1 : 2) + 2 * (int)(blockIdx.x * NS_PAIR_WAVES + (threadIdx.x >> 6));
+    if (j > n) return;   // the whole wave
+    const size_t row = (size_t)j * L.ld;
+    double carry = L.u[row];   // the ring value west of column 1
+    NsPair cur, nxt;
+    ns_pair_load(L, row, lane, nxt);
+    for (int g0 = 0; 2 * g0 + 1 <= n; g0 += 64) {
+        cur = nxt;
+        if (2 * (g0 + 64) + 1 <= n) ns_pair_load(L, row, g0 + 64 + lane, nxt);
+        const int g = g0 + lane, ie = 2 + 2 * g, io = 1 + 2 * g;
+        double ev = 0.0;
+        if (ie <= n) {
+            // ns_offdiag's terms in its order, then the division
+            double s = cur.be;
+#pragma unroll
+            for (int e = 0; e < NSD; ++e) {
+                if (e == E_O) continue;
+                s -= cur.ae[e] * cur.ue[e];
+            }
+            ev = s / cur.ae[E_O];
+            L.u[row + ie] = ev;
+        } else if (ie == n + 1) {
+            ev = L.u[row + ie];   // the ring value east of column n
+        }
+        double west = __shfl_up(ev, 1);
+        if (lane == 0) west = carry;
+        carry = __shfl(ev, 63);
+        if (io <= n) {
+            double s = cur.bo;
+#pragma unroll
+            for (int e = 0; e < NSD; ++e) {
+                if (e == E_O) continue;
+                const double x = e == E_W ? west : e == E_E ? ev : cur.uo[e];
+                s -= cur.ao[e] * x;
+            }
+            L.u[row + io] = s / cur.ao[E_O];
+        }
+    }
 }
 
 // r = b - A u, the centre term last.
@@ -532,10 +604,12 @@ Lev<double> as_lev(const LevN &L)
 bmg_status ns_gs(bmg_ns *h, int l, int sweeps)
 {
     const LevN &L = h->L[l];
-    const int half = (L.n + 1) / 2;
+    // colours 0, 1 (even rows), then 2, 3 (odd rows): rows of each parity
+    const int rows[2] = {(L.n - 1) / 2, (L.n + 1) / 2};
     for (int s = 0; s < sweeps; ++s)
-        for (int c = 0; c < 4; ++c)
-            hipLaunchKernelGGL(k_ns_gs_colour, grid2(half, half, NB), NB, 0, h->st, L, c);
+        for (int rp = 0; rp < 2; ++rp)
+            hipLaunchKernelGGL(k_ns_gs_pair, dim3((rows[rp] + NS_PAIR_WAVES - 1) / NS_PAIR_WAVES),
+                               dim3(64 * NS_PAIR_WAVES), 0, h->st, L, rp);
     LAUNCHCHK();
     return BMG_OK;
 }
