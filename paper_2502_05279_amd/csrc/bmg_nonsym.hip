@@ -473,12 +473,23 @@ __global__ void k_band_expand_ldu(int nc, const double *__restrict__ Lb, const d
     if (l == 0) Dp[s] = s < m ? D[s] : 1.0;
 }
 
-// Sum of the partial sums in order (one thread).
-__global__ void k_ns_sum(const double *__restrict__ part, int np, double *__restrict__ out)
+// Sum of the np <= NPART_ROWS partial sums in order: the wave stages them in
+// LDS (16 loads in flight per lane), then lane 0 adds them up from there.
+__global__ __launch_bounds__(64) void k_ns_sum(const double *__restrict__ part, int np, double *__restrict__ out)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    static_assert(NPART_ROWS <= 16 * 64, "one round of loads stages the partials");
+    __shared__ double sp[NPART_ROWS];
+    const int lane = threadIdx.x;
+    double v[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = lane + 64 * k < np ? part[lane + 64 * k] : 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+        if (lane + 64 * k < np) sp[lane + 64 * k] = v[k];
+    __syncthreads();
+    if (lane != 0) return;
     double s = 0.0;
-    for (int t = 0; t < np; ++t) s += part[t];
+    for (int t = 0; t < np; ++t) s += sp[t];
     *out = s;
 }
 
