@@ -911,15 +911,42 @@ __device__ __forceinline__ T interp_point(const Wts<T> &C, const T *ec, int i, i
     return e;
 }
 
+// u += P e_c by coarse cells: thread (I, J) takes the fine points
+// (2I-1, 2J-1), (2I, 2J-1), (2I-1, 2J), (2I, 2J), I, J = 1 .. nc+1, whose
+// terms all use the weights and e_c around coarse index c = J ldc + I (the
+// expressions of interp_point), so a wave runs no divergent paths; fine
+// points on the ring (column or row n+1) are skipped.
 template <typename T>
 static __global__ void k_interp_add(Lev<T> L, Wts<T> C, const T *__restrict__ ec, const int *stop)
 {
     if (stopped(stop)) return;
-    const int i = 1 + blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = 1 + blockIdx.y * blockDim.y + threadIdx.y;
-    if (i > L.n || j > L.n) return;
-    const size_t p = (size_t)j * L.ld + i;
-    L.u[p] = L.u[p] + interp_point<T>(C, ec, i, j);
+    const int I = 1 + blockIdx.x * blockDim.x + threadIdx.x;
+    const int J = 1 + blockIdx.y * blockDim.y + threadIdx.y;
+    const int n = L.n, nc = (n - 1) / 2;
+    if (I > nc + 1 || J > nc + 1) return;
+    const int ldc = C.ld;
+    const size_t c = (size_t)J * ldc + I;
+    const T e00 = ec[c], e01 = ec[c - 1], e10 = ec[c - ldc], e11 = ec[c - ldc - 1];
+    const size_t p = (size_t)(2 * J - 1) * L.ld + (2 * I - 1);   // the odd-odd point
+    const bool east = 2 * I <= n, north = 2 * J <= n;
+    {
+        T e = C.at(LSW, c) * e11 + C.at(LSE, c) * e10;
+        e = e + C.at(LNW, c) * e01;
+        e = e + C.at(LNE, c) * e00;
+        L.u[p] = L.u[p] + e;
+    }
+    if (east) L.u[p + 1] = L.u[p + 1] + (C.at(LB, c) * e10 + C.at(LA, c) * e00);
+    if (north) L.u[p + L.ld] = L.u[p + L.ld] + (C.at(LL, c) * e01 + C.at(LR, c) * e00);
+    if (east && north) L.u[p + L.ld + 1] = L.u[p + L.ld + 1] + e00;
+}
+
+// k_interp_add over the coarse cells of fine level F.
+template <typename T>
+static inline void launch_interp_add(const Lev<T> &F, const Wts<T> &C, const T *ec, const int *stop, hipStream_t st)
+{
+    const int cells = (F.n - 1) / 2 + 1;
+    const dim3 blk(64, 4), grid((cells + 63) / 64, (cells + 3) / 4);
+    hipLaunchKernelGGL((k_interp_add<T>), grid, blk, 0, st, F, C, ec, stop);
 }
 
 // ------------------------------------------------------------ reductions

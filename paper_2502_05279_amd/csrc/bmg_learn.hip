@@ -746,8 +746,7 @@ void restrict_to(bmg_solver *h, const double *r, int ldf, const Wts<double> &C, 
 void interp_into(bmg_solver *h, Lev<double> F, double *u, const Wts<double> &C, const double *ec)
 {
     F.u = u;
-    hipLaunchKernelGGL((k_interp_add<double>), grid2(F.n, F.n, dim3(64, 4)), dim3(64, 4), 0, h->st, F, C, ec,
-                       nullptr);
+    launch_interp_add<double>(F, C, ec, nullptr, h->st);
 }
 
 }  // namespace

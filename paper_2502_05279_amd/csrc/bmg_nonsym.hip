@@ -646,8 +646,7 @@ bmg_status ns_restrict(bmg_ns *h, int l)
 bmg_status ns_interp(bmg_ns *h, int l)
 {
     const Lev<double> F = as_lev(h->L[l]);
-    hipLaunchKernelGGL((k_interp_add<double>), grid2(F.n, F.n, NB), NB, 0, h->st, F, h->P[l],
-                       (const double *)h->L[l + 1].u, nullptr);
+    launch_interp_add<double>(F, h->P[l], (const double *)h->L[l + 1].u, nullptr, h->st);
     LAUNCHCHK();
     return BMG_OK;
 }

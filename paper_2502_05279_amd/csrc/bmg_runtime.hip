@@ -379,7 +379,7 @@ bmg_status restrict_(bmg_solver *h, const Lev<T> &F, const Wts<T> &C, const Lev<
 template <typename T>
 bmg_status interp(bmg_solver *h, const Lev<T> &F, const Wts<T> &C, const Lev<T> &Cl, const int *stop)
 {
-    hipLaunchKernelGGL((k_interp_add<T>), grid2(F.n, F.n, B2), B2, 0, h->st, F, C, (const T *)Cl.u, stop);
+    launch_interp_add<T>(F, C, (const T *)Cl.u, stop, h->st);
     LAUNCHCHK();
     return BMG_OK;
 }
