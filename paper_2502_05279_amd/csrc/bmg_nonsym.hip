@@ -473,6 +473,26 @@ __global__ void k_band_expand_ldu(int nc, const double *__restrict__ Lb, const d
     if (l == 0) Dp[s] = s < m ? D[s] : 1.0;
 }
 
+// Partial sums of the squared residual of level 0 without storing it: the
+// rows, threads, loop order and block reduction of k_sumsq_partial over the
+// stored residual, and each r formed as k_ns_residual forms it, so the
+// partial sums are the same to the bit.
+__global__ __launch_bounds__(256) void k_ns_resid_sumsq(LevN L, double *__restrict__ part)
+{
+    double acc = 0.0;
+    const int n = L.n;
+    for (int j = 1 + blockIdx.x; j <= n; j += gridDim.x) {
+        for (int i = 1 + threadIdx.x; i <= n; i += blockDim.x) {
+            const size_t p = (size_t)j * L.ld + i;
+            double s = ns_offdiag(L, L.u, p);
+            s -= L.A[E_O][p] * L.u[p];
+            acc += s * s;
+        }
+    }
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
 // Sum of the np <= NPART_ROWS partial sums in order: the wave stages them in
 // LDS (16 loads in flight per lane), then lane 0 adds them up from there.
 __global__ __launch_bounds__(64) void k_ns_sum(const double *__restrict__ part, int np, double *__restrict__ out)
@@ -677,6 +697,17 @@ bmg_status ns_vcycle(bmg_ns *h, int l)
     return ns_gs(h, l, h->opt.nu2);
 }
 
+// sum of squares of level 0's residual into scal[slot] (the value of
+// ns_residual then ns_sumsq of r, without writing r)
+bmg_status ns_resnorm(bmg_ns *h, int slot)
+{
+    const int nb = std::min(NPART_ROWS, h->L[0].n);
+    hipLaunchKernelGGL(k_ns_resid_sumsq, dim3(nb), dim3(256), 0, h->st, h->L[0], h->part);
+    hipLaunchKernelGGL(k_ns_sum, dim3(1), dim3(64), 0, h->st, (const double *)h->part, nb, h->scal + slot);
+    LAUNCHCHK();
+    return BMG_OK;
+}
+
 // sum of squares of level 0's interior of x into scal[slot]
 bmg_status ns_sumsq(bmg_ns *h, const double *x, int slot)
 {
@@ -786,8 +817,7 @@ bmg_status bmg_ns_solve(bmg_ns *h, const double *rhs, double *x, double tol, bmg
         const double nb = sqrt(nb2);
         while (k < h->opt.max_cycles) {
             TRY(ns_vcycle(h, 0));
-            TRY(ns_residual(h, 0));
-            TRY(ns_sumsq(h, L.r, 1));
+            TRY(ns_resnorm(h, 1));
             double rr = 0.0;
             HIPCHK(hipMemcpyAsync(&rr, h->scal + 1, sizeof rr, hipMemcpyDeviceToHost, h->st));
             HIPCHK(hipStreamSynchronize(h->st));
